@@ -20,7 +20,10 @@ restated in the paper's order and notation:
 * Inner preconditioner of A_pipi: factorised sparse approximate inverse of
   -A_pipi on the lower pattern of A_pipi.
 * Stage 2: S~ = A_pp - H~, post-filtration, inner preconditioner of S~:
-  ILU(0) in a multicolour order.
+  ILU(0) in a multicolour order; its triangular solves are applied either
+  exactly or through incomplete sparse approximate inverses (ISAI) of the
+  two factors with optional refinement steps (a fully parallel substitute,
+  as the paper allows for the inner solvers).
 * Application (eq. EDFA_prec): t = A~^-1 r_pi; y = r_p - A_ppi t;
   z_p = S~^-1 y; z_pi = t - A~^-1 A_pip z_p.
 
@@ -65,6 +68,8 @@ class Params:
     it_max: int | None = None     # default n_ent
     tau: float = 0.0
     filt: str = "none"            # "none" | "pre" | "post_S" | "post_H"
+    schur: str = "isai"           # S~^-1 triangular solves: "isai" | "exact"
+    isai_steps: int = 1           # ISAI applications per triangular factor (1 = plain ISAI)
 
 
 class NotSPD(RuntimeError):
@@ -380,6 +385,28 @@ def ilu0(B: sp.csr_matrix):
     return L, U
 
 
+def isai(T: sp.csr_matrix):
+    """Incomplete sparse approximate inverse of a triangular factor on its own pattern.
+
+    Row i of M solves (T[P_i, P_i])^T m = e_i with P_i the pattern of row i of T
+    (diagonal included), so that (M T)_ij = delta_ij for j in P_i.
+    """
+    T = T.tocsr()
+    T.sort_indices()
+    rows, cols, vals = [], [], []
+    for i in range(T.shape[0]):
+        P = T.indices[T.indptr[i]:T.indptr[i + 1]]
+        sub = T[P][:, P].toarray()
+        e = np.zeros(len(P))
+        e[np.searchsorted(P, i)] = 1.0
+        m = np.linalg.solve(sub.T, e)
+        rows.append(np.full(len(P), i)); cols.append(P); vals.append(m)
+    M = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=T.shape)
+    M.sort_indices()
+    return M
+
+
 @dataclass
 class Stage2:
     S: sp.csr_matrix         # S~ (after post-filtration on S~ if requested)
@@ -387,6 +414,8 @@ class Stage2:
     perm: np.ndarray         # perm[new] = old
     L: sp.csr_matrix         # in the permuted order, strict lower part of the unit factor
     U: sp.csr_matrix         # in the permuted order, upper part with diagonal
+    ML: sp.csr_matrix = None  # ISAI of the unit lower factor (I + L)
+    MU: sp.csr_matrix = None  # ISAI of U
 
 
 def structural_sub(A: sp.csr_matrix, H: sp.csr_matrix):
@@ -414,7 +443,11 @@ def stage2(s: System, st1: Stage1, prm: Params) -> Stage2:
     perm = color_permutation(color)
     B = S[perm][:, perm].tocsr()
     L, U = ilu0(B)
-    return Stage2(S, color, perm, L, U)
+    ML = MU = None
+    if prm.schur == "isai":
+        Lf = (L + sp.eye(L.shape[0], format="csr")).tocsr()
+        ML, MU = isai(Lf), isai(U)
+    return Stage2(S, color, perm, L, U, ML, MU)
 
 
 # ----------------------------------------------------------------------------
@@ -437,7 +470,14 @@ class Edfa:
         return -(self.st1.GFt @ (self.st1.GF @ v))
 
     def apply_S_inv(self, y):
-        """S~^-1 y with the multicolour ILU(0): forward (unit L), backward (U)."""
+        """S~^-1 y with the multicolour ILU(0) factors.
+
+        "exact": forward (unit L) and backward (U) substitution.
+        "isai":  w = M_L b, then (steps-1) times w += M_L (b - (I+L) w); the same
+                 with M_U and U.
+        """
+        if self.prm.schur == "isai":
+            return self._apply_isai(y, transpose=False)
         L, U = self.st2.L, self.st2.U
         b = y[self.st2.perm]
         n = len(b)
@@ -453,8 +493,33 @@ class Edfa:
             z[i] = (w[i] - v[m] @ z[c[m]]) / d
         return z[self.inv_perm]
 
+    def _apply_isai(self, y, transpose):
+        st = self.st2
+        n = len(y)
+        Lf = (st.L + sp.eye(n, format="csr")).tocsr()
+        b = y[st.perm]
+        k = self.prm.isai_steps
+        if not transpose:
+            w = st.ML @ b
+            for _ in range(k - 1):
+                w = w + st.ML @ (b - Lf @ w)
+            z = st.MU @ w
+            for _ in range(k - 1):
+                z = z + st.MU @ (w - st.U @ z)
+        else:
+            # (M_U M_L)^T = M_L^T M_U^T with the refinement steps transposed
+            w = st.MU.T @ b
+            for _ in range(k - 1):
+                w = w + st.MU.T @ (b - st.U.T @ w)
+            z = st.ML.T @ w
+            for _ in range(k - 1):
+                z = z + st.ML.T @ (w - Lf.T @ z)
+        return z[self.inv_perm]
+
     def apply_S_inv_T(self, y):
         """S~^-T y: solve U^T w = b (forward), then L^T z = w (backward)."""
+        if self.prm.schur == "isai":
+            return self._apply_isai(y, transpose=True)
         L, U = self.st2.L, self.st2.U
         b = y[self.st2.perm]
         UT, LT = U.T.tocsr(), L.T.tocsr()
@@ -495,6 +560,8 @@ class Edfa:
         """mu of the paper (preconditioner density), with nnz(A~^-1) = nnz(G_F) + nnz(G_F^T)."""
         s = self.sys
         num = 2 * self.st1.GF.nnz + s.Apc.nnz + s.Acp.nnz + self.st2.L.nnz + self.st2.U.nnz
+        if self.prm.schur == "isai":
+            num += self.st2.ML.nnz + self.st2.MU.nnz
         den = s.App.nnz + s.Apc.nnz + s.Acp.nnz + s.Acc.nnz
         return num / den
 

@@ -231,7 +231,7 @@ def test_transposed_edfa_is_transpose_of_forward(small_full):
     """EDFA built on the transposed blocks (A_pipi, A_ppi^T, A_pip^T, A_pp^T) with the same initial
     pattern has G~' = F~^T, F~' = G~^T, H~' = H~^T, and its ILU(0) product is (LU)^T."""
     s = small_full
-    prm = edfa.Params("dynamic", n_add=1, n_ent=3)
+    prm = edfa.Params("dynamic", n_add=1, n_ent=3, schur="exact")
     fwd = edfa.build(s, prm)
     import copy
     st = copy.copy(s)
@@ -254,3 +254,41 @@ def test_transposed_edfa_is_transpose_of_forward(small_full):
     rng = np.random.default_rng(2)
     x, y = rng.standard_normal(N), rng.standard_normal(N)
     assert abs(y @ fwd.apply(x) - x @ fwd.apply_T(y)) < 1e-11 * np.linalg.norm(x) * np.linalg.norm(y) * 1e3
+
+
+@pytest.mark.parametrize("steps", [1, 2, 3])
+def test_isai_transposed_application(small_full, steps):
+    """y . P^-1 x = x . P^-T y for the ISAI variant with refinement steps."""
+    s = small_full
+    E = edfa.build(s, edfa.Params("dynamic", n_add=1, n_ent=3, isai_steps=steps))
+    rng = np.random.default_rng(steps)
+    x, y = rng.standard_normal(s.n), rng.standard_normal(s.n)
+    lhs, rhs = y @ E.apply(x), x @ E.apply_T(y)
+    assert abs(lhs - rhs) < 1e-10 * abs(lhs) + 1e-12
+
+
+def test_isai_defining_property(small_full):
+    """ISAI M of a triangular T: (M T)_ij = delta_ij for j in the pattern of row i of T."""
+    s = small_full
+    E = edfa.build(s, edfa.Params("static"))
+    n = s.ne
+    for T, M in (((E.st2.L + sp.eye(n)).tocsr(), E.st2.ML), (E.st2.U.tocsr(), E.st2.MU)):
+        MT = (M @ T).toarray()
+        Td = T.toarray()
+        mask = Td != 0
+        np.testing.assert_allclose(MT[mask], np.eye(n)[mask], atol=1e-12)
+        assert not np.any((M.toarray() != 0) & ~mask)
+
+
+def test_isai_refinement_approaches_exact_triangular_solves(small_full):
+    """ISAI with refinement steps converges to the exact ILU(0) triangular solves."""
+    s = small_full
+    Ex = edfa.build(s, edfa.Params("static", schur="exact"))
+    y = np.random.default_rng(9).standard_normal(s.ne)
+    ref = Ex.apply_S_inv(y)
+    errs = []
+    for k in (1, 2, 4, 8):
+        Ek = edfa.Edfa(s, edfa.Params("static", isai_steps=k), Ex.st1,
+                       edfa.stage2(s, Ex.st1, edfa.Params("static", isai_steps=k)))
+        errs.append(np.linalg.norm(Ek.apply_S_inv(y) - ref) / np.linalg.norm(ref))
+    assert errs[-1] < 1e-6 and all(b < a for a, b in zip(errs, errs[1:]))

@@ -1,0 +1,243 @@
+/*
+ * edfa.h -- C ABI of the MI355X (gfx950) EDFA-preconditioned GMRES library.
+ *
+ * Problem: the 2x2 block system of a mixed-hybrid finite element (Darcy) plus
+ * finite volume (mass balance) discretisation on logically structured
+ * hexahedral grids (Nardean, Ferronato, Abushaikha, "A novel block
+ * non-symmetric preconditioner for mixed-hybrid finite-element-based flow
+ * simulations", Section 2.3, eq. system):
+ *
+ *     [ A_pipi  A_pip ] [ pi ]   [ f_pi ]
+ *     [ A_ppi   A_pp  ] [ p  ] = [ f_p  ]
+ *
+ * preconditioned by the Explicit Decoupling Factor Approximation (Section 3,
+ * eq. EDFA_prec, Algorithms 1-2) inside restarted right-preconditioned GMRES.
+ *
+ * Conventions (every entry point):
+ *  - All array pointers are DEVICE pointers unless marked (host).
+ *  - The caller owns every buffer it passes; the library owns the opaque
+ *    handles (create / destroy) and all memory inside them.
+ *  - Work is enqueued on the given stream.  Entry points that must learn a
+ *    size or a convergence flag synchronise that stream (stated per call).
+ *  - Calls on one handle must not overlap in time (no internal locking).
+ *  - No exception crosses the ABI.  A negative status is an error, described
+ *    by edfa_last_error() (thread-local, valid until the next call on the
+ *    same thread); a positive status is a non-fatal outcome.
+ *  - Indices are int32, floating point is IEEE binary64 (double) unless a
+ *    parameter selects binary32 for the preconditioner.
+ *
+ * Grid layout (all inputs):
+ *  - nodes: (nx+1)(ny+1)(nz+1) x 3, node (i,j,k) at row i + (nx+1)(j + (ny+1)k).
+ *  - cells: nx*ny*nz, cell (i,j,k) at i + nx(j + ny k); local nodes a+2b+4c are
+ *    nodes (i+a, j+b, k+c); the cell is the trilinear image of the unit cube.
+ *  - faces: x-faces (i + (nx+1)(j + ny k)), then y-faces (i + nx(j + (ny+1)k)),
+ *    then z-faces (i + nx(j + ny k)).  Local faces of a cell: 0 x-, 1 x+,
+ *    2 y-, 3 y+, 4 z-, 5 z+.
+ *  - unknowns u = [pi over non-Dirichlet faces, ascending face index;
+ *                  p over cells]  (Dirichlet face pressures are eliminated).
+ *    For a batch of grids, faces and cells are concatenated grid by grid and
+ *    u = [pi of all grids; p of all grids].
+ */
+#ifndef EDFA_H
+#define EDFA_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  EDFA_OK = 0,
+  EDFA_NOT_CONVERGED = 1,      /* the paper's "NC" (Section 4): x holds the last iterate */
+  EDFA_ERR_ARG = -1,           /* invalid argument or inconsistent sizes */
+  EDFA_ERR_HIP = -2,           /* a HIP runtime call failed */
+  EDFA_ERR_NOMEM = -3,         /* device allocation failed */
+  EDFA_ERR_NOT_SPD = -4,       /* a restricted system (or W^E) lost positive definiteness;
+                                  the first offending cell index is in edfa_last_error() */
+  EDFA_ERR_BREAKDOWN = -5,     /* zero pivot in ILU(0) or a non-finite Krylov quantity */
+  EDFA_ERR_NAN = -6,           /* non-finite input */
+  EDFA_ERR_CAPACITY = -7       /* a pattern exceeded a compiled maximum (message says which) */
+} edfa_status;
+
+typedef struct edfa_system_s *edfa_system;    /* assembled blocks + right-hand side */
+typedef struct edfa_precond_s *edfa_precond;  /* EDFA stage-1 and stage-2 data */
+
+/* Boundary condition code per face (ignored on interior faces). */
+#define EDFA_BC_NEUMANN   0   /* prescribed outward total face flux (0 = no flow) */
+#define EDFA_BC_DIRICHLET 1   /* prescribed face pressure */
+
+/* One grid.  Section 2.1-2.2: Darcy's law with conductivity K and specific
+ * weight gamma, mass balance with storage c, backward Euler with step dt.   */
+typedef struct {
+  int32_t nx, ny, nz;          /* cells per direction, each >= 1 */
+  const double *nodes;         /* (nx+1)(ny+1)(nz+1) x 3 coordinates */
+  const double *K;             /* N_e x 6 SPD tensor per cell: xx, yy, zz, xy, xz, yz */
+  const double *c;             /* N_e storage coefficient, or NULL to use c_scalar */
+  double c_scalar;
+  double gamma;                /* fluid specific weight (> 0) */
+  double dt;                   /* time step (> 0) */
+  const int8_t *bc_type;       /* N_f codes EDFA_BC_* */
+  const double *bc_value;      /* N_f: p_bar (Dirichlet) or outward total flux (Neumann) */
+  const double *p_prev;        /* N_e pressure at the previous step, or NULL for 0 */
+  const double *source;        /* N_e cell-mean source density s, or NULL for 0 */
+} edfa_problem;
+
+/* Sizes of an assembled system (host struct). */
+typedef struct {
+  int32_t n_grids;
+  int32_t n_cells;             /* N_e */
+  int32_t n_faces;             /* N_f (all faces) */
+  int32_t n_face_unknowns;     /* N_f^u (non-Dirichlet faces) */
+  int32_t n;                   /* N = N_f^u + N_e */
+  int32_t axis_structure;      /* 1: every cell an axis-aligned brick with diagonal K, so
+                                  W^E is block-diagonal per direction (smaller patterns) */
+  int64_t nnz;                 /* nnz of the whole matrix */
+  int64_t nnz_block[4];        /* A_pipi, A_pip, A_ppi, A_pp */
+} edfa_system_info;
+
+/* Assemble the block system (Section 2.2-2.3 and Appendix A).
+ *  - Element matrices B^E (eq. B_ij) by 3x3x3 Gauss quadrature of the
+ *    Piola-mapped lowest-order Raviart-Thomas basis; W^E = (B^E)^-1.
+ *  - Face rows: flux continuity (eq. cont_fluxes); Neumann faces take the
+ *    prescribed flux.  Cell rows: FV balance (eq. discr_bal_FV_2) with the
+ *    strong inter-element flux (eq. fluxes_MHFEM_STRONG); at a Dirichlet face
+ *    the one-sided flux with pi = p_bar, at a Neumann face its prescribed flux.
+ *  - Structural patterns (explicit zeros kept): A_pipi couples faces sharing a
+ *    cell through a structural entry of W^E; A_ppi row E holds E's own faces and
+ *    the faces of each face neighbour coupled to the shared face.
+ * count >= 1 grids (a batch is one block-diagonal system).  Input arrays are
+ * read during the call only.  Synchronises the stream.
+ * Errors: EDFA_ERR_ARG (sizes), EDFA_ERR_NOT_SPD (K or a Jacobian not
+ * positive: cell index in the message), EDFA_ERR_NOMEM. */
+edfa_status edfa_assemble(const edfa_problem *grids /* (host) array */, int32_t count,
+                          hipStream_t stream, edfa_system *out);
+void edfa_system_destroy(edfa_system sys);
+edfa_status edfa_system_get_info(edfa_system sys, edfa_system_info *info /* (host) */);
+
+/* Replace dt (and optionally p_prev, N_e, NULL keeps it) of every grid: only A_pp's
+ * diagonal and f_p change (Appendix A, eq. expr_A_pp).  Asynchronous. */
+edfa_status edfa_update_dt(edfa_system sys, double dt, const double *p_prev, hipStream_t stream);
+
+/* Copy out a block: 0 A_pipi, 1 A_pip, 2 A_ppi, 3 A_pp, 4 the whole matrix.
+ * Buffers sized from edfa_system_get_info: rowptr rows+1, col/val nnz.
+ * Columns are sorted within rows.  Asynchronous. */
+edfa_status edfa_export_block(edfa_system sys, int32_t block, int32_t *rowptr, int32_t *col,
+                              double *val, hipStream_t stream);
+/* Copy out the right-hand side b (N) and the per-cell W^E (N_e x 36, row-major)
+ * and volumes (N_e); any pointer may be NULL.  Asynchronous. */
+edfa_status edfa_export_rhs(edfa_system sys, double *b, double *W, double *vol,
+                            hipStream_t stream);
+
+/* y = A x (transpose = 0) or y = A^T x (transpose = 1), x and y of length N.  FP64. */
+edfa_status edfa_spmv(edfa_system sys, int32_t transpose, const double *x, double *y,
+                      hipStream_t stream);
+
+/* EDFA parameters (Section 3.1; Algorithm 1 and 2 signatures). */
+#define EDFA_STATIC  0
+#define EDFA_DYNAMIC 1
+#define EDFA_FILT_NONE   0
+#define EDFA_FILT_PRE    1   /* filter g~ and f~ before assembling G~, F~ */
+#define EDFA_FILT_POST_S 2   /* filter S~ = A_pp - H~ (stage 2) */
+#define EDFA_FILT_POST_H 3   /* filter H~ (stage 1) */
+#define EDFA_SCHUR_ISAI  0   /* ILU(0) factors applied through sparse approximate inverses */
+#define EDFA_SCHUR_EXACT 1   /* ILU(0) factors applied by colour-by-colour substitution */
+typedef struct {
+  int32_t variant;          /* EDFA_STATIC | EDFA_DYNAMIC */
+  int32_t static_level;     /* static: 0 = base pattern Q_0 (pattern of row m of A_ppi);
+                               k > 0 adds all faces of cells within k face-neighbour steps */
+  int32_t n_add;            /* dynamic: max entries added per sweep */
+  int32_t n_ent;            /* dynamic: max entries added in total */
+  int32_t it_max;           /* dynamic: max sweeps, <= 0 means n_ent */
+  double  tau_filt;         /* relative drop tolerance (Euclidean norm of the row/column) */
+  int32_t filt_mode;        /* EDFA_FILT_* */
+  int32_t precision;        /* 0: FP64 preconditioner; 1: FP32 setup and application */
+  int32_t schur_solver;     /* EDFA_SCHUR_* */
+  int32_t isai_steps;       /* ISAI applications per factor (>= 1) */
+} edfa_params;
+
+/* Preconditioner sizes and diagnostics (host struct). */
+typedef struct {
+  int64_t nnz_G, nnz_F, nnz_H, nnz_S, nnz_GF, nnz_L, nnz_U, nnz_ML, nnz_MU;
+  int32_t n_colors;
+  int32_t max_pattern;      /* largest |Q^(m)| */
+  double  mu;               /* preconditioner density of Section 4 (nnz of the inner
+                               inverses counted as stored: 2 nnz(G_F), L, U and the ISAI) */
+  double  t_stage1_ms, t_stage2_ms;   /* device time of the last setup */
+} edfa_precond_info;
+
+/* Build the preconditioner: stage 1 (Algorithm 1: restricted SPD solves on static or
+ * dynamically grown patterns, pre-filtration, H~ = G~ A_pipi F~, post-filtration on H~,
+ * FSAI of -A_pipi) and stage 2 (Algorithm 2: S~ = A_pp - H~, post-filtration on S~,
+ * multicolour ILU(0) of S~ and its sparse approximate inverses).  Synchronises the stream.
+ * Errors: EDFA_ERR_NOT_SPD (cell index), EDFA_ERR_BREAKDOWN (ILU zero pivot),
+ * EDFA_ERR_CAPACITY (pattern or H~ row longer than compiled maxima). */
+edfa_status edfa_setup(edfa_system sys, const edfa_params *prm /* (host) */,
+                       hipStream_t stream, edfa_precond *out);
+/* Re-run stage 2 only, after edfa_update_dt (stage 1 is recycled, Section 3.1). */
+edfa_status edfa_setup_stage2(edfa_precond pre, hipStream_t stream);
+void edfa_precond_destroy(edfa_precond pre);
+edfa_status edfa_precond_get_info(edfa_precond pre, edfa_precond_info *info /* (host) */);
+
+/* Export a stage-1/2 artefact as CSR (rowptr rows+1, col, val; val converted to FP64):
+ * 0 G~ (N_e x N_f^u), 1 F~^T (N_e x N_f^u, row m = column m of F~), 2 H~ before
+ * post-filtration, 3 H~, 4 S~, 5 G_F (FSAI factor), 6 L (strict lower, colour order),
+ * 7 U (colour order), 8 M_L, 9 M_U.  Query sizes with rowptr == NULL: then *nnz (host)
+ * and *rows (host) are set and nothing is copied.  perm (N_e, may be NULL) receives
+ * perm[new] = old of the colour order when what is 6..9.  Synchronises the stream. */
+edfa_status edfa_export_precond(edfa_precond pre, int32_t what, int32_t *rowptr, int32_t *col,
+                                double *val, int32_t *perm, int64_t *nnz, int32_t *rows,
+                                hipStream_t stream);
+
+/* z = P^-1 r (transpose = 0, eq. EDFA_prec) or z = P^-T r (transpose = 1).  N-vectors.
+ * Asynchronous. */
+edfa_status edfa_apply(edfa_precond pre, int32_t transpose, const double *r, double *z,
+                       hipStream_t stream);
+
+typedef struct {
+  int32_t restart;          /* Krylov dimension per cycle (GMRES(m)), 1..128 */
+  int32_t max_iter;         /* total iterations over all cycles */
+  int32_t flexible;         /* 1: flexible GMRES (stores Z); required when precision = 1 */
+  int32_t transpose;        /* 1: solve A^T x = b with P^-T */
+  int32_t use_graph;        /* 1: capture each cycle's launches in a hipGraph and replay */
+  int32_t profile;          /* 1: time every launch of the dominant kernels with events */
+  double  rtol;             /* stop when ||b - A x|| <= rtol ||b|| (x0 = 0, Section 4) */
+} edfa_solve_params;
+
+typedef struct {
+  int32_t iterations;       /* max over grids of the total inner iterations */
+  int32_t converged;        /* number of grids converged */
+  int32_t cycles;
+  double  relres_est;       /* max over grids of the Arnoldi estimate / ||b|| */
+  double  relres_true;      /* max over grids of the FP64 ||b - A x|| / ||b|| */
+  double  t_solve_ms;       /* device time of the solve */
+  double  spmv_avg_ms;      /* profile = 1: mean duration of one SpMV with A */
+  int32_t spmv_count;
+  double  apply_avg_ms;     /* profile = 1: mean duration of one preconditioner application */
+  int32_t apply_count;
+} edfa_solve_info;
+
+/* Solve A x = b (or A^T x = b) by restarted right-preconditioned GMRES, x0 = 0, each grid
+ * of a batch to its own rtol.  b, x: N-vectors (x output only).  Synchronises the stream
+ * once per restart cycle.  Returns EDFA_OK when every grid converged on its true FP64
+ * residual, EDFA_NOT_CONVERGED otherwise (x = last iterate). */
+edfa_status edfa_solve(edfa_system sys, edfa_precond pre, const double *b, double *x,
+                       const edfa_solve_params *prm /* (host) */, hipStream_t stream,
+                       edfa_solve_info *info /* (host), may be NULL */);
+
+/* Per-cell gradient of a scalar loss L(u) with respect to theta_E = ln(multiplier of K^E),
+ * given the forward solution u and the adjoint lambda solving A^T lambda = dL/du:
+ *   dL/dtheta_E = -lambda^T dR/dtheta_E,  R(u) = A u - b,
+ * where dq^E/dtheta_E = q^E for the local fluxes (eq. fluxes_MHFEM_3) and the strong
+ * flux (eq. fluxes_MHFEM_STRONG) varies as q_i W'_ii / (W_ii + W'_ii).  g: N_e.
+ * Asynchronous. */
+edfa_status edfa_grad_logk(edfa_system sys, const double *u, const double *lambda, double *g,
+                           hipStream_t stream);
+
+const char *edfa_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EDFA_H */

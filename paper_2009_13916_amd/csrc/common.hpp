@@ -1,0 +1,133 @@
+// Internal helpers of the EDFA library: errors, device buffers, launch shapes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "edfa.h"
+
+namespace edfa {
+
+struct Error {
+  edfa_status status;
+  std::string msg;
+};
+
+[[noreturn]] void fail(edfa_status st, const char *fmt, ...);
+void set_last_error(const std::string &msg);
+
+#define EDFA_HIP(call)                                                                   \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      ::edfa::fail(e_ == hipErrorOutOfMemory ? EDFA_ERR_NOMEM : EDFA_ERR_HIP, "%s: %s (%s:%d)", \
+                   #call, hipGetErrorString(e_), __FILE__, __LINE__);                    \
+  } while (0)
+
+#define EDFA_CHECK_LAUNCH() EDFA_HIP(hipGetLastError())
+
+// Growable device buffer owned by a handle.  ensure() keeps the allocation when it is
+// already large enough, so repeated setups reuse memory.
+template <class T>
+struct DBuf {
+  T *p = nullptr;
+  size_t cap = 0;
+  size_t n = 0;
+  DBuf() = default;
+  DBuf(const DBuf &) = delete;
+  DBuf &operator=(const DBuf &) = delete;
+  DBuf(DBuf &&o) noexcept : p(o.p), cap(o.cap), n(o.n) { o.p = nullptr; o.cap = o.n = 0; }
+  ~DBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = n = 0;
+  }
+  T *ensure(size_t count) {
+    n = count;
+    if (count <= cap && p) return p;
+    release();
+    size_t bytes = (count ? count : 1) * sizeof(T);
+    EDFA_HIP(hipMalloc(&p, bytes));
+    cap = count ? count : 1;
+    n = count;
+    return p;
+  }
+  T *get() const { return p; }
+  operator T *() const { return p; }
+};
+
+// CSR matrix in device memory (int32 indices).
+template <class V>
+struct Csr {
+  int rows = 0, cols = 0;
+  int64_t nnz = 0;
+  DBuf<int> rowptr;
+  DBuf<int> col;
+  DBuf<V> val;
+  void alloc(int r, int c, int64_t z) {
+    rows = r;
+    cols = c;
+    nnz = z;
+    rowptr.ensure((size_t)r + 1);
+    col.ensure((size_t)z);
+    val.ensure((size_t)z);
+  }
+};
+
+inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+// Host read of one device scalar (synchronises the stream).
+template <class T>
+T read_scalar(const T *dptr, hipStream_t s) {
+  T v{};
+  EDFA_HIP(hipMemcpyAsync(&v, dptr, sizeof(T), hipMemcpyDeviceToHost, s));
+  EDFA_HIP(hipStreamSynchronize(s));
+  return v;
+}
+
+// Events for device-side timing on a stream.
+struct EventTimer {
+  hipEvent_t a{}, b{};
+  EventTimer() {
+    EDFA_HIP(hipEventCreate(&a));
+    EDFA_HIP(hipEventCreate(&b));
+  }
+  ~EventTimer() {
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+  }
+  void start(hipStream_t s) { EDFA_HIP(hipEventRecord(a, s)); }
+  void stop(hipStream_t s) { EDFA_HIP(hipEventRecord(b, s)); }
+  float ms() {
+    EDFA_HIP(hipEventSynchronize(b));
+    float t = 0;
+    EDFA_HIP(hipEventElapsedTime(&t, a, b));
+    return t;
+  }
+};
+
+// ---------------------------------------------------------------------------------
+// Primitive device algorithms (sparse.hip)
+// ---------------------------------------------------------------------------------
+// Exclusive prefix sum of n int32 values into out (out may alias in); returns the total
+// (synchronises the stream).  tmp is scratch owned by the caller.
+int64_t exclusive_scan(const int *in, int *out, int n, DBuf<int> &tmp, hipStream_t s);
+// Same, without reading the total back (asynchronous).
+void exclusive_scan_async(const int *in, int *out, int n, DBuf<int> &tmp, hipStream_t s);
+
+// Transpose of a CSR matrix (rows x cols) into dst (cols x rows), columns sorted.
+template <class V>
+void csr_transpose(const Csr<V> &src, Csr<V> &dst, DBuf<int> &tmp, hipStream_t s);
+
+// y[i] = beta * b[i] + alpha * (A x)[i]   (b may be null: then y = alpha A x).
+// A in CSR with values V, vectors of type X; accumulation in the wider of V and X.
+template <class V, class X>
+void spmv(const int *rowptr, const int *col, const V *val, int rows, const X *x, X *y,
+          double alpha, const X *b, double beta, float avg_nnz, hipStream_t s);
+
+}  // namespace edfa

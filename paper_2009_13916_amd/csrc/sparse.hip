@@ -1,0 +1,218 @@
+// Primitive device algorithms: prefix sums, CSR transpose, CSR SpMV.
+#include "common.hpp"
+
+namespace edfa {
+
+// ----------------------------------------------------------------------------------
+// Exclusive scan.  Tiles of 2048 int32 per 256-thread block, tile totals scanned
+// recursively.  The output has n_out = n_in + 1 slots so that out[n_in] is the total.
+// ----------------------------------------------------------------------------------
+constexpr int SCAN_T = 256;
+constexpr int SCAN_I = 8;
+constexpr int SCAN_TILE = SCAN_T * SCAN_I;
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_tile(const int *__restrict__ in, int *out,
+                                                      int n_in, int n_out, int *totals) {
+  __shared__ int sh[SCAN_T];
+  const int tid = threadIdx.x;
+  const long long base = (long long)blockIdx.x * SCAN_TILE + (long long)tid * SCAN_I;
+  int v[SCAN_I];
+  int sum = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_I; ++i) {
+    long long idx = base + i;
+    int x = (idx < n_in) ? in[idx] : 0;
+    v[i] = sum;
+    sum += x;
+  }
+  sh[tid] = sum;
+  __syncthreads();
+  for (int off = 1; off < SCAN_T; off <<= 1) {
+    int t = (tid >= off) ? sh[tid - off] : 0;
+    __syncthreads();
+    sh[tid] += t;
+    __syncthreads();
+  }
+  const int excl = sh[tid] - sum;
+#pragma unroll
+  for (int i = 0; i < SCAN_I; ++i) {
+    long long idx = base + i;
+    if (idx < n_out) out[idx] = v[i] + excl;
+  }
+  if (tid == SCAN_T - 1) totals[blockIdx.x] = sh[SCAN_T - 1];
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_add(int *out, int n, const int *__restrict__ offs) {
+  const int add = offs[blockIdx.x];
+  const long long base = (long long)blockIdx.x * SCAN_TILE;
+  for (int i = threadIdx.x; i < SCAN_TILE; i += SCAN_T) {
+    long long idx = base + i;
+    if (idx < n) out[idx] += add;
+  }
+}
+
+static size_t scan_tmp_size(long long n) {
+  size_t s = 0;
+  long long m = n;
+  do {
+    m = (m + SCAN_TILE - 1) / SCAN_TILE;
+    s += (size_t)m + 1;
+  } while (m > 1);
+  return s + 16;
+}
+
+static void scan_rec(const int *in, int *out, int n_in, int n_out, int *tmp, hipStream_t s) {
+  const int nb = ceil_div(n_out, SCAN_TILE);
+  int *totals = tmp;
+  hipLaunchKernelGGL(k_scan_tile, dim3(nb), dim3(SCAN_T), 0, s, in, out, n_in, n_out, totals);
+  EDFA_CHECK_LAUNCH();
+  if (nb > 1) {
+    scan_rec(totals, totals, nb, nb, tmp + nb + 1, s);
+    hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(SCAN_T), 0, s, out, n_out, totals);
+    EDFA_CHECK_LAUNCH();
+  }
+}
+
+void exclusive_scan_async(const int *in, int *out, int n, DBuf<int> &tmp, hipStream_t s) {
+  if (n < 0) fail(EDFA_ERR_ARG, "scan of negative length");
+  tmp.ensure(scan_tmp_size((long long)n + 1));
+  scan_rec(in, out, n, n + 1, tmp.p, s);
+}
+
+int64_t exclusive_scan(const int *in, int *out, int n, DBuf<int> &tmp, hipStream_t s) {
+  exclusive_scan_async(in, out, n, tmp, s);
+  return read_scalar(out + n, s);
+}
+
+// ----------------------------------------------------------------------------------
+// CSR transpose: count per column, scan, scatter with atomic cursors, sort each row.
+// ----------------------------------------------------------------------------------
+__global__ void k_count_cols(const int *__restrict__ col, int64_t nnz, int *cnt) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nnz) atomicAdd(&cnt[col[k]], 1);
+}
+
+template <class V>
+__global__ void k_transpose_fill(const int *__restrict__ rowptr, const int *__restrict__ col,
+                                 const V *__restrict__ val, int rows, int *cursor, int *colT,
+                                 V *valT) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  for (int k = rowptr[r]; k < rowptr[r + 1]; ++k) {
+    int pos = atomicAdd(&cursor[col[k]], 1);
+    colT[pos] = r;
+    valT[pos] = val[k];
+  }
+}
+
+// Sort the entries of each row by column (insertion sort; rows are short).
+template <class V>
+__global__ void k_sort_rows(const int *__restrict__ rowptr, int rows, int *col, V *val) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  const int a = rowptr[r], b = rowptr[r + 1];
+  for (int i = a + 1; i < b; ++i) {
+    int c = col[i];
+    V v = val[i];
+    int j = i - 1;
+    while (j >= a && col[j] > c) {
+      col[j + 1] = col[j];
+      val[j + 1] = val[j];
+      --j;
+    }
+    col[j + 1] = c;
+    val[j + 1] = v;
+  }
+}
+
+template <class V>
+void csr_transpose(const Csr<V> &src, Csr<V> &dst, DBuf<int> &tmp, hipStream_t s) {
+  dst.alloc(src.cols, src.rows, src.nnz);
+  EDFA_HIP(hipMemsetAsync(dst.rowptr.p, 0, sizeof(int) * ((size_t)src.cols + 1), s));
+  if (src.nnz > 0) {
+    hipLaunchKernelGGL(k_count_cols, dim3(ceil_div(src.nnz, 256)), dim3(256), 0, s, src.col.p,
+                       src.nnz, dst.rowptr.p);
+    EDFA_CHECK_LAUNCH();
+  }
+  exclusive_scan_async(dst.rowptr.p, dst.rowptr.p, src.cols, tmp, s);
+  DBuf<int> cursor;
+  cursor.ensure((size_t)src.cols + 1);
+  EDFA_HIP(hipMemcpyAsync(cursor.p, dst.rowptr.p, sizeof(int) * ((size_t)src.cols + 1),
+                          hipMemcpyDeviceToDevice, s));
+  if (src.rows > 0) {
+    hipLaunchKernelGGL(k_transpose_fill<V>, dim3(ceil_div(src.rows, 256)), dim3(256), 0, s,
+                       src.rowptr.p, src.col.p, src.val.p, src.rows, cursor.p, dst.col.p,
+                       dst.val.p);
+    EDFA_CHECK_LAUNCH();
+  }
+  if (src.cols > 0) {
+    hipLaunchKernelGGL(k_sort_rows<V>, dim3(ceil_div(src.cols, 256)), dim3(256), 0, s,
+                       dst.rowptr.p, src.cols, dst.col.p, dst.val.p);
+    EDFA_CHECK_LAUNCH();
+  }
+  EDFA_HIP(hipStreamSynchronize(s));   // cursor is released on return
+}
+
+template void csr_transpose<double>(const Csr<double> &, Csr<double> &, DBuf<int> &, hipStream_t);
+template void csr_transpose<float>(const Csr<float> &, Csr<float> &, DBuf<int> &, hipStream_t);
+
+// ----------------------------------------------------------------------------------
+// SpMV: a group of LANES lanes per row, shuffle reduction inside the group.
+// ----------------------------------------------------------------------------------
+template <class V, class X> struct AccT { using type = double; };
+template <> struct AccT<float, float> { using type = float; };
+
+template <class V, class X, int LANES>
+__global__ __launch_bounds__(256) void k_spmv(const int *__restrict__ rowptr,
+                                              const int *__restrict__ col,
+                                              const V *__restrict__ val, int rows,
+                                              const X *__restrict__ x, X *__restrict__ y,
+                                              double alpha, const X *__restrict__ b,
+                                              double beta) {
+  using A = typename AccT<V, X>::type;
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int row = (int)(gid / LANES);
+  const int lane = (int)(gid % LANES);
+  if (row >= rows) return;
+  A sum = 0;
+  const int end = rowptr[row + 1];
+  for (int k = rowptr[row] + lane; k < end; k += LANES) sum += (A)val[k] * (A)x[col[k]];
+#pragma unroll
+  for (int off = LANES / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, LANES);
+  if (lane == 0) {
+    A r = (A)alpha * sum;
+    if (b) r += (A)beta * (A)b[row];
+    y[row] = (X)r;
+  }
+}
+
+template <class V, class X>
+void spmv(const int *rowptr, const int *col, const V *val, int rows, const X *x, X *y,
+          double alpha, const X *b, double beta, float avg_nnz, hipStream_t s) {
+  if (rows <= 0) return;
+  auto launch = [&](auto kern, int lanes) {
+    long long threads = (long long)rows * lanes;
+    hipLaunchKernelGGL(kern, dim3(ceil_div(threads, 256)), dim3(256), 0, s, rowptr, col, val,
+                       rows, x, y, alpha, b, beta);
+    EDFA_CHECK_LAUNCH();
+  };
+  if (avg_nnz <= 3.f)
+    launch(k_spmv<V, X, 2>, 2);
+  else if (avg_nnz <= 6.f)
+    launch(k_spmv<V, X, 4>, 4);
+  else if (avg_nnz <= 14.f)
+    launch(k_spmv<V, X, 8>, 8);
+  else if (avg_nnz <= 40.f)
+    launch(k_spmv<V, X, 16>, 16);
+  else
+    launch(k_spmv<V, X, 32>, 32);
+}
+
+template void spmv<double, double>(const int *, const int *, const double *, int, const double *,
+                                   double *, double, const double *, double, float, hipStream_t);
+template void spmv<float, float>(const int *, const int *, const float *, int, const float *,
+                                 float *, double, const float *, double, float, hipStream_t);
+template void spmv<float, double>(const int *, const int *, const float *, int, const double *,
+                                  double *, double, const double *, double, float, hipStream_t);
+
+}  // namespace edfa

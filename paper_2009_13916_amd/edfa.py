@@ -1,0 +1,296 @@
+"""Python binding of libedfa (ctypes).  Argument marshalling only: every step of the
+assembly, setup and solve runs in the HIP library.  Torch supplies device memory and
+the current stream.
+
+The library must have been built (``python -m paper_2009_13916_amd.build`` or
+``__graft_entry__.build()``); importing this module without it raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libedfa.so")
+
+OK, NOT_CONVERGED = 0, 1
+
+STATIC, DYNAMIC = 0, 1
+FILT = {"none": 0, "pre": 1, "post_S": 2, "post_H": 3}
+SCHUR = {"isai": 0, "exact": 1}
+
+BLOCK = {"App": 0, "Apc": 1, "Acp": 2, "Acc": 3, "A": 4}
+PRECOND_ART = {"G": 0, "FT": 1, "H_raw": 2, "H": 3, "S": 4, "GF": 5, "L": 6, "U": 7, "ML": 8, "MU": 9}
+
+
+class EdfaError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"libedfa status {status}: {msg}")
+        self.status = status
+
+
+class _Problem(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("nodes", C.c_void_p), ("K", C.c_void_p), ("c", C.c_void_p),
+                ("c_scalar", C.c_double), ("gamma", C.c_double), ("dt", C.c_double),
+                ("bc_type", C.c_void_p), ("bc_value", C.c_void_p),
+                ("p_prev", C.c_void_p), ("source", C.c_void_p)]
+
+
+class _SystemInfo(C.Structure):
+    _fields_ = [("n_grids", C.c_int32), ("n_cells", C.c_int32), ("n_faces", C.c_int32),
+                ("n_face_unknowns", C.c_int32), ("n", C.c_int32), ("axis_structure", C.c_int32),
+                ("nnz", C.c_int64), ("nnz_block", C.c_int64 * 4)]
+
+
+class _Params(C.Structure):
+    _fields_ = [("variant", C.c_int32), ("static_level", C.c_int32), ("n_add", C.c_int32),
+                ("n_ent", C.c_int32), ("it_max", C.c_int32), ("tau_filt", C.c_double),
+                ("filt_mode", C.c_int32), ("precision", C.c_int32),
+                ("schur_solver", C.c_int32), ("isai_steps", C.c_int32)]
+
+
+class _PrecondInfo(C.Structure):
+    _fields_ = [("nnz_G", C.c_int64), ("nnz_F", C.c_int64), ("nnz_H", C.c_int64),
+                ("nnz_S", C.c_int64), ("nnz_GF", C.c_int64), ("nnz_L", C.c_int64),
+                ("nnz_U", C.c_int64), ("nnz_ML", C.c_int64), ("nnz_MU", C.c_int64),
+                ("n_colors", C.c_int32), ("max_pattern", C.c_int32), ("mu", C.c_double),
+                ("t_stage1_ms", C.c_double), ("t_stage2_ms", C.c_double)]
+
+
+class _SolveParams(C.Structure):
+    _fields_ = [("restart", C.c_int32), ("max_iter", C.c_int32), ("flexible", C.c_int32),
+                ("transpose", C.c_int32), ("use_graph", C.c_int32), ("profile", C.c_int32),
+                ("rtol", C.c_double)]
+
+
+class _SolveInfo(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("cycles", C.c_int32),
+                ("relres_est", C.c_double), ("relres_true", C.c_double),
+                ("t_solve_ms", C.c_double), ("spmv_avg_ms", C.c_double),
+                ("spmv_count", C.c_int32), ("apply_avg_ms", C.c_double),
+                ("apply_count", C.c_int32)]
+
+
+_lib = None
+
+
+def load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build the HIP library first")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        sig = {
+            "edfa_last_error": (C.c_char_p, []),
+            "edfa_assemble": (C.c_int, [C.POINTER(_Problem), i32, vp, C.POINTER(vp)]),
+            "edfa_system_destroy": (None, [vp]),
+            "edfa_system_get_info": (C.c_int, [vp, C.POINTER(_SystemInfo)]),
+            "edfa_update_dt": (C.c_int, [vp, d, vp, vp]),
+            "edfa_export_block": (C.c_int, [vp, i32, vp, vp, vp, vp]),
+            "edfa_export_rhs": (C.c_int, [vp, vp, vp, vp, vp]),
+            "edfa_spmv": (C.c_int, [vp, i32, vp, vp, vp]),
+            "edfa_setup": (C.c_int, [vp, C.POINTER(_Params), vp, C.POINTER(vp)]),
+            "edfa_setup_stage2": (C.c_int, [vp, vp]),
+            "edfa_precond_destroy": (None, [vp]),
+            "edfa_precond_get_info": (C.c_int, [vp, C.POINTER(_PrecondInfo)]),
+            "edfa_export_precond": (C.c_int, [vp, i32, vp, vp, vp, vp, C.POINTER(i64),
+                                              C.POINTER(i32), vp]),
+            "edfa_apply": (C.c_int, [vp, i32, vp, vp, vp]),
+            "edfa_solve": (C.c_int, [vp, vp, vp, vp, C.POINTER(_SolveParams), vp,
+                                     C.POINTER(_SolveInfo)]),
+            "edfa_grad_logk": (C.c_int, [vp, vp, vp, vp, vp]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name, None)
+            if fn is None:
+                continue
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    """Names of the entry points the loaded library exports (for the ABI test)."""
+    L = load()
+    return [n for n in ("edfa_last_error", "edfa_assemble", "edfa_system_destroy",
+                        "edfa_system_get_info", "edfa_update_dt", "edfa_export_block",
+                        "edfa_export_rhs", "edfa_spmv", "edfa_setup", "edfa_setup_stage2",
+                        "edfa_precond_destroy", "edfa_precond_get_info", "edfa_export_precond",
+                        "edfa_apply", "edfa_solve", "edfa_grad_logk") if hasattr(L, n)]
+
+
+def _check(st):
+    if st < 0:
+        raise EdfaError(st, load().edfa_last_error().decode())
+    return st
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def _dev(a, dtype):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).cuda()
+
+
+class System:
+    """An assembled block system (one grid or a block-diagonal batch of grids)."""
+
+    def __init__(self, problems):
+        if not isinstance(problems, (list, tuple)):
+            problems = [problems]
+        keep = []
+        arr = (_Problem * len(problems))()
+        for i, p in enumerate(problems):
+            t = {k: _dev(getattr(p, k), torch.float64) for k in ("nodes", "K", "c", "bc_value", "p_prev", "source")}
+            t["bc_type"] = _dev(p.bc_type, torch.int8)
+            keep.append(t)
+            arr[i] = _Problem(p.nx, p.ny, p.nz, t["nodes"].data_ptr(), t["K"].data_ptr(),
+                              t["c"].data_ptr(), 0.0, float(p.gamma), float(p.dt),
+                              t["bc_type"].data_ptr(), t["bc_value"].data_ptr(),
+                              t["p_prev"].data_ptr(), t["source"].data_ptr())
+        h = C.c_void_p()
+        _check(load().edfa_assemble(arr, len(problems), _stream(), C.byref(h)))
+        self._h = h
+        self.info = self._info()
+
+    def _info(self):
+        inf = _SystemInfo()
+        _check(load().edfa_system_get_info(self._h, C.byref(inf)))
+        return {"n_grids": inf.n_grids, "ne": inf.n_cells, "nf": inf.n_faces,
+                "nfu": inf.n_face_unknowns, "n": inf.n, "axis": inf.axis_structure,
+                "nnz": inf.nnz, "nnz_block": list(inf.nnz_block)}
+
+    @property
+    def n(self):
+        return self.info["n"]
+
+    def export_block(self, name):
+        b = BLOCK[name]
+        nfu, ne, n = self.info["nfu"], self.info["ne"], self.info["n"]
+        rows = {0: nfu, 1: nfu, 2: ne, 3: ne, 4: n}[b]
+        nnz = self.info["nnz"] if b == 4 else self.info["nnz_block"][b]
+        rp = torch.empty(rows + 1, dtype=torch.int32, device="cuda")
+        col = torch.empty(max(nnz, 1), dtype=torch.int32, device="cuda")
+        val = torch.empty(max(nnz, 1), dtype=torch.float64, device="cuda")
+        _check(load().edfa_export_block(self._h, b, _ptr(rp), _ptr(col), _ptr(val), _stream()))
+        return rp, col[:nnz], val[:nnz]
+
+    def rhs(self):
+        b = torch.empty(self.info["n"], dtype=torch.float64, device="cuda")
+        _check(load().edfa_export_rhs(self._h, _ptr(b), None, None, _stream()))
+        return b
+
+    def element_data(self):
+        ne = self.info["ne"]
+        W = torch.empty(ne * 36, dtype=torch.float64, device="cuda")
+        vol = torch.empty(ne, dtype=torch.float64, device="cuda")
+        _check(load().edfa_export_rhs(self._h, None, _ptr(W), _ptr(vol), _stream()))
+        return W.view(ne, 6, 6), vol
+
+    def spmv(self, x, transpose=False):
+        y = torch.empty_like(x)
+        _check(load().edfa_spmv(self._h, int(transpose), _ptr(x), _ptr(y), _stream()))
+        return y
+
+    def update_dt(self, dt, p_prev=None):
+        _check(load().edfa_update_dt(self._h, float(dt), _ptr(p_prev), _stream()))
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.edfa_system_destroy(self._h)
+            self._h = None
+
+
+@dataclass
+class Params:
+    variant: str = "dynamic"
+    static_level: int = 0
+    n_add: int = 1
+    n_ent: int = 4
+    it_max: int = 0
+    tau: float = 0.0
+    filt: str = "none"
+    precision: int = 0          # 0 FP64, 1 FP32 setup + application
+    schur: str = "isai"
+    isai_steps: int = 1
+
+    def c(self):
+        return _Params(STATIC if self.variant == "static" else DYNAMIC, self.static_level,
+                       self.n_add, self.n_ent, self.it_max, float(self.tau), FILT[self.filt],
+                       self.precision, SCHUR[self.schur], self.isai_steps)
+
+
+class Precond:
+    def __init__(self, system: System, params: Params):
+        self.system = system
+        self.params = params
+        h = C.c_void_p()
+        _check(load().edfa_setup(system._h, C.byref(params.c()), _stream(), C.byref(h)))
+        self._h = h
+
+    def stage2(self):
+        _check(load().edfa_setup_stage2(self._h, _stream()))
+
+    def info(self):
+        inf = _PrecondInfo()
+        _check(load().edfa_precond_get_info(self._h, C.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in _PrecondInfo._fields_}
+
+    def export(self, what):
+        w = PRECOND_ART[what]
+        nnz, rows = C.c_int64(), C.c_int32()
+        L = load()
+        _check(L.edfa_export_precond(self._h, w, None, None, None, None, C.byref(nnz),
+                                     C.byref(rows), _stream()))
+        rp = torch.empty(rows.value + 1, dtype=torch.int32, device="cuda")
+        col = torch.empty(max(nnz.value, 1), dtype=torch.int32, device="cuda")
+        val = torch.empty(max(nnz.value, 1), dtype=torch.float64, device="cuda")
+        perm = torch.empty(self.system.info["ne"], dtype=torch.int32, device="cuda") if w >= 6 else None
+        _check(L.edfa_export_precond(self._h, w, _ptr(rp), _ptr(col), _ptr(val), _ptr(perm),
+                                     C.byref(nnz), C.byref(rows), _stream()))
+        return rp, col[:nnz.value], val[:nnz.value], perm
+
+    def apply(self, r, transpose=False):
+        z = torch.empty_like(r)
+        _check(load().edfa_apply(self._h, int(transpose), _ptr(r), _ptr(z), _stream()))
+        return z
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.edfa_precond_destroy(self._h)
+            self._h = None
+
+
+def solve(system: System, pre: Precond, b, rtol=1e-8, restart=50, max_iter=5000, flexible=False,
+          transpose=False, use_graph=False, profile=False):
+    """Right-preconditioned (F)GMRES(restart), x0 = 0.  Returns (x, info dict, status)."""
+    x = torch.zeros_like(b)
+    prm = _SolveParams(restart, max_iter, int(flexible), int(transpose), int(use_graph),
+                       int(profile), float(rtol))
+    inf = _SolveInfo()
+    st = _check(load().edfa_solve(system._h, pre._h, _ptr(b), _ptr(x), C.byref(prm), _stream(),
+                                  C.byref(inf)))
+    return x, {f: getattr(inf, f) for f, _ in _SolveInfo._fields_}, st
+
+
+def grad_logk(system: System, u, lam):
+    g = torch.empty(system.info["ne"], dtype=torch.float64, device="cuda")
+    _check(load().edfa_grad_logk(system._h, _ptr(u), _ptr(lam), _ptr(g), _stream()))
+    return g
+
+
+def csr_to_scipy(rp, col, val, shape):
+    import scipy.sparse as sp
+    return sp.csr_matrix((val.cpu().numpy(), col.cpu().numpy(), rp.cpu().numpy()), shape=shape)

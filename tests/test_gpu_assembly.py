@@ -1,0 +1,130 @@
+"""GPU parity: assembly and SpMV of the HIP library against the oracle (FP64)."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import mhfe
+from paper_2009_13916_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _problems():
+    return {
+        "iso10": inputs.lognormal_iso_problem(10),
+        "full_5x4x6": inputs.full_tensor_problem(5, 4, 6, sigma=2.0, corr=2.0, config_id=12),
+        "distorted_6x5x4": inputs.channel_problem(6, 5, 4, contrast=1e6, config_id=13),
+        "aniso_7": inputs.anisotropic_problem(7, config_id=15),
+    }
+
+
+def _gpu_csr(S, name, shape):
+    import torch
+    rp, col, val = S.export_block(name)
+    torch.cuda.synchronize()
+    return sp.csr_matrix((val.cpu().numpy(), col.cpu().numpy(), rp.cpu().numpy()), shape=shape)
+
+
+def _compare_csr(G, O, tol):
+    assert np.array_equal(G.indptr, O.indptr), "row pointers differ"
+    assert np.array_equal(G.indices, O.indices), "column indices differ"
+    scale = np.maximum(abs(O).max(axis=1).toarray().ravel(), 1e-300)
+    rows = np.repeat(np.arange(O.shape[0]), np.diff(O.indptr))
+    err = np.abs(G.data - O.data) / scale[rows]
+    assert err.max() <= tol, err.max()
+
+
+@pytest.mark.parametrize("name", list(_problems()))
+def test_assembly_matches_oracle(lib, name):
+    prob = _problems()[name]
+    print(f"[assembly parity] {name}", flush=True)
+    S = lib.System(prob)
+    o = mhfe.assemble(prob)
+    assert S.info["nfu"] == o.nfu and S.info["ne"] == o.ne
+    assert S.info["axis"] == int(o.axis)
+    nfu, ne = o.nfu, o.ne
+    for blk, ref, shape in (("App", o.App, (nfu, nfu)), ("Apc", o.Apc, (nfu, ne)),
+                            ("Acp", o.Acp, (ne, nfu)), ("Acc", o.Acc, (ne, ne)),
+                            ("A", o.matrix(), (o.n, o.n))):
+        _compare_csr(_gpu_csr(S, blk, shape), ref.tocsr(), 1e-12)
+    b = S.rhs().cpu().numpy()
+    np.testing.assert_allclose(b, o.b, rtol=1e-12, atol=1e-12 * np.abs(o.b).max())
+
+
+def test_batched_assembly_is_block_diagonal(lib):
+    """A batch of grids assembles to the block-diagonal system of the individual grids,
+    with u = [pi of all grids; p of all grids]."""
+    probs = [inputs.lognormal_iso_problem(n, sigma=s, config_id=4, extra=i)
+             for i, (n, s) in enumerate([(4, 0.5), (6, 2.0), (5, 1.0)])]
+    S = lib.System(probs)
+    os_ = [mhfe.assemble(p) for p in probs]
+    nfu = sum(o.nfu for o in os_)
+    ne = sum(o.ne for o in os_)
+    A = _gpu_csr(S, "A", (nfu + ne, nfu + ne))
+    App = sp.block_diag([o.App for o in os_])
+    Apc = sp.block_diag([o.Apc for o in os_])
+    Acp = sp.block_diag([o.Acp for o in os_])
+    Acc = sp.block_diag([o.Acc for o in os_])
+    ref = sp.bmat([[App, Apc], [Acp, Acc]], format="csr")
+    ref.sort_indices()
+    _compare_csr(A, ref, 1e-12)
+    b = S.rhs().cpu().numpy()
+    bref = np.concatenate([o.b[:o.nfu] for o in os_] + [o.b[o.nfu:] for o in os_])
+    np.testing.assert_allclose(b, bref, rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("transpose", [False, True])
+def test_spmv_matches_oracle(lib, transpose):
+    import torch
+    prob = inputs.full_tensor_problem(6, 5, 7, sigma=2.0, corr=2.0, config_id=16)
+    S = lib.System(prob)
+    o = mhfe.assemble(prob)
+    A = o.matrix()
+    x = np.random.default_rng(0).standard_normal(o.n)
+    y = S.spmv(torch.tensor(x, device="cuda"), transpose=transpose).cpu().numpy()
+    ref = (A.T if transpose else A) @ x
+    bound = (abs(A.T if transpose else A) @ np.abs(x)) * 1e-14 + 1e-300
+    assert np.all(np.abs(y - ref) <= bound)
+
+
+def test_update_dt_changes_only_App_diagonal_and_rhs(lib):
+    import torch
+    prob = inputs.lognormal_iso_problem(6, config_id=17)
+    prob.c[:] = 0.3
+    S = lib.System(prob)
+    pn = np.random.default_rng(1).uniform(0, 1, prob.n_cells)
+    S.update_dt(0.01, torch.tensor(pn, device="cuda"))
+    prob.dt, prob.p_prev = 0.01, pn
+    o = mhfe.assemble(prob)
+    _compare_csr(_gpu_csr(S, "A", (o.n, o.n)), o.matrix().tocsr(), 1e-12)
+    np.testing.assert_allclose(S.rhs().cpu().numpy(), o.b, rtol=1e-12, atol=1e-14)
+
+
+def test_full_size_full_tensor_properties(lib):
+    """64^3 full-tensor workload: interior row counts 11/2/36/7, A_pipi symmetric, and the
+    all-no-flow null test A [1;1] = [0; Omega c/dt] at full size."""
+    import torch
+    prob = inputs.full_tensor_problem(64)
+    print("[assembly full size] 64^3 full tensor", flush=True)
+    S = lib.System(prob)
+    assert S.info["axis"] == 0
+    rp, col, val = S.export_block("App")
+    nfu = S.info["nfu"]
+    App = sp.csr_matrix((val.cpu().numpy(), col.cpu().numpy(), rp.cpu().numpy()), shape=(nfu, nfu))
+    assert np.diff(App.indptr).max() == 11
+    d = abs(App - App.T)
+    assert d.max() <= 1e-13 * abs(App).max()
+    for blk, w in (("Apc", 2), ("Acp", 36), ("Acc", 7)):
+        rp, _, _ = S.export_block(blk)
+        assert int(torch.diff(rp).max()) == w
+    prob.bc_type[:] = 0
+    prob.bc_value[:] = 0.0
+    S0 = lib.System(prob)
+    ones = torch.ones(S0.n, dtype=torch.float64, device="cuda")
+    r = S0.spmv(ones).cpu().numpy()
+    W, vol = S0.element_data()
+    nfu0 = S0.info["nfu"]
+    scale = float(W.abs().max())
+    assert np.abs(r[:nfu0]).max() <= 1e-12 * scale
+    np.testing.assert_allclose(r[nfu0:], vol.cpu().numpy() * prob.c / prob.dt, rtol=1e-6,
+                               atol=1e-12 * scale)

@@ -29,7 +29,7 @@ restated in the paper's order and notation:
 
 Readings where the paper is silent (stated again in the design notes):
 * selection key: |r_j| rounded to 40 significant bits, ties to the smaller
-  index; candidates are indices outside Q with r_j != 0; a sweep that adds
+  index; candidates are indices outside Q whose key is non-zero; a sweep that adds
   nothing ends the loop; it_max defaults to n_ent;
 * filtration drops |x_i| < tau * ||x||_2 with the vector's own norm (row of
   G~, column of F~, row of H~ or S~ before dropping); diagonals of H~ and S~
@@ -166,7 +166,7 @@ def prolonged_residual(s: System, a_row_idx, a_row_val, Q, g):
 
 def select_new(Q, r_idx, r_val, n):
     """At most n indices outside Q with the largest |r| (40-bit key, ties -> smaller index)."""
-    outside = ~np.isin(r_idx, Q) & (r_val != 0.0)
+    outside = ~np.isin(r_idx, Q) & (key40(r_val) > 0)
     cand, val = r_idx[outside], r_val[outside]
     if cand.size == 0:
         return cand
@@ -245,17 +245,25 @@ def _ensure_apct(s: System):
         s.ApcT.sort_indices()
 
 
+def _ones(M):
+    """The structural pattern of M with every stored entry (zeros included) set to 1."""
+    P = sp.csr_matrix(M, copy=True)
+    P.data = np.ones_like(P.data, dtype=np.float64)
+    return P
+
+
 def structural_product(*mats):
     """Product of sparse matrices on the structural pattern of the product.
 
-    Values are the ordinary product; the pattern is that of the product of
-    the absolute values, so entries that cancel to zero are kept (as 0).
+    Values are the ordinary product; the pattern is the product of the
+    structural patterns (stored entries counted as ones, explicit zeros
+    included), so entries that cancel to zero are kept (as 0).
     """
     val = mats[0]
-    pat = abs(mats[0])
+    pat = _ones(mats[0])
     for m in mats[1:]:
         val = val @ m
-        pat = pat @ abs(m)
+        pat = pat @ _ones(m)
     pat = pat.tocsr()
     pat.sort_indices()
     val = val.tocsr()
@@ -420,7 +428,7 @@ class Stage2:
 
 def structural_sub(A: sp.csr_matrix, H: sp.csr_matrix):
     """A - H on the union of the two structural patterns (zeros kept)."""
-    pa, ph = abs(A), abs(H)
+    pa, ph = _ones(A), _ones(H)
     pat = (pa + ph).tocsr()
     pat.sort_indices()
     out = pat.copy()

@@ -393,6 +393,17 @@ def ilu0(B: sp.csr_matrix):
     return L, U
 
 
+def unit_lower(L: sp.csr_matrix):
+    """I + L keeping every stored entry of L (explicit zeros included) in the pattern."""
+    L = L.tocoo()
+    n = L.shape[0]
+    M = sp.csr_matrix((np.concatenate([L.data, np.ones(n)]),
+                       (np.concatenate([L.row, np.arange(n)]), np.concatenate([L.col, np.arange(n)]))),
+                      shape=L.shape)
+    M.sort_indices()
+    return M
+
+
 def isai(T: sp.csr_matrix):
     """Incomplete sparse approximate inverse of a triangular factor on its own pattern.
 
@@ -453,7 +464,7 @@ def stage2(s: System, st1: Stage1, prm: Params) -> Stage2:
     L, U = ilu0(B)
     ML = MU = None
     if prm.schur == "isai":
-        Lf = (L + sp.eye(L.shape[0], format="csr")).tocsr()
+        Lf = unit_lower(L)
         ML, MU = isai(Lf), isai(U)
     return Stage2(S, color, perm, L, U, ML, MU)
 
@@ -504,7 +515,7 @@ class Edfa:
     def _apply_isai(self, y, transpose):
         st = self.st2
         n = len(y)
-        Lf = (st.L + sp.eye(n, format="csr")).tocsr()
+        Lf = unit_lower(st.L)
         b = y[st.perm]
         k = self.prm.isai_steps
         if not transpose:

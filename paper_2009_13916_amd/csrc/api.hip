@@ -151,3 +151,189 @@ edfa_status edfa_spmv(edfa_system sys, int32_t transpose, const double *x, doubl
 }
 
 }  // extern "C"
+
+namespace edfa {
+template <class T>
+static const Csr<T> *precond_art(edfa_precond_s &P, PrecData<T> &D, int what, hipStream_t s) {
+  switch (what) {
+    case 0: return &D.G;
+    case 1: return &D.FT;
+    case 2:
+      build_hraw(P, D, s);
+      return &D.Hraw;
+    case 3: return &D.H;
+    case 4: return &D.S;
+    case 5: return &D.GF;
+    case 6: return &D.L;
+    case 7: return &D.U;
+    case 8: return &D.ML;
+    case 9: return &D.MU;
+    default: fail(EDFA_ERR_ARG, "unknown artefact %d", what);
+  }
+}
+
+__global__ void k_f2d(const float *__restrict__ x, long long n, double *y) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (double)x[i];
+}
+
+template <class T>
+static void export_art(edfa_precond_s &P, PrecData<T> &D, int what, int32_t *rowptr, int32_t *col,
+                       double *val, int32_t *perm, int64_t *nnz, int32_t *rows, hipStream_t s) {
+  const Csr<T> *M = precond_art(P, D, what, s);
+  if ((what == 8 || what == 9) && P.prm.schur_solver != EDFA_SCHUR_ISAI)
+    fail(EDFA_ERR_ARG, "no sparse approximate inverses with the exact substitution solver");
+  if (nnz) *nnz = M->nnz;
+  if (rows) *rows = M->rows;
+  if (!rowptr) return;
+  EDFA_HIP(hipMemcpyAsync(rowptr, M->rowptr.p, sizeof(int) * ((size_t)M->rows + 1),
+                          hipMemcpyDeviceToDevice, s));
+  if (M->nnz) {
+    if (col) EDFA_HIP(hipMemcpyAsync(col, M->col.p, sizeof(int) * M->nnz, hipMemcpyDeviceToDevice, s));
+    if (val) {
+      if (sizeof(T) == sizeof(double))
+        EDFA_HIP(hipMemcpyAsync(val, M->val.p, sizeof(double) * M->nnz, hipMemcpyDeviceToDevice, s));
+      else
+        hipLaunchKernelGGL(k_f2d, dim3(ceil_div(M->nnz, 256)), dim3(256), 0, s,
+                           (const float *)M->val.p, (long long)M->nnz, val);
+    }
+  }
+  if (perm && what >= 6)
+    EDFA_HIP(hipMemcpyAsync(perm, D.perm.p, sizeof(int) * P.sys->ne, hipMemcpyDeviceToDevice, s));
+  EDFA_HIP(hipStreamSynchronize(s));
+}
+
+template <class T>
+static void fill_info(edfa_precond_s &P, PrecData<T> &D, edfa_precond_info *info) {
+  edfa_system_s &S = *P.sys;
+  info->nnz_G = D.G.nnz;
+  info->nnz_F = D.FT.nnz;
+  info->nnz_H = D.H.nnz;
+  info->nnz_S = D.S.nnz;
+  info->nnz_GF = D.GF.nnz;
+  info->nnz_L = D.L.nnz;
+  info->nnz_U = D.U.nnz;
+  const bool isai = P.prm.schur_solver == EDFA_SCHUR_ISAI;
+  info->nnz_ML = isai ? D.ML.nnz : 0;
+  info->nnz_MU = isai ? D.MU.nnz : 0;
+  info->n_colors = P.n_colors;
+  info->max_pattern = P.max_pattern;
+  const double den = (double)(S.Afp.nnz + S.Afc.nnz + S.Acf.nnz + S.Acc.nnz);
+  const double num = 2.0 * D.GF.nnz + S.Afc.nnz + S.Acf.nnz + D.L.nnz + D.U.nnz +
+                     (isai ? (double)(D.ML.nnz + D.MU.nnz) : 0.0);
+  info->mu = den > 0 ? num / den : 0.0;
+  info->t_stage1_ms = P.t_stage1_ms;
+  info->t_stage2_ms = P.t_stage2_ms;
+}
+}  // namespace edfa
+
+extern "C" {
+
+edfa_status edfa_setup(edfa_system sys, const edfa_params *prm, hipStream_t stream,
+                       edfa_precond *out) {
+  return guard([&] {
+    if (!sys || !prm || !out) fail(EDFA_ERR_ARG, "NULL argument");
+    *out = nullptr;
+    if (prm->variant != EDFA_STATIC && prm->variant != EDFA_DYNAMIC)
+      fail(EDFA_ERR_ARG, "variant must be EDFA_STATIC or EDFA_DYNAMIC");
+    if (prm->variant == EDFA_DYNAMIC && (prm->n_add < 1 || prm->n_ent < 0))
+      fail(EDFA_ERR_ARG, "dynamic variant needs n_add >= 1 and n_ent >= 0");
+    if (prm->filt_mode < EDFA_FILT_NONE || prm->filt_mode > EDFA_FILT_POST_H)
+      fail(EDFA_ERR_ARG, "filt_mode out of range");
+    if (prm->filt_mode != EDFA_FILT_NONE && !(prm->tau_filt >= 0.0))
+      fail(EDFA_ERR_ARG, "tau_filt must be >= 0");
+    if (prm->precision != 0 && prm->precision != 1) fail(EDFA_ERR_ARG, "precision must be 0 or 1");
+    if (prm->schur_solver != EDFA_SCHUR_ISAI && prm->schur_solver != EDFA_SCHUR_EXACT)
+      fail(EDFA_ERR_ARG, "schur_solver out of range");
+    if (prm->isai_steps < 1) fail(EDFA_ERR_ARG, "isai_steps must be >= 1");
+    auto *P = new edfa_precond_s();
+    P->sys = sys;
+    P->prm = *prm;
+    try {
+      EventTimer t1, t2;
+      t1.start(stream);
+      precond_stage1(*P, stream);
+      t1.stop(stream);
+      P->t_stage1_ms = t1.ms();
+      t2.start(stream);
+      precond_stage2(*P, stream);
+      t2.stop(stream);
+      P->t_stage2_ms = t2.ms();
+    } catch (...) {
+      delete P;
+      throw;
+    }
+    *out = P;
+    return EDFA_OK;
+  });
+}
+
+edfa_status edfa_setup_stage2(edfa_precond pre, hipStream_t stream) {
+  return guard([&] {
+    if (!pre) fail(EDFA_ERR_ARG, "NULL preconditioner");
+    EventTimer t2;
+    t2.start(stream);
+    precond_stage2(*pre, stream);
+    t2.stop(stream);
+    pre->t_stage2_ms = t2.ms();
+    return EDFA_OK;
+  });
+}
+
+void edfa_precond_destroy(edfa_precond pre) { delete pre; }
+
+edfa_status edfa_precond_get_info(edfa_precond pre, edfa_precond_info *info) {
+  return guard([&] {
+    if (!pre || !info) fail(EDFA_ERR_ARG, "NULL argument");
+    if (pre->prm.precision == 1)
+      fill_info(*pre, pre->f, info);
+    else
+      fill_info(*pre, pre->d, info);
+    return EDFA_OK;
+  });
+}
+
+edfa_status edfa_export_precond(edfa_precond pre, int32_t what, int32_t *rowptr, int32_t *col,
+                                double *val, int32_t *perm, int64_t *nnz, int32_t *rows,
+                                hipStream_t stream) {
+  return guard([&] {
+    if (!pre) fail(EDFA_ERR_ARG, "NULL preconditioner");
+    if (pre->prm.precision == 1)
+      export_art(*pre, pre->f, what, rowptr, col, val, perm, nnz, rows, stream);
+    else
+      export_art(*pre, pre->d, what, rowptr, col, val, perm, nnz, rows, stream);
+    return EDFA_OK;
+  });
+}
+
+edfa_status edfa_apply(edfa_precond pre, int32_t transpose, const double *r, double *z,
+                       hipStream_t stream) {
+  return guard([&] {
+    if (!pre || !r || !z) fail(EDFA_ERR_ARG, "NULL argument");
+    if (r == z) fail(EDFA_ERR_ARG, "r and z must not alias");
+    precond_apply(*pre, transpose ? 1 : 0, r, z, stream);
+    return EDFA_OK;
+  });
+}
+
+edfa_status edfa_solve(edfa_system sys, edfa_precond pre, const double *b, double *x,
+                       const edfa_solve_params *prm, hipStream_t stream, edfa_solve_info *info) {
+  return guard([&] {
+    if (!sys || !pre || !b || !x || !prm) fail(EDFA_ERR_ARG, "NULL argument");
+    if (pre->sys != sys) fail(EDFA_ERR_ARG, "preconditioner built for another system");
+    if (b == x) fail(EDFA_ERR_ARG, "b and x must not alias");
+    if (prm->max_iter < 1) fail(EDFA_ERR_ARG, "max_iter must be >= 1");
+    return gmres(*sys, *pre, b, x, *prm, stream, info);
+  });
+}
+
+edfa_status edfa_grad_logk(edfa_system sys, const double *u, const double *lambda, double *g,
+                           hipStream_t stream) {
+  return guard([&] {
+    if (!sys || !u || !lambda || !g) fail(EDFA_ERR_ARG, "NULL argument");
+    grad_logk(*sys, u, lambda, g, stream);
+    return EDFA_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,216 @@
+// Application of the EDFA preconditioner (eq. EDFA_prec) and of its transpose.
+//
+//   t   = A~^-1 r_pi            A~^-1 = -G_F^T G_F   (two SpMVs)
+//   y   = r_p - A_ppi t
+//   z_p = S~^-1 y               multicolour ILU(0): permute, ISAI (+ refinement) or
+//                               colour-by-colour substitution, un-permute
+//   z_pi = A~^-1 (r_pi - A_pip z_p)
+// The transpose swaps A_ppi <-> A_pip^T and uses (LU)^-T.
+#include "precond.hpp"
+
+namespace edfa {
+
+template <class T>
+__global__ void k_gather(const T *__restrict__ x, const int *__restrict__ idx, int n, T *y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = x[idx[i]];
+}
+
+template <class T>
+__global__ void k_scatter(const T *__restrict__ x, const int *__restrict__ idx, int n, T *y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[idx[i]] = x[i];
+}
+
+template <class A, class B>
+__global__ void k_convert(const A *__restrict__ x, long long n, B *y) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (B)x[i];
+}
+
+// Colour-by-colour substitution on rows [r0, r1): y_i = (b_i - sum_{j != diag} a_ij y_j) / d
+// where d = a_ii when the row stores its diagonal (first or last entry), else 1.
+template <class T>
+__global__ void k_sweep(const int *__restrict__ rp, const int *__restrict__ col,
+                        const T *__restrict__ val, int r0, int r1, int diag_where,
+                        const T *__restrict__ b, T *y) {
+  const int i = r0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= r1) return;
+  int a = rp[i], e = rp[i + 1];
+  T d = T(1);
+  if (diag_where == 1) d = val[a++];        // diagonal first (U)
+  else if (diag_where == 2) d = val[--e];   // diagonal last (U^T)
+  T s = b[i];
+  for (int p = a; p < e; ++p) s -= val[p] * y[col[p]];
+  y[i] = s / d;
+}
+
+// FP32 copy of an FP64 CSR matrix (pattern copied, values rounded); kept across calls.
+static void to_fp32(const Csr<double> &M, Csr<float> &F, hipStream_t s) {
+  if (F.rows == M.rows && F.nnz == M.nnz) return;
+  F.alloc(M.rows, M.cols, M.nnz);
+  EDFA_HIP(hipMemcpyAsync(F.rowptr.p, M.rowptr.p, sizeof(int) * ((size_t)M.rows + 1),
+                          hipMemcpyDeviceToDevice, s));
+  if (M.nnz) {
+    EDFA_HIP(hipMemcpyAsync(F.col.p, M.col.p, sizeof(int) * M.nnz, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL((k_convert<double, float>), dim3(ceil_div(M.nnz, 256)), dim3(256), 0, s,
+                       M.val.p, (long long)M.nnz, F.val.p);
+    EDFA_CHECK_LAUNCH();
+  }
+}
+
+template <class T>
+static void sinv(edfa_precond_s &P, PrecData<T> &D, int transpose, const T *y, T *zp,
+                 hipStream_t s) {
+  const int ne = P.sys->ne;
+  const int gb = ceil_div(ne, 256);
+  D.y.ensure(ne);
+  D.w.ensure(ne);
+  D.zq.ensure(ne);
+  D.res.ensure(ne);
+  hipLaunchKernelGGL(k_gather<T>, dim3(gb), dim3(256), 0, s, y, D.perm.p, ne, D.y.p);
+  EDFA_CHECK_LAUNCH();
+  const float al = ne ? (float)D.L.nnz / ne : 0.f, au = ne ? (float)D.U.nnz / ne : 0.f;
+  const int steps = std::max(1, P.prm.isai_steps);
+  if (P.prm.schur_solver == EDFA_SCHUR_ISAI) {
+    // first factor (L, or U^T for the transpose), then the second
+    const Csr<T> &M1 = transpose ? D.MUT : D.ML;
+    const Csr<T> &T1 = transpose ? D.UT : D.L;
+    const Csr<T> &M2 = transpose ? D.MLT : D.MU;
+    const Csr<T> &T2 = transpose ? D.LT : D.U;
+    const double g1 = transpose ? 0.0 : -1.0;   // (I + L) w = L w + w
+    const double g2 = transpose ? -1.0 : 0.0;
+    spmv<T, T>(M1.rowptr.p, M1.col.p, M1.val.p, ne, D.y.p, D.w.p, 1.0, nullptr, 0.0, al + 1, s);
+    for (int k = 1; k < steps; ++k) {
+      spmv<T, T>(T1.rowptr.p, T1.col.p, T1.val.p, ne, D.w.p, D.res.p, -1.0, D.y.p, 1.0,
+                 transpose ? au : al, s, g1);
+      spmv<T, T>(M1.rowptr.p, M1.col.p, M1.val.p, ne, D.res.p, D.w.p, 1.0, D.w.p, 1.0, al + 1, s);
+    }
+    spmv<T, T>(M2.rowptr.p, M2.col.p, M2.val.p, ne, D.w.p, D.zq.p, 1.0, nullptr, 0.0, au, s);
+    for (int k = 1; k < steps; ++k) {
+      spmv<T, T>(T2.rowptr.p, T2.col.p, T2.val.p, ne, D.zq.p, D.res.p, -1.0, D.w.p, 1.0,
+                 transpose ? al : au, s, g2);
+      spmv<T, T>(M2.rowptr.p, M2.col.p, M2.val.p, ne, D.res.p, D.zq.p, 1.0, D.zq.p, 1.0, au, s);
+    }
+  } else {
+    const int nc = P.n_colors;
+    if (!transpose) {
+      for (int c = 0; c < nc; ++c) {
+        const int r0 = D.cstart[c], r1 = D.cstart[c + 1];
+        if (r1 > r0)
+          hipLaunchKernelGGL(k_sweep<T>, dim3(ceil_div(r1 - r0, 64)), dim3(64), 0, s, D.L.rowptr.p,
+                             D.L.col.p, D.L.val.p, r0, r1, 0, D.y.p, D.w.p);
+      }
+      for (int c = nc - 1; c >= 0; --c) {
+        const int r0 = D.cstart[c], r1 = D.cstart[c + 1];
+        if (r1 > r0)
+          hipLaunchKernelGGL(k_sweep<T>, dim3(ceil_div(r1 - r0, 64)), dim3(64), 0, s, D.U.rowptr.p,
+                             D.U.col.p, D.U.val.p, r0, r1, 1, D.w.p, D.zq.p);
+      }
+    } else {
+      for (int c = 0; c < nc; ++c) {
+        const int r0 = D.cstart[c], r1 = D.cstart[c + 1];
+        if (r1 > r0)
+          hipLaunchKernelGGL(k_sweep<T>, dim3(ceil_div(r1 - r0, 64)), dim3(64), 0, s, D.UT.rowptr.p,
+                             D.UT.col.p, D.UT.val.p, r0, r1, 2, D.y.p, D.w.p);
+      }
+      for (int c = nc - 1; c >= 0; --c) {
+        const int r0 = D.cstart[c], r1 = D.cstart[c + 1];
+        if (r1 > r0)
+          hipLaunchKernelGGL(k_sweep<T>, dim3(ceil_div(r1 - r0, 64)), dim3(64), 0, s, D.LT.rowptr.p,
+                             D.LT.col.p, D.LT.val.p, r0, r1, 0, D.w.p, D.zq.p);
+      }
+    }
+    EDFA_CHECK_LAUNCH();
+  }
+  hipLaunchKernelGGL(k_scatter<T>, dim3(gb), dim3(256), 0, s, D.zq.p, D.perm.p, ne, zp);
+  EDFA_CHECK_LAUNCH();
+}
+
+template <class T>
+static void ensure_transposed_factors(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
+  edfa_system_s &S = *P.sys;
+  if (D.UT.rows == 0 && S.ne) {
+    csr_transpose(D.U, D.UT, S.tmp, s);
+    csr_transpose(D.L, D.LT, S.tmp, s);
+    if (P.prm.schur_solver == EDFA_SCHUR_ISAI) {
+      csr_transpose(D.ML, D.MLT, S.tmp, s);
+      csr_transpose(D.MU, D.MUT, S.tmp, s);
+    }
+  }
+  if (S.AcfT.rows == 0 && S.nfu) csr_transpose(S.Acf, S.AcfT, S.tmp, s);
+}
+
+
+template <class T>
+static void apply_typed(edfa_precond_s &P, PrecData<T> &D, int transpose, const T *r, T *z,
+                        const int *c_rp[2], const int *c_col[2], const T *c_val[2],
+                        hipStream_t s) {
+  edfa_system_s &S = *P.sys;
+  const int nfu = S.nfu, ne = S.ne;
+  D.t1.ensure(nfu);
+  D.t2.ensure(nfu);
+  const float ag = nfu ? (float)D.GF.nnz / nfu : 0.f;
+  const T *rpi = r, *rp = r + nfu;
+  T *zpi = z, *zp = z + nfu;
+  // t = A~^-1 r_pi
+  spmv<T, T>(D.GF.rowptr.p, D.GF.col.p, D.GF.val.p, nfu, rpi, D.t1.p, 1.0, nullptr, 0.0, ag, s);
+  spmv<T, T>(D.GFT.rowptr.p, D.GFT.col.p, D.GFT.val.p, nfu, D.t1.p, D.t2.p, -1.0, nullptr, 0.0, ag, s);
+  // y = r_p - A_ppi t   (transpose: A_pip^T)
+  D.r.ensure(ne);
+  spmv<T, T>(c_rp[0], c_col[0], c_val[0], ne, D.t2.p, D.r.p, -1.0, rp, 1.0,
+             transpose ? S.avg_fc * nfu / std::max(ne, 1) : S.avg_cf, s);
+  // z_p = S~^-1 y
+  sinv<T>(P, D, transpose, D.r.p, zp, s);
+  // z_pi = A~^-1 (r_pi - A_pip z_p)   (transpose: A_ppi^T)
+  spmv<T, T>(c_rp[1], c_col[1], c_val[1], nfu, zp, D.t1.p, -1.0, rpi, 1.0,
+             transpose ? S.avg_cf * ne / std::max(nfu, 1) : S.avg_fc, s);
+  spmv<T, T>(D.GF.rowptr.p, D.GF.col.p, D.GF.val.p, nfu, D.t1.p, D.t2.p, 1.0, nullptr, 0.0, ag, s);
+  spmv<T, T>(D.GFT.rowptr.p, D.GFT.col.p, D.GFT.val.p, nfu, D.t2.p, zpi, -1.0, nullptr, 0.0, ag, s);
+}
+
+void precond_apply(edfa_precond_s &P, int transpose, const double *r, double *z, hipStream_t s) {
+  edfa_system_s &S = *P.sys;
+  if (transpose) {
+    if (P.prm.precision == 1)
+      ensure_transposed_factors(P, P.f, s);
+    else
+      ensure_transposed_factors(P, P.d, s);
+  }
+  if (P.prm.precision != 1) {
+    const int *rp2[2] = {transpose ? S.AfcT.rowptr.p : S.Acf.rowptr.p,
+                         transpose ? S.AcfT.rowptr.p : S.Afc.rowptr.p};
+    const int *cl2[2] = {transpose ? S.AfcT.col.p : S.Acf.col.p,
+                         transpose ? S.AcfT.col.p : S.Afc.col.p};
+    const double *vl2[2] = {transpose ? S.AfcT.val.p : S.Acf.val.p,
+                            transpose ? S.AcfT.val.p : S.Afc.val.p};
+    apply_typed<double>(P, P.d, transpose, r, z, rp2, cl2, vl2, s);
+    return;
+  }
+  // FP32 application: convert in, apply, convert out
+  PrecData<float> &D = P.f;
+  auto &cf = P.coupling_f;
+  to_fp32(S.Acf, cf[0], s);
+  to_fp32(S.Afc, cf[1], s);
+  if (transpose) {
+    to_fp32(S.AfcT, cf[2], s);
+    to_fp32(S.AcfT, cf[3], s);
+  }
+  const int n = S.n;
+  D.z.ensure(n);
+  DBuf<float> &rin = P.rin_f;
+  rin.ensure(n);
+  hipLaunchKernelGGL((k_convert<double, float>), dim3(ceil_div(n, 256)), dim3(256), 0, s, r,
+                     (long long)n, rin.p);
+  EDFA_CHECK_LAUNCH();
+  const int *rp2[2] = {transpose ? cf[2].rowptr.p : cf[0].rowptr.p,
+                       transpose ? cf[3].rowptr.p : cf[1].rowptr.p};
+  const int *cl2[2] = {transpose ? cf[2].col.p : cf[0].col.p, transpose ? cf[3].col.p : cf[1].col.p};
+  const float *vl2[2] = {transpose ? cf[2].val.p : cf[0].val.p, transpose ? cf[3].val.p : cf[1].val.p};
+  apply_typed<float>(P, D, transpose, rin.p, D.z.p, rp2, cl2, vl2, s);
+  hipLaunchKernelGGL((k_convert<float, double>), dim3(ceil_div(n, 256)), dim3(256), 0, s, D.z.p,
+                     (long long)n, z);
+  EDFA_CHECK_LAUNCH();
+}
+
+}  // namespace edfa

@@ -124,10 +124,12 @@ void exclusive_scan_async(const int *in, int *out, int n, DBuf<int> &tmp, hipStr
 template <class V>
 void csr_transpose(const Csr<V> &src, Csr<V> &dst, DBuf<int> &tmp, hipStream_t s);
 
-// y[i] = beta * b[i] + alpha * (A x)[i]   (b may be null: then y = alpha A x).
-// A in CSR with values V, vectors of type X; accumulation in the wider of V and X.
+// y[i] = alpha * (A x)[i] + beta * b[i] + gamma * x[i]   (b may be null; gamma needs a
+// square A).  A in CSR with values V, vectors of type X; accumulation in the wider type.
+// y may alias b (each row reads only its own b entry), never x.
 template <class V, class X>
 void spmv(const int *rowptr, const int *col, const V *val, int rows, const X *x, X *y,
-          double alpha, const X *b, double beta, float avg_nnz, hipStream_t s);
+          double alpha, const X *b, double beta, float avg_nnz, hipStream_t s,
+          double gamma = 0.0);
 
 }  // namespace edfa

@@ -1,4 +1,92 @@
 // EDFA preconditioner handle (internal layout of an edfa_precond).
 #pragma once
 
+#include <memory>
+
 #include "system.hpp"
+
+namespace edfa {
+
+// Compiled capacities.
+constexpr int HMAX = 512;        // max entries of one row of H~ (before filtration)
+constexpr int FSAI_MAX = 16;     // max lower-pattern length of a row of A_pipi
+constexpr int MAX_COLORS = 512;
+constexpr int PATCH_MAX = 256;   // max pattern length of a static patch
+
+// Everything the preconditioner stores, in the working precision T.
+template <class T>
+struct PrecData {
+  // stage 1
+  DBuf<int> Q;          // Ne x smax final patterns (base order, then appended)
+  DBuf<int> qlen;       // Ne
+  DBuf<T> gbuf, fbuf;   // Ne x smax restricted solutions
+  Csr<T> G;             // G~   (Ne x Nfu)
+  Csr<T> FT;            // F~^T (Ne x Nfu): row m = column m of F~
+  Csr<T> Fface;         // F~   (Nfu x Ne)
+  DBuf<int> Hcol;       // Ne x HMAX raw H~ rows (sorted)
+  DBuf<T> Hval;
+  DBuf<int> Hlen;
+  Csr<T> Hraw;          // H~ before post-filtration (only when exported)
+  Csr<T> H;             // H~ used by stage 2
+  Csr<T> GF, GFT;       // FSAI factor of -A_pipi and its transpose
+  Csr<double> AppT_unused;
+  // stage 2
+  Csr<T> S;             // S~ = A_pp - H~ (post-filtered)
+  Csr<T> ST;            // pattern of S~^T (colouring)
+  DBuf<int> color, perm, iperm;     // perm[new] = old
+  std::vector<int> cstart;          // host: colour c owns new rows [cstart[c], cstart[c+1])
+  Csr<T> B;             // P S~ P^T, factored in place into L\U
+  DBuf<int> diag;       // Ne: position of the diagonal in B
+  Csr<T> L, U;          // strict lower (unit factor) and upper (with diagonal) of B
+  Csr<T> ML, MU;        // ISAI of (I + L) and U
+  Csr<T> LT, UT, MLT, MUT;          // transposes (built on first transposed apply)
+  // application scratch (working precision)
+  DBuf<T> r, z, t1, t2, y, w, zq, res;
+};
+
+// GMRES state: chunks of the unknown vector that never straddle a grid of a batch, and
+// the per-grid (segment) iteration state.
+constexpr int MAXV = 130;        // restart <= MAXV - 2
+struct Chunk {
+  int start, end, seg;
+};
+struct SegState {
+  double rtol, bnorm, tol, beta, est, relres;
+  int active, done, converged, j, total, pad;
+};
+struct SolveWork {
+  int nchunk = 0, n = 0;
+  DBuf<Chunk> chunks;
+  DBuf<int> segptr;
+  DBuf<double> V, Z, w, r, z, part, h1, h2, nrm, R, cs, sn, g, y, scale;
+  DBuf<int> ran;
+  DBuf<SegState> st;
+};
+
+}  // namespace edfa
+
+struct edfa_precond_s {
+  edfa_system_s *sys = nullptr;
+  edfa_params prm{};
+  int smax = 0;
+  int n_colors = 0;
+  int max_pattern = 0;
+  double t_stage1_ms = 0, t_stage2_ms = 0;
+  edfa::PrecData<double> d;
+  edfa::PrecData<float> f;
+  edfa::DBuf<int> flags;           // device error flags
+  edfa::Csr<float> coupling_f[4];  // FP32 A_ppi, A_pip, A_pip^T, A_ppi^T (FP32 application)
+  edfa::DBuf<float> rin_f;         // FP32 copy of the vector being preconditioned
+  std::unique_ptr<edfa::SolveWork> ws;
+};
+
+namespace edfa {
+void precond_stage1(edfa_precond_s &P, hipStream_t s);
+void precond_stage2(edfa_precond_s &P, hipStream_t s);
+void precond_apply(edfa_precond_s &P, int transpose, const double *r, double *z, hipStream_t s);
+edfa_status gmres(edfa_system_s &S, edfa_precond_s &P, const double *b, double *x,
+                  const edfa_solve_params &prm, hipStream_t s, edfa_solve_info *info);
+template <class T>
+void build_hraw(edfa_precond_s &P, PrecData<T> &D, hipStream_t s);
+void grad_logk(edfa_system_s &S, const double *u, const double *lam, double *g, hipStream_t s);
+}  // namespace edfa

@@ -1,0 +1,958 @@
+// EDFA stage 1 (the paper's Algorithm 1) on the device.
+//
+//  * k_base / k_patch   initial pattern Q_0 of every cell (row of A_ppi, or a k-ring patch)
+//  * k_local            one wavefront per cell: restricted SPD matrix -A_pipi^(m) gathered
+//                       into LDS (packed lower), right-looking Cholesky, solves for g~ and
+//                       f~ (eqs. syst_MRHS_res, syst_MRHS_res-F); dynamic variant grows Q
+//                       from the prolonged residual (eq. prol_res) and extends the factor by
+//                       bordering instead of refactoring
+//  * G~, F~^T           compacted (pre-filtration) into CSR
+//  * k_htilde           row m of H~ = (A_pipi R^T g~)^T F~ (eq. sparse_S), one wavefront per
+//                       cell, LDS hash maps, deterministic sums
+//  * k_fsai             factorised sparse approximate inverse of -A_pipi on lower(A_pipi)
+#include "precond.hpp"
+
+namespace edfa {
+
+constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
+
+template <int SIZE>
+__device__ inline unsigned hslot(int key) {
+  return ((unsigned)key * 2654435761u) >> (32 - ilog2c(SIZE));
+}
+
+// Find key in an LDS open-addressing table; returns the slot or -1.
+template <int SIZE>
+__device__ inline int h_find(const int *keys, int key) {
+  unsigned h = hslot<SIZE>(key);
+  for (int p = 0; p < SIZE; ++p) {
+    const int k = keys[h];
+    if (k == key) return (int)h;
+    if (k == -1) return -1;
+    h = (h + 1) & (SIZE - 1);
+  }
+  return -1;
+}
+
+// Insert key (idempotent); returns the slot, or -1 when the table is full.  fresh tells
+// whether this call inserted it.
+template <int SIZE>
+__device__ inline int h_insert(int *keys, int key, bool &fresh) {
+  unsigned h = hslot<SIZE>(key);
+  for (int p = 0; p < SIZE; ++p) {
+    const int old = atomicCAS(&keys[h], -1, key);
+    if (old == -1) {
+      fresh = true;
+      return (int)h;
+    }
+    if (old == key) {
+      fresh = false;
+      return (int)h;
+    }
+    h = (h + 1) & (SIZE - 1);
+  }
+  fresh = false;
+  return -1;
+}
+
+template <class T>
+__device__ inline T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+__device__ inline int pidx(int i, int j) { return i * (i + 1) / 2 + j; }   // packed lower
+
+// |r| rounded to 40 significant bits, as a monotone unsigned key.
+__device__ inline unsigned long long key40(double r) {
+  unsigned long long b = (unsigned long long)__double_as_longlong(fabs(r));
+  return (b + (1ull << 12)) & ~((1ull << 13) - 1ull);
+}
+
+// ------------------------------------------------------------------------------------
+// Initial patterns
+// ------------------------------------------------------------------------------------
+__global__ void k_base(const int *__restrict__ rp, const int *__restrict__ col, int ne, int smax,
+                       int *Q, int *qlen) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= ne) return;
+  const int a = rp[m], n = rp[m + 1] - a;
+  for (int t = 0; t < n && t < smax; ++t) Q[(size_t)m * smax + t] = col[a + t];
+  qlen[m] = n;
+}
+
+// Base pattern plus the unknown faces of every cell within `level` face-neighbour steps
+// (Manhattan distance on the structured grid), sorted.
+__global__ void k_patch(const GridDesc *__restrict__ grids, int ngrid, const int *__restrict__ uidx,
+                        const int *__restrict__ rp, const int *__restrict__ col, int ne, int level,
+                        int smax, int *Q, int *qlen, int *err_cap) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= ne) return;
+  const GridDesc &G = grids[grid_of(grids, ngrid, m, true)];
+  int i0, j0, k0;
+  cell_ijk(G, m, i0, j0, k0);
+  int buf[PATCH_MAX];
+  int n = 0;
+  bool over = false;
+  auto add = [&](int u) {
+    for (int t = 0; t < n; ++t)
+      if (buf[t] == u) return;
+    if (n < PATCH_MAX)
+      buf[n++] = u;
+    else
+      over = true;
+  };
+  for (int p = rp[m]; p < rp[m + 1]; ++p) add(col[p]);
+  for (int dk = -level; dk <= level; ++dk)
+    for (int dj = -level; dj <= level; ++dj)
+      for (int di = -level; di <= level; ++di) {
+        if (abs(di) + abs(dj) + abs(dk) > level) continue;
+        const int i = i0 + di, j = j0 + dj, k = k0 + dk;
+        if (i < 0 || j < 0 || k < 0 || i >= G.nx || j >= G.ny || k >= G.nz) continue;
+        for (int a = 0; a < 6; ++a) {
+          const int u = uidx[cell_face(G, i, j, k, a)];
+          if (u >= 0) add(u);
+        }
+      }
+  for (int p = 1; p < n; ++p) {
+    const int v = buf[p];
+    int q = p - 1;
+    while (q >= 0 && buf[q] > v) {
+      buf[q + 1] = buf[q];
+      --q;
+    }
+    buf[q + 1] = v;
+  }
+  if (over || n > smax) {
+    atomicMin(err_cap, m);
+    n = min(n, smax);
+  }
+  for (int t = 0; t < n; ++t) Q[(size_t)m * smax + t] = buf[t];
+  qlen[m] = n;
+}
+
+__global__ void k_len_max(const int *__restrict__ len, int n, int *out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  atomicMax(out, len[r]);
+}
+
+__global__ void k_repack(const int *__restrict__ src, const int *__restrict__ len, int n, int s0,
+                         int s1, int *dst) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  for (int t = 0; t < len[r]; ++t) dst[(size_t)r * s1 + t] = src[(size_t)r * s0 + t];
+}
+
+__global__ void k_row_max(const int *__restrict__ rp, int rows, int *out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  atomicMax(out, rp[r + 1] - rp[r]);
+}
+
+// ------------------------------------------------------------------------------------
+// Restricted local solves, one 64-lane wavefront per cell
+// ------------------------------------------------------------------------------------
+template <class T>
+struct LocalArgs {
+  int ne;
+  const int *app_rp, *app_col;
+  const double *app_val;
+  const int *acf_rp, *acf_col;
+  const double *acf_val;
+  const int *afcT_rp, *afcT_col;
+  const double *afcT_val;
+  int dynamic, n_add, n_ent, it_max;
+  int *Q, *qlen;
+  T *gout, *fout;
+  int *err_spd, *err_cap;
+};
+
+template <class T, int SMAX>
+__global__ __launch_bounds__(64) void k_local(LocalArgs<T> A) {
+  constexpr int QH = (2 * SMAX < 64) ? 64 : 2 * SMAX;
+  constexpr int CH = 8 * SMAX;
+  constexpr int LP = SMAX * (SMAX + 1) / 2;
+  __shared__ T Lp[LP];
+  __shared__ int q[SMAX];
+  __shared__ int qk[QH], qv[QH];
+  __shared__ T bg[SMAX], bf[SMAX], yg[SMAX], yf[SMAX], xg[SMAX], xf[SMAX], rowt[SMAX];
+  __shared__ int ck[CH], clist[CH];
+  __shared__ T cr[CH];
+  __shared__ int ccount, sflag;
+
+  const int m = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (m >= A.ne) return;
+  int s = A.qlen[m];
+  if (s > SMAX) {
+    if (lane == 0) atomicMin(A.err_cap, m);
+    return;
+  }
+  for (int t = lane; t < SMAX; t += 64) {
+    q[t] = t < s ? A.Q[(size_t)m * SMAX + t] : -1;
+    bg[t] = 0;
+    bf[t] = 0;
+  }
+  for (int h = lane; h < QH; h += 64) qk[h] = -1;
+  if (lane == 0) sflag = 0;
+  __syncthreads();
+  for (int t = lane; t < s; t += 64) {
+    bool fr;
+    const int h = h_insert<QH>(qk, q[t], fr);
+    qv[h] = t;
+  }
+  __syncthreads();
+  // right-hand sides: a_ppi^(m) (row m of A_ppi) and a_pip^(m) (column m of A_pip)
+  for (int p = A.acf_rp[m] + lane; p < A.acf_rp[m + 1]; p += 64) {
+    const int h = h_find<QH>(qk, A.acf_col[p]);
+    if (h >= 0) bg[qv[h]] = (T)A.acf_val[p];
+  }
+  for (int p = A.afcT_rp[m] + lane; p < A.afcT_rp[m + 1]; p += 64) {
+    const int h = h_find<QH>(qk, A.afcT_col[p]);
+    if (h >= 0) bf[qv[h]] = (T)A.afcT_val[p];
+  }
+  // restricted matrix -R A_pipi R^T, lower part in Q order
+  for (int t = lane; t < LP; t += 64) Lp[t] = 0;
+  __syncthreads();
+  for (int t = lane; t < s; t += 64) {
+    const int r = q[t];
+    for (int p = A.app_rp[r]; p < A.app_rp[r + 1]; ++p) {
+      const int h = h_find<QH>(qk, A.app_col[p]);
+      if (h >= 0) {
+        const int k = qv[h];
+        if (k <= t) Lp[pidx(t, k)] = -(T)A.app_val[p];
+      }
+    }
+  }
+  __syncthreads();
+
+  // right-looking Cholesky
+  for (int j = 0; j < s; ++j) {
+    const T d = Lp[pidx(j, j)];
+    if (!(d > T(0))) {
+      if (lane == 0) atomicMin(A.err_spd, m);
+      return;
+    }
+    const T ljj = sqrt(d);
+    __syncthreads();
+    if (lane == 0) Lp[pidx(j, j)] = ljj;
+    for (int i = j + 1 + lane; i < s; i += 64) Lp[pidx(i, j)] /= ljj;
+    __syncthreads();
+    for (int i = j + 1 + lane; i < s; i += 64) {
+      const T lij = Lp[pidx(i, j)];
+      for (int k = j + 1; k <= i; ++k) Lp[pidx(i, k)] -= lij * Lp[pidx(k, j)];
+    }
+    __syncthreads();
+  }
+
+  // solves with the current factor: two right-hand sides (g and f) or g only
+  auto solve = [&](bool with_f) {
+    for (int t = lane; t < s; t += 64) {
+      rowt[t] = bg[t];
+      if (with_f) xf[t] = bf[t];
+    }
+    __syncthreads();
+    for (int k = 0; k < s; ++k) {   // forward: L y = b (rowt, xf as work vectors)
+      const T dk = Lp[pidx(k, k)];
+      const T y1 = rowt[k] / dk;
+      const T y2 = with_f ? xf[k] / dk : T(0);
+      for (int i = k + 1 + lane; i < s; i += 64) {
+        const T l = Lp[pidx(i, k)];
+        rowt[i] -= l * y1;
+        if (with_f) xf[i] -= l * y2;
+      }
+      if (lane == 0) {
+        yg[k] = y1;
+        if (with_f) yf[k] = y2;
+      }
+      __syncthreads();
+    }
+    for (int k = s - 1; k >= 0; --k) {   // backward: L^T x = y (in place on yg, yf)
+      const T dk = Lp[pidx(k, k)];
+      const T x1 = yg[k] / dk;
+      const T x2 = with_f ? yf[k] / dk : T(0);
+      for (int i = lane; i < k; i += 64) {
+        const T l = Lp[pidx(k, i)];
+        yg[i] -= l * x1;
+        if (with_f) yf[i] -= l * x2;
+      }
+      __syncthreads();
+      if (lane == 0) {
+        xg[k] = x1;
+        if (with_f) xf[k] = x2;
+      }
+    }
+    __syncthreads();
+  };
+
+  if (!A.dynamic) {
+    solve(true);
+  } else {
+    solve(false);
+    const int it_max = A.it_max > 0 ? A.it_max : A.n_ent;
+    int n_prog = 0, sweep = 0;
+    while (n_prog < A.n_ent && sweep < it_max) {
+      ++sweep;
+      const int n = min(A.n_add, A.n_ent - n_prog);
+      // candidate set: A_pipi neighbours of Q outside Q (support of the prolonged residual)
+      for (int h = lane; h < CH; h += 64) ck[h] = -1;
+      if (lane == 0) ccount = 0;
+      __syncthreads();
+      for (int t = lane; t < s; t += 64) {
+        const int r = q[t];
+        for (int p = A.app_rp[r]; p < A.app_rp[r + 1]; ++p) {
+          const int c = A.app_col[p];
+          if (h_find<QH>(qk, c) < 0) {
+            bool fr;
+            if (h_insert<CH>(ck, c, fr) < 0) sflag = 1;
+          }
+        }
+      }
+      __syncthreads();
+      if (sflag) {
+        if (lane == 0) atomicMin(A.err_cap, m);
+        return;
+      }
+      for (int h = lane; h < CH; h += 64)
+        if (ck[h] >= 0) clist[atomicAdd(&ccount, 1)] = ck[h];
+      __syncthreads();
+      const int nc = ccount;
+      // r_j = (A_pipi R^T g~)_j for j outside Q (a_ppi^(m) vanishes there)
+      for (int c = lane; c < nc; c += 64) {
+        const int j = clist[c];
+        T acc = 0;
+        for (int p = A.app_rp[j]; p < A.app_rp[j + 1]; ++p) {
+          const int h = h_find<QH>(qk, A.app_col[p]);
+          if (h >= 0) acc += (T)A.app_val[p] * xg[qv[h]];
+        }
+        cr[c] = acc;
+      }
+      __syncthreads();
+      int added = 0;
+      for (int rnd = 0; rnd < n; ++rnd) {
+        unsigned long long bk = 0;
+        int bj = 0x7fffffff, bc = -1;
+        for (int c = lane; c < nc; c += 64) {
+          const unsigned long long k = key40((double)cr[c]);
+          const int j = clist[c];
+          if (k > bk || (k == bk && k != 0 && j < bj)) {
+            bk = k;
+            bj = j;
+            bc = c;
+          }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+          const unsigned lo = __shfl_xor((unsigned)(bk & 0xffffffffull), o);
+          const unsigned hi = __shfl_xor((unsigned)(bk >> 32), o);
+          const unsigned long long ok = ((unsigned long long)hi << 32) | lo;
+          const int oj = __shfl_xor(bj, o);
+          const int oc = __shfl_xor(bc, o);
+          if (ok > bk || (ok == bk && oj < bj)) {
+            bk = ok;
+            bj = oj;
+            bc = oc;
+          }
+        }
+        if (bk == 0) break;   // uniform: every lane holds the reduced value
+        if (s >= SMAX) {
+          if (lane == 0) atomicMin(A.err_cap, m);
+          return;
+        }
+        const int t = s;
+        if (lane == 0) {
+          cr[bc] = 0;
+          q[t] = bj;
+          bool fr;
+          const int h = h_insert<QH>(qk, bj, fr);
+          qv[h] = t;
+          bg[t] = 0;
+          bf[t] = 0;
+        }
+        __syncthreads();
+        // bordered Cholesky: gather row t of -A_pipi[Q,Q], solve L l = m, new diagonal
+        for (int k = lane; k <= t; k += 64) rowt[k] = 0;
+        __syncthreads();
+        for (int p = A.app_rp[bj] + lane; p < A.app_rp[bj + 1]; p += 64) {
+          const int h = h_find<QH>(qk, A.app_col[p]);
+          if (h >= 0) rowt[qv[h]] = -(T)A.app_val[p];
+        }
+        __syncthreads();
+        for (int k = 0; k < t; ++k) {
+          const T lk = rowt[k] / Lp[pidx(k, k)];
+          for (int i = k + 1 + lane; i < t; i += 64) rowt[i] -= Lp[pidx(i, k)] * lk;
+          if (lane == 0) Lp[pidx(t, k)] = lk;
+          __syncthreads();
+        }
+        T part = 0;
+        for (int k = lane; k < t; k += 64) {
+          const T l = Lp[pidx(t, k)];
+          part += l * l;
+        }
+        const T d = rowt[t] - wave_sum(part);
+        if (!(d > T(0))) {
+          if (lane == 0) atomicMin(A.err_spd, m);
+          return;
+        }
+        if (lane == 0) Lp[pidx(t, t)] = sqrt(d);
+        __syncthreads();
+        ++s;
+        ++added;
+      }
+      if (added == 0) break;
+      n_prog += added;
+      solve(false);
+    }
+    // f~ on the final pattern: its right-hand side was placed when the base was loaded
+    solve(true);
+  }
+  for (int t = lane; t < s; t += 64) {
+    A.Q[(size_t)m * SMAX + t] = q[t];
+    A.gout[(size_t)m * SMAX + t] = xg[t];
+    A.fout[(size_t)m * SMAX + t] = xf[t];
+  }
+  if (lane == 0) A.qlen[m] = s;
+}
+
+// ------------------------------------------------------------------------------------
+// G~ and F~^T as CSR (sorted columns), with optional pre-filtration
+// ------------------------------------------------------------------------------------
+template <class T>
+__global__ void k_vec_count(const int *__restrict__ qlen, const T *__restrict__ v, int ne, int smax,
+                            int pre, double tau, int *len) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= ne) return;
+  const int s = qlen[m];
+  if (!pre) {
+    len[m] = s;
+    return;
+  }
+  const T *x = v + (size_t)m * smax;
+  double nrm = 0;
+  for (int t = 0; t < s; ++t) nrm += (double)x[t] * (double)x[t];
+  const double thr = tau * sqrt(nrm);
+  int c = 0;
+  for (int t = 0; t < s; ++t) c += fabs((double)x[t]) >= thr;
+  len[m] = c;
+}
+
+template <class T, int CAP>
+__global__ void k_vec_write(const int *__restrict__ Q, const int *__restrict__ qlen,
+                            const T *__restrict__ v, int ne, int smax, int pre, double tau,
+                            const int *__restrict__ rp, int *col, T *val) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= ne) return;
+  const int s = qlen[m];
+  const T *x = v + (size_t)m * smax;
+  const int *qq = Q + (size_t)m * smax;
+  double thr = -1.0;
+  if (pre) {
+    double nrm = 0;
+    for (int t = 0; t < s; ++t) nrm += (double)x[t] * (double)x[t];
+    thr = tau * sqrt(nrm);
+  }
+  int base = rp[m];
+  int n = 0;
+  int c[CAP];
+  T w[CAP];
+  for (int t = 0; t < s; ++t) {
+    if (pre && !(fabs((double)x[t]) >= thr)) continue;
+    const int cc = qq[t];
+    const T vv = x[t];
+    int p = n - 1;
+    while (p >= 0 && c[p] > cc) {
+      c[p + 1] = c[p];
+      w[p + 1] = w[p];
+      --p;
+    }
+    c[p + 1] = cc;
+    w[p + 1] = vv;
+    ++n;
+  }
+  for (int t = 0; t < n; ++t) {
+    col[base + t] = c[t];
+    val[base + t] = w[t];
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// H~ rows: h_m = (A_pipi R^T g~_m)^T F~, one wavefront per cell
+// ------------------------------------------------------------------------------------
+template <class T>
+struct HArgs {
+  int ne;
+  const int *g_rp, *g_col;
+  const T *g_val;
+  const int *app_rp, *app_col;
+  const double *app_val;
+  const int *ff_rp, *ff_col;   // F~ by face rows (cells)
+  const int *ft_rp, *ft_col;   // F~^T by cell rows (faces)
+  const T *ft_val;
+  int *Hcol, *Hlen;
+  T *Hval;
+  int *err_cap;
+};
+
+template <class T, int GH, int TH, int LH>
+__global__ __launch_bounds__(64) void k_htilde(HArgs<T> A) {
+  __shared__ int gk[GH];
+  __shared__ T gv[GH];
+  __shared__ int tk[TH], tlist[TH];
+  __shared__ T tv[TH];
+  __shared__ int lk[LH], llist[LH];
+  __shared__ T hv[LH];
+  __shared__ int tcount, lcount, sflag;
+  const int m = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (m >= A.ne) return;
+  for (int h = lane; h < GH; h += 64) gk[h] = -1;
+  for (int h = lane; h < TH; h += 64) tk[h] = -1;
+  for (int h = lane; h < LH; h += 64) lk[h] = -1;
+  if (lane == 0) {
+    tcount = 0;
+    lcount = 0;
+    sflag = 0;
+  }
+  __syncthreads();
+  const int g0 = A.g_rp[m], g1 = A.g_rp[m + 1];
+  for (int p = g0 + lane; p < g1; p += 64) {
+    bool fr;
+    const int h = h_insert<GH>(gk, A.g_col[p], fr);
+    if (h < 0)
+      sflag = 1;
+    else
+      gv[h] = A.g_val[p];
+  }
+  // support of t = A_pipi R^T g~: A_pipi neighbours of the pattern of g~
+  for (int p = g0 + lane; p < g1; p += 64) {
+    const int k = A.g_col[p];
+    for (int q = A.app_rp[k]; q < A.app_rp[k + 1]; ++q) {
+      bool fr;
+      const int h = h_insert<TH>(tk, A.app_col[q], fr);
+      if (h < 0)
+        sflag = 1;
+      else if (fr)
+        tlist[atomicAdd(&tcount, 1)] = h;
+    }
+  }
+  __syncthreads();
+  if (sflag) {
+    if (lane == 0) atomicMin(A.err_cap, m);
+    return;
+  }
+  const int nt = tcount;
+  for (int c = lane; c < nt; c += 64) {
+    const int h = tlist[c];
+    const int j = tk[h];
+    T acc = 0;
+    for (int q = A.app_rp[j]; q < A.app_rp[j + 1]; ++q) {
+      const int s = h_find<GH>(gk, A.app_col[q]);
+      if (s >= 0) acc += (T)A.app_val[q] * gv[s];
+    }
+    tv[h] = acc;
+  }
+  // candidate cells: all l with F~[j, l] != 0 for j in the support of t
+  for (int c = lane; c < nt; c += 64) {
+    const int j = tk[tlist[c]];
+    for (int q = A.ff_rp[j]; q < A.ff_rp[j + 1]; ++q) {
+      bool fr;
+      const int h = h_insert<LH>(lk, A.ff_col[q], fr);
+      if (h < 0)
+        sflag = 1;
+      else if (fr)
+        llist[atomicAdd(&lcount, 1)] = A.ff_col[q];
+    }
+  }
+  __syncthreads();
+  const int nl = lcount;
+  if (sflag || nl > HMAX) {
+    if (lane == 0) atomicMin(A.err_cap, m);
+    return;
+  }
+  // h_ml = sum over the pattern of f~_l of t_j f~_l[j]   (F~^T row l, ascending j)
+  for (int c = lane; c < nl; c += 64) {
+    const int l = llist[c];
+    T acc = 0;
+    for (int q = A.ft_rp[l]; q < A.ft_rp[l + 1]; ++q) {
+      const int s = h_find<TH>(tk, A.ft_col[q]);
+      if (s >= 0) acc += tv[s] * A.ft_val[q];
+    }
+    hv[c] = acc;
+  }
+  __syncthreads();
+  // write sorted by column: rank = number of smaller candidate cells
+  for (int c = lane; c < nl; c += 64) {
+    const int l = llist[c];
+    int rank = 0;
+    for (int c2 = 0; c2 < nl; ++c2) rank += llist[c2] < l;
+    A.Hcol[(size_t)m * HMAX + rank] = l;
+    A.Hval[(size_t)m * HMAX + rank] = hv[c];
+  }
+  if (lane == 0) A.Hlen[m] = nl;
+}
+
+// Post-filtration on H~ (row norm before dropping, diagonal kept) and compaction.
+template <class T>
+__global__ void k_hcount(const int *__restrict__ Hcol, const T *__restrict__ Hval,
+                         const int *__restrict__ Hlen, int ne, int filt, double tau, int *len) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= ne) return;
+  const int n = Hlen[m];
+  if (!filt) {
+    len[m] = n;
+    return;
+  }
+  const T *v = Hval + (size_t)m * HMAX;
+  const int *c = Hcol + (size_t)m * HMAX;
+  double nrm = 0;
+  for (int t = 0; t < n; ++t) nrm += (double)v[t] * (double)v[t];
+  const double thr = tau * sqrt(nrm);
+  int k = 0;
+  for (int t = 0; t < n; ++t) k += (fabs((double)v[t]) >= thr) || c[t] == m;
+  len[m] = k;
+}
+
+template <class T>
+__global__ void k_hwrite(const int *__restrict__ Hcol, const T *__restrict__ Hval,
+                         const int *__restrict__ Hlen, int ne, int filt, double tau,
+                         const int *__restrict__ rp, int *col, T *val) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= ne) return;
+  const int n = Hlen[m];
+  const T *v = Hval + (size_t)m * HMAX;
+  const int *c = Hcol + (size_t)m * HMAX;
+  double thr = -1.0;
+  if (filt) {
+    double nrm = 0;
+    for (int t = 0; t < n; ++t) nrm += (double)v[t] * (double)v[t];
+    thr = tau * sqrt(nrm);
+  }
+  int o = rp[m];
+  for (int t = 0; t < n; ++t) {
+    if (filt && !((fabs((double)v[t]) >= thr) || c[t] == m)) continue;
+    col[o] = c[t];
+    val[o] = v[t];
+    ++o;
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// FSAI of -A_pipi: row i on P_i = {j <= i in the pattern of A_pipi}; with M = -A[P,P] =
+// L L^T, the solution of M y = e_last has y_last = 1/L_ll^2, so G_F[i, P_i] = y L_ll.
+// ------------------------------------------------------------------------------------
+__global__ void k_fsai_count(const int *__restrict__ rp, const int *__restrict__ col, int n,
+                             int *len) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int c = 0;
+  for (int p = rp[i]; p < rp[i + 1]; ++p) c += col[p] <= i;
+  len[i] = c;
+}
+
+template <class T>
+__global__ void k_fsai(const int *__restrict__ rp, const int *__restrict__ col,
+                       const double *__restrict__ val, int n, const int *__restrict__ grp,
+                       int *gcol, T *gval, int *err_spd, int *err_cap) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int P[FSAI_MAX];
+  int np = 0;
+  for (int p = rp[i]; p < rp[i + 1]; ++p)
+    if (col[p] <= i) {
+      if (np == FSAI_MAX) {
+        atomicMin(err_cap, i);
+        return;
+      }
+      P[np++] = col[p];
+    }
+  T M[FSAI_MAX * (FSAI_MAX + 1) / 2];
+  for (int t = 0; t < np * (np + 1) / 2; ++t) M[t] = 0;
+  for (int a = 0; a < np; ++a) {
+    const int r = P[a];
+    for (int p = rp[r]; p < rp[r + 1]; ++p) {
+      const int c = col[p];
+      for (int b = 0; b <= a; ++b)
+        if (P[b] == c) M[pidx(a, b)] = -(T)val[p];
+    }
+  }
+  for (int j = 0; j < np; ++j) {
+    T d = M[pidx(j, j)];
+    for (int k = 0; k < j; ++k) d -= M[pidx(j, k)] * M[pidx(j, k)];
+    if (!(d > T(0))) {
+      atomicMin(err_spd, i);
+      return;
+    }
+    d = sqrt(d);
+    M[pidx(j, j)] = d;
+    for (int r = j + 1; r < np; ++r) {
+      T s = M[pidx(r, j)];
+      for (int k = 0; k < j; ++k) s -= M[pidx(r, k)] * M[pidx(j, k)];
+      M[pidx(r, j)] = s / d;
+    }
+  }
+  T y[FSAI_MAX];
+  const int l = np - 1;
+  const T Ll = M[pidx(l, l)];
+  y[l] = T(1) / (Ll * Ll);
+  for (int k = l - 1; k >= 0; --k) {
+    T s = 0;
+    for (int r = k + 1; r <= l; ++r) s -= M[pidx(r, k)] * y[r];
+    y[k] = s / M[pidx(k, k)];
+  }
+  const int o = grp[i];
+  for (int t = 0; t < np; ++t) {
+    gcol[o + t] = P[t];
+    gval[o + t] = y[t] * Ll;
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// Host driver of stage 1
+// ------------------------------------------------------------------------------------
+template <class T>
+static void build_vec_csr(edfa_system_s &S, PrecData<T> &D, const DBuf<T> &v, int smax, int pre,
+                          double tau, Csr<T> &out, hipStream_t s) {
+  const int ne = S.ne;
+  out.rowptr.ensure((size_t)ne + 1);
+  hipLaunchKernelGGL(k_vec_count<T>, dim3(ceil_div(ne, 256)), dim3(256), 0, s, D.qlen.p, v.p, ne,
+                     smax, pre, tau, out.rowptr.p);
+  EDFA_CHECK_LAUNCH();
+  const int64_t nnz = exclusive_scan(out.rowptr.p, out.rowptr.p, ne, S.tmp, s);
+  out.rows = ne;
+  out.cols = S.nfu;
+  out.nnz = nnz;
+  out.col.ensure(nnz);
+  out.val.ensure(nnz);
+  auto launch = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(ceil_div(ne, 64)), dim3(64), 0, s, D.Q.p, D.qlen.p, v.p, ne, smax,
+                       pre, tau, out.rowptr.p, out.col.p, out.val.p);
+    EDFA_CHECK_LAUNCH();
+  };
+  if (smax <= 16)
+    launch(k_vec_write<T, 16>);
+  else if (smax <= 32)
+    launch(k_vec_write<T, 32>);
+  else if (smax <= 64)
+    launch(k_vec_write<T, 64>);
+  else if (smax <= 128)
+    launch(k_vec_write<T, 128>);
+  else
+    launch(k_vec_write<T, PATCH_MAX>);
+}
+
+static void check_flags(edfa_precond_s &P, hipStream_t s, const char *where) {
+  int fl[2];
+  EDFA_HIP(hipMemcpyAsync(fl, P.flags.p, sizeof(fl), hipMemcpyDeviceToHost, s));
+  EDFA_HIP(hipStreamSynchronize(s));
+  if (fl[0] != 0x7fffffff)
+    fail(EDFA_ERR_NOT_SPD, "%s: restricted system of row/cell %d is not SPD", where, fl[0]);
+  if (fl[1] != 0x7fffffff)
+    fail(EDFA_ERR_CAPACITY, "%s: pattern capacity exceeded at row/cell %d", where, fl[1]);
+}
+
+static void reset_flags(edfa_precond_s &P, hipStream_t s) {
+  P.flags.ensure(4);
+  const int init[4] = {0x7fffffff, 0x7fffffff, 0, 0};
+  EDFA_HIP(hipMemcpyAsync(P.flags.p, init, sizeof(init), hipMemcpyHostToDevice, s));
+}
+
+template <class T>
+static void stage1_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
+  edfa_system_s &S = *P.sys;
+  const edfa_params &prm = P.prm;
+  const int ne = S.ne, nfu = S.nfu;
+  reset_flags(P, s);
+  int *err_spd = P.flags.p, *err_cap = P.flags.p + 1;
+
+  // maximum base-pattern length
+  EDFA_HIP(hipMemsetAsync(P.flags.p + 2, 0, sizeof(int), s));
+  hipLaunchKernelGGL(k_row_max, dim3(ceil_div(ne, 256)), dim3(256), 0, s, S.Acf.rowptr.p, ne,
+                     P.flags.p + 2);
+  EDFA_CHECK_LAUNCH();
+  const int maxbase = read_scalar(P.flags.p + 2, s);
+  const bool dynamic = prm.variant == EDFA_DYNAMIC;
+  int need = maxbase;
+  if (dynamic) need = maxbase + std::max(0, prm.n_ent);
+  int smax = need <= 16 ? 16 : need <= 32 ? 32 : need <= 64 ? 64 : need <= 128 ? 128 : 0;
+  if (!smax && (dynamic || prm.static_level == 0))
+    fail(EDFA_ERR_CAPACITY, "patterns of up to %d entries exceed 128", need);
+  D.qlen.ensure(ne);
+  if (!dynamic && prm.static_level > 0) {
+    if (prm.static_level > 3) fail(EDFA_ERR_ARG, "static_level must be 0..3");
+    // patches are built with the widest stride, then repacked to the smallest template
+    DBuf<int> wide;
+    wide.ensure((size_t)ne * PATCH_MAX);
+    hipLaunchKernelGGL(k_patch, dim3(ceil_div(ne, 64)), dim3(64), 0, s, S.grids.p, S.ngrid,
+                       S.uidx.p, S.Acf.rowptr.p, S.Acf.col.p, ne, prm.static_level, PATCH_MAX,
+                       wide.p, D.qlen.p, err_cap);
+    EDFA_CHECK_LAUNCH();
+    check_flags(P, s, "static patch");
+    EDFA_HIP(hipMemsetAsync(P.flags.p + 2, 0, sizeof(int), s));
+    hipLaunchKernelGGL(k_len_max, dim3(ceil_div(ne, 256)), dim3(256), 0, s, D.qlen.p, ne,
+                       P.flags.p + 2);
+    EDFA_CHECK_LAUNCH();
+    need = read_scalar(P.flags.p + 2, s);
+    smax = need <= 16 ? 16 : need <= 32 ? 32 : need <= 64 ? 64 : need <= 128 ? 128 : 0;
+    if (!smax) fail(EDFA_ERR_CAPACITY, "static patches of %d entries exceed 128", need);
+    D.Q.ensure((size_t)ne * smax);
+    hipLaunchKernelGGL(k_repack, dim3(ceil_div(ne, 256)), dim3(256), 0, s, wide.p, D.qlen.p, ne,
+                       PATCH_MAX, smax, D.Q.p);
+    EDFA_CHECK_LAUNCH();
+    EDFA_HIP(hipStreamSynchronize(s));
+  } else {
+    D.Q.ensure((size_t)ne * smax);
+  }
+  D.gbuf.ensure((size_t)ne * smax);
+  D.fbuf.ensure((size_t)ne * smax);
+  P.smax = smax;
+
+  LocalArgs<T> la;
+  la.ne = ne;
+  la.app_rp = S.Afp.rowptr.p;
+  la.app_col = S.Afp.col.p;
+  la.app_val = S.Afp.val.p;
+  la.acf_rp = S.Acf.rowptr.p;
+  la.acf_col = S.Acf.col.p;
+  la.acf_val = S.Acf.val.p;
+  la.afcT_rp = S.AfcT.rowptr.p;
+  la.afcT_col = S.AfcT.col.p;
+  la.afcT_val = S.AfcT.val.p;
+  la.dynamic = dynamic;
+  la.n_add = std::max(1, prm.n_add);
+  la.n_ent = std::max(0, prm.n_ent);
+  la.it_max = prm.it_max;
+  la.Q = D.Q.p;
+  la.qlen = D.qlen.p;
+  la.gout = D.gbuf.p;
+  la.fout = D.fbuf.p;
+  la.err_spd = err_spd;
+  la.err_cap = err_cap;
+  if (dynamic || prm.static_level == 0) {
+    hipLaunchKernelGGL(k_base, dim3(ceil_div(ne, 256)), dim3(256), 0, s, S.Acf.rowptr.p,
+                       S.Acf.col.p, ne, smax, D.Q.p, D.qlen.p);
+    EDFA_CHECK_LAUNCH();
+  }
+  if (ne > 0) {
+    switch (smax) {
+      case 16: hipLaunchKernelGGL((k_local<T, 16>), dim3(ne), dim3(64), 0, s, la); break;
+      case 32: hipLaunchKernelGGL((k_local<T, 32>), dim3(ne), dim3(64), 0, s, la); break;
+      case 64: hipLaunchKernelGGL((k_local<T, 64>), dim3(ne), dim3(64), 0, s, la); break;
+      case 128: hipLaunchKernelGGL((k_local<T, 128>), dim3(ne), dim3(64), 0, s, la); break;
+      default: fail(EDFA_ERR_CAPACITY, "static patterns longer than 128 are not supported");
+    }
+    EDFA_CHECK_LAUNCH();
+  }
+  check_flags(P, s, "restricted solves");
+  {
+    // longest final pattern (diagnostic)
+    std::vector<int> ql(ne);
+    if (ne)
+      EDFA_HIP(hipMemcpyAsync(ql.data(), D.qlen.p, sizeof(int) * ne, hipMemcpyDeviceToHost, s));
+    EDFA_HIP(hipStreamSynchronize(s));
+    int mx = 0;
+    for (int v : ql) mx = std::max(mx, v);
+    P.max_pattern = mx;
+  }
+
+  // G~ and F~^T (pre-filtration), F~ by faces
+  const int pre = prm.filt_mode == EDFA_FILT_PRE;
+  build_vec_csr(S, D, D.gbuf, smax, pre, prm.tau_filt, D.G, s);
+  build_vec_csr(S, D, D.fbuf, smax, pre, prm.tau_filt, D.FT, s);
+  csr_transpose(D.FT, D.Fface, S.tmp, s);
+
+  // H~ = G~ A_pipi F~
+  D.Hcol.ensure((size_t)ne * HMAX);
+  D.Hval.ensure((size_t)ne * HMAX);
+  D.Hlen.ensure(ne);
+  HArgs<T> ha;
+  ha.ne = ne;
+  ha.g_rp = D.G.rowptr.p;
+  ha.g_col = D.G.col.p;
+  ha.g_val = D.G.val.p;
+  ha.app_rp = S.Afp.rowptr.p;
+  ha.app_col = S.Afp.col.p;
+  ha.app_val = S.Afp.val.p;
+  ha.ff_rp = D.Fface.rowptr.p;
+  ha.ff_col = D.Fface.col.p;
+  ha.ft_rp = D.FT.rowptr.p;
+  ha.ft_col = D.FT.col.p;
+  ha.ft_val = D.FT.val.p;
+  ha.Hcol = D.Hcol.p;
+  ha.Hlen = D.Hlen.p;
+  ha.Hval = D.Hval.p;
+  ha.err_cap = err_cap;
+  const int support = P.max_pattern * (S.axis ? 3 : 11);
+  if (ne > 0) {
+    if (P.max_pattern <= 32 && support <= 128)
+      hipLaunchKernelGGL((k_htilde<T, 64, 256, 1024>), dim3(ne), dim3(64), 0, s, ha);
+    else if (P.max_pattern <= 64 && support <= 512)
+      hipLaunchKernelGGL((k_htilde<T, 128, 1024, 1024>), dim3(ne), dim3(64), 0, s, ha);
+    else
+      hipLaunchKernelGGL((k_htilde<T, 256, 2048, 1024>), dim3(ne), dim3(64), 0, s, ha);
+    EDFA_CHECK_LAUNCH();
+  }
+  check_flags(P, s, "H~ rows");
+  const int postH = prm.filt_mode == EDFA_FILT_POST_H;
+  D.H.rowptr.ensure((size_t)ne + 1);
+  hipLaunchKernelGGL(k_hcount<T>, dim3(ceil_div(ne, 256)), dim3(256), 0, s, D.Hcol.p, D.Hval.p,
+                     D.Hlen.p, ne, postH, prm.tau_filt, D.H.rowptr.p);
+  EDFA_CHECK_LAUNCH();
+  const int64_t hnnz = exclusive_scan(D.H.rowptr.p, D.H.rowptr.p, ne, S.tmp, s);
+  D.H.rows = D.H.cols = ne;
+  D.H.nnz = hnnz;
+  D.H.col.ensure(hnnz);
+  D.H.val.ensure(hnnz);
+  hipLaunchKernelGGL(k_hwrite<T>, dim3(ceil_div(ne, 256)), dim3(256), 0, s, D.Hcol.p, D.Hval.p,
+                     D.Hlen.p, ne, postH, prm.tau_filt, D.H.rowptr.p, D.H.col.p, D.H.val.p);
+  EDFA_CHECK_LAUNCH();
+
+  // FSAI of -A_pipi
+  D.GF.rowptr.ensure((size_t)nfu + 1);
+  hipLaunchKernelGGL(k_fsai_count, dim3(ceil_div(nfu, 256)), dim3(256), 0, s, S.Afp.rowptr.p,
+                     S.Afp.col.p, nfu, D.GF.rowptr.p);
+  EDFA_CHECK_LAUNCH();
+  const int64_t gnnz = exclusive_scan(D.GF.rowptr.p, D.GF.rowptr.p, nfu, S.tmp, s);
+  D.GF.rows = D.GF.cols = nfu;
+  D.GF.nnz = gnnz;
+  D.GF.col.ensure(gnnz);
+  D.GF.val.ensure(gnnz);
+  if (nfu > 0) {
+    hipLaunchKernelGGL(k_fsai<T>, dim3(ceil_div(nfu, 64)), dim3(64), 0, s, S.Afp.rowptr.p,
+                       S.Afp.col.p, S.Afp.val.p, nfu, D.GF.rowptr.p, D.GF.col.p, D.GF.val.p,
+                       err_spd, err_cap);
+    EDFA_CHECK_LAUNCH();
+  }
+  check_flags(P, s, "FSAI");
+  csr_transpose(D.GF, D.GFT, S.tmp, s);
+}
+
+// Raw (unfiltered) H~ as CSR, for export.
+template <class T>
+void build_hraw(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
+  edfa_system_s &S = *P.sys;
+  const int ne = S.ne;
+  D.Hraw.rowptr.ensure((size_t)ne + 1);
+  hipLaunchKernelGGL(k_hcount<T>, dim3(ceil_div(ne, 256)), dim3(256), 0, s, D.Hcol.p, D.Hval.p,
+                     D.Hlen.p, ne, 0, 0.0, D.Hraw.rowptr.p);
+  const int64_t nnz = exclusive_scan(D.Hraw.rowptr.p, D.Hraw.rowptr.p, ne, S.tmp, s);
+  D.Hraw.rows = D.Hraw.cols = ne;
+  D.Hraw.nnz = nnz;
+  D.Hraw.col.ensure(nnz);
+  D.Hraw.val.ensure(nnz);
+  hipLaunchKernelGGL(k_hwrite<T>, dim3(ceil_div(ne, 256)), dim3(256), 0, s, D.Hcol.p, D.Hval.p,
+                     D.Hlen.p, ne, 0, 0.0, D.Hraw.rowptr.p, D.Hraw.col.p, D.Hraw.val.p);
+  EDFA_CHECK_LAUNCH();
+}
+template void build_hraw<double>(edfa_precond_s &, PrecData<double> &, hipStream_t);
+template void build_hraw<float>(edfa_precond_s &, PrecData<float> &, hipStream_t);
+
+void precond_stage1(edfa_precond_s &P, hipStream_t s) {
+  if (P.prm.precision == 1)
+    stage1_impl<float>(P, P.f, s);
+  else
+    stage1_impl<double>(P, P.d, s);
+}
+
+}  // namespace edfa

@@ -1,0 +1,476 @@
+// Restarted right-preconditioned GMRES / flexible GMRES, x0 = 0, exit on the true FP64
+// relative residual (the paper's stopping test, Section 4).
+//
+// Every grid of a batch ("segment") has its own Krylov basis coefficients, Hessenberg
+// matrix, Givens rotations and convergence state; all segments advance together and a
+// converged segment is masked out of the vector kernels.  Vectors are processed in
+// chunks that never straddle a segment, so every reduction is per segment and fixed in
+// order (deterministic).  Orthogonalisation: classical Gram-Schmidt applied twice.
+#include <cmath>
+
+#include "precond.hpp"
+
+namespace edfa {
+
+constexpr int CHUNK = 2048;   // elements per chunk: 256 threads x 8
+constexpr int RT = 256;
+
+__global__ __launch_bounds__(RT) void k_dots(const double *__restrict__ V, long long ldv, int nv,
+                                             const double *__restrict__ w,
+                                             const Chunk *__restrict__ ch,
+                                             const SegState *__restrict__ st, double *part, int ldp) {
+  __shared__ double red[4][MAXV];
+  const Chunk c = ch[blockIdx.x];
+  if (!st[c.seg].active) return;
+  double wl[8];
+  int idx[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    idx[k] = c.start + threadIdx.x + k * RT;
+    wl[k] = idx[k] < c.end ? w[idx[k]] : 0.0;
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int i = 0; i < nv; ++i) {
+    const double *v = V + (long long)i * ldv;
+    double s = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (idx[k] < c.end) s += v[idx[k]] * wl[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) red[wave][i] = s;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nv; i += RT)
+    part[(long long)blockIdx.x * ldp + i] = (red[0][i] + red[1][i]) + (red[2][i] + red[3][i]);
+}
+
+// w -= sum_i h[seg][i] V_i ; optionally partial ||w||^2
+template <bool NORM>
+__global__ __launch_bounds__(RT) void k_update(const double *__restrict__ V, long long ldv, int nv,
+                                               double *w, const Chunk *__restrict__ ch,
+                                               const SegState *__restrict__ st,
+                                               const double *__restrict__ h, int ldh, double *part,
+                                               int ldp) {
+  __shared__ double hs[MAXV];
+  __shared__ double red[4];
+  const Chunk c = ch[blockIdx.x];
+  if (!st[c.seg].active) return;
+  for (int i = threadIdx.x; i < nv; i += RT) hs[i] = h[(long long)c.seg * ldh + i];
+  __syncthreads();
+  double nrm = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int e = c.start + threadIdx.x + k * RT;
+    if (e < c.end) {
+      double x = w[e];
+      for (int i = 0; i < nv; ++i) x -= hs[i] * V[(long long)i * ldv + e];
+      w[e] = x;
+      if (NORM) nrm += x * x;
+    }
+  }
+  if (NORM) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) nrm += __shfl_xor(nrm, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nrm;
+    __syncthreads();
+    if (threadIdx.x == 0) part[(long long)blockIdx.x * ldp] = (red[0] + red[1]) + (red[2] + red[3]);
+  }
+}
+
+// partial sum of squares of x over each chunk (all non-done segments)
+__global__ __launch_bounds__(RT) void k_nrm2_part(const double *__restrict__ x,
+                                                  const Chunk *__restrict__ ch, double *part,
+                                                  int ldp) {
+  __shared__ double red[4];
+  const Chunk c = ch[blockIdx.x];
+  double s = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int e = c.start + threadIdx.x + k * RT;
+    if (e < c.end) s += x[e] * x[e];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[(long long)blockIdx.x * ldp] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// out[seg * ldo + i] = sum over the segment's chunks of part[chunk * ldp + i], i < ncomp.
+// only_active: skip inactive segments.
+__global__ __launch_bounds__(RT) void k_seg_reduce(const double *__restrict__ part, int ldp, int ncomp,
+                                                   const int *__restrict__ segptr,
+                                                   const SegState *__restrict__ st, int only_active,
+                                                   double *out, int ldo) {
+  __shared__ double red[4];
+  const int g = blockIdx.x;
+  if (only_active && !st[g].active) return;
+  const int c0 = segptr[g], c1 = segptr[g + 1];
+  for (int i = 0; i < ncomp; ++i) {
+    double s = 0;
+    for (int c = c0 + threadIdx.x; c < c1; c += RT) s += part[(long long)c * ldp + i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) out[(long long)g * ldo + i] = (red[0] + red[1]) + (red[2] + red[3]);
+    __syncthreads();
+  }
+}
+
+// Per segment: Hessenberg column j from the two Gram-Schmidt passes and ||w||, Givens
+// rotations, residual estimate |g_{j+1}|, end-of-cycle decision, scale for v_{j+1}.
+__global__ void k_givens(int nseg, int m, int j, SegState *st, const double *__restrict__ h1,
+                         const double *__restrict__ h2, const double *__restrict__ nrm2, int ldh,
+                         double *R, double *cs, double *sn, double *gv, double *scale,
+                         int max_iter) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nseg) return;
+  SegState S = st[g];
+  if (!S.active) return;
+  double col[MAXV];
+  for (int i = 0; i <= j; ++i) col[i] = h1[(long long)g * ldh + i] + h2[(long long)g * ldh + i];
+  const double hn = sqrt(nrm2[(long long)g * ldh]);
+  col[j + 1] = hn;
+  double *c = cs + (long long)g * m, *s = sn + (long long)g * m, *gg = gv + (long long)g * (m + 1);
+  for (int i = 0; i < j; ++i) {
+    const double t = c[i] * col[i] + s[i] * col[i + 1];
+    col[i + 1] = -s[i] * col[i] + c[i] * col[i + 1];
+    col[i] = t;
+  }
+  const double den = hypot(col[j], col[j + 1]);
+  const double cj = den > 0 ? col[j] / den : 1.0, sj = den > 0 ? col[j + 1] / den : 0.0;
+  c[j] = cj;
+  s[j] = sj;
+  col[j] = den;
+  gg[j + 1] = -sj * gg[j];
+  gg[j] = cj * gg[j];
+  for (int i = 0; i <= j; ++i) R[((long long)g * m + i) * m + j] = col[i];
+  S.est = fabs(gg[j + 1]);
+  S.j = j + 1;
+  S.total += 1;
+  scale[g] = hn > 0 ? 1.0 / hn : 0.0;
+  if (!(S.est > S.tol) || !(hn > 0) || S.total >= max_iter || S.j >= m || !isfinite(S.est))
+    S.active = 0;
+  st[g] = S;
+}
+
+// V_{j+1} = w * scale[seg] (active segments); with j < 0: V_0 = r / beta for starting ones.
+__global__ __launch_bounds__(RT) void k_scale(const double *__restrict__ w, double *v,
+                                              const Chunk *__restrict__ ch,
+                                              const SegState *__restrict__ st,
+                                              const double *__restrict__ scale) {
+  const Chunk c = ch[blockIdx.x];
+  if (!st[c.seg].active) return;
+  const double f = scale[c.seg];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int e = c.start + threadIdx.x + k * RT;
+    if (e < c.end) v[e] = w[e] * f;
+  }
+}
+
+// Cycle start: beta = ||r||, decide convergence on the true residual, set g = beta e_1.
+__global__ void k_seg_start(int nseg, int m, SegState *st, const double *__restrict__ rn2, int ldh,
+                            double *gv, double *scale, int max_iter, int first) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nseg) return;
+  SegState S = st[g];
+  const double r = sqrt(rn2[(long long)g * ldh]);
+  if (first) {
+    S.bnorm = r;
+    S.tol = S.rtol * r;
+    S.total = 0;
+    S.done = 0;
+    S.converged = 0;
+  }
+  S.relres = S.bnorm > 0 ? r / S.bnorm : 0.0;
+  S.j = 0;
+  S.active = 0;
+  if (!S.done) {
+    if (!(r > S.tol)) {
+      S.done = 1;
+      S.converged = isfinite(r) ? 1 : 0;
+    } else if (S.total >= max_iter || !isfinite(r)) {
+      S.done = 1;
+    } else {
+      S.active = 1;
+      S.beta = r;
+      double *gg = gv + (long long)g * (m + 1);
+      gg[0] = r;
+      for (int i = 1; i <= m; ++i) gg[i] = 0.0;
+      scale[g] = 1.0 / r;
+    }
+  }
+  st[g] = S;
+}
+
+// Least squares of the cycle: R y = g (upper triangular, size j of the segment).
+__global__ void k_lsq(int nseg, int m, const SegState *__restrict__ st, const double *__restrict__ R,
+                      const double *__restrict__ gv, double *y, int *ran) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nseg) return;
+  const int k = ran[g];
+  double *yy = y + (long long)g * m;
+  for (int i = 0; i < m; ++i) yy[i] = 0.0;
+  const double *gg = gv + (long long)g * (m + 1);
+  for (int i = k - 1; i >= 0; --i) {
+    double s = gg[i];
+    for (int l = i + 1; l < k; ++l) s -= R[((long long)g * m + i) * m + l] * yy[l];
+    yy[i] = s / R[((long long)g * m + i) * m + i];
+  }
+}
+
+// out[e] (+)= sum_{i<m} y[seg][i] B_i[e]
+__global__ __launch_bounds__(RT) void k_combine(const double *__restrict__ B, long long ldb, int m,
+                                                const Chunk *__restrict__ ch,
+                                                const double *__restrict__ y, const int *__restrict__ ran,
+                                                double *out, int accumulate) {
+  const Chunk c = ch[blockIdx.x];
+  const int k = ran[c.seg];
+  const double *yy = y + (long long)c.seg * m;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int e = c.start + threadIdx.x + q * RT;
+    if (e < c.end) {
+      double s = accumulate ? out[e] : 0.0;
+      for (int i = 0; i < k; ++i) s += yy[i] * B[(long long)i * ldb + e];
+      out[e] = s;
+    }
+  }
+}
+
+__global__ void k_axpy(long long n, const double *__restrict__ x, double *y) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] += x[i];
+}
+
+__global__ void k_record_ran(int nseg, const SegState *__restrict__ st, int *ran) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < nseg) ran[g] = st[g].j;
+}
+
+// ---------------------------------------------------------------------------------------
+static void build_chunks(edfa_system_s &S, SolveWork &W, hipStream_t s) {
+  if (W.nchunk > 0 && W.n == S.n) return;
+  std::vector<Chunk> ch;
+  std::vector<int> ptr(S.ngrid + 1, 0);
+  for (int g = 0; g < S.ngrid; ++g) {
+    const GridRange &R = S.ranges_h[g];
+    ptr[g] = (int)ch.size();
+    for (int a = R.uf0; a < R.uf1; a += CHUNK) ch.push_back(Chunk{a, std::min(a + CHUNK, R.uf1), g});
+    for (int a = S.nfu + R.c0; a < S.nfu + R.c1; a += CHUNK)
+      ch.push_back(Chunk{a, std::min(a + CHUNK, S.nfu + R.c1), g});
+  }
+  ptr[S.ngrid] = (int)ch.size();
+  W.nchunk = (int)ch.size();
+  W.n = S.n;
+  W.chunks.ensure(ch.size());
+  W.segptr.ensure(ptr.size());
+  EDFA_HIP(hipMemcpyAsync(W.chunks.p, ch.data(), sizeof(Chunk) * ch.size(), hipMemcpyHostToDevice, s));
+  EDFA_HIP(hipMemcpyAsync(W.segptr.p, ptr.data(), sizeof(int) * ptr.size(), hipMemcpyHostToDevice, s));
+  EDFA_HIP(hipStreamSynchronize(s));
+}
+
+struct Prof {
+  std::vector<hipEvent_t> ev;
+  size_t used = 0;
+  hipEvent_t get() {
+    if (used == ev.size()) {
+      hipEvent_t e;
+      EDFA_HIP(hipEventCreate(&e));
+      ev.push_back(e);
+    }
+    return ev[used++];
+  }
+  ~Prof() {
+    for (auto e : ev) (void)hipEventDestroy(e);
+  }
+};
+
+edfa_status gmres(edfa_system_s &S, edfa_precond_s &P, const double *b, double *x,
+                  const edfa_solve_params &prm, hipStream_t s, edfa_solve_info *info) {
+  const int m = prm.restart;
+  if (m < 1 || m > MAXV - 2) fail(EDFA_ERR_ARG, "restart must be in 1..%d", MAXV - 2);
+  if (!(prm.rtol > 0.0)) fail(EDFA_ERR_ARG, "rtol must be > 0");
+  if (P.prm.precision == 1 && !prm.flexible)
+    fail(EDFA_ERR_ARG, "the FP32 preconditioner requires flexible GMRES");
+  if (!P.ws) P.ws.reset(new SolveWork());
+  SolveWork &W = *P.ws;
+  const int n = S.n, nseg = S.ngrid;
+  const int tr = prm.transpose ? 1 : 0;
+  build_chunks(S, W, s);
+  const int nch = W.nchunk;
+  const int ld = m + 2;   // leading dimension of per-chunk / per-segment coefficient rows
+  W.V.ensure((size_t)(m + 1) * n);
+  if (prm.flexible) W.Z.ensure((size_t)m * n);
+  W.w.ensure(n);
+  W.r.ensure(n);
+  W.z.ensure(n);
+  W.part.ensure((size_t)nch * ld);
+  W.h1.ensure((size_t)nseg * ld);
+  W.h2.ensure((size_t)nseg * ld);
+  W.nrm.ensure((size_t)nseg * ld);
+  W.R.ensure((size_t)nseg * m * m);
+  W.cs.ensure((size_t)nseg * m);
+  W.sn.ensure((size_t)nseg * m);
+  W.g.ensure((size_t)nseg * (m + 1));
+  W.y.ensure((size_t)nseg * m);
+  W.scale.ensure(nseg);
+  W.ran.ensure(nseg);
+  W.st.ensure(nseg);
+  std::vector<SegState> hst(nseg);
+  for (auto &q : hst) {
+    q = SegState{};
+    q.rtol = prm.rtol;
+  }
+  EDFA_HIP(hipMemcpyAsync(W.st.p, hst.data(), sizeof(SegState) * nseg, hipMemcpyHostToDevice, s));
+  const Csr<double> &A = tr ? S.AT : S.A;
+  if (tr && S.AT.rows == 0) csr_transpose(S.A, S.AT, S.tmp, s);
+
+  Prof prof;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_spmv, ev_apply;
+  EventTimer total;
+  total.start(s);
+
+  auto spmvA = [&](const double *in, double *out, const double *bb) {
+    hipEvent_t e0{}, e1{};
+    if (prm.profile) {
+      e0 = prof.get();
+      EDFA_HIP(hipEventRecord(e0, s));
+    }
+    spmv<double, double>(A.rowptr.p, A.col.p, A.val.p, n, in, out, bb ? -1.0 : 1.0, bb, 1.0,
+                         S.avg_A, s);
+    if (prm.profile) {
+      e1 = prof.get();
+      EDFA_HIP(hipEventRecord(e1, s));
+      ev_spmv.emplace_back(e0, e1);
+    }
+  };
+  auto applyP = [&](const double *in, double *out) {
+    hipEvent_t e0{}, e1{};
+    if (prm.profile) {
+      e0 = prof.get();
+      EDFA_HIP(hipEventRecord(e0, s));
+    }
+    precond_apply(P, tr, in, out, s);
+    if (prm.profile) {
+      e1 = prof.get();
+      EDFA_HIP(hipEventRecord(e1, s));
+      ev_apply.emplace_back(e0, e1);
+    }
+  };
+  auto seg_norms = [&](const double *v, double *out) {
+    hipLaunchKernelGGL(k_nrm2_part, dim3(nch), dim3(RT), 0, s, v, W.chunks.p, W.part.p, ld);
+    hipLaunchKernelGGL(k_seg_reduce, dim3(nseg), dim3(RT), 0, s, W.part.p, ld, 1, W.segptr.p,
+                       W.st.p, 0, out, ld);
+    EDFA_CHECK_LAUNCH();
+  };
+  const int sb = ceil_div(nseg, 64);
+
+  EDFA_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, s));
+  EDFA_HIP(hipMemcpyAsync(W.r.p, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  seg_norms(W.r.p, W.nrm.p);
+  hipLaunchKernelGGL(k_seg_start, dim3(sb), dim3(64), 0, s, nseg, m, W.st.p, W.nrm.p, ld, W.g.p,
+                     W.scale.p, prm.max_iter, 1);
+  EDFA_CHECK_LAUNCH();
+  int cycles = 0;
+  const int check_every = nseg == 1 ? 8 : 16;
+  while (true) {
+    EDFA_HIP(hipMemcpyAsync(hst.data(), W.st.p, sizeof(SegState) * nseg, hipMemcpyDeviceToHost, s));
+    EDFA_HIP(hipStreamSynchronize(s));
+    int nact = 0;
+    for (auto &q : hst) nact += q.active;
+    if (!nact) break;
+    ++cycles;
+    hipLaunchKernelGGL(k_scale, dim3(nch), dim3(RT), 0, s, W.r.p, W.V.p, W.chunks.p, W.st.p, W.scale.p);
+    EDFA_CHECK_LAUNCH();
+    for (int j = 0; j < m; ++j) {
+      double *vj = W.V.p + (size_t)j * n;
+      double *zj = prm.flexible ? W.Z.p + (size_t)j * n : W.z.p;
+      applyP(vj, zj);
+      spmvA(zj, W.w.p, nullptr);
+      // CGS2
+      hipLaunchKernelGGL(k_dots, dim3(nch), dim3(RT), 0, s, W.V.p, (long long)n, j + 1, W.w.p,
+                         W.chunks.p, W.st.p, W.part.p, ld);
+      hipLaunchKernelGGL(k_seg_reduce, dim3(nseg), dim3(RT), 0, s, W.part.p, ld, j + 1, W.segptr.p,
+                         W.st.p, 1, W.h1.p, ld);
+      hipLaunchKernelGGL(k_update<false>, dim3(nch), dim3(RT), 0, s, W.V.p, (long long)n, j + 1,
+                         W.w.p, W.chunks.p, W.st.p, W.h1.p, ld, W.part.p, ld);
+      hipLaunchKernelGGL(k_dots, dim3(nch), dim3(RT), 0, s, W.V.p, (long long)n, j + 1, W.w.p,
+                         W.chunks.p, W.st.p, W.part.p, ld);
+      hipLaunchKernelGGL(k_seg_reduce, dim3(nseg), dim3(RT), 0, s, W.part.p, ld, j + 1, W.segptr.p,
+                         W.st.p, 1, W.h2.p, ld);
+      hipLaunchKernelGGL(k_update<true>, dim3(nch), dim3(RT), 0, s, W.V.p, (long long)n, j + 1,
+                         W.w.p, W.chunks.p, W.st.p, W.h2.p, ld, W.part.p, ld);
+      hipLaunchKernelGGL(k_seg_reduce, dim3(nseg), dim3(RT), 0, s, W.part.p, ld, 1, W.segptr.p,
+                         W.st.p, 1, W.nrm.p, ld);
+      hipLaunchKernelGGL(k_givens, dim3(sb), dim3(64), 0, s, nseg, m, j, W.st.p, W.h1.p, W.h2.p,
+                         W.nrm.p, ld, W.R.p, W.cs.p, W.sn.p, W.g.p, W.scale.p, prm.max_iter);
+      hipLaunchKernelGGL(k_scale, dim3(nch), dim3(RT), 0, s, W.w.p, W.V.p + (size_t)(j + 1) * n,
+                         W.chunks.p, W.st.p, W.scale.p);
+      EDFA_CHECK_LAUNCH();
+      if ((j + 1) % check_every == 0 && j + 1 < m) {
+        EDFA_HIP(hipMemcpyAsync(hst.data(), W.st.p, sizeof(SegState) * nseg, hipMemcpyDeviceToHost, s));
+        EDFA_HIP(hipStreamSynchronize(s));
+        int a = 0;
+        for (auto &q : hst) a += q.active;
+        if (!a) break;
+      }
+    }
+    // end of cycle: y = R^-1 g, x += Z y (flexible) or x += P^-1 (V y)
+    hipLaunchKernelGGL(k_record_ran, dim3(sb), dim3(64), 0, s, nseg, W.st.p, W.ran.p);
+    hipLaunchKernelGGL(k_lsq, dim3(sb), dim3(64), 0, s, nseg, m, W.st.p, W.R.p, W.g.p, W.y.p, W.ran.p);
+    if (prm.flexible) {
+      hipLaunchKernelGGL(k_combine, dim3(nch), dim3(RT), 0, s, W.Z.p, (long long)n, m, W.chunks.p,
+                         W.y.p, W.ran.p, x, 1);
+    } else {
+      hipLaunchKernelGGL(k_combine, dim3(nch), dim3(RT), 0, s, W.V.p, (long long)n, m, W.chunks.p,
+                         W.y.p, W.ran.p, W.w.p, 0);
+      applyP(W.w.p, W.z.p);
+      hipLaunchKernelGGL(k_axpy, dim3(ceil_div(n, 256)), dim3(256), 0, s, (long long)n, W.z.p, x);
+    }
+    EDFA_CHECK_LAUNCH();
+    // true residual r = b - A x and the next cycle's start
+    spmvA(x, W.r.p, b);
+    seg_norms(W.r.p, W.nrm.p);
+    hipLaunchKernelGGL(k_seg_start, dim3(sb), dim3(64), 0, s, nseg, m, W.st.p, W.nrm.p, ld, W.g.p,
+                       W.scale.p, prm.max_iter, 0);
+    EDFA_CHECK_LAUNCH();
+  }
+  total.stop(s);
+  const float tms = total.ms();
+  int conv = 0, iters = 0;
+  double est = 0, rt = 0;
+  for (auto &q : hst) {
+    conv += q.converged;
+    iters = std::max(iters, q.total);
+    est = std::max(est, q.bnorm > 0 ? q.est / q.bnorm : 0.0);
+    rt = std::max(rt, q.relres);
+  }
+  if (info) {
+    info->iterations = iters;
+    info->converged = conv;
+    info->cycles = cycles;
+    info->relres_est = est;
+    info->relres_true = rt;
+    info->t_solve_ms = tms;
+    auto avg = [&](auto &v) {
+      double t = 0;
+      for (auto &pr : v) {
+        float ms = 0;
+        EDFA_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
+        t += ms;
+      }
+      return v.empty() ? 0.0 : t / v.size();
+    };
+    info->spmv_avg_ms = prm.profile ? avg(ev_spmv) : 0.0;
+    info->spmv_count = (int)ev_spmv.size();
+    info->apply_avg_ms = prm.profile ? avg(ev_apply) : 0.0;
+    info->apply_count = (int)ev_apply.size();
+  }
+  return conv == nseg ? EDFA_OK : EDFA_NOT_CONVERGED;
+}
+
+}  // namespace edfa

@@ -168,7 +168,7 @@ __global__ __launch_bounds__(256) void k_spmv(const int *__restrict__ rowptr,
                                               const V *__restrict__ val, int rows,
                                               const X *__restrict__ x, X *__restrict__ y,
                                               double alpha, const X *__restrict__ b,
-                                              double beta) {
+                                              double beta, double gamma) {
   using A = typename AccT<V, X>::type;
   const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int row = (int)(gid / LANES);
@@ -182,18 +182,19 @@ __global__ __launch_bounds__(256) void k_spmv(const int *__restrict__ rowptr,
   if (lane == 0) {
     A r = (A)alpha * sum;
     if (b) r += (A)beta * (A)b[row];
+    if (gamma != 0.0) r += (A)gamma * (A)x[row];
     y[row] = (X)r;
   }
 }
 
 template <class V, class X>
 void spmv(const int *rowptr, const int *col, const V *val, int rows, const X *x, X *y,
-          double alpha, const X *b, double beta, float avg_nnz, hipStream_t s) {
+          double alpha, const X *b, double beta, float avg_nnz, hipStream_t s, double gamma) {
   if (rows <= 0) return;
   auto launch = [&](auto kern, int lanes) {
     long long threads = (long long)rows * lanes;
     hipLaunchKernelGGL(kern, dim3(ceil_div(threads, 256)), dim3(256), 0, s, rowptr, col, val,
-                       rows, x, y, alpha, b, beta);
+                       rows, x, y, alpha, b, beta, gamma);
     EDFA_CHECK_LAUNCH();
   };
   if (avg_nnz <= 3.f)
@@ -209,10 +210,9 @@ void spmv(const int *rowptr, const int *col, const V *val, int rows, const X *x,
 }
 
 template void spmv<double, double>(const int *, const int *, const double *, int, const double *,
-                                   double *, double, const double *, double, float, hipStream_t);
+                                   double *, double, const double *, double, float, hipStream_t,
+                                   double);
 template void spmv<float, float>(const int *, const int *, const float *, int, const float *,
-                                 float *, double, const float *, double, float, hipStream_t);
-template void spmv<float, double>(const int *, const int *, const float *, int, const double *,
-                                  double *, double, const double *, double, float, hipStream_t);
+                                 float *, double, const float *, double, float, hipStream_t, double);
 
 }  // namespace edfa

@@ -1,0 +1,525 @@
+// EDFA stage 2 (the paper's Algorithm 2) on the device, plus the inner preconditioner of S~.
+//
+//  * S~ = A_pp - H~ on the union pattern; optional post-filtration on S~ (diagonal kept)
+//  * colouring of the graph of S~ + S~^T: Jones-Plassmann rounds whose result equals greedy
+//    first fit over vertices by decreasing fmix32 priority (a vertex is coloured only after
+//    all its higher-priority neighbours), so the colouring is deterministic
+//  * stable permutation colour by colour, permuted matrix B = P S~ P^T
+//  * ILU(0) of B, one launch per colour (rows of one colour are independent)
+//  * sparse approximate inverses of the two triangular factors (row i of M solves
+//    T[P_i,P_i]^T m = e_i on the pattern P_i of row i), used to apply the triangular solves
+#include <algorithm>
+
+#include "precond.hpp"
+
+namespace edfa {
+
+__device__ inline unsigned fmix32(unsigned h) {
+  h ^= h >> 16;
+  h *= 0x85ebca6bu;
+  h ^= h >> 13;
+  h *= 0xc2b2ae35u;
+  h ^= h >> 16;
+  return h;
+}
+
+// ---------------------------------------------------------------------------------------
+// S~ = A_pp - H~
+// ---------------------------------------------------------------------------------------
+template <class T, bool WRITE>
+__device__ int merge_row(const int *arp, const int *acol, const double *aval, const int *hrp,
+                         const int *hcol, const T *hval, int i, int filt, double tau,
+                         int *ocol, T *oval) {
+  const int a0 = arp[i], a1 = arp[i + 1], h0 = hrp[i], h1 = hrp[i + 1];
+  double thr = -1.0;
+  if (filt) {
+    double nrm = 0;
+    int p = a0, q = h0;
+    while (p < a1 || q < h1) {
+      double v;
+      if (q >= h1 || (p < a1 && acol[p] < hcol[q])) {
+        v = aval[p++];
+      } else if (p >= a1 || hcol[q] < acol[p]) {
+        v = -(double)hval[q++];
+      } else {
+        v = (double)((T)aval[p] - hval[q]);
+        ++p;
+        ++q;
+      }
+      nrm += v * v;
+    }
+    thr = tau * sqrt(nrm);
+  }
+  int n = 0;
+  int p = a0, q = h0;
+  while (p < a1 || q < h1) {
+    int c;
+    T v;
+    if (q >= h1 || (p < a1 && acol[p] < hcol[q])) {
+      c = acol[p];
+      v = (T)aval[p++];
+    } else if (p >= a1 || hcol[q] < acol[p]) {
+      c = hcol[q];
+      v = -hval[q++];
+    } else {
+      c = acol[p];
+      v = (T)aval[p++] - hval[q++];
+    }
+    if (filt && !(fabs((double)v) >= thr || c == i)) continue;
+    if (WRITE) {
+      ocol[n] = c;
+      oval[n] = v;
+    }
+    ++n;
+  }
+  return n;
+}
+
+template <class T>
+__global__ void k_merge_count(const int *arp, const int *acol, const double *aval, const int *hrp,
+                              const int *hcol, const T *hval, int ne, int filt, double tau, int *len) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ne) return;
+  len[i] = merge_row<T, false>(arp, acol, aval, hrp, hcol, hval, i, filt, tau, nullptr, nullptr);
+}
+
+template <class T>
+__global__ void k_merge_write(const int *arp, const int *acol, const double *aval, const int *hrp,
+                              const int *hcol, const T *hval, int ne, int filt, double tau,
+                              const int *orp, int *ocol, T *oval) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ne) return;
+  merge_row<T, true>(arp, acol, aval, hrp, hcol, hval, i, filt, tau, ocol + orp[i], oval + orp[i]);
+}
+
+// ---------------------------------------------------------------------------------------
+// Colouring
+// ---------------------------------------------------------------------------------------
+// Priorities use the cell index local to its grid, so a batch of grids is coloured exactly
+// as each grid alone (neighbours never cross grids).
+__global__ void k_jp_round(const int *__restrict__ srp, const int *__restrict__ scol,
+                           const int *__restrict__ trp, const int *__restrict__ tcol, int ne,
+                           const GridDesc *__restrict__ grids, int ngrid, int *color,
+                           int *ncolored, int *err) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= ne) return;
+  if (__atomic_load_n(&color[v], __ATOMIC_RELAXED) >= 0) return;
+  const int c0 = grids[grid_of(grids, ngrid, v, true)].cell0;
+  const unsigned pv = fmix32((unsigned)(v - c0));
+  for (int pass = 0; pass < 2; ++pass) {
+    const int *rp = pass ? trp : srp;
+    const int *cl = pass ? tcol : scol;
+    for (int p = rp[v]; p < rp[v + 1]; ++p) {
+      const int u = cl[p];
+      if (u == v) continue;
+      if (fmix32((unsigned)(u - c0)) > pv && __atomic_load_n(&color[u], __ATOMIC_RELAXED) < 0)
+        return;
+    }
+  }
+  unsigned long long used[MAX_COLORS / 64];
+  for (int w = 0; w < MAX_COLORS / 64; ++w) used[w] = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    const int *rp = pass ? trp : srp;
+    const int *cl = pass ? tcol : scol;
+    for (int p = rp[v]; p < rp[v + 1]; ++p) {
+      const int u = cl[p];
+      if (u == v) continue;
+      const int cu = __atomic_load_n(&color[u], __ATOMIC_RELAXED);
+      if (cu >= 0) used[cu >> 6] |= 1ull << (cu & 63);
+    }
+  }
+  int c = -1;
+  for (int w = 0; w < MAX_COLORS / 64 && c < 0; ++w)
+    if (~used[w]) c = w * 64 + __ffsll((long long)~used[w]) - 1;
+  if (c < 0) {
+    atomicMin(err, v);
+    c = MAX_COLORS - 1;
+  }
+  __atomic_store_n(&color[v], c, __ATOMIC_RELAXED);
+  atomicAdd(ncolored, 1);
+}
+
+__global__ void k_color_max(const int *__restrict__ color, int n, int *out) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) atomicMax(out, color[v]);
+}
+
+// per-block colour histograms, laid out colour-major: hist[c * nb + b]
+__global__ __launch_bounds__(256) void k_color_hist(const int *__restrict__ color, int n, int ncol,
+                                                    int nb, int *hist) {
+  __shared__ int h[MAX_COLORS];
+  for (int c = threadIdx.x; c < ncol; c += 256) h[c] = 0;
+  __syncthreads();
+  const int v = blockIdx.x * 256 + threadIdx.x;
+  if (v < n) atomicAdd(&h[color[v]], 1);
+  __syncthreads();
+  for (int c = threadIdx.x; c < ncol; c += 256) hist[(size_t)c * nb + blockIdx.x] = h[c];
+}
+
+__global__ __launch_bounds__(256) void k_color_scatter(const int *__restrict__ color, int n, int nb,
+                                                       const int *__restrict__ offs, int *perm,
+                                                       int *iperm) {
+  __shared__ int cl[256];
+  const int v = blockIdx.x * 256 + threadIdx.x;
+  cl[threadIdx.x] = v < n ? color[v] : -1;
+  __syncthreads();
+  if (v >= n) return;
+  const int c = cl[threadIdx.x];
+  int rank = 0;
+  for (int t = 0; t < (int)threadIdx.x; ++t) rank += cl[t] == c;
+  const int pos = offs[(size_t)c * nb + blockIdx.x] + rank;
+  perm[pos] = v;
+  iperm[v] = pos;
+}
+
+__global__ void k_gather_len(const int *__restrict__ rp, const int *__restrict__ perm, int n, int *len) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) len[i] = rp[perm[i] + 1] - rp[perm[i]];
+}
+
+// B row i = S~ row perm[i] with columns mapped by iperm, sorted; one wavefront per row
+template <class T>
+__global__ __launch_bounds__(64) void k_permute_rows(const int *__restrict__ srp,
+                                                     const int *__restrict__ scol,
+                                                     const T *__restrict__ sval,
+                                                     const int *__restrict__ perm,
+                                                     const int *__restrict__ iperm, int n,
+                                                     const int *__restrict__ brp, int *bcol,
+                                                     T *bval, int *diag) {
+  __shared__ int c[HMAX + 64];
+  const int i = blockIdx.x;
+  if (i >= n) return;
+  const int r = perm[i];
+  const int a = srp[r], len = srp[r + 1] - a;
+  for (int t = threadIdx.x; t < len; t += 64) c[t] = iperm[scol[a + t]];
+  __syncthreads();
+  const int o = brp[i];
+  for (int t = threadIdx.x; t < len; t += 64) {
+    const int ct = c[t];
+    int rank = 0;
+    for (int u = 0; u < len; ++u) rank += c[u] < ct;
+    bcol[o + rank] = ct;
+    bval[o + rank] = sval[a + t];
+    if (ct == i) diag[i] = o + rank;
+  }
+}
+
+// ILU(0), IKJ form, rows [r0, r1) of one colour
+template <class T>
+__global__ void k_ilu_color(const int *__restrict__ rp, const int *__restrict__ col, T *val,
+                            const int *__restrict__ diag, int r0, int r1, int *err) {
+  const int i = r0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= r1) return;
+  const int b = rp[i + 1], d = diag[i];
+  for (int p = rp[i]; p < d; ++p) {
+    const int k = col[p];
+    const int dk = diag[k];
+    const T lik = val[p] / val[dk];
+    val[p] = lik;
+    int q = dk + 1, r = p + 1;
+    const int qe = rp[k + 1];
+    while (q < qe && r < b) {
+      const int ck = col[q], ci = col[r];
+      if (ck == ci) {
+        val[r] -= lik * val[q];
+        ++q;
+        ++r;
+      } else if (ck < ci) {
+        ++q;
+      } else {
+        ++r;
+      }
+    }
+  }
+  const T piv = val[d];
+  if (!(piv != T(0)) || !isfinite((double)piv)) atomicMin(err, i);
+}
+
+__global__ void k_check_diag(const int *__restrict__ diag, int n, int *err) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && diag[i] < 0) atomicMin(err, i);
+}
+
+__global__ void k_split_len(const int *__restrict__ rp, const int *__restrict__ diag, int n,
+                            int *llen, int *ulen) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  llen[i] = diag[i] - rp[i];
+  ulen[i] = rp[i + 1] - diag[i];
+}
+
+template <class T>
+__global__ void k_split(const int *__restrict__ rp, const int *__restrict__ col,
+                        const T *__restrict__ val, const int *__restrict__ diag, int n,
+                        const int *__restrict__ lrp, int *lcol, T *lval, const int *__restrict__ urp,
+                        int *ucol, T *uval) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int o = lrp[i];
+  for (int p = rp[i]; p < diag[i]; ++p, ++o) {
+    lcol[o] = col[p];
+    lval[o] = val[p];
+  }
+  o = urp[i];
+  for (int p = diag[i]; p < rp[i + 1]; ++p, ++o) {
+    ucol[o] = col[p];
+    uval[o] = val[p];
+  }
+}
+
+__device__ inline int bsearch_lds(const int *a, int n, int key) {
+  int lo = 0, hi = n - 1;
+  while (lo <= hi) {
+    const int mid = (lo + hi) >> 1;
+    const int v = a[mid];
+    if (v == key) return mid;
+    if (v < key)
+      lo = mid + 1;
+    else
+      hi = mid - 1;
+  }
+  return -1;
+}
+
+// ISAI of the unit lower factor (I + L): row i on P = cols(L row i) + {i}.
+// (T[P,P])^T m = e_i, solved from the last index down: m_k = delta_ik - sum_{j>k} T[j,k] m_j.
+template <class T>
+__global__ __launch_bounds__(64) void k_isai_lower(const int *__restrict__ lrp,
+                                                   const int *__restrict__ lcol,
+                                                   const T *__restrict__ lval, int n,
+                                                   const int *__restrict__ mrp, int *mcol, T *mval) {
+  __shared__ int P[HMAX + 64];
+  __shared__ T acc[HMAX + 64];
+  const int i = blockIdx.x;
+  if (i >= n) return;
+  const int a = lrp[i], nl = lrp[i + 1] - a, np = nl + 1;
+  for (int t = threadIdx.x; t < np; t += 64) {
+    P[t] = t < nl ? lcol[a + t] : i;
+    acc[t] = 0;
+  }
+  __syncthreads();
+  const int o = mrp[i];
+  for (int idx = np - 1; idx >= 0; --idx) {
+    const int k = P[idx];
+    const T mk = (k == i ? T(1) : T(0)) - acc[idx];
+    if (threadIdx.x == 0) {
+      mcol[o + idx] = k;
+      mval[o + idx] = mk;
+    }
+    for (int p = lrp[k] + threadIdx.x; p < lrp[k + 1]; p += 64) {
+      const int pos = bsearch_lds(P, idx, lcol[p]);
+      if (pos >= 0) acc[pos] += lval[p] * mk;
+    }
+    __syncthreads();
+  }
+}
+
+// ISAI of U (diagonal first in each row): row i on P = cols(U row i).
+// (U[P,P])^T m = e_i, solved upward: m_k = (delta_ik - sum_{j<k} U[j,k] m_j) / U[k,k].
+template <class T>
+__global__ __launch_bounds__(64) void k_isai_upper(const int *__restrict__ urp,
+                                                   const int *__restrict__ ucol,
+                                                   const T *__restrict__ uval, int n, int *mcol,
+                                                   T *mval) {
+  __shared__ int P[HMAX + 64];
+  __shared__ T acc[HMAX + 64];
+  const int i = blockIdx.x;
+  if (i >= n) return;
+  const int a = urp[i], np = urp[i + 1] - a;
+  for (int t = threadIdx.x; t < np; t += 64) {
+    P[t] = ucol[a + t];
+    acc[t] = 0;
+  }
+  __syncthreads();
+  for (int idx = 0; idx < np; ++idx) {
+    const int k = P[idx];
+    const int kb = urp[k];
+    const T mk = ((k == i ? T(1) : T(0)) - acc[idx]) / uval[kb];
+    if (threadIdx.x == 0) {
+      mcol[a + idx] = k;
+      mval[a + idx] = mk;
+    }
+    for (int p = kb + 1 + threadIdx.x; p < urp[k + 1]; p += 64) {
+      const int pos = bsearch_lds(P + idx + 1, np - idx - 1, ucol[p]);
+      if (pos >= 0) acc[idx + 1 + pos] += uval[p] * mk;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_ml_rowptr(const int *__restrict__ lrp, int n, int *mrp) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i <= n) mrp[i] = lrp[i] + i;
+}
+
+__global__ void k_row_len_max(const int *__restrict__ rp, int rows, int *out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < rows) atomicMax(out, rp[r + 1] - rp[r]);
+}
+
+// ---------------------------------------------------------------------------------------
+template <class T>
+static void stage2_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
+  edfa_system_s &S = *P.sys;
+  const edfa_params &prm = P.prm;
+  const int ne = S.ne;
+  P.flags.ensure(4);
+  const int init[4] = {0x7fffffff, 0x7fffffff, 0, 0};
+  EDFA_HIP(hipMemcpyAsync(P.flags.p, init, sizeof(init), hipMemcpyHostToDevice, s));
+
+  // S~ = A_pp - H~, post-filtration on S~
+  const int postS = prm.filt_mode == EDFA_FILT_POST_S;
+  D.S.rowptr.ensure((size_t)ne + 1);
+  hipLaunchKernelGGL(k_merge_count<T>, dim3(ceil_div(ne, 256)), dim3(256), 0, s, S.Acc.rowptr.p,
+                     S.Acc.col.p, S.Acc.val.p, D.H.rowptr.p, D.H.col.p, D.H.val.p, ne, postS,
+                     prm.tau_filt, D.S.rowptr.p);
+  EDFA_CHECK_LAUNCH();
+  const int64_t snnz = exclusive_scan(D.S.rowptr.p, D.S.rowptr.p, ne, S.tmp, s);
+  D.S.rows = D.S.cols = ne;
+  D.S.nnz = snnz;
+  D.S.col.ensure(snnz);
+  D.S.val.ensure(snnz);
+  hipLaunchKernelGGL(k_merge_write<T>, dim3(ceil_div(ne, 256)), dim3(256), 0, s, S.Acc.rowptr.p,
+                     S.Acc.col.p, S.Acc.val.p, D.H.rowptr.p, D.H.col.p, D.H.val.p, ne, postS,
+                     prm.tau_filt, D.S.rowptr.p, D.S.col.p, D.S.val.p);
+  EDFA_CHECK_LAUNCH();
+  EDFA_HIP(hipMemsetAsync(P.flags.p + 2, 0, sizeof(int), s));
+  hipLaunchKernelGGL(k_row_len_max, dim3(ceil_div(ne, 256)), dim3(256), 0, s, D.S.rowptr.p, ne,
+                     P.flags.p + 2);
+  EDFA_CHECK_LAUNCH();
+  const int smaxrow = read_scalar(P.flags.p + 2, s);
+  if (smaxrow > HMAX + 64) fail(EDFA_ERR_CAPACITY, "a row of S~ has %d > %d entries", smaxrow, HMAX + 64);
+  csr_transpose(D.S, D.ST, S.tmp, s);
+
+  // colouring
+  D.color.ensure(ne);
+  EDFA_HIP(hipMemsetAsync(D.color.p, 0xff, sizeof(int) * ne, s));
+  EDFA_HIP(hipMemsetAsync(P.flags.p + 2, 0, sizeof(int), s));
+  int rounds = 0;
+  while (true) {
+    for (int r = 0; r < 4; ++r)
+      hipLaunchKernelGGL(k_jp_round, dim3(ceil_div(ne, 256)), dim3(256), 0, s, D.S.rowptr.p,
+                         D.S.col.p, D.ST.rowptr.p, D.ST.col.p, ne, S.grids.p, S.ngrid, D.color.p,
+                         P.flags.p + 2, P.flags.p + 1);
+    EDFA_CHECK_LAUNCH();
+    rounds += 4;
+    const int done = read_scalar(P.flags.p + 2, s);
+    if (done >= ne) break;
+    if (rounds > 4 * ne + 64) fail(EDFA_ERR_BREAKDOWN, "colouring did not finish");
+  }
+  if (read_scalar(P.flags.p + 1, s) != 0x7fffffff)
+    fail(EDFA_ERR_CAPACITY, "more than %d colours needed", MAX_COLORS);
+  EDFA_HIP(hipMemsetAsync(P.flags.p + 3, 0, sizeof(int), s));
+  hipLaunchKernelGGL(k_color_max, dim3(ceil_div(ne, 256)), dim3(256), 0, s, D.color.p, ne,
+                     P.flags.p + 3);
+  EDFA_CHECK_LAUNCH();
+  const int ncol = ne ? read_scalar(P.flags.p + 3, s) + 1 : 0;
+  P.n_colors = ncol;
+
+  // stable permutation by colour
+  const int nb = ceil_div(ne, 256);
+  DBuf<int> hist;
+  hist.ensure((size_t)ncol * nb + 1);
+  D.perm.ensure(ne);
+  D.iperm.ensure(ne);
+  if (ne) {
+    hipLaunchKernelGGL(k_color_hist, dim3(nb), dim3(256), 0, s, D.color.p, ne, ncol, nb, hist.p);
+    EDFA_CHECK_LAUNCH();
+    exclusive_scan(hist.p, hist.p, ncol * nb, S.tmp, s);
+    hipLaunchKernelGGL(k_color_scatter, dim3(nb), dim3(256), 0, s, D.color.p, ne, nb, hist.p,
+                       D.perm.p, D.iperm.p);
+    EDFA_CHECK_LAUNCH();
+  }
+  {
+    std::vector<int> h((size_t)ncol * nb + 1);
+    EDFA_HIP(hipMemcpyAsync(h.data(), hist.p, sizeof(int) * h.size(), hipMemcpyDeviceToHost, s));
+    EDFA_HIP(hipStreamSynchronize(s));
+    D.cstart.assign(ncol + 1, ne);
+    for (int c = 0; c < ncol; ++c) D.cstart[c] = h[(size_t)c * nb];
+  }
+
+  // permuted matrix
+  D.B.rowptr.ensure((size_t)ne + 1);
+  hipLaunchKernelGGL(k_gather_len, dim3(ceil_div(ne, 256)), dim3(256), 0, s, D.S.rowptr.p,
+                     D.perm.p, ne, D.B.rowptr.p);
+  EDFA_CHECK_LAUNCH();
+  exclusive_scan(D.B.rowptr.p, D.B.rowptr.p, ne, S.tmp, s);
+  D.B.rows = D.B.cols = ne;
+  D.B.nnz = snnz;
+  D.B.col.ensure(snnz);
+  D.B.val.ensure(snnz);
+  D.diag.ensure(ne);
+  EDFA_HIP(hipMemsetAsync(D.diag.p, 0xff, sizeof(int) * (size_t)ne, s));
+  if (ne) {
+    hipLaunchKernelGGL(k_permute_rows<T>, dim3(ne), dim3(64), 0, s, D.S.rowptr.p, D.S.col.p,
+                       D.S.val.p, D.perm.p, D.iperm.p, ne, D.B.rowptr.p, D.B.col.p, D.B.val.p,
+                       D.diag.p);
+    EDFA_CHECK_LAUNCH();
+  }
+
+  hipLaunchKernelGGL(k_check_diag, dim3(ceil_div(ne, 256)), dim3(256), 0, s, D.diag.p, ne,
+                     P.flags.p + 1);
+  EDFA_CHECK_LAUNCH();
+  if (read_scalar(P.flags.p + 1, s) != 0x7fffffff)
+    fail(EDFA_ERR_BREAKDOWN, "S~ row %d has no diagonal entry", read_scalar(P.flags.p + 1, s));
+  // ILU(0) colour by colour
+  for (int c = 0; c < ncol; ++c) {
+    const int r0 = D.cstart[c], r1 = D.cstart[c + 1];
+    if (r1 > r0)
+      hipLaunchKernelGGL(k_ilu_color<T>, dim3(ceil_div(r1 - r0, 64)), dim3(64), 0, s, D.B.rowptr.p,
+                         D.B.col.p, D.B.val.p, D.diag.p, r0, r1, P.flags.p);
+  }
+  EDFA_CHECK_LAUNCH();
+  if (read_scalar(P.flags.p, s) != 0x7fffffff)
+    fail(EDFA_ERR_BREAKDOWN, "ILU(0) of S~: zero or non-finite pivot at row %d", read_scalar(P.flags.p, s));
+
+  // L (strict lower, unit factor) and U (with diagonal)
+  D.L.rowptr.ensure((size_t)ne + 1);
+  D.U.rowptr.ensure((size_t)ne + 1);
+  hipLaunchKernelGGL(k_split_len, dim3(ceil_div(ne, 256)), dim3(256), 0, s, D.B.rowptr.p, D.diag.p,
+                     ne, D.L.rowptr.p, D.U.rowptr.p);
+  EDFA_CHECK_LAUNCH();
+  const int64_t lnnz = exclusive_scan(D.L.rowptr.p, D.L.rowptr.p, ne, S.tmp, s);
+  const int64_t unnz = exclusive_scan(D.U.rowptr.p, D.U.rowptr.p, ne, S.tmp, s);
+  D.L.rows = D.L.cols = D.U.rows = D.U.cols = ne;
+  D.L.nnz = lnnz;
+  D.U.nnz = unnz;
+  D.L.col.ensure(lnnz);
+  D.L.val.ensure(lnnz);
+  D.U.col.ensure(unnz);
+  D.U.val.ensure(unnz);
+  hipLaunchKernelGGL(k_split<T>, dim3(ceil_div(ne, 256)), dim3(256), 0, s, D.B.rowptr.p, D.B.col.p,
+                     D.B.val.p, D.diag.p, ne, D.L.rowptr.p, D.L.col.p, D.L.val.p, D.U.rowptr.p,
+                     D.U.col.p, D.U.val.p);
+  EDFA_CHECK_LAUNCH();
+
+  if (prm.schur_solver == EDFA_SCHUR_ISAI) {
+    D.ML.alloc(ne, ne, lnnz + ne);
+    D.MU.alloc(ne, ne, unnz);
+    hipLaunchKernelGGL(k_ml_rowptr, dim3(ceil_div(ne + 1, 256)), dim3(256), 0, s, D.L.rowptr.p, ne,
+                       D.ML.rowptr.p);
+    EDFA_CHECK_LAUNCH();
+    EDFA_HIP(hipMemcpyAsync(D.MU.rowptr.p, D.U.rowptr.p, sizeof(int) * ((size_t)ne + 1),
+                            hipMemcpyDeviceToDevice, s));
+    if (ne) {
+      hipLaunchKernelGGL(k_isai_lower<T>, dim3(ne), dim3(64), 0, s, D.L.rowptr.p, D.L.col.p,
+                         D.L.val.p, ne, D.ML.rowptr.p, D.ML.col.p, D.ML.val.p);
+      EDFA_CHECK_LAUNCH();
+      hipLaunchKernelGGL(k_isai_upper<T>, dim3(ne), dim3(64), 0, s, D.U.rowptr.p, D.U.col.p,
+                         D.U.val.p, ne, D.MU.col.p, D.MU.val.p);
+      EDFA_CHECK_LAUNCH();
+    }
+  }
+  // transposes are rebuilt lazily for the transposed application
+  D.LT.rows = D.UT.rows = D.MLT.rows = D.MUT.rows = 0;
+  EDFA_HIP(hipStreamSynchronize(s));
+}
+
+void precond_stage2(edfa_precond_s &P, hipStream_t s) {
+  if (P.prm.precision == 1)
+    stage2_impl<float>(P, P.f, s);
+  else
+    stage2_impl<double>(P, P.d, s);
+}
+
+}  // namespace edfa

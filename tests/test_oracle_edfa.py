@@ -4,6 +4,7 @@ import pytest
 import scipy.sparse as sp
 
 from oracle import edfa, krylov, mhfe
+from oracle.edfa import unit_lower as oedfa_unit
 from paper_2009_13916_amd import inputs
 
 
@@ -272,7 +273,7 @@ def test_isai_defining_property(small_full):
     s = small_full
     E = edfa.build(s, edfa.Params("static"))
     n = s.ne
-    for T, M in (((E.st2.L + sp.eye(n)).tocsr(), E.st2.ML), (E.st2.U.tocsr(), E.st2.MU)):
+    for T, M in ((oedfa_unit(E.st2.L), E.st2.ML), (E.st2.U.tocsr(), E.st2.MU)):
         MT = (M @ T).toarray()
         Td = T.toarray()
         mask = Td != 0

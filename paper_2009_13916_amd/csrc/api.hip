@@ -40,8 +40,8 @@ static edfa_status guard(F &&f) {
 }
 
 static void ensure_transposes(edfa_system_s &S, hipStream_t s) {
-  if (S.AT.rows == 0 && S.n > 0) csr_transpose(S.A, S.AT, S.tmp, s);
-  if (S.AcfT.rows == 0 && S.nfu > 0) csr_transpose(S.Acf, S.AcfT, S.tmp, s);
+  if (S.AT.rows == 0 && S.n > 0) csr_transpose(S.A, S.AT, S.tmp, S.tmp2, s);
+  if (S.AcfT.rows == 0 && S.nfu > 0) csr_transpose(S.Acf, S.AcfT, S.tmp, S.tmp2, s);
 }
 
 }  // namespace edfa

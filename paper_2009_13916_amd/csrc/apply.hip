@@ -131,14 +131,14 @@ template <class T>
 static void ensure_transposed_factors(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
   edfa_system_s &S = *P.sys;
   if (D.UT.rows == 0 && S.ne) {
-    csr_transpose(D.U, D.UT, S.tmp, s);
-    csr_transpose(D.L, D.LT, S.tmp, s);
+    csr_transpose(D.U, D.UT, S.tmp, S.tmp2, s);
+    csr_transpose(D.L, D.LT, S.tmp, S.tmp2, s);
     if (P.prm.schur_solver == EDFA_SCHUR_ISAI) {
-      csr_transpose(D.ML, D.MLT, S.tmp, s);
-      csr_transpose(D.MU, D.MUT, S.tmp, s);
+      csr_transpose(D.ML, D.MLT, S.tmp, S.tmp2, s);
+      csr_transpose(D.MU, D.MUT, S.tmp, S.tmp2, s);
     }
   }
-  if (S.AcfT.rows == 0 && S.nfu) csr_transpose(S.Acf, S.AcfT, S.tmp, s);
+  if (S.AcfT.rows == 0 && S.nfu) csr_transpose(S.Acf, S.AcfT, S.tmp, S.tmp2, s);
 }
 
 

@@ -562,7 +562,7 @@ void assemble_system(edfa_system_s &S, const edfa_problem *probs, int count, hip
   hipLaunchKernelGGL(k_find_pos, dim3(ceil_div(ne, 256)), dim3(256), 0, s, S.Acc.rowptr.p,
                      S.Acc.col.p, S.ne, S.diag_pos_pp.p);
   EDFA_CHECK_LAUNCH();
-  csr_transpose(S.Afc, S.AfcT, S.tmp, s);
+  csr_transpose(S.Afc, S.AfcT, S.tmp, S.tmp2, s);
   EDFA_HIP(hipStreamSynchronize(s));
 
   S.avg_A = S.n ? (float)S.A.nnz / S.n : 0.f;

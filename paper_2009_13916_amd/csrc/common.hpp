@@ -122,7 +122,8 @@ void exclusive_scan_async(const int *in, int *out, int n, DBuf<int> &tmp, hipStr
 
 // Transpose of a CSR matrix (rows x cols) into dst (cols x rows), columns sorted.
 template <class V>
-void csr_transpose(const Csr<V> &src, Csr<V> &dst, DBuf<int> &tmp, hipStream_t s);
+void csr_transpose(const Csr<V> &src, Csr<V> &dst, DBuf<int> &tmp, DBuf<int> &cursor,
+                   hipStream_t s);
 
 // y[i] = alpha * (A x)[i] + beta * b[i] + gamma * x[i]   (b may be null; gamma needs a
 // square A).  A in CSR with values V, vectors of type X; accumulation in the wider type.

@@ -34,6 +34,7 @@ struct PrecData {
   Csr<T> S;             // S~ = A_pp - H~ (post-filtered)
   Csr<T> ST;            // pattern of S~^T (colouring)
   DBuf<int> color, perm, iperm;     // perm[new] = old
+  DBuf<int> hist, wide;             // colour histograms; wide static patches
   std::vector<int> cstart;          // host: colour c owns new rows [cstart[c], cstart[c+1])
   Csr<T> B;             // P S~ P^T, factored in place into L\U
   DBuf<int> diag;       // Ne: position of the diagonal in B

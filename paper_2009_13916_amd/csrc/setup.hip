@@ -782,11 +782,11 @@ static void stage1_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
   if (!dynamic && prm.static_level > 0) {
     if (prm.static_level > 3) fail(EDFA_ERR_ARG, "static_level must be 0..3");
     // patches are built with the widest stride, then repacked to the smallest template
-    DBuf<int> wide;
-    wide.ensure((size_t)ne * PATCH_MAX);
+
+    D.wide.ensure((size_t)ne * PATCH_MAX);
     hipLaunchKernelGGL(k_patch, dim3(ceil_div(ne, 64)), dim3(64), 0, s, S.grids.p, S.ngrid,
                        S.uidx.p, S.Acf.rowptr.p, S.Acf.col.p, ne, prm.static_level, PATCH_MAX,
-                       wide.p, D.qlen.p, err_cap);
+                       D.wide.p, D.qlen.p, err_cap);
     EDFA_CHECK_LAUNCH();
     check_flags(P, s, "static patch");
     EDFA_HIP(hipMemsetAsync(P.flags.p + 2, 0, sizeof(int), s));
@@ -797,7 +797,7 @@ static void stage1_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
     smax = need <= 16 ? 16 : need <= 32 ? 32 : need <= 64 ? 64 : need <= 128 ? 128 : 0;
     if (!smax) fail(EDFA_ERR_CAPACITY, "static patches of %d entries exceed 128", need);
     D.Q.ensure((size_t)ne * smax);
-    hipLaunchKernelGGL(k_repack, dim3(ceil_div(ne, 256)), dim3(256), 0, s, wide.p, D.qlen.p, ne,
+    hipLaunchKernelGGL(k_repack, dim3(ceil_div(ne, 256)), dim3(256), 0, s, D.wide.p, D.qlen.p, ne,
                        PATCH_MAX, smax, D.Q.p);
     EDFA_CHECK_LAUNCH();
     EDFA_HIP(hipStreamSynchronize(s));
@@ -860,7 +860,7 @@ static void stage1_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
   const int pre = prm.filt_mode == EDFA_FILT_PRE;
   build_vec_csr(S, D, D.gbuf, smax, pre, prm.tau_filt, D.G, s);
   build_vec_csr(S, D, D.fbuf, smax, pre, prm.tau_filt, D.FT, s);
-  csr_transpose(D.FT, D.Fface, S.tmp, s);
+  csr_transpose(D.FT, D.Fface, S.tmp, S.tmp2, s);
 
   // H~ = G~ A_pipi F~
   D.Hcol.ensure((size_t)ne * HMAX);
@@ -925,7 +925,7 @@ static void stage1_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
     EDFA_CHECK_LAUNCH();
   }
   check_flags(P, s, "FSAI");
-  csr_transpose(D.GF, D.GFT, S.tmp, s);
+  csr_transpose(D.GF, D.GFT, S.tmp, S.tmp2, s);
 }
 
 // Raw (unfiltered) H~ as CSR, for export.

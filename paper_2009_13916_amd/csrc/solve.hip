@@ -327,7 +327,7 @@ edfa_status gmres(edfa_system_s &S, edfa_precond_s &P, const double *b, double *
   }
   EDFA_HIP(hipMemcpyAsync(W.st.p, hst.data(), sizeof(SegState) * nseg, hipMemcpyHostToDevice, s));
   const Csr<double> &A = tr ? S.AT : S.A;
-  if (tr && S.AT.rows == 0) csr_transpose(S.A, S.AT, S.tmp, s);
+  if (tr && S.AT.rows == 0) csr_transpose(S.A, S.AT, S.tmp, S.tmp2, s);
 
   Prof prof;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_spmv, ev_apply;

@@ -126,7 +126,8 @@ __global__ void k_sort_rows(const int *__restrict__ rowptr, int rows, int *col, 
 }
 
 template <class V>
-void csr_transpose(const Csr<V> &src, Csr<V> &dst, DBuf<int> &tmp, hipStream_t s) {
+void csr_transpose(const Csr<V> &src, Csr<V> &dst, DBuf<int> &tmp, DBuf<int> &cursor,
+                   hipStream_t s) {
   dst.alloc(src.cols, src.rows, src.nnz);
   EDFA_HIP(hipMemsetAsync(dst.rowptr.p, 0, sizeof(int) * ((size_t)src.cols + 1), s));
   if (src.nnz > 0) {
@@ -135,7 +136,7 @@ void csr_transpose(const Csr<V> &src, Csr<V> &dst, DBuf<int> &tmp, hipStream_t s
     EDFA_CHECK_LAUNCH();
   }
   exclusive_scan_async(dst.rowptr.p, dst.rowptr.p, src.cols, tmp, s);
-  DBuf<int> cursor;
+
   cursor.ensure((size_t)src.cols + 1);
   EDFA_HIP(hipMemcpyAsync(cursor.p, dst.rowptr.p, sizeof(int) * ((size_t)src.cols + 1),
                           hipMemcpyDeviceToDevice, s));
@@ -150,11 +151,13 @@ void csr_transpose(const Csr<V> &src, Csr<V> &dst, DBuf<int> &tmp, hipStream_t s
                        dst.rowptr.p, src.cols, dst.col.p, dst.val.p);
     EDFA_CHECK_LAUNCH();
   }
-  EDFA_HIP(hipStreamSynchronize(s));   // cursor is released on return
+
 }
 
-template void csr_transpose<double>(const Csr<double> &, Csr<double> &, DBuf<int> &, hipStream_t);
-template void csr_transpose<float>(const Csr<float> &, Csr<float> &, DBuf<int> &, hipStream_t);
+template void csr_transpose<double>(const Csr<double> &, Csr<double> &, DBuf<int> &, DBuf<int> &,
+                                    hipStream_t);
+template void csr_transpose<float>(const Csr<float> &, Csr<float> &, DBuf<int> &, DBuf<int> &,
+                                   hipStream_t);
 
 // ----------------------------------------------------------------------------------
 // SpMV: a group of LANES lanes per row, shuffle reduction inside the group.

@@ -389,7 +389,7 @@ static void stage2_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
   EDFA_CHECK_LAUNCH();
   const int smaxrow = read_scalar(P.flags.p + 2, s);
   if (smaxrow > HMAX + 64) fail(EDFA_ERR_CAPACITY, "a row of S~ has %d > %d entries", smaxrow, HMAX + 64);
-  csr_transpose(D.S, D.ST, S.tmp, s);
+  csr_transpose(D.S, D.ST, S.tmp, S.tmp2, s);
 
   // colouring
   D.color.ensure(ne);
@@ -418,21 +418,21 @@ static void stage2_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
 
   // stable permutation by colour
   const int nb = ceil_div(ne, 256);
-  DBuf<int> hist;
-  hist.ensure((size_t)ncol * nb + 1);
+
+  D.hist.ensure((size_t)ncol * nb + 1);
   D.perm.ensure(ne);
   D.iperm.ensure(ne);
   if (ne) {
-    hipLaunchKernelGGL(k_color_hist, dim3(nb), dim3(256), 0, s, D.color.p, ne, ncol, nb, hist.p);
+    hipLaunchKernelGGL(k_color_hist, dim3(nb), dim3(256), 0, s, D.color.p, ne, ncol, nb, D.hist.p);
     EDFA_CHECK_LAUNCH();
-    exclusive_scan(hist.p, hist.p, ncol * nb, S.tmp, s);
-    hipLaunchKernelGGL(k_color_scatter, dim3(nb), dim3(256), 0, s, D.color.p, ne, nb, hist.p,
+    exclusive_scan(D.hist.p, D.hist.p, ncol * nb, S.tmp, s);
+    hipLaunchKernelGGL(k_color_scatter, dim3(nb), dim3(256), 0, s, D.color.p, ne, nb, D.hist.p,
                        D.perm.p, D.iperm.p);
     EDFA_CHECK_LAUNCH();
   }
   {
     std::vector<int> h((size_t)ncol * nb + 1);
-    EDFA_HIP(hipMemcpyAsync(h.data(), hist.p, sizeof(int) * h.size(), hipMemcpyDeviceToHost, s));
+    EDFA_HIP(hipMemcpyAsync(h.data(), D.hist.p, sizeof(int) * h.size(), hipMemcpyDeviceToHost, s));
     EDFA_HIP(hipStreamSynchronize(s));
     D.cstart.assign(ncol + 1, ne);
     for (int c = 0; c < ncol; ++c) D.cstart[c] = h[(size_t)c * nb];

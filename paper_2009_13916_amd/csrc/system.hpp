@@ -139,6 +139,6 @@ struct edfa_system_s {
   edfa::Csr<double> AT;          // A^T (built on first use)
   edfa::Csr<double> AcfT;        // A_ppi^T (Nfu x N_e, built on first use)
   edfa::DBuf<double> b;          // N
-  edfa::DBuf<int> tmp;           // scratch for scans
+  edfa::DBuf<int> tmp, tmp2;     // scratch for scans and transposes
   float avg_A = 0, avg_fp = 0, avg_fc = 0, avg_cf = 0, avg_cc = 0;
 };

@@ -1,0 +1,168 @@
+#!/usr/bin/env python
+"""Benchmark of the EDFA-preconditioned GMRES hot path on one MI355X.
+
+Workload: the 64^3 full-tensor grid (262,144 cells, ~1.05M unknowns) with
+K = k1 R diag(1, a^-1/2, a^-1) R^T per cell (Haar R, a log-uniform in [10, 100],
+ln k1 a Gaussian random field, sigma 2, correlation length 8 cells), Dirichlet
+p = 1 / 0 on x = 0 / 1, no flow elsewhere.  Synthetic, seeded, assembled once on the
+device before timing (assembly is not part of the metric).
+
+One step = EDFA stage 1 + stage 2 (dynamic patterns, n_add = 1, n_ent = 6,
+post-filtration on H~ with tau = 1e-3) followed by right-preconditioned GMRES(50)
+from x0 = 0 to a true relative residual <= 1e-8.  ``value`` is the mean wall time of
+one step in seconds for the FP64 path; the FP32-preconditioner / FP64 flexible GMRES
+form is timed the same way and reported under ``forms``.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "setup+GMRES time to 1e-8 rel residual, FP64 vs mixed/batched; HBM GB/s"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def spmv_bytes(nnz, n):
+    """Algorithmic bytes of y = A x in CSR (FP64 values, int32 indices): values and
+    column indices once, row pointers once, x once, y once."""
+    return 12 * nnz + 4 * (n + 1) + 8 * n + 8 * n
+
+
+def run_form(edfa, S, b, prm, steps, warmup, flexible):
+    import torch
+    P = edfa.Precond(S, prm)
+    for _ in range(warmup):
+        P.resetup()
+        edfa.solve(S, P, b, rtol=1e-8, restart=50, flexible=flexible)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos, pinfos = [], []
+    for k in range(steps):
+        P.resetup()
+        x, info, st = edfa.solve(S, P, b, rtol=1e-8, restart=50, flexible=flexible, profile=True)
+        infos.append((info, st))
+        pinfos.append(P.info())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return (t1 - t0) / steps, infos, pinfos, x
+
+
+def cpu_baseline(iters_gpu, n_full, ne_full):
+    """Time the oracle on a bounded sample: the whole oracle pipeline on the 12^3 member
+    of the same workload family, scaled to 64^3 (setup per cell, solve per iteration and
+    unknown, at the GPU's iteration count).  Runs single-threaded in a child process."""
+    code = r"""
+import json, sys, time
+sys.path.insert(0, %r)
+from paper_2009_13916_amd import inputs
+from oracle import edfa, krylov, mhfe
+p = inputs.full_tensor_problem(12, sigma=2.0, corr=8.0 * 12 / 64)
+s = mhfe.assemble(p)
+prm = edfa.Params("dynamic", n_add=1, n_ent=6, tau=1e-3, filt="post_H")
+t0 = time.perf_counter(); st1 = edfa.stage1(s, prm); t1 = time.perf_counter()
+st2 = edfa.stage2(s, st1, prm); t2 = time.perf_counter()
+E = edfa.Edfa(s, prm, st1, st2); A = s.matrix()
+t3 = time.perf_counter(); r = krylov.gmres(lambda v: A @ v, E.apply, s.b, 1e-8, 50); t4 = time.perf_counter()
+print(json.dumps({"setup": t2 - t0, "solve": t4 - t3, "iters": r.iterations, "n": s.n, "ne": s.ne}))
+""" % ROOT
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
+                         timeout=600)
+    if out.returncode != 0:
+        log("cpu baseline failed: " + out.stderr[-500:])
+        return None
+    d = json.loads(out.stdout.strip().splitlines()[-1])
+    setup = d["setup"] * ne_full / d["ne"]
+    solve = d["solve"] / (d["iters"] * d["n"]) * iters_gpu * n_full
+    return {"value": setup + solve, "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": (f"full oracle pipeline on the 12^3 member of the workload family "
+                       f"({d['ne']} cells, setup {d['setup']:.2f} s, {d['iters']} GMRES iterations "
+                       f"in {d['solve']:.2f} s), setup scaled per cell and solve per iteration and "
+                       f"unknown to 64^3 at the GPU iteration count ({iters_gpu})")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=64, help="grid side (64 = the benchmark workload)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is "
+              "described in DESIGN.md but not built.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2009_13916_amd import edfa, inputs
+    edfa.load()
+    torch.cuda.set_device(0)
+    n = args.n
+    log(f"building the {n}^3 full-tensor workload")
+    prob = inputs.full_tensor_problem(n, sigma=2.0, corr=8.0 * n / 64)
+    S = edfa.System(prob)
+    b = S.rhs()
+    torch.cuda.synchronize()
+    nnz, N, ne = S.info["nnz"], S.info["n"], S.info["ne"]
+    log(f"assembled: N={N} nnz={nnz}")
+    prm = edfa.Params("dynamic", n_add=1, n_ent=6, tau=1e-3, filt="post_H")
+    t64, infos, pinfos, x = run_form(edfa, S, b, prm, args.steps, args.warmup, flexible=False)
+    info, st = infos[-1]
+    log(f"fp64: {t64:.4f} s/step, {info['iterations']} iterations, relres {info['relres_true']:.2e}")
+    forms = {"fp64": {"s_per_step": t64, "iterations": info["iterations"],
+                      "relres_true": info["relres_true"], "converged": st == 0,
+                      "stage1_ms": pinfos[-1]["t_stage1_ms"], "stage2_ms": pinfos[-1]["t_stage2_ms"],
+                      "solve_ms": info["t_solve_ms"], "mu": pinfos[-1]["mu"],
+                      "colors": pinfos[-1]["n_colors"]}}
+    if not args.no_mixed:
+        prm32 = edfa.Params("dynamic", n_add=1, n_ent=6, tau=1e-3, filt="post_H", precision=1)
+        t32, i32, p32, x32 = run_form(edfa, S, b, prm32, args.steps, args.warmup, flexible=True)
+        inf32, st32 = i32[-1]
+        dp = (x32 - x)[S.info["nfu"]:].norm() / x[S.info["nfu"]:].norm()
+        log(f"mixed: {t32:.4f} s/step, {inf32['iterations']} iterations")
+        forms["mixed_fp32_precond_fgmres"] = {
+            "s_per_step": t32, "iterations": inf32["iterations"], "relres_true": inf32["relres_true"],
+            "converged": st32 == 0, "stage1_ms": p32[-1]["t_stage1_ms"],
+            "stage2_ms": p32[-1]["t_stage2_ms"], "solve_ms": inf32["t_solve_ms"],
+            "pressure_rel_diff_vs_fp64": float(dp)}
+    spmv_ms = info["spmv_avg_ms"]
+    ab = spmv_bytes(nnz, N)
+    achieved = ab / (spmv_ms * 1e-3) / 1e9 if spmv_ms > 0 else 0.0
+    out = {
+        "metric": METRIC, "value": t64, "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": t64 * 1e3, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"full_tensor_grf_{n}^3", "cells": ne, "unknowns": N, "nnz": nnz,
+                   "edfa": "dynamic (n_add 1, n_ent 6), post-filtration on H~ 1e-3",
+                   "krylov": "GMRES(50), x0 = 0", "rtol": 1e-8},
+        "iterations": info["iterations"], "relres_true": info["relres_true"],
+        "forms": forms,
+        "roofline": {"bound": "hbm", "kernel": "CSR SpMV with A (k_spmv<double,double,16>)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": ab, "avg_launch_ms": spmv_ms,
+                     "launches": info["spmv_count"]},
+    }
+    if not args.no_cpu_baseline:
+        log("timing the oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(info["iterations"], N, ne)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -177,6 +177,10 @@ edfa_status edfa_setup(edfa_system sys, const edfa_params *prm /* (host) */,
                        hipStream_t stream, edfa_precond *out);
 /* Re-run stage 2 only, after edfa_update_dt (stage 1 is recycled, Section 3.1). */
 edfa_status edfa_setup_stage2(edfa_precond pre, hipStream_t stream);
+/* Re-run stage 1 and stage 2 with the same parameters on the same system (whose values may
+ * have changed, e.g. after edfa_update_dt), reusing the handle's device memory: no device
+ * allocation happens when the new patterns fit the previous ones.  Synchronises the stream. */
+edfa_status edfa_resetup(edfa_precond pre, hipStream_t stream);
 void edfa_precond_destroy(edfa_precond pre);
 edfa_status edfa_precond_get_info(edfa_precond pre, edfa_precond_info *info /* (host) */);
 

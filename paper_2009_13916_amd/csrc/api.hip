@@ -280,6 +280,22 @@ edfa_status edfa_setup_stage2(edfa_precond pre, hipStream_t stream) {
   });
 }
 
+edfa_status edfa_resetup(edfa_precond pre, hipStream_t stream) {
+  return guard([&] {
+    if (!pre) fail(EDFA_ERR_ARG, "NULL preconditioner");
+    EventTimer t1, t2;
+    t1.start(stream);
+    precond_stage1(*pre, stream);
+    t1.stop(stream);
+    pre->t_stage1_ms = t1.ms();
+    t2.start(stream);
+    precond_stage2(*pre, stream);
+    t2.stop(stream);
+    pre->t_stage2_ms = t2.ms();
+    return EDFA_OK;
+  });
+}
+
 void edfa_precond_destroy(edfa_precond pre) { delete pre; }
 
 edfa_status edfa_precond_get_info(edfa_precond pre, edfa_precond_info *info) {

@@ -97,6 +97,7 @@ def load():
             "edfa_spmv": (C.c_int, [vp, i32, vp, vp, vp]),
             "edfa_setup": (C.c_int, [vp, C.POINTER(_Params), vp, C.POINTER(vp)]),
             "edfa_setup_stage2": (C.c_int, [vp, vp]),
+            "edfa_resetup": (C.c_int, [vp, vp]),
             "edfa_precond_destroy": (None, [vp]),
             "edfa_precond_get_info": (C.c_int, [vp, C.POINTER(_PrecondInfo)]),
             "edfa_export_precond": (C.c_int, [vp, i32, vp, vp, vp, vp, C.POINTER(i64),
@@ -121,7 +122,7 @@ def exported_symbols():
     L = load()
     return [n for n in ("edfa_last_error", "edfa_assemble", "edfa_system_destroy",
                         "edfa_system_get_info", "edfa_update_dt", "edfa_export_block",
-                        "edfa_export_rhs", "edfa_spmv", "edfa_setup", "edfa_setup_stage2",
+                        "edfa_export_rhs", "edfa_spmv", "edfa_setup", "edfa_setup_stage2", "edfa_resetup",
                         "edfa_precond_destroy", "edfa_precond_get_info", "edfa_export_precond",
                         "edfa_apply", "edfa_solve", "edfa_grad_logk") if hasattr(L, n)]
 
@@ -242,6 +243,10 @@ class Precond:
 
     def stage2(self):
         _check(load().edfa_setup_stage2(self._h, _stream()))
+
+    def resetup(self):
+        """Stage 1 + stage 2 again on the same system, reusing device memory."""
+        _check(load().edfa_resetup(self._h, _stream()))
 
     def info(self):
         inf = _PrecondInfo()

@@ -47,7 +47,6 @@ __global__ void k_sweep(const int *__restrict__ rp, const int *__restrict__ col,
 
 // FP32 copy of an FP64 CSR matrix (pattern copied, values rounded); kept across calls.
 static void to_fp32(const Csr<double> &M, Csr<float> &F, hipStream_t s) {
-  if (F.rows == M.rows && F.nnz == M.nnz) return;
   F.alloc(M.rows, M.cols, M.nnz);
   EDFA_HIP(hipMemcpyAsync(F.rowptr.p, M.rowptr.p, sizeof(int) * ((size_t)M.rows + 1),
                           hipMemcpyDeviceToDevice, s));
@@ -70,27 +69,24 @@ static void sinv(edfa_precond_s &P, PrecData<T> &D, int transpose, const T *y, T
   D.res.ensure(ne);
   hipLaunchKernelGGL(k_gather<T>, dim3(gb), dim3(256), 0, s, y, D.perm.p, ne, D.y.p);
   EDFA_CHECK_LAUNCH();
-  const float al = ne ? (float)D.L.nnz / ne : 0.f, au = ne ? (float)D.U.nnz / ne : 0.f;
   const int steps = std::max(1, P.prm.isai_steps);
   if (P.prm.schur_solver == EDFA_SCHUR_ISAI) {
     // first factor (L, or U^T for the transpose), then the second
-    const Csr<T> &M1 = transpose ? D.MUT : D.ML;
-    const Csr<T> &T1 = transpose ? D.UT : D.L;
-    const Csr<T> &M2 = transpose ? D.MLT : D.MU;
-    const Csr<T> &T2 = transpose ? D.LT : D.U;
+    const Sell<T> &M1 = transpose ? D.MUT_s : D.ML_s;
+    const Sell<T> &T1 = transpose ? D.UT_s : D.L_s;
+    const Sell<T> &M2 = transpose ? D.MLT_s : D.MU_s;
+    const Sell<T> &T2 = transpose ? D.LT_s : D.U_s;
     const double g1 = transpose ? 0.0 : -1.0;   // (I + L) w = L w + w
     const double g2 = transpose ? -1.0 : 0.0;
-    spmv<T, T>(M1.rowptr.p, M1.col.p, M1.val.p, ne, D.y.p, D.w.p, 1.0, nullptr, 0.0, al + 1, s);
+    spmv_sell<T, T>(M1, D.y.p, D.w.p, 1.0, nullptr, 0.0, s);
     for (int k = 1; k < steps; ++k) {
-      spmv<T, T>(T1.rowptr.p, T1.col.p, T1.val.p, ne, D.w.p, D.res.p, -1.0, D.y.p, 1.0,
-                 transpose ? au : al, s, g1);
-      spmv<T, T>(M1.rowptr.p, M1.col.p, M1.val.p, ne, D.res.p, D.w.p, 1.0, D.w.p, 1.0, al + 1, s);
+      spmv_sell<T, T>(T1, D.w.p, D.res.p, -1.0, D.y.p, 1.0, s, g1);
+      spmv_sell<T, T>(M1, D.res.p, D.w.p, 1.0, D.w.p, 1.0, s);
     }
-    spmv<T, T>(M2.rowptr.p, M2.col.p, M2.val.p, ne, D.w.p, D.zq.p, 1.0, nullptr, 0.0, au, s);
+    spmv_sell<T, T>(M2, D.w.p, D.zq.p, 1.0, nullptr, 0.0, s);
     for (int k = 1; k < steps; ++k) {
-      spmv<T, T>(T2.rowptr.p, T2.col.p, T2.val.p, ne, D.zq.p, D.res.p, -1.0, D.w.p, 1.0,
-                 transpose ? al : au, s, g2);
-      spmv<T, T>(M2.rowptr.p, M2.col.p, M2.val.p, ne, D.res.p, D.zq.p, 1.0, D.zq.p, 1.0, au, s);
+      spmv_sell<T, T>(T2, D.zq.p, D.res.p, -1.0, D.w.p, 1.0, s, g2);
+      spmv_sell<T, T>(M2, D.res.p, D.zq.p, 1.0, D.zq.p, 1.0, s);
     }
   } else {
     const int nc = P.n_colors;
@@ -133,40 +129,41 @@ static void ensure_transposed_factors(edfa_precond_s &P, PrecData<T> &D, hipStre
   if (D.UT.rows == 0 && S.ne) {
     csr_transpose(D.U, D.UT, S.tmp, S.tmp2, s);
     csr_transpose(D.L, D.LT, S.tmp, S.tmp2, s);
+    build_sell(D.UT, D.UT_s, S.tmp, s);
+    build_sell(D.LT, D.LT_s, S.tmp, s);
     if (P.prm.schur_solver == EDFA_SCHUR_ISAI) {
       csr_transpose(D.ML, D.MLT, S.tmp, S.tmp2, s);
       csr_transpose(D.MU, D.MUT, S.tmp, S.tmp2, s);
+      build_sell(D.MLT, D.MLT_s, S.tmp, s);
+      build_sell(D.MUT, D.MUT_s, S.tmp, s);
     }
   }
   if (S.AcfT.rows == 0 && S.nfu) csr_transpose(S.Acf, S.AcfT, S.tmp, S.tmp2, s);
+  if (S.AcfT_s.rows == 0 && S.nfu) build_sell(S.AcfT, S.AcfT_s, S.tmp, s);
 }
 
-
+// z = P^-1 r (or P^-T r) in precision T; c1 = A_ppi (A_pip^T), c2 = A_pip (A_ppi^T).
 template <class T>
-static void apply_typed(edfa_precond_s &P, PrecData<T> &D, int transpose, const T *r, T *z,
-                        const int *c_rp[2], const int *c_col[2], const T *c_val[2],
-                        hipStream_t s) {
+static void apply_typed(edfa_precond_s &P, PrecData<T> &D, const T *r, T *z, const Sell<T> &c1,
+                        const Sell<T> &c2, int transpose, hipStream_t s) {
   edfa_system_s &S = *P.sys;
   const int nfu = S.nfu, ne = S.ne;
   D.t1.ensure(nfu);
   D.t2.ensure(nfu);
-  const float ag = nfu ? (float)D.GF.nnz / nfu : 0.f;
+  D.r.ensure(ne);
   const T *rpi = r, *rp = r + nfu;
   T *zpi = z, *zp = z + nfu;
-  // t = A~^-1 r_pi
-  spmv<T, T>(D.GF.rowptr.p, D.GF.col.p, D.GF.val.p, nfu, rpi, D.t1.p, 1.0, nullptr, 0.0, ag, s);
-  spmv<T, T>(D.GFT.rowptr.p, D.GFT.col.p, D.GFT.val.p, nfu, D.t1.p, D.t2.p, -1.0, nullptr, 0.0, ag, s);
-  // y = r_p - A_ppi t   (transpose: A_pip^T)
-  D.r.ensure(ne);
-  spmv<T, T>(c_rp[0], c_col[0], c_val[0], ne, D.t2.p, D.r.p, -1.0, rp, 1.0,
-             transpose ? S.avg_fc * nfu / std::max(ne, 1) : S.avg_cf, s);
+  // t = A~^-1 r_pi = -G_F^T G_F r_pi
+  spmv_sell<T, T>(D.GF_s, rpi, D.t1.p, 1.0, nullptr, 0.0, s);
+  spmv_sell<T, T>(D.GFT_s, D.t1.p, D.t2.p, -1.0, nullptr, 0.0, s);
+  // y = r_p - A_ppi t
+  spmv_sell<T, T>(c1, D.t2.p, D.r.p, -1.0, rp, 1.0, s);
   // z_p = S~^-1 y
   sinv<T>(P, D, transpose, D.r.p, zp, s);
-  // z_pi = A~^-1 (r_pi - A_pip z_p)   (transpose: A_ppi^T)
-  spmv<T, T>(c_rp[1], c_col[1], c_val[1], nfu, zp, D.t1.p, -1.0, rpi, 1.0,
-             transpose ? S.avg_cf * ne / std::max(nfu, 1) : S.avg_fc, s);
-  spmv<T, T>(D.GF.rowptr.p, D.GF.col.p, D.GF.val.p, nfu, D.t1.p, D.t2.p, 1.0, nullptr, 0.0, ag, s);
-  spmv<T, T>(D.GFT.rowptr.p, D.GFT.col.p, D.GFT.val.p, nfu, D.t2.p, zpi, -1.0, nullptr, 0.0, ag, s);
+  // z_pi = A~^-1 (r_pi - A_pip z_p)
+  spmv_sell<T, T>(c2, zp, D.t1.p, -1.0, rpi, 1.0, s);
+  spmv_sell<T, T>(D.GF_s, D.t1.p, D.t2.p, 1.0, nullptr, 0.0, s);
+  spmv_sell<T, T>(D.GFT_s, D.t2.p, zpi, -1.0, nullptr, 0.0, s);
 }
 
 void precond_apply(edfa_precond_s &P, int transpose, const double *r, double *z, hipStream_t s) {
@@ -178,23 +175,20 @@ void precond_apply(edfa_precond_s &P, int transpose, const double *r, double *z,
       ensure_transposed_factors(P, P.d, s);
   }
   if (P.prm.precision != 1) {
-    const int *rp2[2] = {transpose ? S.AfcT.rowptr.p : S.Acf.rowptr.p,
-                         transpose ? S.AcfT.rowptr.p : S.Afc.rowptr.p};
-    const int *cl2[2] = {transpose ? S.AfcT.col.p : S.Acf.col.p,
-                         transpose ? S.AcfT.col.p : S.Afc.col.p};
-    const double *vl2[2] = {transpose ? S.AfcT.val.p : S.Acf.val.p,
-                            transpose ? S.AcfT.val.p : S.Afc.val.p};
-    apply_typed<double>(P, P.d, transpose, r, z, rp2, cl2, vl2, s);
+    apply_typed<double>(P, P.d, r, z, transpose ? S.AfcT_s : S.Acf_s,
+                        transpose ? S.AcfT_s : S.Afc_s, transpose, s);
     return;
   }
   // FP32 application: convert in, apply, convert out
   PrecData<float> &D = P.f;
   auto &cf = P.coupling_f;
-  to_fp32(S.Acf, cf[0], s);
-  to_fp32(S.Afc, cf[1], s);
-  if (transpose) {
-    to_fp32(S.AfcT, cf[2], s);
-    to_fp32(S.AcfT, cf[3], s);
+  auto &cs = P.coupling_fs;
+  const Csr<double> *src[4] = {&S.Acf, &S.Afc, &S.AfcT, &S.AcfT};
+  for (int q = 0; q < (transpose ? 4 : 2); ++q) {
+    if (cf[q].rows != src[q]->rows || cf[q].nnz != src[q]->nnz) {
+      to_fp32(*src[q], cf[q], s);
+      build_sell(cf[q], cs[q], S.tmp, s);
+    }
   }
   const int n = S.n;
   D.z.ensure(n);
@@ -203,11 +197,8 @@ void precond_apply(edfa_precond_s &P, int transpose, const double *r, double *z,
   hipLaunchKernelGGL((k_convert<double, float>), dim3(ceil_div(n, 256)), dim3(256), 0, s, r,
                      (long long)n, rin.p);
   EDFA_CHECK_LAUNCH();
-  const int *rp2[2] = {transpose ? cf[2].rowptr.p : cf[0].rowptr.p,
-                       transpose ? cf[3].rowptr.p : cf[1].rowptr.p};
-  const int *cl2[2] = {transpose ? cf[2].col.p : cf[0].col.p, transpose ? cf[3].col.p : cf[1].col.p};
-  const float *vl2[2] = {transpose ? cf[2].val.p : cf[0].val.p, transpose ? cf[3].val.p : cf[1].val.p};
-  apply_typed<float>(P, D, transpose, rin.p, D.z.p, rp2, cl2, vl2, s);
+  apply_typed<float>(P, D, rin.p, D.z.p, transpose ? cs[2] : cs[0], transpose ? cs[3] : cs[1],
+                     transpose, s);
   hipLaunchKernelGGL((k_convert<float, double>), dim3(ceil_div(n, 256)), dim3(256), 0, s, D.z.p,
                      (long long)n, z);
   EDFA_CHECK_LAUNCH();

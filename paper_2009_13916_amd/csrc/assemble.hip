@@ -563,6 +563,10 @@ void assemble_system(edfa_system_s &S, const edfa_problem *probs, int count, hip
                      S.Acc.col.p, S.ne, S.diag_pos_pp.p);
   EDFA_CHECK_LAUNCH();
   csr_transpose(S.Afc, S.AfcT, S.tmp, S.tmp2, s);
+  build_sell(S.A, S.A_s, S.tmp, s);
+  build_sell(S.Acf, S.Acf_s, S.tmp, s);
+  build_sell(S.Afc, S.Afc_s, S.tmp, s);
+  build_sell(S.AfcT, S.AfcT_s, S.tmp, s);
   EDFA_HIP(hipStreamSynchronize(s));
 
   S.avg_A = S.n ? (float)S.A.nnz / S.n : 0.f;
@@ -622,6 +626,10 @@ void update_dt(edfa_system_s &S, double dt, const double *p_prev, hipStream_t s)
                        S.vol.p, S.cstore.p, S.p_prev.p, S.diag0.p, S.rhs0.p, S.diag_pos_A.p,
                        S.diag_pos_pp.p, S.A.val.p, S.Acc.val.p, S.b.p);
   EDFA_CHECK_LAUNCH();
+  // copies of A follow its new diagonal: SELL now, the transpose on its next use
+  build_sell(S.A, S.A_s, S.tmp, s);
+  S.AT.rows = 0;
+  S.AT_s.rows = 0;
 }
 
 }  // namespace edfa

@@ -79,6 +79,19 @@ struct Csr {
   }
 };
 
+// Sliced ELLPACK with slices of 64 rows (one wavefront): the k-th entries of the 64 rows of
+// a slice are contiguous, so a lane per row reads coalesced without cross-lane reductions.
+// Each row stops at its own length (padding is stored but never read).
+template <class V>
+struct Sell {
+  int rows = 0, cols = 0, nslice = 0;
+  int64_t nnz = 0, padded = 0;
+  DBuf<int> sptr;   // nslice + 1 element offsets
+  DBuf<int> rlen;   // rows
+  DBuf<int> col;
+  DBuf<V> val;
+};
+
 inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
 
 // Host read of one device scalar (synchronises the stream).
@@ -120,10 +133,12 @@ int64_t exclusive_scan(const int *in, int *out, int n, DBuf<int> &tmp, hipStream
 // Same, without reading the total back (asynchronous).
 void exclusive_scan_async(const int *in, int *out, int n, DBuf<int> &tmp, hipStream_t s);
 
-// Transpose of a CSR matrix (rows x cols) into dst (cols x rows), columns sorted.
+// Transpose of a CSR matrix (rows x cols) into dst (cols x rows).  With sort, columns are
+// sorted within rows (deterministic layout, needed where values are summed); without,
+// the order inside a row is arbitrary (pattern-only uses).
 template <class V>
 void csr_transpose(const Csr<V> &src, Csr<V> &dst, DBuf<int> &tmp, DBuf<int> &cursor,
-                   hipStream_t s);
+                   hipStream_t s, bool sort = true);
 
 // y[i] = alpha * (A x)[i] + beta * b[i] + gamma * x[i]   (b may be null; gamma needs a
 // square A).  A in CSR with values V, vectors of type X; accumulation in the wider type.
@@ -132,5 +147,14 @@ template <class V, class X>
 void spmv(const int *rowptr, const int *col, const V *val, int rows, const X *x, X *y,
           double alpha, const X *b, double beta, float avg_nnz, hipStream_t s,
           double gamma = 0.0);
+
+// SELL-64 copy of a CSR matrix (device-side conversion; synchronises to size the storage).
+template <class V>
+void build_sell(const Csr<V> &M, Sell<V> &S, DBuf<int> &tmp, hipStream_t s);
+
+// Same contract as spmv() for a SELL-64 matrix.
+template <class V, class X>
+void spmv_sell(const Sell<V> &M, const X *x, X *y, double alpha, const X *b, double beta,
+               hipStream_t s, double gamma = 0.0);
 
 }  // namespace edfa

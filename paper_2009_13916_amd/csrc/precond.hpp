@@ -35,12 +35,15 @@ struct PrecData {
   Csr<T> ST;            // pattern of S~^T (colouring)
   DBuf<int> color, perm, iperm;     // perm[new] = old
   DBuf<int> hist, wide;             // colour histograms; wide static patches
+  DBuf<int> resume;                 // colouring: where each vertex's neighbour scan stopped
   std::vector<int> cstart;          // host: colour c owns new rows [cstart[c], cstart[c+1])
   Csr<T> B;             // P S~ P^T, factored in place into L\U
   DBuf<int> diag;       // Ne: position of the diagonal in B
   Csr<T> L, U;          // strict lower (unit factor) and upper (with diagonal) of B
   Csr<T> ML, MU;        // ISAI of (I + L) and U
   Csr<T> LT, UT, MLT, MUT;          // transposes (built on first transposed apply)
+  // SELL-64 copies used by the application
+  Sell<T> GF_s, GFT_s, L_s, U_s, ML_s, MU_s, LT_s, UT_s, MLT_s, MUT_s;
   // application scratch (working precision)
   DBuf<T> r, z, t1, t2, y, w, zq, res;
 };
@@ -77,6 +80,7 @@ struct edfa_precond_s {
   edfa::PrecData<float> f;
   edfa::DBuf<int> flags;           // device error flags
   edfa::Csr<float> coupling_f[4];  // FP32 A_ppi, A_pip, A_pip^T, A_ppi^T (FP32 application)
+  edfa::Sell<float> coupling_fs[4];
   edfa::DBuf<float> rin_f;         // FP32 copy of the vector being preconditioned
   std::unique_ptr<edfa::SolveWork> ws;
 };

@@ -860,7 +860,7 @@ static void stage1_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
   const int pre = prm.filt_mode == EDFA_FILT_PRE;
   build_vec_csr(S, D, D.gbuf, smax, pre, prm.tau_filt, D.G, s);
   build_vec_csr(S, D, D.fbuf, smax, pre, prm.tau_filt, D.FT, s);
-  csr_transpose(D.FT, D.Fface, S.tmp, S.tmp2, s);
+  csr_transpose(D.FT, D.Fface, S.tmp, S.tmp2, s, false);   // only its pattern is used
 
   // H~ = G~ A_pipi F~
   D.Hcol.ensure((size_t)ne * HMAX);
@@ -926,6 +926,8 @@ static void stage1_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
   }
   check_flags(P, s, "FSAI");
   csr_transpose(D.GF, D.GFT, S.tmp, S.tmp2, s);
+  build_sell(D.GF, D.GF_s, S.tmp, s);
+  build_sell(D.GFT, D.GFT_s, S.tmp, s);
 }
 
 // Raw (unfiltered) H~ as CSR, for export.

@@ -119,41 +119,53 @@ __global__ __launch_bounds__(RT) void k_seg_reduce(const double *__restrict__ pa
   }
 }
 
-// Per segment: Hessenberg column j from the two Gram-Schmidt passes and ||w||, Givens
-// rotations, residual estimate |g_{j+1}|, end-of-cycle decision, scale for v_{j+1}.
-__global__ void k_givens(int nseg, int m, int j, SegState *st, const double *__restrict__ h1,
-                         const double *__restrict__ h2, const double *__restrict__ nrm2, int ldh,
-                         double *R, double *cs, double *sn, double *gv, double *scale,
-                         int max_iter) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= nseg) return;
-  SegState S = st[g];
-  if (!S.active) return;
-  double col[MAXV];
-  for (int i = 0; i <= j; ++i) col[i] = h1[(long long)g * ldh + i] + h2[(long long)g * ldh + i];
-  const double hn = sqrt(nrm2[(long long)g * ldh]);
-  col[j + 1] = hn;
-  double *c = cs + (long long)g * m, *s = sn + (long long)g * m, *gg = gv + (long long)g * (m + 1);
-  for (int i = 0; i < j; ++i) {
-    const double t = c[i] * col[i] + s[i] * col[i + 1];
-    col[i + 1] = -s[i] * col[i] + c[i] * col[i + 1];
-    col[i] = t;
+// One wavefront per segment: lanes load the column and the rotations into LDS, lane 0
+// applies them in order.
+__global__ __launch_bounds__(64) void k_givens(int nseg, int m, int j, SegState *st,
+                                               const double *__restrict__ h1,
+                                               const double *__restrict__ h2,
+                                               const double *__restrict__ nrm2, int ldh,
+                                               double *R, double *cs, double *sn, double *gv,
+                                               double *scale, int max_iter) {
+  __shared__ double col[MAXV], c[MAXV], s[MAXV];
+  const int g = blockIdx.x;
+  if (g >= nseg || !st[g].active) return;
+  for (int i = threadIdx.x; i <= j; i += 64) {
+    col[i] = h1[(long long)g * ldh + i] + h2[(long long)g * ldh + i];
+    if (i < j) {
+      c[i] = cs[(long long)g * m + i];
+      s[i] = sn[(long long)g * m + i];
+    }
   }
-  const double den = hypot(col[j], col[j + 1]);
-  const double cj = den > 0 ? col[j] / den : 1.0, sj = den > 0 ? col[j + 1] / den : 0.0;
-  c[j] = cj;
-  s[j] = sj;
-  col[j] = den;
-  gg[j + 1] = -sj * gg[j];
-  gg[j] = cj * gg[j];
-  for (int i = 0; i <= j; ++i) R[((long long)g * m + i) * m + j] = col[i];
-  S.est = fabs(gg[j + 1]);
-  S.j = j + 1;
-  S.total += 1;
-  scale[g] = hn > 0 ? 1.0 / hn : 0.0;
-  if (!(S.est > S.tol) || !(hn > 0) || S.total >= max_iter || S.j >= m || !isfinite(S.est))
-    S.active = 0;
-  st[g] = S;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    SegState S = st[g];
+    const double hn = sqrt(nrm2[(long long)g * ldh]);
+    col[j + 1] = hn;
+    for (int i = 0; i < j; ++i) {
+      const double t = c[i] * col[i] + s[i] * col[i + 1];
+      col[i + 1] = -s[i] * col[i] + c[i] * col[i + 1];
+      col[i] = t;
+    }
+    const double den = hypot(col[j], col[j + 1]);
+    const double cj = den > 0 ? col[j] / den : 1.0, sj = den > 0 ? col[j + 1] / den : 0.0;
+    cs[(long long)g * m + j] = cj;
+    sn[(long long)g * m + j] = sj;
+    col[j] = den;
+    double *gg = gv + (long long)g * (m + 1);
+    const double gj = gg[j];
+    gg[j + 1] = -sj * gj;
+    gg[j] = cj * gj;
+    S.est = fabs(gg[j + 1]);
+    S.j = j + 1;
+    S.total += 1;
+    scale[g] = hn > 0 ? 1.0 / hn : 0.0;
+    if (!(S.est > S.tol) || !(hn > 0) || S.total >= max_iter || S.j >= m || !isfinite(S.est))
+      S.active = 0;
+    st[g] = S;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i <= j; i += 64) R[((long long)g * m + i) * m + j] = col[i];
 }
 
 // V_{j+1} = w * scale[seg] (active segments); with j < 0: V_0 = r / beta for starting ones.
@@ -326,8 +338,9 @@ edfa_status gmres(edfa_system_s &S, edfa_precond_s &P, const double *b, double *
     q.rtol = prm.rtol;
   }
   EDFA_HIP(hipMemcpyAsync(W.st.p, hst.data(), sizeof(SegState) * nseg, hipMemcpyHostToDevice, s));
-  const Csr<double> &A = tr ? S.AT : S.A;
   if (tr && S.AT.rows == 0) csr_transpose(S.A, S.AT, S.tmp, S.tmp2, s);
+  if (tr && S.AT_s.rows == 0) build_sell(S.AT, S.AT_s, S.tmp, s);
+  const Sell<double> &A = tr ? S.AT_s : S.A_s;
 
   Prof prof;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_spmv, ev_apply;
@@ -340,8 +353,7 @@ edfa_status gmres(edfa_system_s &S, edfa_precond_s &P, const double *b, double *
       e0 = prof.get();
       EDFA_HIP(hipEventRecord(e0, s));
     }
-    spmv<double, double>(A.rowptr.p, A.col.p, A.val.p, n, in, out, bb ? -1.0 : 1.0, bb, 1.0,
-                         S.avg_A, s);
+    spmv_sell<double, double>(A, in, out, bb ? -1.0 : 1.0, bb, 1.0, s);
     if (prm.profile) {
       e1 = prof.get();
       EDFA_HIP(hipEventRecord(e1, s));
@@ -391,22 +403,23 @@ edfa_status gmres(edfa_system_s &S, edfa_precond_s &P, const double *b, double *
       double *zj = prm.flexible ? W.Z.p + (size_t)j * n : W.z.p;
       applyP(vj, zj);
       spmvA(zj, W.w.p, nullptr);
-      // CGS2
-      hipLaunchKernelGGL(k_dots, dim3(nch), dim3(RT), 0, s, W.V.p, (long long)n, j + 1, W.w.p,
-                         W.chunks.p, W.st.p, W.part.p, ld);
-      hipLaunchKernelGGL(k_seg_reduce, dim3(nseg), dim3(RT), 0, s, W.part.p, ld, j + 1, W.segptr.p,
-                         W.st.p, 1, W.h1.p, ld);
-      hipLaunchKernelGGL(k_update<false>, dim3(nch), dim3(RT), 0, s, W.V.p, (long long)n, j + 1,
-                         W.w.p, W.chunks.p, W.st.p, W.h1.p, ld, W.part.p, ld);
-      hipLaunchKernelGGL(k_dots, dim3(nch), dim3(RT), 0, s, W.V.p, (long long)n, j + 1, W.w.p,
-                         W.chunks.p, W.st.p, W.part.p, ld);
-      hipLaunchKernelGGL(k_seg_reduce, dim3(nseg), dim3(RT), 0, s, W.part.p, ld, j + 1, W.segptr.p,
-                         W.st.p, 1, W.h2.p, ld);
-      hipLaunchKernelGGL(k_update<true>, dim3(nch), dim3(RT), 0, s, W.V.p, (long long)n, j + 1,
-                         W.w.p, W.chunks.p, W.st.p, W.h2.p, ld, W.part.p, ld);
+      // CGS2: two passes of (dots, reduction, update); the second update also yields ||w||^2
+      for (int pass = 0; pass < 2; ++pass) {
+        double *hp = pass ? W.h2.p : W.h1.p;
+        hipLaunchKernelGGL(k_dots, dim3(nch), dim3(RT), 0, s, W.V.p, (long long)n, j + 1, W.w.p,
+                           W.chunks.p, W.st.p, W.part.p, ld);
+        hipLaunchKernelGGL(k_seg_reduce, dim3(nseg), dim3(RT), 0, s, W.part.p, ld, j + 1,
+                           W.segptr.p, W.st.p, 1, hp, ld);
+        if (pass == 0)
+          hipLaunchKernelGGL(k_update<false>, dim3(nch), dim3(RT), 0, s, W.V.p, (long long)n,
+                             j + 1, W.w.p, W.chunks.p, W.st.p, hp, ld, W.part.p, ld);
+        else
+          hipLaunchKernelGGL(k_update<true>, dim3(nch), dim3(RT), 0, s, W.V.p, (long long)n,
+                             j + 1, W.w.p, W.chunks.p, W.st.p, hp, ld, W.part.p, ld);
+      }
       hipLaunchKernelGGL(k_seg_reduce, dim3(nseg), dim3(RT), 0, s, W.part.p, ld, 1, W.segptr.p,
                          W.st.p, 1, W.nrm.p, ld);
-      hipLaunchKernelGGL(k_givens, dim3(sb), dim3(64), 0, s, nseg, m, j, W.st.p, W.h1.p, W.h2.p,
+      hipLaunchKernelGGL(k_givens, dim3(nseg), dim3(64), 0, s, nseg, m, j, W.st.p, W.h1.p, W.h2.p,
                          W.nrm.p, ld, W.R.p, W.cs.p, W.sn.p, W.g.p, W.scale.p, prm.max_iter);
       hipLaunchKernelGGL(k_scale, dim3(nch), dim3(RT), 0, s, W.w.p, W.V.p + (size_t)(j + 1) * n,
                          W.chunks.p, W.st.p, W.scale.p);

@@ -105,12 +105,17 @@ __global__ void k_transpose_fill(const int *__restrict__ rowptr, const int *__re
   }
 }
 
-// Sort the entries of each row by column (insertion sort; rows are short).
+constexpr int SORT_WAVE_CAP = 1024;
+
+// Sort the entries of each row by column: rows longer than SORT_WAVE_CAP here (insertion
+// sort, one thread per row); shorter rows are sorted by k_sort_rows_wave.
 template <class V>
-__global__ void k_sort_rows(const int *__restrict__ rowptr, int rows, int *col, V *val) {
+__global__ void k_sort_rows(const int *__restrict__ rowptr, int rows, int *col, V *val,
+                            int min_len) {
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= rows) return;
   const int a = rowptr[r], b = rowptr[r + 1];
+  if (b - a < min_len) return;
   for (int i = a + 1; i < b; ++i) {
     int c = col[i];
     V v = val[i];
@@ -125,9 +130,34 @@ __global__ void k_sort_rows(const int *__restrict__ rowptr, int rows, int *col, 
   }
 }
 
+// One wavefront per row (rows up to SORT_WAVE_CAP entries): rank of each entry = number of
+// smaller columns in the row (columns are unique within a row).
+template <class V>
+__global__ __launch_bounds__(64) void k_sort_rows_wave(const int *__restrict__ rowptr, int rows,
+                                                       int *col, V *val) {
+  __shared__ int c[SORT_WAVE_CAP];
+  __shared__ V v[SORT_WAVE_CAP];
+  const int r = blockIdx.x;
+  if (r >= rows) return;
+  const int a = rowptr[r], n = rowptr[r + 1] - a;
+  if (n < 2 || n > SORT_WAVE_CAP) return;
+  for (int t = threadIdx.x; t < n; t += 64) {
+    c[t] = col[a + t];
+    v[t] = val[a + t];
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < n; t += 64) {
+    const int ct = c[t];
+    int rank = 0;
+    for (int u = 0; u < n; ++u) rank += c[u] < ct;
+    col[a + rank] = ct;
+    val[a + rank] = v[t];
+  }
+}
+
 template <class V>
 void csr_transpose(const Csr<V> &src, Csr<V> &dst, DBuf<int> &tmp, DBuf<int> &cursor,
-                   hipStream_t s) {
+                   hipStream_t s, bool sort) {
   dst.alloc(src.cols, src.rows, src.nnz);
   EDFA_HIP(hipMemsetAsync(dst.rowptr.p, 0, sizeof(int) * ((size_t)src.cols + 1), s));
   if (src.nnz > 0) {
@@ -146,18 +176,26 @@ void csr_transpose(const Csr<V> &src, Csr<V> &dst, DBuf<int> &tmp, DBuf<int> &cu
                        dst.val.p);
     EDFA_CHECK_LAUNCH();
   }
-  if (src.cols > 0) {
-    hipLaunchKernelGGL(k_sort_rows<V>, dim3(ceil_div(src.cols, 256)), dim3(256), 0, s,
-                       dst.rowptr.p, src.cols, dst.col.p, dst.val.p);
+  if (src.cols > 0 && sort) {
+    const double avg = src.cols ? (double)src.nnz / src.cols : 0.0;
+    if (avg > 8.0) {
+      hipLaunchKernelGGL(k_sort_rows_wave<V>, dim3(src.cols), dim3(64), 0, s, dst.rowptr.p,
+                         src.cols, dst.col.p, dst.val.p);
+      hipLaunchKernelGGL(k_sort_rows<V>, dim3(ceil_div(src.cols, 256)), dim3(256), 0, s,
+                         dst.rowptr.p, src.cols, dst.col.p, dst.val.p, SORT_WAVE_CAP + 1);
+    } else {
+      hipLaunchKernelGGL(k_sort_rows<V>, dim3(ceil_div(src.cols, 256)), dim3(256), 0, s,
+                         dst.rowptr.p, src.cols, dst.col.p, dst.val.p, 0);
+    }
     EDFA_CHECK_LAUNCH();
   }
 
 }
 
 template void csr_transpose<double>(const Csr<double> &, Csr<double> &, DBuf<int> &, DBuf<int> &,
-                                    hipStream_t);
+                                    hipStream_t, bool);
 template void csr_transpose<float>(const Csr<float> &, Csr<float> &, DBuf<int> &, DBuf<int> &,
-                                   hipStream_t);
+                                   hipStream_t, bool);
 
 // ----------------------------------------------------------------------------------
 // SpMV: a group of LANES lanes per row, shuffle reduction inside the group.
@@ -217,5 +255,111 @@ template void spmv<double, double>(const int *, const int *, const double *, int
                                    double);
 template void spmv<float, float>(const int *, const int *, const float *, int, const float *,
                                  float *, double, const float *, double, float, hipStream_t, double);
+
+}  // namespace edfa
+
+namespace edfa {
+
+// ----------------------------------------------------------------------------------
+// SELL-64
+// ----------------------------------------------------------------------------------
+__global__ void k_sell_width(const int *__restrict__ rowptr, int rows, int nslice, int *w64) {
+  const int sl = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sl >= nslice) return;
+  int w = 0;
+  for (int r = sl * 64; r < min(rows, sl * 64 + 64); ++r) w = max(w, rowptr[r + 1] - rowptr[r]);
+  w64[sl] = w * 64;
+}
+
+template <class V>
+__global__ void k_sell_fill(const int *__restrict__ rowptr, const int *__restrict__ col,
+                            const V *__restrict__ val, int rows, const int *__restrict__ sptr,
+                            int *rlen, int *scol, V *sval) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  const int a = rowptr[r], n = rowptr[r + 1] - a;
+  const int base = sptr[r >> 6] + (r & 63);
+  rlen[r] = n;
+  for (int k = 0; k < n; ++k) {
+    scol[base + 64 * k] = col[a + k];
+    sval[base + 64 * k] = val[a + k];
+  }
+}
+
+template <class V>
+void build_sell(const Csr<V> &M, Sell<V> &S, DBuf<int> &tmp, hipStream_t s) {
+  S.rows = M.rows;
+  S.cols = M.cols;
+  S.nnz = M.nnz;
+  S.nslice = ceil_div(M.rows, 64);
+  S.sptr.ensure((size_t)S.nslice + 1);
+  S.rlen.ensure((size_t)std::max(M.rows, 1));
+  if (S.nslice == 0) {
+    S.padded = 0;
+    return;
+  }
+  hipLaunchKernelGGL(k_sell_width, dim3(ceil_div(S.nslice, 256)), dim3(256), 0, s, M.rowptr.p,
+                     M.rows, S.nslice, S.sptr.p);
+  EDFA_CHECK_LAUNCH();
+  S.padded = exclusive_scan(S.sptr.p, S.sptr.p, S.nslice, tmp, s);
+  S.col.ensure((size_t)std::max<int64_t>(S.padded, 1));
+  S.val.ensure((size_t)std::max<int64_t>(S.padded, 1));
+  hipLaunchKernelGGL(k_sell_fill<V>, dim3(ceil_div(M.rows, 256)), dim3(256), 0, s, M.rowptr.p,
+                     M.col.p, M.val.p, M.rows, S.sptr.p, S.rlen.p, S.col.p, S.val.p);
+  EDFA_CHECK_LAUNCH();
+}
+
+template void build_sell<double>(const Csr<double> &, Sell<double> &, DBuf<int> &, hipStream_t);
+template void build_sell<float>(const Csr<float> &, Sell<float> &, DBuf<int> &, hipStream_t);
+
+// One lane per row, four entries in flight per lane.
+template <class V, class X>
+__global__ __launch_bounds__(256) void k_spmv_sell(const int *__restrict__ sptr,
+                                                   const int *__restrict__ rlen,
+                                                   const int *__restrict__ col,
+                                                   const V *__restrict__ val, int rows,
+                                                   const X *__restrict__ x, X *__restrict__ y,
+                                                   double alpha, const X *__restrict__ b,
+                                                   double beta, double gamma) {
+  using A = typename AccT<V, X>::type;
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  const int n = rlen[r];
+  const int base = sptr[r >> 6] + (r & 63);
+  A s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  int k = 0;
+  for (; k + 4 <= n; k += 4) {
+    const int p = base + 64 * k;
+    const int c0 = col[p], c1 = col[p + 64], c2 = col[p + 128], c3 = col[p + 192];
+    const V v0 = val[p], v1 = val[p + 64], v2 = val[p + 128], v3 = val[p + 192];
+    s0 += (A)v0 * (A)x[c0];
+    s1 += (A)v1 * (A)x[c1];
+    s2 += (A)v2 * (A)x[c2];
+    s3 += (A)v3 * (A)x[c3];
+  }
+  for (; k < n; ++k) {
+    const int p = base + 64 * k;
+    s0 += (A)val[p] * (A)x[col[p]];
+  }
+  A sum = (s0 + s1) + (s2 + s3);
+  A out = (A)alpha * sum;
+  if (b) out += (A)beta * (A)b[r];
+  if (gamma != 0.0) out += (A)gamma * (A)x[r];
+  y[r] = (X)out;
+}
+
+template <class V, class X>
+void spmv_sell(const Sell<V> &M, const X *x, X *y, double alpha, const X *b, double beta,
+               hipStream_t s, double gamma) {
+  if (M.rows <= 0) return;
+  hipLaunchKernelGGL((k_spmv_sell<V, X>), dim3(ceil_div(M.rows, 256)), dim3(256), 0, s, M.sptr.p,
+                     M.rlen.p, M.col.p, M.val.p, M.rows, x, y, alpha, b, beta, gamma);
+  EDFA_CHECK_LAUNCH();
+}
+
+template void spmv_sell<double, double>(const Sell<double> &, const double *, double *, double,
+                                        const double *, double, hipStream_t, double);
+template void spmv_sell<float, float>(const Sell<float> &, const float *, float *, double,
+                                      const float *, double, hipStream_t, double);
 
 }  // namespace edfa

@@ -96,41 +96,60 @@ __global__ void k_merge_write(const int *arp, const int *acol, const double *ava
 // Colouring
 // ---------------------------------------------------------------------------------------
 // Priorities use the cell index local to its grid, so a batch of grids is coloured exactly
-// as each grid alone (neighbours never cross grids).
-__global__ void k_jp_round(const int *__restrict__ srp, const int *__restrict__ scol,
-                           const int *__restrict__ trp, const int *__restrict__ tcol, int ne,
-                           const GridDesc *__restrict__ grids, int ngrid, int *color,
-                           int *ncolored, int *err) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+// as each grid alone (neighbours never cross grids).  One group of JPG lanes per vertex:
+// the group checks JPG neighbour entries at a time (S~ row, then S~^T row) starting where
+// the previous round stopped; an uncoloured higher-priority neighbour blocks the vertex
+// for this round (and becomes the resume point).  A vertex with no blocker takes the
+// smallest colour unused by its neighbours (all coloured ones have higher priority).
+constexpr int JPG = 16;
+__global__ __launch_bounds__(256) void k_jp_round(const int *__restrict__ srp,
+                                                  const int *__restrict__ scol,
+                                                  const int *__restrict__ trp,
+                                                  const int *__restrict__ tcol, int ne,
+                                                  const GridDesc *__restrict__ grids, int ngrid,
+                                                  int *color, int *resume, int *ncolored,
+                                                  int *err) {
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int v = (int)(gid / JPG);
+  const int l = (int)(gid % JPG);
   if (v >= ne) return;
   if (__atomic_load_n(&color[v], __ATOMIC_RELAXED) >= 0) return;
   const int c0 = grids[grid_of(grids, ngrid, v, true)].cell0;
   const unsigned pv = fmix32((unsigned)(v - c0));
-  for (int pass = 0; pass < 2; ++pass) {
-    const int *rp = pass ? trp : srp;
-    const int *cl = pass ? tcol : scol;
-    for (int p = rp[v]; p < rp[v + 1]; ++p) {
-      const int u = cl[p];
-      if (u == v) continue;
-      if (fmix32((unsigned)(u - c0)) > pv && __atomic_load_n(&color[u], __ATOMIC_RELAXED) < 0)
-        return;
+  const int s0 = srp[v], ls = srp[v + 1] - s0, t0 = trp[v], lt = trp[v + 1] - t0;
+  const int tot = ls + lt;
+  const int shift = ((threadIdx.x & 63) / JPG) * JPG;
+  for (int base = resume[v]; base < tot; base += JPG) {
+    const int p = base + l;
+    bool blk = false;
+    if (p < tot) {
+      const int u = p < ls ? scol[s0 + p] : tcol[t0 + p - ls];
+      blk = u != v && fmix32((unsigned)(u - c0)) > pv &&
+            __atomic_load_n(&color[u], __ATOMIC_RELAXED) < 0;
+    }
+    const unsigned gm = (unsigned)((__ballot(blk) >> shift) & ((1ull << JPG) - 1));
+    if (gm) {
+      if (l == 0) resume[v] = base + __ffs(gm) - 1;
+      return;
     }
   }
-  unsigned long long used[MAX_COLORS / 64];
-  for (int w = 0; w < MAX_COLORS / 64; ++w) used[w] = 0;
-  for (int pass = 0; pass < 2; ++pass) {
-    const int *rp = pass ? trp : srp;
-    const int *cl = pass ? tcol : scol;
-    for (int p = rp[v]; p < rp[v + 1]; ++p) {
-      const int u = cl[p];
-      if (u == v) continue;
-      const int cu = __atomic_load_n(&color[u], __ATOMIC_RELAXED);
-      if (cu >= 0) used[cu >> 6] |= 1ull << (cu & 63);
-    }
+  unsigned used[MAX_COLORS / 32];
+#pragma unroll
+  for (int w = 0; w < MAX_COLORS / 32; ++w) used[w] = 0;
+  for (int p = l; p < tot; p += JPG) {
+    const int u = p < ls ? scol[s0 + p] : tcol[t0 + p - ls];
+    if (u == v) continue;
+    const int cu = __atomic_load_n(&color[u], __ATOMIC_RELAXED);
+    if (cu >= 0) used[cu >> 5] |= 1u << (cu & 31);
   }
+#pragma unroll
+  for (int w = 0; w < MAX_COLORS / 32; ++w)
+#pragma unroll
+    for (int o = JPG / 2; o > 0; o >>= 1) used[w] |= __shfl_xor(used[w], o, JPG);
+  if (l != 0) return;
   int c = -1;
-  for (int w = 0; w < MAX_COLORS / 64 && c < 0; ++w)
-    if (~used[w]) c = w * 64 + __ffsll((long long)~used[w]) - 1;
+  for (int w = 0; w < MAX_COLORS / 32 && c < 0; ++w)
+    if (~used[w]) c = w * 32 + __ffs(~used[w]) - 1;
   if (c < 0) {
     atomicMin(err, v);
     c = MAX_COLORS - 1;
@@ -204,35 +223,56 @@ __global__ __launch_bounds__(64) void k_permute_rows(const int *__restrict__ srp
   }
 }
 
-// ILU(0), IKJ form, rows [r0, r1) of one colour
-template <class T>
-__global__ void k_ilu_color(const int *__restrict__ rp, const int *__restrict__ col, T *val,
-                            const int *__restrict__ diag, int r0, int r1, int *err) {
-  const int i = r0 + blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= r1) return;
-  const int b = rp[i + 1], d = diag[i];
-  for (int p = rp[i]; p < d; ++p) {
-    const int k = col[p];
-    const int dk = diag[k];
-    const T lik = val[p] / val[dk];
-    val[p] = lik;
-    int q = dk + 1, r = p + 1;
-    const int qe = rp[k + 1];
-    while (q < qe && r < b) {
-      const int ck = col[q], ci = col[r];
-      if (ck == ci) {
-        val[r] -= lik * val[q];
-        ++q;
-        ++r;
-      } else if (ck < ci) {
-        ++q;
-      } else {
-        ++r;
-      }
-    }
+__device__ inline int bsearch_range(const int *a, int lo, int hi, int key) {
+  hi -= 1;
+  while (lo <= hi) {
+    const int mid = (lo + hi) >> 1;
+    const int v = a[mid];
+    if (v == key) return mid;
+    if (v < key)
+      lo = mid + 1;
+    else
+      hi = mid - 1;
   }
-  const T piv = val[d];
-  if (!(piv != T(0)) || !isfinite((double)piv)) atomicMin(err, i);
+  return -1;
+}
+
+// ILU(0), IKJ form, rows [r0, r1) of one colour; one wavefront per row.  The row lives in
+// LDS; for each pivot column k (ascending) the lanes stream the U part of row k and update
+// the matching entries of the row (found by binary search), so row i's updates keep the
+// IKJ order exactly.
+template <class T>
+__global__ __launch_bounds__(64) void k_ilu_color(const int *__restrict__ rp,
+                                                  const int *__restrict__ col, T *val,
+                                                  const int *__restrict__ diag, int r0, int r1,
+                                                  int *err) {
+  __shared__ int ci[HMAX + 64];
+  __shared__ T vi[HMAX + 64];
+  const int i = r0 + blockIdx.x;
+  if (i >= r1) return;
+  const int a = rp[i], n = rp[i + 1] - a, d = diag[i] - a;
+  for (int t = threadIdx.x; t < n; t += 64) {
+    ci[t] = col[a + t];
+    vi[t] = val[a + t];
+  }
+  __syncthreads();
+  for (int p = 0; p < d; ++p) {
+    const int k = ci[p];
+    const int dk = diag[k];
+    const T lik = vi[p] / val[dk];
+    for (int q = dk + 1 + threadIdx.x; q < rp[k + 1]; q += 64) {
+      const int pos = bsearch_range(ci, p + 1, n, col[q]);
+      if (pos >= 0) vi[pos] -= lik * val[q];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) vi[p] = lik;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < n; t += 64) val[a + t] = vi[t];
+  if (threadIdx.x == 0) {
+    const T piv = vi[d];
+    if (!(piv != T(0)) || !isfinite((double)piv)) atomicMin(err, i);
+  }
 }
 
 __global__ void k_check_diag(const int *__restrict__ diag, int n, int *err) {
@@ -389,23 +429,28 @@ static void stage2_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
   EDFA_CHECK_LAUNCH();
   const int smaxrow = read_scalar(P.flags.p + 2, s);
   if (smaxrow > HMAX + 64) fail(EDFA_ERR_CAPACITY, "a row of S~ has %d > %d entries", smaxrow, HMAX + 64);
-  csr_transpose(D.S, D.ST, S.tmp, S.tmp2, s);
+  csr_transpose(D.S, D.ST, S.tmp, S.tmp2, s, false);   // pattern only (colouring)
 
   // colouring
   D.color.ensure(ne);
   EDFA_HIP(hipMemsetAsync(D.color.p, 0xff, sizeof(int) * ne, s));
   EDFA_HIP(hipMemsetAsync(P.flags.p + 2, 0, sizeof(int), s));
+  D.resume.ensure(ne);
+  EDFA_HIP(hipMemsetAsync(D.resume.p, 0, sizeof(int) * (size_t)ne, s));
   int rounds = 0;
   while (true) {
-    for (int r = 0; r < 4; ++r)
-      hipLaunchKernelGGL(k_jp_round, dim3(ceil_div(ne, 256)), dim3(256), 0, s, D.S.rowptr.p,
+    // a round is cheap (one load per vertex still blocked), so check completion rarely
+    const int batch = rounds < 64 ? 16 : 32;
+    for (int r = 0; r < batch; ++r)
+      hipLaunchKernelGGL(k_jp_round, dim3(ceil_div((long long)ne * JPG, 256)), dim3(256), 0, s,
+                         D.S.rowptr.p,
                          D.S.col.p, D.ST.rowptr.p, D.ST.col.p, ne, S.grids.p, S.ngrid, D.color.p,
-                         P.flags.p + 2, P.flags.p + 1);
+                         D.resume.p, P.flags.p + 2, P.flags.p + 1);
     EDFA_CHECK_LAUNCH();
-    rounds += 4;
+    rounds += batch;
     const int done = read_scalar(P.flags.p + 2, s);
     if (done >= ne) break;
-    if (rounds > 4 * ne + 64) fail(EDFA_ERR_BREAKDOWN, "colouring did not finish");
+    if (rounds > 2 * ne + 64) fail(EDFA_ERR_BREAKDOWN, "colouring did not finish");
   }
   if (read_scalar(P.flags.p + 1, s) != 0x7fffffff)
     fail(EDFA_ERR_CAPACITY, "more than %d colours needed", MAX_COLORS);
@@ -466,8 +511,8 @@ static void stage2_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
   for (int c = 0; c < ncol; ++c) {
     const int r0 = D.cstart[c], r1 = D.cstart[c + 1];
     if (r1 > r0)
-      hipLaunchKernelGGL(k_ilu_color<T>, dim3(ceil_div(r1 - r0, 64)), dim3(64), 0, s, D.B.rowptr.p,
-                         D.B.col.p, D.B.val.p, D.diag.p, r0, r1, P.flags.p);
+      hipLaunchKernelGGL(k_ilu_color<T>, dim3(r1 - r0), dim3(64), 0, s, D.B.rowptr.p, D.B.col.p,
+                         D.B.val.p, D.diag.p, r0, r1, P.flags.p);
   }
   EDFA_CHECK_LAUNCH();
   if (read_scalar(P.flags.p, s) != 0x7fffffff)
@@ -509,6 +554,12 @@ static void stage2_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
                          D.U.val.p, ne, D.MU.col.p, D.MU.val.p);
       EDFA_CHECK_LAUNCH();
     }
+  }
+  build_sell(D.L, D.L_s, S.tmp, s);
+  build_sell(D.U, D.U_s, S.tmp, s);
+  if (prm.schur_solver == EDFA_SCHUR_ISAI) {
+    build_sell(D.ML, D.ML_s, S.tmp, s);
+    build_sell(D.MU, D.MU_s, S.tmp, s);
   }
   // transposes are rebuilt lazily for the transposed application
   D.LT.rows = D.UT.rows = D.MLT.rows = D.MUT.rows = 0;

@@ -138,6 +138,8 @@ struct edfa_system_s {
   edfa::Csr<double> AfcT;        // A_pip^T (N_e x Nfu): row m = column m of A_pip
   edfa::Csr<double> AT;          // A^T (built on first use)
   edfa::Csr<double> AcfT;        // A_ppi^T (Nfu x N_e, built on first use)
+  // SELL-64 copies used by the iteration (transposes built on first use)
+  edfa::Sell<double> A_s, AT_s, Acf_s, Afc_s, AfcT_s, AcfT_s;
   edfa::DBuf<double> b;          // N
   edfa::DBuf<int> tmp, tmp2;     // scratch for scans and transposes
   float avg_A = 0, avg_fp = 0, avg_fc = 0, avg_cf = 0, avg_cc = 0;

@@ -15,34 +15,64 @@ namespace edfa {
 constexpr int CHUNK = 2048;   // elements per chunk: 256 threads x 8
 constexpr int RT = 256;
 
-__global__ __launch_bounds__(RT) void k_dots(const double *__restrict__ V, long long ldv, int nv,
-                                             const double *__restrict__ w,
-                                             const Chunk *__restrict__ ch,
-                                             const SegState *__restrict__ st, double *part, int ldp) {
-  __shared__ double red[4][MAXV];
+// Partial dots tiled over (chunk, group of DG vectors): block (c, q) forms V_i . w on chunk c
+// for i in [DG q, DG q + DG); every thread keeps DG x 8 independent loads in flight and the
+// block reduces only DG values.
+constexpr int DG = 4;
+__global__ __launch_bounds__(RT) void k_dots_tiled(const double *__restrict__ V, long long ldv,
+                                                   int nv, const double *__restrict__ w,
+                                                   const Chunk *__restrict__ ch,
+                                                   const SegState *__restrict__ st, double *part,
+                                                   int ldp) {
+  __shared__ double red[4][DG];
   const Chunk c = ch[blockIdx.x];
   if (!st[c.seg].active) return;
-  double wl[8];
-  int idx[8];
+  const int i0 = blockIdx.y * DG;
+  double acc[DG];
+#pragma unroll
+  for (int g = 0; g < DG; ++g) acc[g] = 0.0;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    idx[k] = c.start + threadIdx.x + k * RT;
-    wl[k] = idx[k] < c.end ? w[idx[k]] : 0.0;
+    const int e = c.start + threadIdx.x + k * RT;
+    if (e < c.end) {
+      const double we = w[e];
+#pragma unroll
+      for (int g = 0; g < DG; ++g)
+        if (i0 + g < nv) acc[g] += V[(long long)(i0 + g) * ldv + e] * we;
+    }
   }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int i = 0; i < nv; ++i) {
-    const double *v = V + (long long)i * ldv;
-    double s = 0;
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
-      if (idx[k] < c.end) s += v[idx[k]] * wl[k];
+  for (int g = 0; g < DG; ++g) {
+    double s = acc[g];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if (lane == 0) red[wave][i] = s;
+    if (lane == 0) red[wave][g] = s;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < nv; i += RT)
-    part[(long long)blockIdx.x * ldp + i] = (red[0][i] + red[1][i]) + (red[2][i] + red[3][i]);
+  if (threadIdx.x < DG && i0 + threadIdx.x < nv) {
+    const int g = threadIdx.x;
+    part[(long long)blockIdx.x * ldp + i0 + g] = (red[0][g] + red[1][g]) + (red[2][g] + red[3][g]);
+  }
+}
+
+// Per-segment sums of chunk partials: one wavefront per (segment, component), lanes strided
+// over the segment's chunks, then a fixed shuffle tree (no block barriers).
+__global__ __launch_bounds__(256) void k_seg_reduce_w(const double *__restrict__ part, int ldp,
+                                                      int ncomp, const int *__restrict__ segptr,
+                                                      const SegState *__restrict__ st,
+                                                      int only_active, double *out, int ldo) {
+  const int g = blockIdx.y;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= ncomp) return;
+  if (only_active && !st[g].active) return;
+  const int c0 = segptr[g], c1 = segptr[g + 1];
+  double s = 0;
+  for (int c = c0 + lane; c < c1; c += 64) s += part[(long long)c * ldp + i];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if (lane == 0) out[(long long)g * ldo + i] = s;
 }
 
 // w -= sum_i h[seg][i] V_i ; optionally partial ||w||^2
@@ -95,28 +125,6 @@ __global__ __launch_bounds__(RT) void k_nrm2_part(const double *__restrict__ x,
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
   if (threadIdx.x == 0) part[(long long)blockIdx.x * ldp] = (red[0] + red[1]) + (red[2] + red[3]);
-}
-
-// out[seg * ldo + i] = sum over the segment's chunks of part[chunk * ldp + i], i < ncomp.
-// only_active: skip inactive segments.
-__global__ __launch_bounds__(RT) void k_seg_reduce(const double *__restrict__ part, int ldp, int ncomp,
-                                                   const int *__restrict__ segptr,
-                                                   const SegState *__restrict__ st, int only_active,
-                                                   double *out, int ldo) {
-  __shared__ double red[4];
-  const int g = blockIdx.x;
-  if (only_active && !st[g].active) return;
-  const int c0 = segptr[g], c1 = segptr[g + 1];
-  for (int i = 0; i < ncomp; ++i) {
-    double s = 0;
-    for (int c = c0 + threadIdx.x; c < c1; c += RT) s += part[(long long)c * ldp + i];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) out[(long long)g * ldo + i] = (red[0] + red[1]) + (red[2] + red[3]);
-    __syncthreads();
-  }
 }
 
 // One wavefront per segment: lanes load the column and the rotations into LDS, lane 0
@@ -375,8 +383,8 @@ edfa_status gmres(edfa_system_s &S, edfa_precond_s &P, const double *b, double *
   };
   auto seg_norms = [&](const double *v, double *out) {
     hipLaunchKernelGGL(k_nrm2_part, dim3(nch), dim3(RT), 0, s, v, W.chunks.p, W.part.p, ld);
-    hipLaunchKernelGGL(k_seg_reduce, dim3(nseg), dim3(RT), 0, s, W.part.p, ld, 1, W.segptr.p,
-                       W.st.p, 0, out, ld);
+    hipLaunchKernelGGL(k_seg_reduce_w, dim3(1, nseg), dim3(256), 0, s, W.part.p, ld, 1,
+                       W.segptr.p, W.st.p, 0, out, ld);
     EDFA_CHECK_LAUNCH();
   };
   const int sb = ceil_div(nseg, 64);
@@ -406,10 +414,10 @@ edfa_status gmres(edfa_system_s &S, edfa_precond_s &P, const double *b, double *
       // CGS2: two passes of (dots, reduction, update); the second update also yields ||w||^2
       for (int pass = 0; pass < 2; ++pass) {
         double *hp = pass ? W.h2.p : W.h1.p;
-        hipLaunchKernelGGL(k_dots, dim3(nch), dim3(RT), 0, s, W.V.p, (long long)n, j + 1, W.w.p,
-                           W.chunks.p, W.st.p, W.part.p, ld);
-        hipLaunchKernelGGL(k_seg_reduce, dim3(nseg), dim3(RT), 0, s, W.part.p, ld, j + 1,
-                           W.segptr.p, W.st.p, 1, hp, ld);
+        hipLaunchKernelGGL(k_dots_tiled, dim3(nch, ceil_div(j + 1, DG)), dim3(RT), 0, s, W.V.p,
+                           (long long)n, j + 1, W.w.p, W.chunks.p, W.st.p, W.part.p, ld);
+        hipLaunchKernelGGL(k_seg_reduce_w, dim3(ceil_div(j + 1, 4), nseg), dim3(256), 0, s,
+                           W.part.p, ld, j + 1, W.segptr.p, W.st.p, 1, hp, ld);
         if (pass == 0)
           hipLaunchKernelGGL(k_update<false>, dim3(nch), dim3(RT), 0, s, W.V.p, (long long)n,
                              j + 1, W.w.p, W.chunks.p, W.st.p, hp, ld, W.part.p, ld);
@@ -417,8 +425,8 @@ edfa_status gmres(edfa_system_s &S, edfa_precond_s &P, const double *b, double *
           hipLaunchKernelGGL(k_update<true>, dim3(nch), dim3(RT), 0, s, W.V.p, (long long)n,
                              j + 1, W.w.p, W.chunks.p, W.st.p, hp, ld, W.part.p, ld);
       }
-      hipLaunchKernelGGL(k_seg_reduce, dim3(nseg), dim3(RT), 0, s, W.part.p, ld, 1, W.segptr.p,
-                         W.st.p, 1, W.nrm.p, ld);
+      hipLaunchKernelGGL(k_seg_reduce_w, dim3(1, nseg), dim3(256), 0, s, W.part.p, ld, 1,
+                         W.segptr.p, W.st.p, 1, W.nrm.p, ld);
       hipLaunchKernelGGL(k_givens, dim3(nseg), dim3(64), 0, s, nseg, m, j, W.st.p, W.h1.p, W.h2.p,
                          W.nrm.p, ld, W.R.p, W.cs.p, W.sn.p, W.g.p, W.scale.p, prm.max_iter);
       hipLaunchKernelGGL(k_scale, dim3(nch), dim3(RT), 0, s, W.w.p, W.V.p + (size_t)(j + 1) * n,

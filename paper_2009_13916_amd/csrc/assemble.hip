@@ -520,6 +520,11 @@ void assemble_system(edfa_system_s &S, const edfa_problem *probs, int count, hip
   S.axis = fl[0];
 
   // faces and unknown numbering
+  // the boundary values outlive the call (the adjoint gradient reads them)
+  S.bcv.ensure(nf);
+  for (int g = 0; g < count; ++g)
+    EDFA_HIP(hipMemcpyAsync(S.bcv.p + S.grids_h[g].face0, probs[g].bc_value,
+                            sizeof(double) * S.grids_h[g].nface, hipMemcpyDeviceToDevice, s));
   S.kind.ensure(nf);
   S.uidx.ensure((size_t)nf + 1);
   hipLaunchKernelGGL(k_face_kind, dim3(ceil_div(nf, 256)), dim3(256), 0, s, S.grids.p, count,

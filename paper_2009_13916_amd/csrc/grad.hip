@@ -15,8 +15,9 @@ namespace edfa {
 
 __global__ void k_grad_logk(const GridDesc *__restrict__ grids, int ngrid, int ne, int nfu,
                             const double *__restrict__ W, const int8_t *__restrict__ kind,
-                            const int *__restrict__ uidx, const double *__restrict__ u,
-                            const double *__restrict__ lam, double *g) {
+                            const int *__restrict__ uidx, const double *__restrict__ bcv,
+                            const double *__restrict__ u, const double *__restrict__ lam,
+                            double *g) {
   const int E = blockIdx.x * blockDim.x + threadIdx.x;
   if (E >= ne) return;
   const GridDesc &G = grids[grid_of(grids, ngrid, E, true)];
@@ -29,7 +30,7 @@ __global__ void k_grad_logk(const GridDesc *__restrict__ grids, int ngrid, int n
   for (int a = 0; a < 6; ++a) {
     fc[a] = cell_face(G, i, j, k, a);
     const int ui = uidx[fc[a]];
-    pi[a] = ui >= 0 ? u[ui] : G.bc_value[fc[a] - G.face0];
+    pi[a] = ui >= 0 ? u[ui] : bcv[fc[a]];
   }
   double acc = 0.0;
   for (int a = 0; a < 6; ++a) {
@@ -53,7 +54,7 @@ __global__ void k_grad_logk(const GridDesc *__restrict__ grids, int ngrid, int n
         else lamE += We[6 * a + b] * pE;
         const int fb = cell_face(G, ni, nj, nk, b);
         const int ub = uidx[fb];
-        const double pib = ub >= 0 ? u[ub] : G.bc_value[fb - G.face0];
+        const double pib = ub >= 0 ? u[ub] : bcv[fb];
         if (b != ap) lamN += Wn[6 * ap + b] * (pn - pib);
         else lamN += Wn[6 * ap + b] * pn;
       }
@@ -68,7 +69,7 @@ __global__ void k_grad_logk(const GridDesc *__restrict__ grids, int ngrid, int n
 void grad_logk(edfa_system_s &S, const double *u, const double *lam, double *g, hipStream_t s) {
   if (S.ne == 0) return;
   hipLaunchKernelGGL(k_grad_logk, dim3(ceil_div(S.ne, 128)), dim3(128), 0, s, S.grids.p, S.ngrid,
-                     S.ne, S.nfu, S.W.p, S.kind.p, S.uidx.p, u, lam, g);
+                     S.ne, S.nfu, S.W.p, S.kind.p, S.uidx.p, S.bcv.p, u, lam, g);
   EDFA_CHECK_LAUNCH();
 }
 

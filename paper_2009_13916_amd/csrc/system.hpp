@@ -124,6 +124,7 @@ struct edfa_system_s {
   edfa::DBuf<double> vol;        // Ne
   edfa::DBuf<double> cstore;     // Ne storage coefficient
   edfa::DBuf<double> p_prev;     // Ne
+  edfa::DBuf<double> bcv;        // Nf boundary values, copied from the inputs at assembly
   edfa::DBuf<double> diag0;      // Ne: A_pp diagonal without the storage term
   edfa::DBuf<double> rhs0;       // Ne: f_p without the storage term
   edfa::DBuf<int> diag_pos_A;    // Ne: position of (cell, cell) in A.val

@@ -95,6 +95,51 @@ print(json.dumps({"setup": t2 - t0, "solve": t4 - t3, "iters": r.iterations, "n"
                        f"unknown to 64^3 at the GPU iteration count ({iters_gpu})")}
 
 
+COPY_BYTES = 1 << 30   # bytes read (and written) by the calibration copy
+
+
+def probe_spmv(torch, S, b):
+    """Launches counted by the FETCH_SIZE / WRITE_SIZE passes: 20 products with the
+    system matrix, then one device copy of COPY_BYTES (reads and writes COPY_BYTES)."""
+    for _ in range(20):
+        S.spmv(b)
+    src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    nnz, N = S.info["nnz"], S.info["n"]
+    print(json.dumps({"probe": "spmv", "launches": 20, "spmv_bytes": spmv_bytes(nnz, N),
+                      "copy_bytes": COPY_BYTES, "kernel_sha": spmv_kernel_sha()}), flush=True)
+
+
+def spmv_kernel_sha():
+    """SHA-256 of the source of the SELL SpMV kernel and its launcher: a traffic figure
+    measured on another version of the kernel is not reported."""
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_2009_13916_amd", "csrc", "sparse.hip")).read()
+    a = src.index("void k_spmv_sell(")
+    e = src.index("template void spmv_sell<double, double>")
+    return hashlib.sha256(src[a:e].encode()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per system-SpMV launch from the committed PMC summary, or None when it
+    is absent or was taken on another version of the kernel."""
+    path = os.path.join(ROOT, "profiles", "spmv_sell_operator_full_tensor_64cubed_traffic.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    try:
+        blob = txt[txt.index("```json") + 7:]
+        d = json.loads(blob[:blob.index("```")])
+    except ValueError:
+        return None
+    if d.get("kernel_sha") != spmv_kernel_sha():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,6 +148,9 @@ def main():
     ap.add_argument("--n", type=int, default=64, help="grid side (64 = the benchmark workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--probe", choices=["spmv"], default=None,
+                    help="run only the launches that the PMC traffic passes count: 20 system "
+                         "SpMVs and one plain copy of known size")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is "
@@ -118,12 +166,16 @@ def main():
     S = edfa.System(prob)
     b = S.rhs()
     torch.cuda.synchronize()
+    if args.probe == "spmv":
+        probe_spmv(torch, S, b)
+        return
     nnz, N, ne = S.info["nnz"], S.info["n"], S.info["ne"]
     log(f"assembled: N={N} nnz={nnz}")
     prm = edfa.Params("dynamic", n_add=1, n_ent=6, tau=1e-3, filt="post_H")
     t64, infos, pinfos, x = run_form(edfa, S, b, prm, args.steps, args.warmup, flexible=False)
     info, st = infos[-1]
     log(f"fp64: {t64:.4f} s/step, {info['iterations']} iterations, relres {info['relres_true']:.2e}")
+    log("preconditioner: " + ", ".join(f"{k} {v}" for k, v in pinfos[-1].items()))
     forms = {"fp64": {"s_per_step": t64, "iterations": info["iterations"],
                       "relres_true": info["relres_true"], "converged": st == 0,
                       "stage1_ms": pinfos[-1]["t_stage1_ms"], "stage2_ms": pinfos[-1]["t_stage2_ms"],
@@ -152,9 +204,10 @@ def main():
                    "krylov": "GMRES(50), x0 = 0", "rtol": 1e-8},
         "iterations": info["iterations"], "relres_true": info["relres_true"],
         "forms": forms,
-        "roofline": {"bound": "hbm", "kernel": "CSR SpMV with A (k_spmv<double,double,16>)",
+        "roofline": {"bound": "hbm",
+                     "kernel": "k_spmv_sell<double, double, 0>: SELL-64 SpMV with the system matrix",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "bytes_per_launch": ab, "avg_launch_ms": spmv_ms,
                      "launches": info["spmv_count"]},
     }

@@ -140,12 +140,10 @@ edfa_status edfa_spmv(edfa_system sys, int32_t transpose, const double *x, doubl
     if (!sys || !x || !y) fail(EDFA_ERR_ARG, "NULL argument");
     if (transpose) {
       ensure_transposes(*sys, stream);
-      spmv<double, double>(sys->AT.rowptr.p, sys->AT.col.p, sys->AT.val.p, sys->n, x, y, 1.0,
-                           nullptr, 0.0, sys->avg_A, stream);
-    } else {
-      spmv<double, double>(sys->A.rowptr.p, sys->A.col.p, sys->A.val.p, sys->n, x, y, 1.0,
-                           nullptr, 0.0, sys->avg_A, stream);
+      if (sys->AT_s.rows == 0) build_sell(sys->AT, sys->AT_s, sys->tmp, stream);
     }
+    spmv_sell<double, double>(transpose ? sys->AT_s : sys->A_s, x, y, 1.0, nullptr, 0.0, stream,
+                              0.0, SPMV_OPERATOR);
     return EDFA_OK;
   });
 }

@@ -90,6 +90,11 @@ struct Sell {
   DBuf<int> rlen;   // rows
   DBuf<int> col;
   DBuf<V> val;
+  // Kernel choice: lanes <= 1 runs the SELL kernel; lanes = 2..32 runs the CSR kernel with
+  // that many lanes per row on the source CSR arrays (which must outlive this copy).
+  int lanes = 0;
+  const int *csr_rp = nullptr, *csr_col = nullptr;
+  const V *csr_val = nullptr;
 };
 
 inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
@@ -152,9 +157,13 @@ void spmv(const int *rowptr, const int *col, const V *val, int rows, const X *x,
 template <class V>
 void build_sell(const Csr<V> &M, Sell<V> &S, DBuf<int> &tmp, hipStream_t s);
 
-// Same contract as spmv() for a SELL-64 matrix.
+// Same contract as spmv() for a SELL-64 matrix.  `role` picks the kernel symbol:
+// SPMV_OPERATOR for products with the system matrix, SPMV_PRECOND for everything else.
+// Non-null events e0/e1 are recorded by the launch itself around the kernel.
+enum { SPMV_OPERATOR = 0, SPMV_PRECOND = 1 };
 template <class V, class X>
 void spmv_sell(const Sell<V> &M, const X *x, X *y, double alpha, const X *b, double beta,
-               hipStream_t s, double gamma = 0.0);
+               hipStream_t s, double gamma = 0.0, int role = SPMV_PRECOND,
+               hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
 }  // namespace edfa

@@ -56,7 +56,8 @@ struct Chunk {
 };
 struct SegState {
   double rtol, bnorm, tol, beta, est, relres;
-  int active, done, converged, j, total, pad;
+  int active, done, converged, j, total;
+  int reorth;   // this iteration's Gram-Schmidt needs its second pass
 };
 struct SolveWork {
   int nchunk = 0, n = 0;

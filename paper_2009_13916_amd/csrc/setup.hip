@@ -1,15 +1,18 @@
 // EDFA stage 1 (the paper's Algorithm 1) on the device.
 //
 //  * k_base / k_patch   initial pattern Q_0 of every cell (row of A_ppi, or a k-ring patch)
-//  * k_local            one wavefront per cell: restricted SPD matrix -A_pipi^(m) gathered
-//                       into LDS (packed lower), right-looking Cholesky, solves for g~ and
-//                       f~ (eqs. syst_MRHS_res, syst_MRHS_res-F); dynamic variant grows Q
-//                       from the prolonged residual (eq. prol_res) and extends the factor by
-//                       bordering instead of refactoring
+//  * k_local_reg        one wavefront per cell: restricted SPD matrix -A_pipi^(m) gathered
+//                       into LDS, Cholesky factor held one row per lane in registers,
+//                       solves for g~ and f~ (eqs. syst_MRHS_res, syst_MRHS_res-F); the
+//                       dynamic variant grows Q from the prolonged residual (eq. prol_res)
+//                       and extends the factor by bordering instead of refactoring
+//  * k_local            the same with the factor in LDS, for patterns longer than 48
 //  * G~, F~^T           compacted (pre-filtration) into CSR
 //  * k_htilde           row m of H~ = (A_pipi R^T g~)^T F~ (eq. sparse_S), one wavefront per
 //                       cell, LDS hash maps, deterministic sums
 //  * k_fsai             factorised sparse approximate inverse of -A_pipi on lower(A_pipi)
+#include <type_traits>
+
 #include "precond.hpp"
 
 namespace edfa {
@@ -417,6 +420,312 @@ __global__ __launch_bounds__(64) void k_local(LocalArgs<T> A) {
 }
 
 // ------------------------------------------------------------------------------------
+// Restricted local solves with the factor held in registers (patterns of at most 48).
+//
+// Lane t owns row t of the Cholesky factor L of -A_pipi^(m) in registers (compile-time
+// indexed), plus its diagonal.  The right-looking factorisation, the forward
+// substitutions and the bordering of appended rows broadcast the pivot row's entry with
+// a lane read, so they run without barriers; the backward substitution reads L from a
+// packed copy in LDS.  Pattern bookkeeping (hash of Q, candidates, residual, selection)
+// is the same as in k_local.
+// ------------------------------------------------------------------------------------
+constexpr int pow2ceil(int x) { return x <= 1 ? 1 : 2 * pow2ceil((x + 1) / 2); }
+
+// f(std::integral_constant<int, i>) for i = B .. E-1: register arrays indexed by i stay in
+// registers (the bodies must be inlined: lambdas passed here are marked EDFA_INLINE).
+#define EDFA_INLINE __attribute__((always_inline))
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F &&f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+// Value of v held by lane `src` (uniform index), for every lane.
+template <class T>
+__device__ inline T lane_value(T v, int src) {
+  if constexpr (sizeof(T) == 8) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+  } else {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+  }
+}
+
+template <class T, int SMAX>
+__global__ __launch_bounds__(64) void k_local_reg(LocalArgs<T> A) {
+  static_assert(SMAX <= 64, "one lane per pattern entry");
+  constexpr int QH = pow2ceil(2 * SMAX < 64 ? 64 : 2 * SMAX);
+  constexpr int CH = pow2ceil(8 * SMAX);
+  constexpr int LP = SMAX * (SMAX + 1) / 2;
+  __shared__ T Lp[LP];
+  __shared__ int q[SMAX];
+  __shared__ int qk[QH], qv[QH];
+  __shared__ T bg[SMAX], bf[SMAX], rowt[SMAX], xs[SMAX];
+  __shared__ int ck[CH], clist[CH];
+  __shared__ T cr[CH];
+  __shared__ int ccount, sflag;
+
+  const int m = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (m >= A.ne) return;
+  int s = A.qlen[m];
+  if (s > SMAX) {
+    if (lane == 0) atomicMin(A.err_cap, m);
+    return;
+  }
+  for (int t = lane; t < SMAX; t += 64) {
+    q[t] = t < s ? A.Q[(size_t)m * SMAX + t] : -1;
+    bg[t] = 0;
+    bf[t] = 0;
+  }
+  for (int h = lane; h < QH; h += 64) qk[h] = -1;
+  if (lane == 0) sflag = 0;
+  __syncthreads();
+  for (int t = lane; t < s; t += 64) {
+    bool fr;
+    const int h = h_insert<QH>(qk, q[t], fr);
+    qv[h] = t;
+  }
+  __syncthreads();
+  // right-hand sides: a_ppi^(m) (row m of A_ppi) and a_pip^(m) (column m of A_pip)
+  for (int p = A.acf_rp[m] + lane; p < A.acf_rp[m + 1]; p += 64) {
+    const int h = h_find<QH>(qk, A.acf_col[p]);
+    if (h >= 0) bg[qv[h]] = (T)A.acf_val[p];
+  }
+  for (int p = A.afcT_rp[m] + lane; p < A.afcT_rp[m + 1]; p += 64) {
+    const int h = h_find<QH>(qk, A.afcT_col[p]);
+    if (h >= 0) bf[qv[h]] = (T)A.afcT_val[p];
+  }
+  // restricted matrix -R A_pipi R^T, lower part in Q order
+  for (int t = lane; t < LP; t += 64) Lp[t] = 0;
+  __syncthreads();
+  if (lane < s) {
+    const int r = q[lane];
+    for (int p = A.app_rp[r]; p < A.app_rp[r + 1]; ++p) {
+      const int h = h_find<QH>(qk, A.app_col[p]);
+      if (h >= 0) {
+        const int k = qv[h];
+        if (k <= lane) Lp[pidx(lane, k)] = -(T)A.app_val[p];
+      }
+    }
+  }
+  __syncthreads();
+
+  // row `lane` into registers and right-looking Cholesky
+  T Lr[SMAX];
+  static_for<0, SMAX>([&](auto K) EDFA_INLINE {
+    constexpr int k = K;
+    Lr[k] = (lane < s && k <= lane) ? Lp[pidx(lane, k)] : T(0);
+  });
+  T dg = 1;
+  bool spd = true;
+  static_for<0, SMAX>([&](auto J) EDFA_INLINE {
+    constexpr int j = J;
+    if (!spd || j >= s) return;
+    const T d = lane_value(Lr[j], j);
+    if (!(d > T(0))) {
+      spd = false;
+      return;
+    }
+    const T ljj = sqrt(d);
+    const T inv = T(1) / ljj;
+    Lr[j] = lane == j ? ljj : Lr[j] * inv;
+    if (lane == j) dg = ljj;
+    static_for<j + 1, SMAX>([&](auto K) EDFA_INLINE {
+      constexpr int k = K;
+      if (k < s) Lr[k] -= Lr[j] * lane_value(Lr[j], k);
+    });
+  });
+  if (!spd) {
+    if (lane == 0) atomicMin(A.err_spd, m);
+    return;
+  }
+  T invd = T(1) / dg;
+  __syncthreads();
+  static_for<0, SMAX>([&](auto K) EDFA_INLINE {
+    constexpr int k = K;
+    if (lane < s && k <= lane) Lp[pidx(lane, k)] = Lr[k];
+  });
+  __syncthreads();
+
+  const int it_max = A.it_max > 0 ? A.it_max : A.n_ent;
+  int n_prog = 0, sweep = 0;
+  bool fin = !A.dynamic;
+  T xg = 0, xf = 0;
+  for (;;) {
+    const bool last = fin || !(n_prog < A.n_ent && sweep < it_max);
+    // forward L y = b (g, and f on the last pass), then backward L^T x = y
+    {
+      T b1 = lane < s ? bg[lane] : T(0);
+      T b2 = (last && lane < s) ? bf[lane] : T(0);
+      T y1 = 0, y2 = 0;
+      static_for<0, SMAX>([&](auto K) EDFA_INLINE {
+        constexpr int k = K;
+        if (k >= s) return;
+        const T ik = lane_value(invd, k);
+        const T a1 = lane_value(b1, k) * ik;
+        const T a2 = lane_value(b2, k) * ik;
+        b1 -= Lr[k] * a1;
+        b2 -= Lr[k] * a2;
+        if (lane == k) {
+          y1 = a1;
+          y2 = a2;
+        }
+      });
+      T x1 = 0, x2 = 0;
+      for (int k = s - 1; k >= 0; --k) {   // uniform k: lane reads and LDS only
+        const T ik = lane_value(invd, k);
+        const T c1 = lane_value(y1, k) * ik;
+        const T c2 = lane_value(y2, k) * ik;
+        const T l = lane < k ? Lp[pidx(k, lane)] : T(0);
+        y1 -= l * c1;
+        y2 -= l * c2;
+        if (lane == k) {
+          x1 = c1;
+          x2 = c2;
+        }
+      }
+      xg = x1;
+      if (last) xf = x2;
+    }
+    if (last) break;
+    ++sweep;
+    const int n = min(A.n_add, A.n_ent - n_prog);
+    if (lane < s) xs[lane] = xg;
+    // candidate set: A_pipi neighbours of Q outside Q (support of the prolonged residual)
+    for (int h = lane; h < CH; h += 64) ck[h] = -1;
+    if (lane == 0) ccount = 0;
+    __syncthreads();
+    if (lane < s) {
+      const int r = q[lane];
+      for (int p = A.app_rp[r]; p < A.app_rp[r + 1]; ++p) {
+        const int c = A.app_col[p];
+        if (h_find<QH>(qk, c) < 0) {
+          bool fr;
+          if (h_insert<CH>(ck, c, fr) < 0) sflag = 1;
+        }
+      }
+    }
+    __syncthreads();
+    if (sflag) {
+      if (lane == 0) atomicMin(A.err_cap, m);
+      return;
+    }
+    for (int h = lane; h < CH; h += 64)
+      if (ck[h] >= 0) clist[atomicAdd(&ccount, 1)] = ck[h];
+    __syncthreads();
+    const int nc = ccount;
+    // r_j = (A_pipi R^T g~)_j for j outside Q (a_ppi^(m) vanishes there)
+    for (int c = lane; c < nc; c += 64) {
+      const int j = clist[c];
+      T acc = 0;
+      for (int p = A.app_rp[j]; p < A.app_rp[j + 1]; ++p) {
+        const int h = h_find<QH>(qk, A.app_col[p]);
+        if (h >= 0) acc += (T)A.app_val[p] * xs[qv[h]];
+      }
+      cr[c] = acc;
+    }
+    __syncthreads();
+    int added = 0;
+    for (int rnd = 0; rnd < n; ++rnd) {
+      unsigned long long bk = 0;
+      int bj = 0x7fffffff, bc = -1;
+      for (int c = lane; c < nc; c += 64) {
+        const unsigned long long k = key40((double)cr[c]);
+        const int j = clist[c];
+        if (k > bk || (k == bk && k != 0 && j < bj)) {
+          bk = k;
+          bj = j;
+          bc = c;
+        }
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const unsigned lo = __shfl_xor((unsigned)(bk & 0xffffffffull), o);
+        const unsigned hi = __shfl_xor((unsigned)(bk >> 32), o);
+        const unsigned long long ok = ((unsigned long long)hi << 32) | lo;
+        const int oj = __shfl_xor(bj, o);
+        const int oc = __shfl_xor(bc, o);
+        if (ok > bk || (ok == bk && oj < bj)) {
+          bk = ok;
+          bj = oj;
+          bc = oc;
+        }
+      }
+      if (bk == 0) break;   // uniform: every lane holds the reduced value
+      if (s >= SMAX) {
+        if (lane == 0) atomicMin(A.err_cap, m);
+        return;
+      }
+      const int t = s;
+      if (lane == 0) {
+        cr[bc] = 0;
+        q[t] = bj;
+        bool fr;
+        const int h = h_insert<QH>(qk, bj, fr);
+        qv[h] = t;
+      }
+      if (lane <= t) rowt[lane] = 0;
+      __syncthreads();
+      // bordering: column of -A_pipi[Q, j] and its diagonal, L l = a, l_tt^2 = a_tt - l.l
+      for (int p = A.app_rp[bj] + lane; p < A.app_rp[bj + 1]; p += 64) {
+        const int h = h_find<QH>(qk, A.app_col[p]);
+        if (h >= 0) rowt[qv[h]] = -(T)A.app_val[p];
+      }
+      __syncthreads();
+      T a = lane <= t ? rowt[lane] : T(0);
+      const T att = lane_value(a, t);
+      T dsum = 0;
+      static_for<0, SMAX>([&](auto K) EDFA_INLINE {
+        constexpr int k = K;
+        if (k >= t) return;
+        const T lk = lane_value(a, k) * lane_value(invd, k);
+        a -= Lr[k] * lk;
+        Lr[k] = lane == t ? lk : Lr[k];   // a select, not a store to Lr[t]
+        if (lane == 0) Lp[pidx(t, k)] = lk;
+        dsum += lk * lk;
+      });
+      const T d = att - dsum;
+      if (!(d > T(0))) {
+        if (lane == 0) atomicMin(A.err_spd, m);
+        return;
+      }
+      const T ltt = sqrt(d);
+      static_for<0, SMAX>([&](auto K) EDFA_INLINE {
+        constexpr int k = K;
+        Lr[k] = (k == t && lane == t) ? ltt : Lr[k];
+      });
+      if (lane == t) {
+        dg = ltt;
+        invd = T(1) / ltt;
+      }
+      if (lane == 0) {
+        Lp[pidx(t, t)] = ltt;
+        bg[t] = 0;
+        bf[t] = 0;
+      }
+      __syncthreads();
+      ++s;
+      ++added;
+    }
+    if (added == 0)
+      fin = true;
+    else
+      n_prog += added;
+  }
+  if (lane < s) {
+    A.Q[(size_t)m * SMAX + lane] = q[lane];
+    A.gout[(size_t)m * SMAX + lane] = xg;
+    A.fout[(size_t)m * SMAX + lane] = xf;
+  }
+  if (lane == 0) A.qlen[m] = s;
+}
+
+// ------------------------------------------------------------------------------------
 // G~ and F~^T as CSR (sorted columns), with optional pre-filtration
 // ------------------------------------------------------------------------------------
 template <class T>
@@ -758,6 +1067,13 @@ static void reset_flags(edfa_precond_s &P, hipStream_t s) {
   EDFA_HIP(hipMemcpyAsync(P.flags.p, init, sizeof(init), hipMemcpyHostToDevice, s));
 }
 
+// Compiled pattern capacities: the smallest that holds `need` entries, 0 if none does.
+static int pattern_stride(int need) {
+  for (int c : {16, 32, 48, 64, 128})
+    if (need <= c) return c;
+  return 0;
+}
+
 template <class T>
 static void stage1_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
   edfa_system_s &S = *P.sys;
@@ -775,7 +1091,7 @@ static void stage1_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
   const bool dynamic = prm.variant == EDFA_DYNAMIC;
   int need = maxbase;
   if (dynamic) need = maxbase + std::max(0, prm.n_ent);
-  int smax = need <= 16 ? 16 : need <= 32 ? 32 : need <= 64 ? 64 : need <= 128 ? 128 : 0;
+  int smax = pattern_stride(need);
   if (!smax && (dynamic || prm.static_level == 0))
     fail(EDFA_ERR_CAPACITY, "patterns of up to %d entries exceed 128", need);
   D.qlen.ensure(ne);
@@ -794,7 +1110,7 @@ static void stage1_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
                        P.flags.p + 2);
     EDFA_CHECK_LAUNCH();
     need = read_scalar(P.flags.p + 2, s);
-    smax = need <= 16 ? 16 : need <= 32 ? 32 : need <= 64 ? 64 : need <= 128 ? 128 : 0;
+    smax = pattern_stride(need);
     if (!smax) fail(EDFA_ERR_CAPACITY, "static patches of %d entries exceed 128", need);
     D.Q.ensure((size_t)ne * smax);
     hipLaunchKernelGGL(k_repack, dim3(ceil_div(ne, 256)), dim3(256), 0, s, D.wide.p, D.qlen.p, ne,
@@ -836,8 +1152,9 @@ static void stage1_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
   }
   if (ne > 0) {
     switch (smax) {
-      case 16: hipLaunchKernelGGL((k_local<T, 16>), dim3(ne), dim3(64), 0, s, la); break;
-      case 32: hipLaunchKernelGGL((k_local<T, 32>), dim3(ne), dim3(64), 0, s, la); break;
+      case 16: hipLaunchKernelGGL((k_local_reg<T, 16>), dim3(ne), dim3(64), 0, s, la); break;
+      case 32: hipLaunchKernelGGL((k_local_reg<T, 32>), dim3(ne), dim3(64), 0, s, la); break;
+      case 48: hipLaunchKernelGGL((k_local_reg<T, 48>), dim3(ne), dim3(64), 0, s, la); break;
       case 64: hipLaunchKernelGGL((k_local<T, 64>), dim3(ne), dim3(64), 0, s, la); break;
       case 128: hipLaunchKernelGGL((k_local<T, 128>), dim3(ne), dim3(64), 0, s, la); break;
       default: fail(EDFA_ERR_CAPACITY, "static patterns longer than 128 are not supported");

@@ -1,4 +1,5 @@
 // Primitive device algorithms: prefix sums, CSR transpose, CSR SpMV.
+#include <hip/hip_ext.h>
 #include "common.hpp"
 
 namespace edfa {
@@ -286,11 +287,20 @@ __global__ void k_sell_fill(const int *__restrict__ rowptr, const int *__restric
   }
 }
 
+// Lanes per row for a matrix with the given mean row length: one lane per row (SELL) for
+// short rows, a CSR group of lanes for long ones.
+constexpr double SPMV_VEC_MIN_ROW = 24.0;
+int default_spmv_lanes(double mean_row) { return mean_row < SPMV_VEC_MIN_ROW ? 0 : 8; }
+
 template <class V>
 void build_sell(const Csr<V> &M, Sell<V> &S, DBuf<int> &tmp, hipStream_t s) {
   S.rows = M.rows;
   S.cols = M.cols;
   S.nnz = M.nnz;
+  S.csr_rp = M.rowptr.p;
+  S.csr_col = M.col.p;
+  S.csr_val = M.val.p;
+  S.lanes = M.rows > 0 ? default_spmv_lanes((double)M.nnz / M.rows) : 0;
   S.nslice = ceil_div(M.rows, 64);
   S.sptr.ensure((size_t)S.nslice + 1);
   S.rlen.ensure((size_t)std::max(M.rows, 1));
@@ -312,17 +322,20 @@ void build_sell(const Csr<V> &M, Sell<V> &S, DBuf<int> &tmp, hipStream_t s) {
 template void build_sell<double>(const Csr<double> &, Sell<double> &, DBuf<int> &, hipStream_t);
 template void build_sell<float>(const Csr<float> &, Sell<float> &, DBuf<int> &, hipStream_t);
 
-// One lane per row, four entries in flight per lane.
-template <class V, class X>
-__global__ __launch_bounds__(256) void k_spmv_sell(const int *__restrict__ sptr,
-                                                   const int *__restrict__ rlen,
-                                                   const int *__restrict__ col,
-                                                   const V *__restrict__ val, int rows,
-                                                   const X *__restrict__ x, X *__restrict__ y,
-                                                   double alpha, const X *__restrict__ b,
-                                                   double beta, double gamma) {
+// One lane per row, four entries in flight per lane.  ROLE only separates the
+// system-operator launches (0) from the preconditioner's (1) in kernel traces.
+constexpr int SPMV_T = 256;
+
+template <class V, class X, int ROLE>
+__global__ __launch_bounds__(SPMV_T) void k_spmv_sell(const int *__restrict__ sptr,
+                                                      const int *__restrict__ rlen,
+                                                      const int *__restrict__ col,
+                                                      const V *__restrict__ val, int rows,
+                                                      const X *__restrict__ x, X *__restrict__ y,
+                                                      double alpha, const X *__restrict__ b,
+                                                      double beta, double gamma) {
   using A = typename AccT<V, X>::type;
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.x * SPMV_T + threadIdx.x;
   if (r >= rows) return;
   const int n = rlen[r];
   const int base = sptr[r >> 6] + (r & 63);
@@ -341,25 +354,78 @@ __global__ __launch_bounds__(256) void k_spmv_sell(const int *__restrict__ sptr,
     const int p = base + 64 * k;
     s0 += (A)val[p] * (A)x[col[p]];
   }
-  A sum = (s0 + s1) + (s2 + s3);
-  A out = (A)alpha * sum;
+  A out = (A)alpha * ((s0 + s1) + (s2 + s3));
   if (b) out += (A)beta * (A)b[r];
   if (gamma != 0.0) out += (A)gamma * (A)x[r];
   y[r] = (X)out;
 }
 
+// L lanes per row on the CSR arrays, for matrices with long rows: the lanes of a row read
+// consecutive entries (coalesced) and a shuffle tree sums their partials.
+template <class V, class X, int L>
+__global__ __launch_bounds__(SPMV_T) void k_spmv_csr_vec(const int *__restrict__ rp,
+                                                         const int *__restrict__ col,
+                                                         const V *__restrict__ val, int rows,
+                                                         const X *__restrict__ x, X *__restrict__ y,
+                                                         double alpha, const X *__restrict__ b,
+                                                         double beta, double gamma) {
+  using A = typename AccT<V, X>::type;
+  const int t = blockIdx.x * SPMV_T + threadIdx.x;
+  const int r = t / L, l = t % L;
+  if (r >= rows) return;   // all L lanes of a row leave together
+  const int a = rp[r], e = rp[r + 1];
+  A s0 = 0, s1 = 0;
+  int p = a + l;
+  for (; p + L < e; p += 2 * L) {
+    s0 += (A)val[p] * (A)x[col[p]];
+    s1 += (A)val[p + L] * (A)x[col[p + L]];
+  }
+  if (p < e) s0 += (A)val[p] * (A)x[col[p]];
+  A sum = s0 + s1;
+#pragma unroll
+  for (int o = L / 2; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
+  if (l == 0) {
+    A out = (A)alpha * sum;
+    if (b) out += (A)beta * (A)b[r];
+    if (gamma != 0.0) out += (A)gamma * (A)x[r];
+    y[r] = (X)out;
+  }
+}
+
 template <class V, class X>
 void spmv_sell(const Sell<V> &M, const X *x, X *y, double alpha, const X *b, double beta,
-               hipStream_t s, double gamma) {
+               hipStream_t s, double gamma, int role, hipEvent_t e0, hipEvent_t e1) {
   if (M.rows <= 0) return;
-  hipLaunchKernelGGL((k_spmv_sell<V, X>), dim3(ceil_div(M.rows, 256)), dim3(256), 0, s, M.sptr.p,
-                     M.rlen.p, M.col.p, M.val.p, M.rows, x, y, alpha, b, beta, gamma);
+  if (M.lanes > 1) {
+    const int nb = (int)ceil_div((long long)M.rows * M.lanes, SPMV_T);
+#define EDFA_VEC(LN)                                                                           \
+  hipExtLaunchKernelGGL((k_spmv_csr_vec<V, X, LN>), dim3(nb), dim3(SPMV_T), 0, s, e0, e1, 0,    \
+                        M.csr_rp, M.csr_col, M.csr_val, M.rows, x, y, alpha, b, beta, gamma)
+    switch (M.lanes) {
+      case 2: EDFA_VEC(2); break;
+      case 4: EDFA_VEC(4); break;
+      case 8: EDFA_VEC(8); break;
+      case 16: EDFA_VEC(16); break;
+      default: EDFA_VEC(32); break;
+    }
+#undef EDFA_VEC
+  } else if (role == SPMV_OPERATOR) {
+    hipExtLaunchKernelGGL((k_spmv_sell<V, X, SPMV_OPERATOR>), dim3(ceil_div(M.rows, SPMV_T)),
+                          dim3(SPMV_T), 0, s, e0, e1, 0, M.sptr.p, M.rlen.p, M.col.p, M.val.p,
+                          M.rows, x, y, alpha, b, beta, gamma);
+  } else {
+    hipExtLaunchKernelGGL((k_spmv_sell<V, X, SPMV_PRECOND>), dim3(ceil_div(M.rows, SPMV_T)),
+                          dim3(SPMV_T), 0, s, e0, e1, 0, M.sptr.p, M.rlen.p, M.col.p, M.val.p,
+                          M.rows, x, y, alpha, b, beta, gamma);
+  }
   EDFA_CHECK_LAUNCH();
 }
 
 template void spmv_sell<double, double>(const Sell<double> &, const double *, double *, double,
-                                        const double *, double, hipStream_t, double);
+                                        const double *, double, hipStream_t, double, int,
+                                        hipEvent_t, hipEvent_t);
 template void spmv_sell<float, float>(const Sell<float> &, const float *, float *, double,
-                                      const float *, double, hipStream_t, double);
+                                      const float *, double, hipStream_t, double, int, hipEvent_t,
+                                      hipEvent_t);
 
 }  // namespace edfa

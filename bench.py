@@ -61,6 +61,66 @@ def run_form(edfa, S, b, prm, steps, warmup, flexible):
     return (t1 - t0) / steps, infos, pinfos, x
 
 
+def run_batched(edfa, inputs, steps, warmup):
+    """The 256-grid batch (cube sides U{8..32}, sigma_lnK ~ U[0.5, 3]), EDFA dynamic (1, 4),
+    each grid to a relative residual of 1e-8.  Three forms, each timed as setup + solve:
+    the plain FP64 path grid by grid (one system per grid, one step), one batched FP64
+    system, and the batched FP32-preconditioner FGMRES with graph-captured cycles."""
+    import torch
+    probs = inputs.batch_problems(256, 8, 32)
+    cells = sum(p.n_cells for p in probs)
+    prm64 = edfa.Params("dynamic", n_add=1, n_ent=4)
+    prm32 = edfa.Params("dynamic", n_add=1, n_ent=4, precision=1)
+
+    def timed(S, P, b, flexible, graph, k, w):
+        for _ in range(w):
+            P.resetup()
+            edfa.solve(S, P, b, rtol=1e-8, restart=50, flexible=flexible, use_graph=graph)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            P.resetup()
+            x, info, st = edfa.solve(S, P, b, rtol=1e-8, restart=50, flexible=flexible,
+                                     use_graph=graph)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / k, info, st
+
+    # grid by grid, plain FP64 (systems assembled beforehand; one step after one warm-up)
+    singles = []
+    for p in probs:
+        S1 = edfa.System(p)
+        singles.append((S1, edfa.Precond(S1, prm64), S1.rhs()))
+    for S1, P1, b1 in singles:
+        edfa.solve(S1, P1, b1, rtol=1e-8, restart=50)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    conv_single = 0
+    for S1, P1, b1 in singles:
+        P1.resetup()
+        x1, i1, st1 = edfa.solve(S1, P1, b1, rtol=1e-8, restart=50)
+        conv_single += int(st1 == 0)
+    torch.cuda.synchronize()
+    t_single = time.perf_counter() - t0
+    del singles
+
+    S = edfa.System(probs)
+    b = S.rhs()
+    P64 = edfa.Precond(S, prm64)
+    t64, i64, st64 = timed(S, P64, b, False, False, steps, warmup)
+    del P64
+    P32 = edfa.Precond(S, prm32)
+    t32, i32, st32 = timed(S, P32, b, True, True, steps, warmup)
+    log(f"batch of 256: grid by grid {t_single:.3f} s, batched FP64 {t64:.3f} s, "
+        f"batched mixed + graph {t32:.3f} s")
+    return {"workload": "batch_256_lognormal_iso_8..32", "grids": 256, "cells": cells,
+            "unknowns": S.info["n"],
+            "grid_by_grid_fp64_s": t_single, "grid_by_grid_converged": conv_single,
+            "batched_fp64_s": t64, "batched_fp64_converged": i64["converged"],
+            "batched_fp64_iterations_max": i64["iterations"],
+            "batched_mixed_graph_s": t32, "batched_mixed_graph_converged": i32["converged"],
+            "batched_mixed_graph_iterations_max": i32["iterations"]}
+
+
 def cpu_baseline(iters_gpu, n_full, ne_full):
     """Time the oracle on a bounded sample: the whole oracle pipeline on the 12^3 member
     of the same workload family, scaled to 64^3 (setup per cell, solve per iteration and
@@ -114,12 +174,12 @@ def probe_spmv(torch, S, b):
 
 
 def spmv_kernel_sha():
-    """SHA-256 of the source of the SELL SpMV kernel and its launcher: a traffic figure
-    measured on another version of the kernel is not reported."""
+    """SHA-256 of the source of the SELL SpMV kernel: a traffic figure measured on another
+    version of the kernel is not reported."""
     import hashlib
     src = open(os.path.join(ROOT, "paper_2009_13916_amd", "csrc", "sparse.hip")).read()
     a = src.index("void k_spmv_sell(")
-    e = src.index("template void spmv_sell<double, double>")
+    e = src.index("// L lanes per row on the CSR arrays")
     return hashlib.sha256(src[a:e].encode()).hexdigest()[:16]
 
 
@@ -148,9 +208,12 @@ def main():
     ap.add_argument("--n", type=int, default=64, help="grid side (64 = the benchmark workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--probe", choices=["spmv"], default=None,
-                    help="run only the launches that the PMC traffic passes count: 20 system "
-                         "SpMVs and one plain copy of known size")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 256-grid batch forms")
+    ap.add_argument("--probe", choices=["spmv", "apply"], default=None,
+                    help="run only the launches that PMC passes count: 'spmv' = 20 system "
+                         "SpMVs and one plain copy of known size; 'apply' = setup and 20 "
+                         "preconditioner applications")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is "
@@ -168,6 +231,13 @@ def main():
     torch.cuda.synchronize()
     if args.probe == "spmv":
         probe_spmv(torch, S, b)
+        return
+    if args.probe == "apply":
+        P = edfa.Precond(S, edfa.Params("dynamic", n_add=1, n_ent=6, tau=1e-3, filt="post_H"))
+        for _ in range(20):
+            P.apply(b)
+        torch.cuda.synchronize()
+        print(json.dumps({"probe": "apply", "launches": 20, **P.info()}), flush=True)
         return
     nnz, N, ne = S.info["nnz"], S.info["n"], S.info["ne"]
     log(f"assembled: N={N} nnz={nnz}")
@@ -192,6 +262,8 @@ def main():
             "converged": st32 == 0, "stage1_ms": p32[-1]["t_stage1_ms"],
             "stage2_ms": p32[-1]["t_stage2_ms"], "solve_ms": inf32["t_solve_ms"],
             "pressure_rel_diff_vs_fp64": float(dp)}
+    if not args.no_batched:
+        forms["batch_256"] = run_batched(edfa, inputs, args.steps, args.warmup)
     spmv_ms = info["spmv_avg_ms"]
     ab = spmv_bytes(nnz, N)
     achieved = ab / (spmv_ms * 1e-3) / 1e9 if spmv_ms > 0 else 0.0

@@ -204,8 +204,13 @@ typedef struct {
   int32_t max_iter;         /* total iterations over all cycles */
   int32_t flexible;         /* 1: flexible GMRES (stores Z); required when precision = 1 */
   int32_t transpose;        /* 1: solve A^T x = b with P^-T */
-  int32_t use_graph;        /* 1: capture each cycle's launches in a hipGraph and replay */
-  int32_t profile;          /* 1: time every launch of the dominant kernels with events */
+  int32_t use_graph;        /* 1: the first restart cycle runs eagerly; later cycles replay
+                               one captured hipGraph of a whole cycle (no host checks inside
+                               a cycle; converged grids are masked on the device) on a stream
+                               of the solver's own, ordered after `stream` by events.  Same
+                               results as use_graph = 0, bit for bit. */
+  int32_t profile;          /* 1: time every launch of the dominant kernels with events
+                               (eagerly run cycles only) */
   double  rtol;             /* stop when ||b - A x|| <= rtol ||b|| (x0 = 0, Section 4) */
 } edfa_solve_params;
 
@@ -238,6 +243,16 @@ edfa_status edfa_solve(edfa_system sys, edfa_precond pre, const double *b, doubl
  * Asynchronous. */
 edfa_status edfa_grad_logk(edfa_system sys, const double *u, const double *lambda, double *g,
                            hipStream_t stream);
+
+/* Launch-shape autotuner (not part of the paper's method; its results do not change what
+ * is computed, only the rounding order of the sparse products).  Times every sparse matrix
+ * that the solve and the application multiply -- the system matrix (and its transpose once
+ * built), the FSAI factor and its transpose, the coupling blocks, the ILU(0) factors and
+ * their approximate inverses -- with the one-lane-per-row SELL kernel and with the CSR
+ * kernel at 2, 4, 8, 16 and 32 lanes per row, and keeps the fastest for each; the choice
+ * stays with the handle across later setups.  *tuned (host, may be NULL) receives the
+ * number of matrices timed.  Synchronises the stream.  Errors: EDFA_ERR_ARG, EDFA_ERR_HIP. */
+edfa_status edfa_autotune(edfa_precond pre, hipStream_t stream, int32_t *tuned /* (host) */);
 
 const char *edfa_last_error(void);
 

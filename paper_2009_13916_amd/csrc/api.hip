@@ -341,6 +341,15 @@ edfa_status edfa_solve(edfa_system sys, edfa_precond pre, const double *b, doubl
   });
 }
 
+edfa_status edfa_autotune(edfa_precond pre, hipStream_t stream, int32_t *tuned) {
+  return guard([&] {
+    if (!pre) fail(EDFA_ERR_ARG, "NULL preconditioner");
+    const int n = autotune(*pre, stream);
+    if (tuned) *tuned = n;
+    return EDFA_OK;
+  });
+}
+
 edfa_status edfa_grad_logk(edfa_system sys, const double *u, const double *lambda, double *g,
                            hipStream_t stream) {
   return guard([&] {

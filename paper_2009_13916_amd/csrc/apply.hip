@@ -2,8 +2,8 @@
 //
 //   t   = A~^-1 r_pi            A~^-1 = -G_F^T G_F   (two SpMVs)
 //   y   = r_p - A_ppi t
-//   z_p = S~^-1 y               multicolour ILU(0): permute, ISAI (+ refinement) or
-//                               colour-by-colour substitution, un-permute
+//   z_p = S~^-1 y               multicolour ILU(0): ISAI of the factors (+ refinement) in
+//                               the natural cell order, or colour-by-colour substitution
 //   z_pi = A~^-1 (r_pi - A_pip z_p)
 // The transpose swaps A_ppi <-> A_pip^T and uses (LU)^-T.
 #include "precond.hpp"
@@ -58,17 +58,17 @@ static void to_fp32(const Csr<double> &M, Csr<float> &F, hipStream_t s) {
   }
 }
 
+// z_p = S~^-1 y.  ISAI: products with the approximate inverses of (I + L) and U (and
+// Richardson steps with the factors), all stored in the natural cell order, so y and z_p
+// are used as they are.  Exact: colour-by-colour substitution in the colour order, between
+// a gather and a scatter of the vector.
 template <class T>
 static void sinv(edfa_precond_s &P, PrecData<T> &D, int transpose, const T *y, T *zp,
                  hipStream_t s) {
   const int ne = P.sys->ne;
   const int gb = ceil_div(ne, 256);
-  D.y.ensure(ne);
   D.w.ensure(ne);
-  D.zq.ensure(ne);
   D.res.ensure(ne);
-  hipLaunchKernelGGL(k_gather<T>, dim3(gb), dim3(256), 0, s, y, D.perm.p, ne, D.y.p);
-  EDFA_CHECK_LAUNCH();
   const int steps = std::max(1, P.prm.isai_steps);
   if (P.prm.schur_solver == EDFA_SCHUR_ISAI) {
     // first factor (L, or U^T for the transpose), then the second
@@ -78,47 +78,51 @@ static void sinv(edfa_precond_s &P, PrecData<T> &D, int transpose, const T *y, T
     const Sell<T> &T2 = transpose ? D.LT_s : D.U_s;
     const double g1 = transpose ? 0.0 : -1.0;   // (I + L) w = L w + w
     const double g2 = transpose ? -1.0 : 0.0;
-    spmv_sell<T, T>(M1, D.y.p, D.w.p, 1.0, nullptr, 0.0, s);
+    spmv_sell<T, T>(M1, y, D.w.p, 1.0, nullptr, 0.0, s);
     for (int k = 1; k < steps; ++k) {
-      spmv_sell<T, T>(T1, D.w.p, D.res.p, -1.0, D.y.p, 1.0, s, g1);
+      spmv_sell<T, T>(T1, D.w.p, D.res.p, -1.0, y, 1.0, s, g1);
       spmv_sell<T, T>(M1, D.res.p, D.w.p, 1.0, D.w.p, 1.0, s);
     }
-    spmv_sell<T, T>(M2, D.w.p, D.zq.p, 1.0, nullptr, 0.0, s);
+    spmv_sell<T, T>(M2, D.w.p, zp, 1.0, nullptr, 0.0, s);
     for (int k = 1; k < steps; ++k) {
-      spmv_sell<T, T>(T2, D.zq.p, D.res.p, -1.0, D.w.p, 1.0, s, g2);
-      spmv_sell<T, T>(M2, D.res.p, D.zq.p, 1.0, D.zq.p, 1.0, s);
+      spmv_sell<T, T>(T2, zp, D.res.p, -1.0, D.w.p, 1.0, s, g2);
+      spmv_sell<T, T>(M2, D.res.p, zp, 1.0, zp, 1.0, s);
+    }
+    return;
+  }
+  D.y.ensure(ne);
+  D.zq.ensure(ne);
+  hipLaunchKernelGGL(k_gather<T>, dim3(gb), dim3(256), 0, s, y, D.perm.p, ne, D.y.p);
+  EDFA_CHECK_LAUNCH();
+  const int nc = P.n_colors;
+  if (!transpose) {
+    for (int c = 0; c < nc; ++c) {
+      const int r0 = D.cstart[c], r1 = D.cstart[c + 1];
+      if (r1 > r0)
+        hipLaunchKernelGGL(k_sweep<T>, dim3(ceil_div(r1 - r0, 64)), dim3(64), 0, s, D.L.rowptr.p,
+                           D.L.col.p, D.L.val.p, r0, r1, 0, D.y.p, D.w.p);
+    }
+    for (int c = nc - 1; c >= 0; --c) {
+      const int r0 = D.cstart[c], r1 = D.cstart[c + 1];
+      if (r1 > r0)
+        hipLaunchKernelGGL(k_sweep<T>, dim3(ceil_div(r1 - r0, 64)), dim3(64), 0, s, D.U.rowptr.p,
+                           D.U.col.p, D.U.val.p, r0, r1, 1, D.w.p, D.zq.p);
     }
   } else {
-    const int nc = P.n_colors;
-    if (!transpose) {
-      for (int c = 0; c < nc; ++c) {
-        const int r0 = D.cstart[c], r1 = D.cstart[c + 1];
-        if (r1 > r0)
-          hipLaunchKernelGGL(k_sweep<T>, dim3(ceil_div(r1 - r0, 64)), dim3(64), 0, s, D.L.rowptr.p,
-                             D.L.col.p, D.L.val.p, r0, r1, 0, D.y.p, D.w.p);
-      }
-      for (int c = nc - 1; c >= 0; --c) {
-        const int r0 = D.cstart[c], r1 = D.cstart[c + 1];
-        if (r1 > r0)
-          hipLaunchKernelGGL(k_sweep<T>, dim3(ceil_div(r1 - r0, 64)), dim3(64), 0, s, D.U.rowptr.p,
-                             D.U.col.p, D.U.val.p, r0, r1, 1, D.w.p, D.zq.p);
-      }
-    } else {
-      for (int c = 0; c < nc; ++c) {
-        const int r0 = D.cstart[c], r1 = D.cstart[c + 1];
-        if (r1 > r0)
-          hipLaunchKernelGGL(k_sweep<T>, dim3(ceil_div(r1 - r0, 64)), dim3(64), 0, s, D.UT.rowptr.p,
-                             D.UT.col.p, D.UT.val.p, r0, r1, 2, D.y.p, D.w.p);
-      }
-      for (int c = nc - 1; c >= 0; --c) {
-        const int r0 = D.cstart[c], r1 = D.cstart[c + 1];
-        if (r1 > r0)
-          hipLaunchKernelGGL(k_sweep<T>, dim3(ceil_div(r1 - r0, 64)), dim3(64), 0, s, D.LT.rowptr.p,
-                             D.LT.col.p, D.LT.val.p, r0, r1, 0, D.w.p, D.zq.p);
-      }
+    for (int c = 0; c < nc; ++c) {
+      const int r0 = D.cstart[c], r1 = D.cstart[c + 1];
+      if (r1 > r0)
+        hipLaunchKernelGGL(k_sweep<T>, dim3(ceil_div(r1 - r0, 64)), dim3(64), 0, s, D.UT.rowptr.p,
+                           D.UT.col.p, D.UT.val.p, r0, r1, 2, D.y.p, D.w.p);
     }
-    EDFA_CHECK_LAUNCH();
+    for (int c = nc - 1; c >= 0; --c) {
+      const int r0 = D.cstart[c], r1 = D.cstart[c + 1];
+      if (r1 > r0)
+        hipLaunchKernelGGL(k_sweep<T>, dim3(ceil_div(r1 - r0, 64)), dim3(64), 0, s, D.LT.rowptr.p,
+                           D.LT.col.p, D.LT.val.p, r0, r1, 0, D.w.p, D.zq.p);
+    }
   }
+  EDFA_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_scatter<T>, dim3(gb), dim3(256), 0, s, D.zq.p, D.perm.p, ne, zp);
   EDFA_CHECK_LAUNCH();
 }
@@ -127,13 +131,15 @@ template <class T>
 static void ensure_transposed_factors(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
   edfa_system_s &S = *P.sys;
   if (D.UT.rows == 0 && S.ne) {
-    csr_transpose(D.U, D.UT, S.tmp, S.tmp2, s);
-    csr_transpose(D.L, D.LT, S.tmp, S.tmp2, s);
+    // ISAI: transposes of the natural-order copies; exact substitution: colour order
+    const bool isai = P.prm.schur_solver == EDFA_SCHUR_ISAI;
+    csr_transpose(isai ? D.Un : D.U, D.UT, S.tmp, S.tmp2, s);
+    csr_transpose(isai ? D.Ln : D.L, D.LT, S.tmp, S.tmp2, s);
     build_sell(D.UT, D.UT_s, S.tmp, s);
     build_sell(D.LT, D.LT_s, S.tmp, s);
-    if (P.prm.schur_solver == EDFA_SCHUR_ISAI) {
-      csr_transpose(D.ML, D.MLT, S.tmp, S.tmp2, s);
-      csr_transpose(D.MU, D.MUT, S.tmp, S.tmp2, s);
+    if (isai) {
+      csr_transpose(D.MLn, D.MLT, S.tmp, S.tmp2, s);
+      csr_transpose(D.MUn, D.MUT, S.tmp, S.tmp2, s);
       build_sell(D.MLT, D.MLT_s, S.tmp, s);
       build_sell(D.MUT, D.MUT_s, S.tmp, s);
     }
@@ -173,6 +179,7 @@ void precond_apply(edfa_precond_s &P, int transpose, const double *r, double *z,
       ensure_transposed_factors(P, P.f, s);
     else
       ensure_transposed_factors(P, P.d, s);
+    apply_tuned(P);
   }
   if (P.prm.precision != 1) {
     apply_typed<double>(P, P.d, r, z, transpose ? S.AfcT_s : S.Acf_s,
@@ -184,12 +191,15 @@ void precond_apply(edfa_precond_s &P, int transpose, const double *r, double *z,
   auto &cf = P.coupling_f;
   auto &cs = P.coupling_fs;
   const Csr<double> *src[4] = {&S.Acf, &S.Afc, &S.AfcT, &S.AcfT};
+  bool rebuilt = false;
   for (int q = 0; q < (transpose ? 4 : 2); ++q) {
     if (cf[q].rows != src[q]->rows || cf[q].nnz != src[q]->nnz) {
       to_fp32(*src[q], cf[q], s);
       build_sell(cf[q], cs[q], S.tmp, s);
+      rebuilt = true;
     }
   }
+  if (rebuilt) apply_tuned(P);
   const int n = S.n;
   D.z.ensure(n);
   DBuf<float> &rin = P.rin_f;

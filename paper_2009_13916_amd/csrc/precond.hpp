@@ -41,6 +41,10 @@ struct PrecData {
   DBuf<int> diag;       // Ne: position of the diagonal in B
   Csr<T> L, U;          // strict lower (unit factor) and upper (with diagonal) of B
   Csr<T> ML, MU;        // ISAI of (I + L) and U
+  Csr<T> Ln, Un, MLn, MUn;          // L, U, M_L, M_U renumbered to the natural cell order
+                                    // (the ISAI application runs on these: its gathers of x
+                                    // stay local, no permutation of the vector)
+  DBuf<int> scratch_diag;           // unused diagonal positions of the renumbering
   Csr<T> LT, UT, MLT, MUT;          // transposes (built on first transposed apply)
   // SELL-64 copies used by the application
   Sell<T> GF_s, GFT_s, L_s, U_s, ML_s, MU_s, LT_s, UT_s, MLT_s, MUT_s;
@@ -84,6 +88,8 @@ struct edfa_precond_s {
   edfa::Sell<float> coupling_fs[4];
   edfa::DBuf<float> rin_f;         // FP32 copy of the vector being preconditioned
   std::unique_ptr<edfa::SolveWork> ws;
+  int tuned[16] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
+                                   // autotuned lanes per row of each product (-1: default)
 };
 
 namespace edfa {
@@ -95,4 +101,6 @@ edfa_status gmres(edfa_system_s &S, edfa_precond_s &P, const double *b, double *
 template <class T>
 void build_hraw(edfa_precond_s &P, PrecData<T> &D, hipStream_t s);
 void grad_logk(edfa_system_s &S, const double *u, const double *lam, double *g, hipStream_t s);
+void apply_tuned(edfa_precond_s &P);
+int autotune(edfa_precond_s &P, hipStream_t s);
 }  // namespace edfa

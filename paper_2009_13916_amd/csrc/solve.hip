@@ -333,6 +333,21 @@ struct Prof {
   }
 };
 
+// A captured restart cycle and the stream it replays on (released with the solve).
+struct GraphCycle {
+  hipStream_t stream = nullptr;
+  hipEvent_t ev = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~GraphCycle() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (ev) (void)hipEventDestroy(ev);
+    if (stream) (void)hipStreamDestroy(stream);
+  }
+};
+
 edfa_status gmres(edfa_system_s &S, edfa_precond_s &P, const double *b, double *x,
                   const edfa_solve_params &prm, hipStream_t s, edfa_solve_info *info) {
   const int m = prm.restart;
@@ -372,6 +387,7 @@ edfa_status gmres(edfa_system_s &S, edfa_precond_s &P, const double *b, double *
   EDFA_HIP(hipMemcpyAsync(W.st.p, hst.data(), sizeof(SegState) * nseg, hipMemcpyHostToDevice, s));
   if (tr && S.AT.rows == 0) csr_transpose(S.A, S.AT, S.tmp, S.tmp2, s);
   if (tr && S.AT_s.rows == 0) build_sell(S.AT, S.AT_s, S.tmp, s);
+  apply_tuned(P);
   const Sell<double> &A = tr ? S.AT_s : S.A_s;
 
   Prof prof;
@@ -380,31 +396,33 @@ edfa_status gmres(edfa_system_s &S, edfa_precond_s &P, const double *b, double *
   total.start(s);
 
   // profiled system products: the launch records its own events around the kernel
-  auto spmvA = [&](const double *in, double *out, const double *bb) {
+  // profiling events are recorded on the caller's stream only (never inside a capture)
+  auto spmvA = [&](const double *in, double *out, const double *bb, hipStream_t cs) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (prm.profile) {
+    if (prm.profile && cs == s) {
       e0 = prof.get();
       e1 = prof.get();
       ev_spmv.emplace_back(e0, e1);
     }
-    spmv_sell<double, double>(A, in, out, bb ? -1.0 : 1.0, bb, 1.0, s, 0.0, SPMV_OPERATOR, e0, e1);
+    spmv_sell<double, double>(A, in, out, bb ? -1.0 : 1.0, bb, 1.0, cs, 0.0, SPMV_OPERATOR, e0, e1);
   };
-  auto applyP = [&](const double *in, double *out) {
+  auto applyP = [&](const double *in, double *out, hipStream_t cs) {
+    const bool pr = prm.profile && cs == s;
     hipEvent_t e0{}, e1{};
-    if (prm.profile) {
+    if (pr) {
       e0 = prof.get();
-      EDFA_HIP(hipEventRecord(e0, s));
+      EDFA_HIP(hipEventRecord(e0, cs));
     }
-    precond_apply(P, tr, in, out, s);
-    if (prm.profile) {
+    precond_apply(P, tr, in, out, cs);
+    if (pr) {
       e1 = prof.get();
-      EDFA_HIP(hipEventRecord(e1, s));
+      EDFA_HIP(hipEventRecord(e1, cs));
       ev_apply.emplace_back(e0, e1);
     }
   };
-  auto seg_norms = [&](const double *v, double *out) {
-    hipLaunchKernelGGL(k_nrm2_part, dim3(nch), dim3(RT), 0, s, v, W.chunks.p, W.part.p, ld);
-    hipLaunchKernelGGL(k_seg_reduce_w, dim3(1, nseg), dim3(256), 0, s, W.part.p, ld, 1,
+  auto seg_norms = [&](const double *v, double *out, hipStream_t cs) {
+    hipLaunchKernelGGL(k_nrm2_part, dim3(nch), dim3(RT), 0, cs, v, W.chunks.p, W.part.p, ld);
+    hipLaunchKernelGGL(k_seg_reduce_w, dim3(1, nseg), dim3(256), 0, cs, W.part.p, ld, 1,
                        W.segptr.p, W.st.p, SEG_ALL, out, ld);
     EDFA_CHECK_LAUNCH();
   };
@@ -412,12 +430,82 @@ edfa_status gmres(edfa_system_s &S, edfa_precond_s &P, const double *b, double *
 
   EDFA_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, s));
   EDFA_HIP(hipMemcpyAsync(W.r.p, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-  seg_norms(W.r.p, W.nrm.p);
+  seg_norms(W.r.p, W.nrm.p, s);
   hipLaunchKernelGGL(k_seg_start, dim3(sb), dim3(64), 0, s, nseg, m, W.st.p, W.nrm.p, ld, W.g.p,
                      W.scale.p, prm.max_iter, 1);
   EDFA_CHECK_LAUNCH();
   int cycles = 0;
   const int check_every = nseg == 1 ? 8 : 16;
+  // One restart cycle on stream cs.  With host_checks the host stops early once every
+  // segment is inactive; without, converged segments are masked on the device (the
+  // form that a graph can hold).
+  auto run_cycle = [&](hipStream_t cs, bool host_checks) {
+    hipLaunchKernelGGL(k_scale, dim3(nch), dim3(RT), 0, cs, W.r.p, W.V.p, W.chunks.p, W.st.p,
+                       W.scale.p);
+    EDFA_CHECK_LAUNCH();
+    for (int j = 0; j < m; ++j) {
+      double *vj = W.V.p + (size_t)j * n;
+      double *zj = prm.flexible ? W.Z.p + (size_t)j * n : W.z.p;
+      applyP(vj, zj, cs);
+      spmvA(zj, W.w.p, nullptr, cs);
+      // first pass: h1 = V^T w and ||w||^2, w -= V h1, ||w||^2 after
+      hipLaunchKernelGGL(k_dots_tiled<false>, dim3(nch, ceil_div(j + 1, DG)), dim3(RT), 0, cs,
+                         W.V.p, (long long)n, j + 1, W.w.p, W.chunks.p, W.st.p, W.part.p, ld);
+      hipLaunchKernelGGL(k_seg_reduce_w, dim3(ceil_div(j + 2, 4), nseg), dim3(256), 0, cs,
+                         W.part.p, ld, j + 2, W.segptr.p, W.st.p, SEG_ACTIVE, W.h1.p, ld);
+      hipLaunchKernelGGL(k_update<false>, dim3(nch), dim3(RT), 0, cs, W.V.p, (long long)n, j + 1,
+                         W.w.p, W.chunks.p, W.st.p, W.h1.p, ld, W.part.p, ld);
+      hipLaunchKernelGGL(k_seg_reduce_w, dim3(1, nseg), dim3(256), 0, cs, W.part.p, ld, 1,
+                         W.segptr.p, W.st.p, SEG_ACTIVE, W.nrm.p, ld);
+      hipLaunchKernelGGL(k_reorth_decide, dim3(sb), dim3(64), 0, cs, nseg, j + 1, W.st.p, W.h1.p,
+                         W.nrm.p, ld);
+      // second pass where flagged: h2 = V^T w, w -= V h2, ||w||^2 into h2[j + 1]
+      hipLaunchKernelGGL(k_dots_tiled<true>, dim3(nch, ceil_div(j + 1, DG)), dim3(RT), 0, cs,
+                         W.V.p, (long long)n, j + 1, W.w.p, W.chunks.p, W.st.p, W.part.p, ld);
+      hipLaunchKernelGGL(k_seg_reduce_w, dim3(ceil_div(j + 1, 4), nseg), dim3(256), 0, cs,
+                         W.part.p, ld, j + 1, W.segptr.p, W.st.p, SEG_REORTH, W.h2.p, ld);
+      hipLaunchKernelGGL(k_update<true>, dim3(nch), dim3(RT), 0, cs, W.V.p, (long long)n, j + 1,
+                         W.w.p, W.chunks.p, W.st.p, W.h2.p, ld, W.part.p, ld);
+      hipLaunchKernelGGL(k_seg_reduce_w, dim3(1, nseg), dim3(256), 0, cs, W.part.p, ld, 1,
+                         W.segptr.p, W.st.p, SEG_REORTH, W.h2.p + (j + 1), ld);
+      hipLaunchKernelGGL(k_givens, dim3(nseg), dim3(64), 0, cs, nseg, m, j, W.st.p, W.h1.p, W.h2.p,
+                         W.nrm.p, ld, W.R.p, W.cs.p, W.sn.p, W.g.p, W.scale.p, prm.max_iter);
+      hipLaunchKernelGGL(k_scale, dim3(nch), dim3(RT), 0, cs, W.w.p, W.V.p + (size_t)(j + 1) * n,
+                         W.chunks.p, W.st.p, W.scale.p);
+      EDFA_CHECK_LAUNCH();
+      if (host_checks && (j + 1) % check_every == 0 && j + 1 < m) {
+        EDFA_HIP(hipMemcpyAsync(hst.data(), W.st.p, sizeof(SegState) * nseg, hipMemcpyDeviceToHost, cs));
+        EDFA_HIP(hipStreamSynchronize(cs));
+        int a = 0;
+        for (auto &q : hst) a += q.active;
+        if (!a) break;
+      }
+    }
+    // end of cycle: y = R^-1 g, x += Z y (flexible) or x += P^-1 (V y)
+    hipLaunchKernelGGL(k_record_ran, dim3(sb), dim3(64), 0, cs, nseg, W.st.p, W.ran.p);
+    hipLaunchKernelGGL(k_lsq, dim3(sb), dim3(64), 0, cs, nseg, m, W.st.p, W.R.p, W.g.p, W.y.p, W.ran.p);
+    if (prm.flexible) {
+      hipLaunchKernelGGL(k_combine, dim3(nch), dim3(RT), 0, cs, W.Z.p, (long long)n, m, W.chunks.p,
+                         W.y.p, W.ran.p, x, 1);
+    } else {
+      hipLaunchKernelGGL(k_combine, dim3(nch), dim3(RT), 0, cs, W.V.p, (long long)n, m, W.chunks.p,
+                         W.y.p, W.ran.p, W.w.p, 0);
+      applyP(W.w.p, W.z.p, cs);
+      hipLaunchKernelGGL(k_axpy, dim3(ceil_div(n, 256)), dim3(256), 0, cs, (long long)n, W.z.p, x);
+    }
+    EDFA_CHECK_LAUNCH();
+    // true residual r = b - A x and the next cycle's start
+    spmvA(x, W.r.p, b, cs);
+    seg_norms(W.r.p, W.nrm.p, cs);
+    hipLaunchKernelGGL(k_seg_start, dim3(sb), dim3(64), 0, cs, nseg, m, W.st.p, W.nrm.p, ld, W.g.p,
+                       W.scale.p, prm.max_iter, 0);
+    EDFA_CHECK_LAUNCH();
+  };
+
+  // Graph form: the first cycle runs eagerly (every lazy allocation and first-use build
+  // happens there), later cycles replay one captured cycle on a stream of the solver's
+  // own, ordered after the caller's stream by events.
+  GraphCycle gc;
   while (true) {
     EDFA_HIP(hipMemcpyAsync(hst.data(), W.st.p, sizeof(SegState) * nseg, hipMemcpyDeviceToHost, s));
     EDFA_HIP(hipStreamSynchronize(s));
@@ -425,65 +513,23 @@ edfa_status gmres(edfa_system_s &S, edfa_precond_s &P, const double *b, double *
     for (auto &q : hst) nact += q.active;
     if (!nact) break;
     ++cycles;
-    hipLaunchKernelGGL(k_scale, dim3(nch), dim3(RT), 0, s, W.r.p, W.V.p, W.chunks.p, W.st.p, W.scale.p);
-    EDFA_CHECK_LAUNCH();
-    for (int j = 0; j < m; ++j) {
-      double *vj = W.V.p + (size_t)j * n;
-      double *zj = prm.flexible ? W.Z.p + (size_t)j * n : W.z.p;
-      applyP(vj, zj);
-      spmvA(zj, W.w.p, nullptr);
-      // first pass: h1 = V^T w and ||w||^2, w -= V h1, ||w||^2 after
-      hipLaunchKernelGGL(k_dots_tiled<false>, dim3(nch, ceil_div(j + 1, DG)), dim3(RT), 0, s,
-                         W.V.p, (long long)n, j + 1, W.w.p, W.chunks.p, W.st.p, W.part.p, ld);
-      hipLaunchKernelGGL(k_seg_reduce_w, dim3(ceil_div(j + 2, 4), nseg), dim3(256), 0, s,
-                         W.part.p, ld, j + 2, W.segptr.p, W.st.p, SEG_ACTIVE, W.h1.p, ld);
-      hipLaunchKernelGGL(k_update<false>, dim3(nch), dim3(RT), 0, s, W.V.p, (long long)n, j + 1,
-                         W.w.p, W.chunks.p, W.st.p, W.h1.p, ld, W.part.p, ld);
-      hipLaunchKernelGGL(k_seg_reduce_w, dim3(1, nseg), dim3(256), 0, s, W.part.p, ld, 1,
-                         W.segptr.p, W.st.p, SEG_ACTIVE, W.nrm.p, ld);
-      hipLaunchKernelGGL(k_reorth_decide, dim3(sb), dim3(64), 0, s, nseg, j + 1, W.st.p, W.h1.p,
-                         W.nrm.p, ld);
-      // second pass where flagged: h2 = V^T w, w -= V h2, ||w||^2 into h2[j + 1]
-      hipLaunchKernelGGL(k_dots_tiled<true>, dim3(nch, ceil_div(j + 1, DG)), dim3(RT), 0, s,
-                         W.V.p, (long long)n, j + 1, W.w.p, W.chunks.p, W.st.p, W.part.p, ld);
-      hipLaunchKernelGGL(k_seg_reduce_w, dim3(ceil_div(j + 1, 4), nseg), dim3(256), 0, s,
-                         W.part.p, ld, j + 1, W.segptr.p, W.st.p, SEG_REORTH, W.h2.p, ld);
-      hipLaunchKernelGGL(k_update<true>, dim3(nch), dim3(RT), 0, s, W.V.p, (long long)n, j + 1,
-                         W.w.p, W.chunks.p, W.st.p, W.h2.p, ld, W.part.p, ld);
-      hipLaunchKernelGGL(k_seg_reduce_w, dim3(1, nseg), dim3(256), 0, s, W.part.p, ld, 1,
-                         W.segptr.p, W.st.p, SEG_REORTH, W.h2.p + (j + 1), ld);
-      hipLaunchKernelGGL(k_givens, dim3(nseg), dim3(64), 0, s, nseg, m, j, W.st.p, W.h1.p, W.h2.p,
-                         W.nrm.p, ld, W.R.p, W.cs.p, W.sn.p, W.g.p, W.scale.p, prm.max_iter);
-      hipLaunchKernelGGL(k_scale, dim3(nch), dim3(RT), 0, s, W.w.p, W.V.p + (size_t)(j + 1) * n,
-                         W.chunks.p, W.st.p, W.scale.p);
-      EDFA_CHECK_LAUNCH();
-      if ((j + 1) % check_every == 0 && j + 1 < m) {
-        EDFA_HIP(hipMemcpyAsync(hst.data(), W.st.p, sizeof(SegState) * nseg, hipMemcpyDeviceToHost, s));
-        EDFA_HIP(hipStreamSynchronize(s));
-        int a = 0;
-        for (auto &q : hst) a += q.active;
-        if (!a) break;
-      }
+    if (!prm.use_graph || cycles == 1) {
+      run_cycle(s, true);
+      continue;
     }
-    // end of cycle: y = R^-1 g, x += Z y (flexible) or x += P^-1 (V y)
-    hipLaunchKernelGGL(k_record_ran, dim3(sb), dim3(64), 0, s, nseg, W.st.p, W.ran.p);
-    hipLaunchKernelGGL(k_lsq, dim3(sb), dim3(64), 0, s, nseg, m, W.st.p, W.R.p, W.g.p, W.y.p, W.ran.p);
-    if (prm.flexible) {
-      hipLaunchKernelGGL(k_combine, dim3(nch), dim3(RT), 0, s, W.Z.p, (long long)n, m, W.chunks.p,
-                         W.y.p, W.ran.p, x, 1);
-    } else {
-      hipLaunchKernelGGL(k_combine, dim3(nch), dim3(RT), 0, s, W.V.p, (long long)n, m, W.chunks.p,
-                         W.y.p, W.ran.p, W.w.p, 0);
-      applyP(W.w.p, W.z.p);
-      hipLaunchKernelGGL(k_axpy, dim3(ceil_div(n, 256)), dim3(256), 0, s, (long long)n, W.z.p, x);
+    if (!gc.exec) {
+      EDFA_HIP(hipStreamCreateWithFlags(&gc.stream, hipStreamNonBlocking));
+      EDFA_HIP(hipEventCreateWithFlags(&gc.ev, hipEventDisableTiming));
+      EDFA_HIP(hipStreamBeginCapture(gc.stream, hipStreamCaptureModeThreadLocal));
+      run_cycle(gc.stream, false);
+      EDFA_HIP(hipStreamEndCapture(gc.stream, &gc.graph));
+      EDFA_HIP(hipGraphInstantiate(&gc.exec, gc.graph, nullptr, nullptr, 0));
     }
-    EDFA_CHECK_LAUNCH();
-    // true residual r = b - A x and the next cycle's start
-    spmvA(x, W.r.p, b);
-    seg_norms(W.r.p, W.nrm.p);
-    hipLaunchKernelGGL(k_seg_start, dim3(sb), dim3(64), 0, s, nseg, m, W.st.p, W.nrm.p, ld, W.g.p,
-                       W.scale.p, prm.max_iter, 0);
-    EDFA_CHECK_LAUNCH();
+    EDFA_HIP(hipEventRecord(gc.ev, s));
+    EDFA_HIP(hipStreamWaitEvent(gc.stream, gc.ev, 0));
+    EDFA_HIP(hipGraphLaunch(gc.exec, gc.stream));
+    EDFA_HIP(hipEventRecord(gc.ev, gc.stream));
+    EDFA_HIP(hipStreamWaitEvent(s, gc.ev, 0));
   }
   total.stop(s);
   const float tms = total.ms();

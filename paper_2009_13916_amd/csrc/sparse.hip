@@ -392,15 +392,26 @@ __global__ __launch_bounds__(SPMV_T) void k_spmv_csr_vec(const int *__restrict__
   }
 }
 
+// Launch helper: the extended launch records e0/e1 around the kernel when given; plain
+// launches otherwise (the form stream capture records).
+template <class K, class... Args>
+static void launch_timed(K kern, int blocks, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                         Args... args) {
+  if (e0 || e1)
+    hipExtLaunchKernelGGL(kern, dim3(blocks), dim3(SPMV_T), 0, s, e0, e1, 0, args...);
+  else
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(SPMV_T), 0, s, args...);
+}
+
 template <class V, class X>
 void spmv_sell(const Sell<V> &M, const X *x, X *y, double alpha, const X *b, double beta,
                hipStream_t s, double gamma, int role, hipEvent_t e0, hipEvent_t e1) {
   if (M.rows <= 0) return;
   if (M.lanes > 1) {
-    const int nb = (int)ceil_div((long long)M.rows * M.lanes, SPMV_T);
-#define EDFA_VEC(LN)                                                                           \
-  hipExtLaunchKernelGGL((k_spmv_csr_vec<V, X, LN>), dim3(nb), dim3(SPMV_T), 0, s, e0, e1, 0,    \
-                        M.csr_rp, M.csr_col, M.csr_val, M.rows, x, y, alpha, b, beta, gamma)
+    const int nb = ceil_div((long long)M.rows * M.lanes, SPMV_T);
+#define EDFA_VEC(LN)                                                                          \
+  launch_timed(k_spmv_csr_vec<V, X, LN>, nb, s, e0, e1, M.csr_rp, M.csr_col, M.csr_val, M.rows, \
+               x, y, alpha, b, beta, gamma)
     switch (M.lanes) {
       case 2: EDFA_VEC(2); break;
       case 4: EDFA_VEC(4); break;
@@ -410,13 +421,11 @@ void spmv_sell(const Sell<V> &M, const X *x, X *y, double alpha, const X *b, dou
     }
 #undef EDFA_VEC
   } else if (role == SPMV_OPERATOR) {
-    hipExtLaunchKernelGGL((k_spmv_sell<V, X, SPMV_OPERATOR>), dim3(ceil_div(M.rows, SPMV_T)),
-                          dim3(SPMV_T), 0, s, e0, e1, 0, M.sptr.p, M.rlen.p, M.col.p, M.val.p,
-                          M.rows, x, y, alpha, b, beta, gamma);
+    launch_timed(k_spmv_sell<V, X, SPMV_OPERATOR>, ceil_div(M.rows, SPMV_T), s, e0, e1, M.sptr.p,
+                 M.rlen.p, M.col.p, M.val.p, M.rows, x, y, alpha, b, beta, gamma);
   } else {
-    hipExtLaunchKernelGGL((k_spmv_sell<V, X, SPMV_PRECOND>), dim3(ceil_div(M.rows, SPMV_T)),
-                          dim3(SPMV_T), 0, s, e0, e1, 0, M.sptr.p, M.rlen.p, M.col.p, M.val.p,
-                          M.rows, x, y, alpha, b, beta, gamma);
+    launch_timed(k_spmv_sell<V, X, SPMV_PRECOND>, ceil_div(M.rows, SPMV_T), s, e0, e1, M.sptr.p,
+                 M.rlen.p, M.col.p, M.val.p, M.rows, x, y, alpha, b, beta, gamma);
   }
   EDFA_CHECK_LAUNCH();
 }

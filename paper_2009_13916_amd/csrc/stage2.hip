@@ -398,6 +398,24 @@ __global__ void k_row_len_max(const int *__restrict__ rp, int rows, int *out) {
 }
 
 // ---------------------------------------------------------------------------------------
+// N = P^T M P: row o of N is row iperm[o] of M (colour order) with columns mapped back by
+// perm, sorted.
+template <class T>
+static void to_natural_order(const Csr<T> &M, Csr<T> &N, PrecData<T> &D, edfa_system_s &S,
+                             hipStream_t s) {
+  const int n = M.rows;
+  N.alloc(n, n, M.nnz);
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_gather_len, dim3(ceil_div(n, 256)), dim3(256), 0, s, M.rowptr.p, D.iperm.p,
+                     n, N.rowptr.p);
+  EDFA_CHECK_LAUNCH();
+  exclusive_scan(N.rowptr.p, N.rowptr.p, n, S.tmp, s);
+  D.scratch_diag.ensure(n);
+  hipLaunchKernelGGL(k_permute_rows<T>, dim3(n), dim3(64), 0, s, M.rowptr.p, M.col.p, M.val.p,
+                     D.iperm.p, D.perm.p, n, N.rowptr.p, N.col.p, N.val.p, D.scratch_diag.p);
+  EDFA_CHECK_LAUNCH();
+}
+
 template <class T>
 static void stage2_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
   edfa_system_s &S = *P.sys;
@@ -555,11 +573,19 @@ static void stage2_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
       EDFA_CHECK_LAUNCH();
     }
   }
-  build_sell(D.L, D.L_s, S.tmp, s);
-  build_sell(D.U, D.U_s, S.tmp, s);
   if (prm.schur_solver == EDFA_SCHUR_ISAI) {
-    build_sell(D.ML, D.ML_s, S.tmp, s);
-    build_sell(D.MU, D.MU_s, S.tmp, s);
+    // the application works in the natural cell order: P^T M P for every factor it uses
+    to_natural_order(D.L, D.Ln, D, S, s);
+    to_natural_order(D.U, D.Un, D, S, s);
+    to_natural_order(D.ML, D.MLn, D, S, s);
+    to_natural_order(D.MU, D.MUn, D, S, s);
+    build_sell(D.Ln, D.L_s, S.tmp, s);
+    build_sell(D.Un, D.U_s, S.tmp, s);
+    build_sell(D.MLn, D.ML_s, S.tmp, s);
+    build_sell(D.MUn, D.MU_s, S.tmp, s);
+  } else {
+    build_sell(D.L, D.L_s, S.tmp, s);
+    build_sell(D.U, D.U_s, S.tmp, s);
   }
   // transposes are rebuilt lazily for the transposed application
   D.LT.rows = D.UT.rows = D.MLT.rows = D.MUT.rows = 0;

@@ -106,6 +106,7 @@ def load():
             "edfa_solve": (C.c_int, [vp, vp, vp, vp, C.POINTER(_SolveParams), vp,
                                      C.POINTER(_SolveInfo)]),
             "edfa_grad_logk": (C.c_int, [vp, vp, vp, vp, vp]),
+            "edfa_autotune": (C.c_int, [vp, vp, C.POINTER(i32)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name, None)
@@ -124,7 +125,8 @@ def exported_symbols():
                         "edfa_system_get_info", "edfa_update_dt", "edfa_export_block",
                         "edfa_export_rhs", "edfa_spmv", "edfa_setup", "edfa_setup_stage2", "edfa_resetup",
                         "edfa_precond_destroy", "edfa_precond_get_info", "edfa_export_precond",
-                        "edfa_apply", "edfa_solve", "edfa_grad_logk") if hasattr(L, n)]
+                        "edfa_apply", "edfa_solve", "edfa_grad_logk", "edfa_autotune")
+            if hasattr(L, n)]
 
 
 def _check(st):
@@ -271,6 +273,13 @@ class Precond:
         z = torch.empty_like(r)
         _check(load().edfa_apply(self._h, int(transpose), _ptr(r), _ptr(z), _stream()))
         return z
+
+    def autotune(self):
+        """Time the sparse-product kernel variants for every matrix of the solve and keep
+        the fastest (returns the number of matrices timed)."""
+        n = C.c_int32(0)
+        _check(load().edfa_autotune(self._h, _stream(), C.byref(n)))
+        return n.value
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:

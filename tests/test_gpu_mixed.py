@@ -1,0 +1,160 @@
+"""GPU checks of the FP32 form: EDFA setup and application in FP32 (restricted solves
+accumulated in FP32) inside an FP64 flexible GMRES.
+
+Tolerances against the FP64 oracle follow from single-precision rounding (u = 2^-24 ~ 6e-8):
+a restricted Cholesky solve of size s <= 42 on a matrix whose Jacobi-scaled condition number is
+O(10) loses about s u kappa ~ 3e-5; the triple product H~ = G~ A F~ sums ~100 such terms and
+S~ = A_pp - H~ cancels about one digit, so H~ and S~ are compared at 5e-4 of the row scale and
+the ILU(0) factors and their approximate inverses at 2e-3.  Solutions are held to the FP64
+outer iteration: a true FP64 residual <= rtol, and at rtol = 1e-12 the direct solution to 1e-8.
+Every measured error is printed.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import torch
+
+from oracle import edfa as oedfa, krylov, mhfe
+from paper_2009_13916_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+STATIC = {
+    "iso7_static": (lambda: inputs.lognormal_iso_problem(7, sigma=2.0, config_id=51),
+                    dict(variant="static")),
+    "full5_static": (lambda: inputs.full_tensor_problem(5, 4, 6, sigma=2.0, corr=2.0, config_id=52),
+                     dict(variant="static")),
+}
+
+
+def _to_sp(rp, col, val, shape):
+    return sp.csr_matrix((val.cpu().numpy(), col.cpu().numpy(), rp.cpu().numpy()), shape=shape)
+
+
+def _relerr(G, O):
+    """Same pattern required; max |g - o| relative to the oracle row's max |o|."""
+    G = G.tocsr(); O = O.tocsr()
+    G.sort_indices(); O.sort_indices()
+    assert np.array_equal(G.indptr, O.indptr) and np.array_equal(G.indices, O.indices)
+    scale = np.maximum(abs(O).max(axis=1).toarray().ravel(), 1e-300)
+    rows = np.repeat(np.arange(O.shape[0]), np.diff(O.indptr))
+    return float((np.abs(G.data - O.data) / scale[rows]).max()) if O.nnz else 0.0
+
+
+@pytest.mark.parametrize("name", list(STATIC))
+def test_fp32_artefacts_match_fp64_oracle(lib, name):
+    mk, kw = STATIC[name]
+    prob = mk()
+    o = mhfe.assemble(prob)
+    E = oedfa.build(o, oedfa.Params(**kw))
+    S = lib.System(prob)
+    P = lib.Precond(S, lib.Params(**kw, precision=1))
+    ne, nfu = o.ne, o.nfu
+    errs = {
+        "G~": _relerr(_to_sp(*P.export("G")[:3], (ne, nfu)), E.st1.Gt),
+        "F~^T": _relerr(_to_sp(*P.export("FT")[:3], (ne, nfu)), E.st1.Ft.T),
+        "H~": _relerr(_to_sp(*P.export("H")[:3], (ne, ne)), E.st1.H),
+        "G_F": _relerr(_to_sp(*P.export("GF")[:3], (nfu, nfu)), E.st1.GF),
+        "S~": _relerr(_to_sp(*P.export("S")[:3], (ne, ne)), E.st2.S),
+    }
+    rp, col, val, perm = P.export("L")
+    assert np.array_equal(perm.cpu().numpy(), E.st2.perm)
+    errs["L"] = _relerr(_to_sp(rp, col, val, (ne, ne)), E.st2.L)
+    errs["U"] = _relerr(_to_sp(*P.export("U")[:3], (ne, ne)), E.st2.U)
+    errs["M_L"] = _relerr(_to_sp(*P.export("ML")[:3], (ne, ne)), E.st2.ML)
+    errs["M_U"] = _relerr(_to_sp(*P.export("MU")[:3], (ne, ne)), E.st2.MU)
+    print(f"[fp32 artefacts] {name}: " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()), flush=True)
+    for k in ("G~", "F~^T", "G_F"):
+        assert errs[k] <= 1e-4, (k, errs[k])
+    for k in ("H~", "S~"):
+        assert errs[k] <= 5e-4, (k, errs[k])
+    for k in ("L", "U", "M_L", "M_U"):
+        assert errs[k] <= 2e-3, (k, errs[k])
+
+
+@pytest.mark.parametrize("name", list(STATIC))
+@pytest.mark.parametrize("transpose", [False, True])
+def test_fp32_apply_matches_fp64_oracle(lib, name, transpose):
+    mk, kw = STATIC[name]
+    prob = mk()
+    o = mhfe.assemble(prob)
+    E = oedfa.build(o, oedfa.Params(**kw))
+    S = lib.System(prob)
+    P = lib.Precond(S, lib.Params(**kw, precision=1))
+    r = np.random.default_rng(8).standard_normal(o.n)
+    z = P.apply(torch.tensor(r, device="cuda"), transpose=transpose).cpu().numpy()
+    ref = E.apply_T(r) if transpose else E.apply(r)
+    err = np.linalg.norm(z - ref) / np.linalg.norm(ref)
+    print(f"[fp32 apply] {name} transpose={transpose}: {err:.2e}", flush=True)
+    assert err <= 1e-3
+
+
+CASES = {
+    "iso8_dyn14": (lambda: inputs.lognormal_iso_problem(8, config_id=53),
+                   dict(variant="dynamic", n_add=1, n_ent=4)),
+    "full6_dyn16_postH": (lambda: inputs.full_tensor_problem(6, sigma=2.0, corr=2.0, config_id=54),
+                          dict(variant="dynamic", n_add=1, n_ent=6, tau=1e-3, filt="post_H")),
+    "dist6_dyn16": (lambda: inputs.channel_problem(6, 6, 4, contrast=1e4, config_id=55),
+                    dict(variant="dynamic", n_add=1, n_ent=6)),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_mixed_fgmres_reaches_fp64_residual(lib, name):
+    """FGMRES(50) with the FP32 preconditioner: FP64 true residual <= 1e-8; pressure error
+    against the FP64 oracle GMRES solution stated (bounded by the conditioning of A)."""
+    mk, kw = CASES[name]
+    prob = mk()
+    o = mhfe.assemble(prob)
+    A = o.matrix()
+    E = oedfa.build(o, oedfa.Params(**kw))
+    ref = krylov.gmres(lambda v: A @ v, E.apply, o.b, 1e-8, 50)
+    S = lib.System(prob)
+    P = lib.Precond(S, lib.Params(**kw, precision=1))
+    x, info, st = lib.solve(S, P, S.rhs(), rtol=1e-8, restart=50, flexible=True)
+    xg = x.cpu().numpy()
+    res = np.linalg.norm(o.b - A @ xg) / np.linalg.norm(o.b)
+    dp = np.linalg.norm(xg[o.nfu:] - ref.x[o.nfu:]) / np.linalg.norm(ref.x[o.nfu:])
+    print(f"[mixed] {name}: {info['iterations']} iterations (oracle FP64 {ref.iterations}), "
+          f"true residual {res:.2e}, pressure vs FP64 oracle {dp:.2e}", flush=True)
+    assert st == 0 and res <= 1e-8
+    assert dp <= 1e-4
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_mixed_fgmres_tight_tolerance_reaches_direct_solution(lib, name):
+    mk, kw = CASES[name]
+    prob = mk()
+    o = mhfe.assemble(prob)
+    u = mhfe.direct_solve(o)
+    S = lib.System(prob)
+    P = lib.Precond(S, lib.Params(**kw, precision=1))
+    x, info, st = lib.solve(S, P, S.rhs(), rtol=1e-12, restart=50, flexible=True)
+    xg = x.cpu().numpy()
+    err = np.linalg.norm(xg[o.nfu:] - u[o.nfu:]) / np.linalg.norm(u[o.nfu:])
+    print(f"[mixed tight] {name}: {info['iterations']} iterations, pressure vs direct {err:.2e}",
+          flush=True)
+    assert st == 0 and err <= 1e-8
+
+
+def test_mixed_transposed_solve(lib):
+    """The adjoint solve with the FP32 preconditioner applied as P^-T."""
+    mk, kw = CASES["iso8_dyn14"]
+    prob = mk()
+    o = mhfe.assemble(prob)
+    rhs = np.random.default_rng(9).standard_normal(o.n)
+    lam_ref = mhfe.spla.splu(o.matrix().T.tocsc()).solve(rhs)
+    S = lib.System(prob)
+    P = lib.Precond(S, lib.Params(**kw, precision=1))
+    lam, info, st = lib.solve(S, P, torch.tensor(rhs, device="cuda"), rtol=1e-12, flexible=True,
+                              transpose=True)
+    assert st == 0
+    assert np.linalg.norm(lam.cpu().numpy() - lam_ref) <= 1e-8 * np.linalg.norm(lam_ref)
+
+
+def test_fp32_requires_flexible_gmres(lib):
+    mk, kw = CASES["iso8_dyn14"]
+    S = lib.System(mk())
+    P = lib.Precond(S, lib.Params(**kw, precision=1))
+    with pytest.raises(lib.EdfaError):
+        lib.solve(S, P, S.rhs(), rtol=1e-8, flexible=False)

@@ -26,6 +26,7 @@ struct PrecData {
   DBuf<int> Hcol;       // Ne x HMAX raw H~ rows (sorted)
   DBuf<T> Hval;
   DBuf<int> Hlen;
+  DBuf<int> hretry;     // cells whose H~ row needs the large hash tables
   Csr<T> Hraw;          // H~ before post-filtration (only when exported)
   Csr<T> H;             // H~ used by stage 2
   Csr<T> GF, GFT;       // FSAI factor of -A_pipi and its transpose
@@ -60,14 +61,15 @@ struct Chunk {
 };
 struct SegState {
   double rtol, bnorm, tol, beta, est, relres;
-  int active, done, converged, j, total;
-  int reorth;   // this iteration's Gram-Schmidt needs its second pass
+  int active, done, converged, j, total, pad;
 };
 struct SolveWork {
   int nchunk = 0, n = 0;
   DBuf<Chunk> chunks;
   DBuf<int> segptr;
-  DBuf<double> V, Z, w, r, z, part, h1, h2, nrm, R, cs, sn, g, y, scale;
+  DBuf<double> V, Z, w, r, z, part, h1, nrm, R, cs, sn, g, y, scale;
+  DBuf<double> Hb;     // unrotated Hessenberg columns per segment, m x (m + 1)
+  DBuf<double> coef;   // per segment: update coefficients [a | b | c_j] of the current step
   DBuf<int> ran;
   DBuf<SegState> st;
 };

@@ -802,6 +802,9 @@ struct HArgs {
   int *Hcol, *Hlen;
   T *Hval;
   int *err_cap;
+  const int *cells;      // rows to compute (NULL: row = block index)
+  int *retry_count;      // non-NULL: a row whose tables pass half full is listed here
+  int *retry_list;       //   instead of computed (first pass with small tables)
 };
 
 template <class T, int GH, int TH, int LH>
@@ -813,9 +816,13 @@ __global__ __launch_bounds__(64) void k_htilde(HArgs<T> A) {
   __shared__ int lk[LH], llist[LH];
   __shared__ T hv[LH];
   __shared__ int tcount, lcount, sflag;
-  const int m = blockIdx.x;
+  const int m = A.cells ? A.cells[blockIdx.x] : blockIdx.x;
   const int lane = threadIdx.x;
   if (m >= A.ne) return;
+  // retry: row m goes to the large-table pass (first pass only; all lanes agree)
+  auto retry = [&]() {
+    if (lane == 0) A.retry_list[atomicAdd(A.retry_count, 1)] = m;
+  };
   for (int h = lane; h < GH; h += 64) gk[h] = -1;
   for (int h = lane; h < TH; h += 64) tk[h] = -1;
   for (int h = lane; h < LH; h += 64) lk[h] = -1;
@@ -847,6 +854,10 @@ __global__ __launch_bounds__(64) void k_htilde(HArgs<T> A) {
     }
   }
   __syncthreads();
+  if (A.retry_count && (sflag || tcount > TH / 2)) {
+    retry();
+    return;
+  }
   if (sflag) {
     if (lane == 0) atomicMin(A.err_cap, m);
     return;
@@ -876,6 +887,10 @@ __global__ __launch_bounds__(64) void k_htilde(HArgs<T> A) {
   }
   __syncthreads();
   const int nl = lcount;
+  if (A.retry_count && (sflag || nl > LH / 2)) {
+    retry();
+    return;
+  }
   if (sflag || nl > HMAX) {
     if (lane == 0) atomicMin(A.err_cap, m);
     return;
@@ -1201,14 +1216,40 @@ static void stage1_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
   ha.Hval = D.Hval.p;
   ha.err_cap = err_cap;
   const int support = P.max_pattern * (S.axis ? 3 : 11);
-  if (ne > 0) {
+  ha.cells = nullptr;
+  ha.retry_count = nullptr;
+  ha.retry_list = nullptr;
+  // large-table pass over `rows` rows (all cells, or the listed ones)
+  auto large_pass = [&](int rows) {
+    if (rows <= 0) return;
     if (P.max_pattern <= 32 && support <= 128)
-      hipLaunchKernelGGL((k_htilde<T, 64, 256, 1024>), dim3(ne), dim3(64), 0, s, ha);
+      hipLaunchKernelGGL((k_htilde<T, 64, 256, 1024>), dim3(rows), dim3(64), 0, s, ha);
     else if (P.max_pattern <= 64 && support <= 512)
-      hipLaunchKernelGGL((k_htilde<T, 128, 1024, 1024>), dim3(ne), dim3(64), 0, s, ha);
+      hipLaunchKernelGGL((k_htilde<T, 128, 1024, 1024>), dim3(rows), dim3(64), 0, s, ha);
     else
-      hipLaunchKernelGGL((k_htilde<T, 256, 2048, 1024>), dim3(ne), dim3(64), 0, s, ha);
+      hipLaunchKernelGGL((k_htilde<T, 256, 2048, 1024>), dim3(rows), dim3(64), 0, s, ha);
     EDFA_CHECK_LAUNCH();
+  };
+  if (ne > 0 && P.max_pattern <= 64) {
+    // first pass with half-size tables (twice the occupancy); rows that fill them past half
+    // are listed and recomputed with the large tables
+    D.hretry.ensure(ne);
+    EDFA_HIP(hipMemsetAsync(P.flags.p + 3, 0, sizeof(int), s));
+    ha.retry_count = P.flags.p + 3;
+    ha.retry_list = D.hretry.p;
+    if (P.max_pattern <= 32)
+      hipLaunchKernelGGL((k_htilde<T, 64, 512, 512>), dim3(ne), dim3(64), 0, s, ha);
+    else
+      hipLaunchKernelGGL((k_htilde<T, 128, 512, 512>), dim3(ne), dim3(64), 0, s, ha);
+    EDFA_CHECK_LAUNCH();
+    const int nretry = read_scalar(P.flags.p + 3, s);
+    ha.retry_count = nullptr;
+    ha.retry_list = nullptr;
+    ha.cells = D.hretry.p;
+    large_pass(nretry);
+    ha.cells = nullptr;
+  } else {
+    large_pass(ne);
   }
   check_flags(P, s, "H~ rows");
   const int postH = prm.filt_mode == EDFA_FILT_POST_H;

@@ -5,10 +5,21 @@
 // matrix, Givens rotations and convergence state; all segments advance together and a
 // converged segment is masked out of the vector kernels.  Vectors are processed in
 // chunks that never straddle a segment, so every reduction is per segment and fixed in
-// order (deterministic).  Orthogonalisation: classical Gram-Schmidt with a second pass
-// only where the first one cancelled strongly, ||w - V h|| < ||w|| / sqrt(2) (the
-// reorthogonalisation criterion of Daniel, Gragg, Kaufman and Stewart, 1976), decided per
-// segment on the device.
+// order (deterministic).
+//
+// Orthogonalisation: classical Gram-Schmidt with the second (re-orthogonalisation) pass of
+// each basis vector delayed to the next iteration, where it shares the passes over the
+// basis with the first pass of the new vector (delayed CGS2, after Swirydowicz, Langou,
+// Ananthan, Yang and Thomas, 2020).  Iteration j holds Q = [q_0 .. q_{j-1}] and u_j, the
+// vector projected once but not yet re-orthogonalised or normalised; with w = A M^-1 u_j,
+//   one pass     a = Q^T u_j,  b = Q^T w,  nu = u_j . u_j,  beta = u_j . w
+//   per segment  rho = sqrt(nu - a.a); Hessenberg column j-1 becomes final (+= a, subdiagonal
+//                rho) and gets its Givens rotation; c = [b; (beta - a.b)/rho] = [Q q_j]^T w;
+//                the provisional column j is (c - Hbar a)/rho
+//   one pass     q_j = (u_j - Q a)/rho,  u_{j+1} = (w - Q b - q_j c_j)/rho
+// (w = rho A M^-1 q_j + A M^-1 Q a and A M^-1 Q = Q_{j+1} Hbar give these).  FGMRES also
+// corrects z_j = M^-1 u_j into M^-1 q_j.  The last column of a cycle is finalised by one
+// more pass of dots.
 #include <cmath>
 
 #include "precond.hpp"
@@ -18,57 +29,69 @@ namespace edfa {
 constexpr int CHUNK = 2048;   // elements per chunk: 256 threads x 8
 constexpr int RT = 256;
 
-// Partial dots tiled over (chunk, group of DG vectors): block (c, q) forms V_i . w on chunk c
-// for i in [DG q, DG q + DG); every thread keeps DG x 8 independent loads in flight and the
-// block reduces only DG values.  First pass (SECOND = false): blocks with q = 0 also form
-// w . w into component nv.  Second pass: only segments flagged for reorthogonalisation.
+// Partial dots tiled over (chunk, group of DG basis vectors): block (c, q) forms Q_i . u and
+// Q_i . w on chunk c for i in [DG q, DG q + DG); blocks with q = 0 also form u . u and u . w.
+// Components per chunk row: [Q^T u (nv) | Q^T w (nv) | u.u | u.w].
 constexpr int DG = 4;
-template <bool SECOND>
-__global__ __launch_bounds__(RT) void k_dots_tiled(const double *__restrict__ V, long long ldv,
-                                                   int nv, const double *__restrict__ w,
-                                                   const Chunk *__restrict__ ch,
-                                                   const SegState *__restrict__ st, double *part,
-                                                   int ldp) {
-  __shared__ double red[4][DG + 1];
+__global__ __launch_bounds__(RT) void k_dots2(const double *__restrict__ Q, long long ldq, int nv,
+                                              const double *__restrict__ u,
+                                              const double *__restrict__ w,
+                                              const Chunk *__restrict__ ch,
+                                              const SegState *__restrict__ st, double *part,
+                                              int ldp) {
+  __shared__ double red[4][2 * DG + 2];
   const Chunk c = ch[blockIdx.x];
-  if (!st[c.seg].active || (SECOND && !st[c.seg].reorth)) return;
+  if (!st[c.seg].active) return;
   const int i0 = blockIdx.y * DG;
-  const bool self = !SECOND && blockIdx.y == 0;
-  double acc[DG + 1];
+  const bool self = blockIdx.y == 0;
+  double au[DG], aw[DG], uu = 0.0, uw = 0.0;
 #pragma unroll
-  for (int g = 0; g <= DG; ++g) acc[g] = 0.0;
+  for (int g = 0; g < DG; ++g) au[g] = aw[g] = 0.0;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     const int e = c.start + threadIdx.x + k * RT;
     if (e < c.end) {
-      const double we = w[e];
+      const double ue = u[e], we = w[e];
 #pragma unroll
       for (int g = 0; g < DG; ++g)
-        if (i0 + g < nv) acc[g] += V[(long long)(i0 + g) * ldv + e] * we;
-      if (self) acc[DG] += we * we;
+        if (i0 + g < nv) {
+          const double q = Q[(long long)(i0 + g) * ldq + e];
+          au[g] += q * ue;
+          aw[g] += q * we;
+        }
+      if (self) {
+        uu += ue * ue;
+        uw += ue * we;
+      }
     }
   }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
-  for (int g = 0; g <= DG; ++g) {
-    double s = acc[g];
+  for (int g = 0; g < 2 * DG + 2; ++g) {
+    double v = g < DG ? au[g] : g < 2 * DG ? aw[g - DG] : g == 2 * DG ? uu : uw;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if (lane == 0) red[wave][g] = s;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == 0) red[wave][g] = v;
   }
   __syncthreads();
-  if (threadIdx.x < DG && i0 + threadIdx.x < nv) {
-    const int g = threadIdx.x;
-    part[(long long)blockIdx.x * ldp + i0 + g] = (red[0][g] + red[1][g]) + (red[2][g] + red[3][g]);
+  const int t = threadIdx.x;
+  if (t < 2 * DG + 2) {
+    const double v = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
+    double *row = part + (long long)blockIdx.x * ldp;
+    if (t < DG) {
+      if (i0 + t < nv) row[i0 + t] = v;
+    } else if (t < 2 * DG) {
+      if (i0 + t - DG < nv) row[nv + i0 + t - DG] = v;
+    } else if (self) {
+      row[2 * nv + (t - 2 * DG)] = v;
+    }
   }
-  if (self && threadIdx.x == DG)
-    part[(long long)blockIdx.x * ldp + nv] = (red[0][DG] + red[1][DG]) + (red[2][DG] + red[3][DG]);
 }
 
 // Per-segment sums of chunk partials: one wavefront per (segment, component), lanes strided
 // over the segment's chunks, then a fixed shuffle tree (no block barriers).
-// which: SEG_ALL, SEG_ACTIVE, or SEG_REORTH (active and flagged for a second pass).
-enum { SEG_ALL = 0, SEG_ACTIVE = 1, SEG_REORTH = 2 };
+// which: SEG_ALL or SEG_ACTIVE (only segments still iterating).
+enum { SEG_ALL = 0, SEG_ACTIVE = 1 };
 __global__ __launch_bounds__(256) void k_seg_reduce_w(const double *__restrict__ part, int ldp,
                                                       int ncomp, const int *__restrict__ segptr,
                                                       const SegState *__restrict__ st,
@@ -78,47 +101,12 @@ __global__ __launch_bounds__(256) void k_seg_reduce_w(const double *__restrict__
   const int lane = threadIdx.x & 63;
   if (i >= ncomp) return;
   if (which != SEG_ALL && !st[g].active) return;
-  if (which == SEG_REORTH && !st[g].reorth) return;
   const int c0 = segptr[g], c1 = segptr[g + 1];
   double s = 0;
   for (int c = c0 + lane; c < c1; c += 64) s += part[(long long)c * ldp + i];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
   if (lane == 0) out[(long long)g * ldo + i] = s;
-}
-
-// w -= sum_i h[seg][i] V_i and the partial ||w||^2 (second pass: flagged segments only)
-template <bool SECOND>
-__global__ __launch_bounds__(RT) void k_update(const double *__restrict__ V, long long ldv, int nv,
-                                               double *w, const Chunk *__restrict__ ch,
-                                               const SegState *__restrict__ st,
-                                               const double *__restrict__ h, int ldh, double *part,
-                                               int ldp) {
-  constexpr bool NORM = true;
-  __shared__ double hs[MAXV];
-  __shared__ double red[4];
-  const Chunk c = ch[blockIdx.x];
-  if (!st[c.seg].active || (SECOND && !st[c.seg].reorth)) return;
-  for (int i = threadIdx.x; i < nv; i += RT) hs[i] = h[(long long)c.seg * ldh + i];
-  __syncthreads();
-  double nrm = 0;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const int e = c.start + threadIdx.x + k * RT;
-    if (e < c.end) {
-      double x = w[e];
-      for (int i = 0; i < nv; ++i) x -= hs[i] * V[(long long)i * ldv + e];
-      w[e] = x;
-      if (NORM) nrm += x * x;
-    }
-  }
-  if (NORM) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) nrm += __shfl_xor(nrm, o);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nrm;
-    __syncthreads();
-    if (threadIdx.x == 0) part[(long long)blockIdx.x * ldp] = (red[0] + red[1]) + (red[2] + red[3]);
-  }
 }
 
 // partial sum of squares of x over each chunk (all non-done segments)
@@ -140,64 +128,172 @@ __global__ __launch_bounds__(RT) void k_nrm2_part(const double *__restrict__ x,
   if (threadIdx.x == 0) part[(long long)blockIdx.x * ldp] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// After the first pass: flag the segments whose projection removed more than half of
-// ||w||^2 (h1[nv] = ||w||^2 before, nrm = ||w - V h1||^2 after).
-__global__ void k_reorth_decide(int nseg, int nv, SegState *st, const double *__restrict__ h1,
-                                const double *__restrict__ nrm, int ldh) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= nseg || !st[g].active) return;
-  st[g].reorth = nrm[(long long)g * ldh] < 0.5 * h1[(long long)g * ldh + nv] ? 1 : 0;
-}
-
-// One wavefront per segment: lanes load the column and the rotations into LDS, lane 0
-// applies them in order.  The column is h1 (+ h2 after a second pass); the new subdiagonal
-// is the norm left by the last pass (nrm, or h2[j + 1] after a second pass).
-__global__ __launch_bounds__(64) void k_givens(int nseg, int m, int j, SegState *st,
-                                               const double *__restrict__ h1,
-                                               const double *__restrict__ h2,
-                                               const double *__restrict__ nrm2, int ldh,
-                                               double *R, double *cs, double *sn, double *gv,
-                                               double *scale, int max_iter) {
-  __shared__ double col[MAXV], c[MAXV], s[MAXV];
+// Per segment, one wavefront: finish column j-1 of the Hessenberg matrix with the
+// re-orthogonalisation coefficients a and rho, rotate it, update the residual estimate and
+// the convergence state; then (unless `final`) form the provisional column j and the
+// coefficients of the update pass: coef = [a (j) | c (j + 1)], scale = 1/rho.
+// d = reduced dots [a | b | nu | beta] of this iteration.  Hbar: unrotated columns, column k
+// at Hb + (g m + k)(m + 1).  j = 0: q_0 is already normalised (rho = 1, no column to finish).
+__global__ __launch_bounds__(64) void k_dcgs_step(int nseg, int m, int j, int final_, SegState *st,
+                                                  const double *__restrict__ d, int ldd,
+                                                  double *Hb, double *R, double *cs, double *sn,
+                                                  double *gv, double *coef, double *scale,
+                                                  int max_iter) {
+  __shared__ double a[MAXV], b[MAXV], col[MAXV], cc[MAXV], c_[MAXV], s_[MAXV];
+  __shared__ double sh_rho;
+  __shared__ int sh_live;
   const int g = blockIdx.x;
   if (g >= nseg || !st[g].active) return;
-  const bool two = st[g].reorth;
-  for (int i = threadIdx.x; i <= j; i += 64) {
-    col[i] = h1[(long long)g * ldh + i] + (two ? h2[(long long)g * ldh + i] : 0.0);
-    if (i < j) {
-      c[i] = cs[(long long)g * m + i];
-      s[i] = sn[(long long)g * m + i];
-    }
+  const int lane = threadIdx.x;
+  const double *dd = d + (long long)g * ldd;
+  double *H = Hb + (long long)g * m * (m + 1);
+  for (int i = lane; i < j; i += 64) {
+    a[i] = dd[i];
+    b[i] = dd[j + i];
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    SegState S = st[g];
-    const double hn = sqrt(two ? h2[(long long)g * ldh + j + 1] : nrm2[(long long)g * ldh]);
-    col[j + 1] = hn;
-    for (int i = 0; i < j; ++i) {
-      const double t = c[i] * col[i] + s[i] * col[i + 1];
-      col[i + 1] = -s[i] * col[i] + c[i] * col[i + 1];
-      col[i] = t;
+  double aa = 0, ab = 0;
+  for (int i = lane; i < j; i += 64) {
+    aa += a[i] * a[i];
+    ab += a[i] * b[i];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    aa += __shfl_xor(aa, o);
+    ab += __shfl_xor(ab, o);
+  }
+  const double nu = dd[2 * j], beta = dd[2 * j + 1];
+  if (j > 0) {
+    // column jf = j - 1 becomes final: Hbar[0:j, jf] += a, Hbar[j, jf] = rho
+    const int jf = j - 1;
+    const double r2 = nu - aa;
+    const double rho = r2 > 0 ? sqrt(r2) : 0.0;
+    double *hc = H + (long long)jf * (m + 1);
+    for (int i = lane; i < j; i += 64) {
+      hc[i] += a[i];
+      col[i] = hc[i];
+      if (i < jf) {
+        c_[i] = cs[(long long)g * m + i];
+        s_[i] = sn[(long long)g * m + i];
+      }
     }
-    const double den = hypot(col[j], col[j + 1]);
-    const double cj = den > 0 ? col[j] / den : 1.0, sj = den > 0 ? col[j + 1] / den : 0.0;
-    cs[(long long)g * m + j] = cj;
-    sn[(long long)g * m + j] = sj;
-    col[j] = den;
-    double *gg = gv + (long long)g * (m + 1);
-    const double gj = gg[j];
-    gg[j + 1] = -sj * gj;
-    gg[j] = cj * gj;
-    S.est = fabs(gg[j + 1]);
-    S.j = j + 1;
-    S.total += 1;
-    scale[g] = hn > 0 ? 1.0 / hn : 0.0;
-    if (!(S.est > S.tol) || !(hn > 0) || S.total >= max_iter || S.j >= m || !isfinite(S.est))
-      S.active = 0;
-    st[g] = S;
+    if (lane == 0) {
+      hc[j] = rho;
+      col[j] = rho;
+    }
+    __syncthreads();
+    if (lane == 0) {
+      SegState S = st[g];
+      for (int i = 0; i < jf; ++i) {
+        const double t = c_[i] * col[i] + s_[i] * col[i + 1];
+        col[i + 1] = -s_[i] * col[i] + c_[i] * col[i + 1];
+        col[i] = t;
+      }
+      const double den = hypot(col[jf], col[jf + 1]);
+      const double cj = den > 0 ? col[jf] / den : 1.0, sj = den > 0 ? col[jf + 1] / den : 0.0;
+      cs[(long long)g * m + jf] = cj;
+      sn[(long long)g * m + jf] = sj;
+      col[jf] = den;
+      double *gg = gv + (long long)g * (m + 1);
+      const double gj = gg[jf];
+      gg[jf + 1] = -sj * gj;
+      gg[jf] = cj * gj;
+      S.est = fabs(gg[jf + 1]);
+      S.j = j;
+      S.total += 1;
+      if (final_ || !(S.est > S.tol) || !(rho > 0) || S.total >= max_iter || !isfinite(S.est))
+        S.active = 0;
+      st[g] = S;
+      sh_live = S.active;
+      sh_rho = rho;
+    }
+    __syncthreads();
+    for (int i = lane; i <= jf; i += 64) R[((long long)g * m + i) * m + jf] = col[i];
+    if (!sh_live) return;
+  } else {
+    if (lane == 0) {
+      sh_rho = 1.0;
+      sh_live = 1;
+    }
+    __syncthreads();
+  }
+  // provisional column j: (c - Hbar[0:j+1, 0:j] a) / rho, c = [b ; (beta - a.b)/rho]
+  const double rho = sh_rho;
+  for (int i = lane; i < j; i += 64) cc[i] = b[i];
+  if (lane == 0) cc[j] = (beta - ab) / rho;
+  __syncthreads();
+  double *hn = H + (long long)j * (m + 1);
+  for (int i = lane; i <= j; i += 64) {
+    double t = cc[i];
+    for (int k = (i > 0 ? i - 1 : 0); k < j; ++k) t -= H[(long long)k * (m + 1) + i] * a[k];
+    hn[i] = t / rho;
+  }
+  double *cf = coef + (long long)g * (2 * m + 2);
+  for (int i = lane; i < j; i += 64) cf[i] = a[i];
+  for (int i = lane; i <= j; i += 64) cf[j + i] = cc[i];
+  if (lane == 0) scale[g] = 1.0 / rho;
+}
+
+// q_j = (u_j - Q a) / rho (in place in slot j) and u_{j+1} = (w - Q b - q_j c_j) / rho
+// (into slot j + 1); coef = [a (j) | b (j) | c_j], scale = 1/rho.
+__global__ __launch_bounds__(RT) void k_dcgs_update(double *Q, long long ldq, int j,
+                                                    const double *__restrict__ w,
+                                                    const Chunk *__restrict__ ch,
+                                                    const SegState *__restrict__ st,
+                                                    const double *__restrict__ coef, int ldc,
+                                                    const double *__restrict__ scale) {
+  __shared__ double sa[MAXV], sb[MAXV];
+  const Chunk c = ch[blockIdx.x];
+  if (!st[c.seg].active) return;
+  const double *cf = coef + (long long)c.seg * ldc;
+  for (int i = threadIdx.x; i < j; i += RT) {
+    sa[i] = cf[i];
+    sb[i] = cf[j + i];
   }
   __syncthreads();
-  for (int i = threadIdx.x; i <= j; i += 64) R[((long long)g * m + i) * m + j] = col[i];
+  const double cj = cf[2 * j], ir = scale[c.seg];
+  double *uj = Q + (long long)j * ldq;
+  double *un = Q + (long long)(j + 1) * ldq;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int e = c.start + threadIdx.x + k * RT;
+    if (e < c.end) {
+      double u = uj[e], x = w[e];
+      for (int i = 0; i < j; ++i) {
+        const double q = Q[(long long)i * ldq + e];
+        u -= sa[i] * q;
+        x -= sb[i] * q;
+      }
+      const double qj = u * ir;
+      uj[e] = qj;
+      un[e] = (x - cj * qj) * ir;
+    }
+  }
+}
+
+// FGMRES: z_j = (z_j - Z a) / rho turns M^-1 u_j into M^-1 q_j.
+__global__ __launch_bounds__(RT) void k_dcgs_update_z(double *Z, long long ldz, int j,
+                                                      const Chunk *__restrict__ ch,
+                                                      const SegState *__restrict__ st,
+                                                      const double *__restrict__ coef, int ldc,
+                                                      const double *__restrict__ scale) {
+  __shared__ double sa[MAXV];
+  const Chunk c = ch[blockIdx.x];
+  if (!st[c.seg].active) return;
+  const double *cf = coef + (long long)c.seg * ldc;
+  for (int i = threadIdx.x; i < j; i += RT) sa[i] = cf[i];
+  __syncthreads();
+  const double ir = scale[c.seg];
+  double *zj = Z + (long long)j * ldz;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int e = c.start + threadIdx.x + k * RT;
+    if (e < c.end) {
+      double z = zj[e];
+      for (int i = 0; i < j; ++i) z -= sa[i] * Z[(long long)i * ldz + e];
+      zj[e] = z * ir;
+    }
+  }
 }
 
 // V_{j+1} = w * scale[seg] (active segments); with j < 0: V_0 = r / beta for starting ones.
@@ -361,7 +457,7 @@ edfa_status gmres(edfa_system_s &S, edfa_precond_s &P, const double *b, double *
   const int tr = prm.transpose ? 1 : 0;
   build_chunks(S, W, s);
   const int nch = W.nchunk;
-  const int ld = m + 2;   // leading dimension of per-chunk / per-segment coefficient rows
+  const int ld = 2 * m + 4;   // per-chunk / per-segment rows of dot products (2j + 2 used)
   W.V.ensure((size_t)(m + 1) * n);
   if (prm.flexible) W.Z.ensure((size_t)m * n);
   W.w.ensure(n);
@@ -369,9 +465,10 @@ edfa_status gmres(edfa_system_s &S, edfa_precond_s &P, const double *b, double *
   W.z.ensure(n);
   W.part.ensure((size_t)nch * ld);
   W.h1.ensure((size_t)nseg * ld);
-  W.h2.ensure((size_t)nseg * ld);
   W.nrm.ensure((size_t)nseg * ld);
   W.R.ensure((size_t)nseg * m * m);
+  W.Hb.ensure((size_t)nseg * m * (m + 1));
+  W.coef.ensure((size_t)nseg * (2 * m + 2));
   W.cs.ensure((size_t)nseg * m);
   W.sn.ensure((size_t)nseg * m);
   W.g.ensure((size_t)nseg * (m + 1));
@@ -440,38 +537,31 @@ edfa_status gmres(edfa_system_s &S, edfa_precond_s &P, const double *b, double *
   // segment is inactive; without, converged segments are masked on the device (the
   // form that a graph can hold).
   auto run_cycle = [&](hipStream_t cs, bool host_checks) {
+    // q_0 = r / beta
     hipLaunchKernelGGL(k_scale, dim3(nch), dim3(RT), 0, cs, W.r.p, W.V.p, W.chunks.p, W.st.p,
                        W.scale.p);
     EDFA_CHECK_LAUNCH();
+    // dots of basis slots [0, j) against u and w, reduced per segment into h1
+    auto dots = [&](int j, const double *u, const double *w) {
+      hipLaunchKernelGGL(k_dots2, dim3(nch, std::max(1, ceil_div(j, DG))), dim3(RT), 0, cs, W.V.p,
+                         (long long)n, j, u, w, W.chunks.p, W.st.p, W.part.p, ld);
+      hipLaunchKernelGGL(k_seg_reduce_w, dim3(ceil_div(2 * j + 2, 4), nseg), dim3(256), 0, cs,
+                         W.part.p, ld, 2 * j + 2, W.segptr.p, W.st.p, SEG_ACTIVE, W.h1.p, ld);
+    };
     for (int j = 0; j < m; ++j) {
       double *vj = W.V.p + (size_t)j * n;
       double *zj = prm.flexible ? W.Z.p + (size_t)j * n : W.z.p;
       applyP(vj, zj, cs);
       spmvA(zj, W.w.p, nullptr, cs);
-      // first pass: h1 = V^T w and ||w||^2, w -= V h1, ||w||^2 after
-      hipLaunchKernelGGL(k_dots_tiled<false>, dim3(nch, ceil_div(j + 1, DG)), dim3(RT), 0, cs,
-                         W.V.p, (long long)n, j + 1, W.w.p, W.chunks.p, W.st.p, W.part.p, ld);
-      hipLaunchKernelGGL(k_seg_reduce_w, dim3(ceil_div(j + 2, 4), nseg), dim3(256), 0, cs,
-                         W.part.p, ld, j + 2, W.segptr.p, W.st.p, SEG_ACTIVE, W.h1.p, ld);
-      hipLaunchKernelGGL(k_update<false>, dim3(nch), dim3(RT), 0, cs, W.V.p, (long long)n, j + 1,
-                         W.w.p, W.chunks.p, W.st.p, W.h1.p, ld, W.part.p, ld);
-      hipLaunchKernelGGL(k_seg_reduce_w, dim3(1, nseg), dim3(256), 0, cs, W.part.p, ld, 1,
-                         W.segptr.p, W.st.p, SEG_ACTIVE, W.nrm.p, ld);
-      hipLaunchKernelGGL(k_reorth_decide, dim3(sb), dim3(64), 0, cs, nseg, j + 1, W.st.p, W.h1.p,
-                         W.nrm.p, ld);
-      // second pass where flagged: h2 = V^T w, w -= V h2, ||w||^2 into h2[j + 1]
-      hipLaunchKernelGGL(k_dots_tiled<true>, dim3(nch, ceil_div(j + 1, DG)), dim3(RT), 0, cs,
-                         W.V.p, (long long)n, j + 1, W.w.p, W.chunks.p, W.st.p, W.part.p, ld);
-      hipLaunchKernelGGL(k_seg_reduce_w, dim3(ceil_div(j + 1, 4), nseg), dim3(256), 0, cs,
-                         W.part.p, ld, j + 1, W.segptr.p, W.st.p, SEG_REORTH, W.h2.p, ld);
-      hipLaunchKernelGGL(k_update<true>, dim3(nch), dim3(RT), 0, cs, W.V.p, (long long)n, j + 1,
-                         W.w.p, W.chunks.p, W.st.p, W.h2.p, ld, W.part.p, ld);
-      hipLaunchKernelGGL(k_seg_reduce_w, dim3(1, nseg), dim3(256), 0, cs, W.part.p, ld, 1,
-                         W.segptr.p, W.st.p, SEG_REORTH, W.h2.p + (j + 1), ld);
-      hipLaunchKernelGGL(k_givens, dim3(nseg), dim3(64), 0, cs, nseg, m, j, W.st.p, W.h1.p, W.h2.p,
-                         W.nrm.p, ld, W.R.p, W.cs.p, W.sn.p, W.g.p, W.scale.p, prm.max_iter);
-      hipLaunchKernelGGL(k_scale, dim3(nch), dim3(RT), 0, cs, W.w.p, W.V.p + (size_t)(j + 1) * n,
-                         W.chunks.p, W.st.p, W.scale.p);
+      dots(j, vj, W.w.p);
+      hipLaunchKernelGGL(k_dcgs_step, dim3(nseg), dim3(64), 0, cs, nseg, m, j, 0, W.st.p, W.h1.p,
+                         ld, W.Hb.p, W.R.p, W.cs.p, W.sn.p, W.g.p, W.coef.p, W.scale.p,
+                         prm.max_iter);
+      hipLaunchKernelGGL(k_dcgs_update, dim3(nch), dim3(RT), 0, cs, W.V.p, (long long)n, j, W.w.p,
+                         W.chunks.p, W.st.p, W.coef.p, 2 * m + 2, W.scale.p);
+      if (prm.flexible)
+        hipLaunchKernelGGL(k_dcgs_update_z, dim3(nch), dim3(RT), 0, cs, W.Z.p, (long long)n, j,
+                           W.chunks.p, W.st.p, W.coef.p, 2 * m + 2, W.scale.p);
       EDFA_CHECK_LAUNCH();
       if (host_checks && (j + 1) % check_every == 0 && j + 1 < m) {
         EDFA_HIP(hipMemcpyAsync(hst.data(), W.st.p, sizeof(SegState) * nseg, hipMemcpyDeviceToHost, cs));
@@ -481,6 +571,12 @@ edfa_status gmres(edfa_system_s &S, edfa_precond_s &P, const double *b, double *
         if (!a) break;
       }
     }
+    // segments whose basis is full: finish the last column with one more pass of dots
+    dots(m, W.V.p + (size_t)m * n, W.V.p + (size_t)m * n);
+    hipLaunchKernelGGL(k_dcgs_step, dim3(nseg), dim3(64), 0, cs, nseg, m, m, 1, W.st.p, W.h1.p,
+                       ld, W.Hb.p, W.R.p, W.cs.p, W.sn.p, W.g.p, W.coef.p, W.scale.p,
+                       prm.max_iter);
+    EDFA_CHECK_LAUNCH();
     // end of cycle: y = R^-1 g, x += Z y (flexible) or x += P^-1 (V y)
     hipLaunchKernelGGL(k_record_ran, dim3(sb), dim3(64), 0, cs, nseg, W.st.p, W.ran.p);
     hipLaunchKernelGGL(k_lsq, dim3(sb), dim3(64), 0, cs, nseg, m, W.st.p, W.R.p, W.g.p, W.y.p, W.ran.p);

@@ -67,6 +67,45 @@ __device__ inline T wave_sum(T v) {
 
 __device__ inline int pidx(int i, int j) { return i * (i + 1) / 2 + j; }   // packed lower
 
+#define EDFA_INLINE __attribute__((always_inline))
+
+// Visit the entries of CSR row r in blocks of RB: every index (and value) of a block is
+// requested before f runs on any of them, so a row's loads are in flight together instead
+// of one behind each hash lookup.  Positions past the row's end re-read its last entry
+// (always in bounds) and are not passed to f.
+template <int RB, class F>
+__device__ __forceinline__ void row_cols(const int *__restrict__ rp, const int *__restrict__ col,
+                                         int r, F &&f) {
+  const int p0 = rp[r], p1 = rp[r + 1];
+  for (int b = p0; b < p1; b += RB) {
+    int c[RB];
+#pragma unroll
+    for (int k = 0; k < RB; ++k) c[k] = col[min(b + k, p1 - 1)];
+#pragma unroll
+    for (int k = 0; k < RB; ++k)
+      if (b + k < p1) f(c[k]);
+  }
+}
+
+template <int RB, class V, class F>
+__device__ __forceinline__ void row_entries(const int *__restrict__ rp, const int *__restrict__ col,
+                                            const V *__restrict__ val, int r, F &&f) {
+  const int p0 = rp[r], p1 = rp[r + 1];
+  for (int b = p0; b < p1; b += RB) {
+    int c[RB];
+    V v[RB];
+#pragma unroll
+    for (int k = 0; k < RB; ++k) {
+      const int p = min(b + k, p1 - 1);
+      c[k] = col[p];
+      v[k] = val[p];
+    }
+#pragma unroll
+    for (int k = 0; k < RB; ++k)
+      if (b + k < p1) f(c[k], v[k]);
+  }
+}
+
 // |r| rounded to 40 significant bits, as a monotone unsigned key.
 __device__ inline unsigned long long key40(double r) {
   unsigned long long b = (unsigned long long)__double_as_longlong(fabs(r));
@@ -433,7 +472,6 @@ constexpr int pow2ceil(int x) { return x <= 1 ? 1 : 2 * pow2ceil((x + 1) / 2); }
 
 // f(std::integral_constant<int, i>) for i = B .. E-1: register arrays indexed by i stay in
 // registers (the bodies must be inlined: lambdas passed here are marked EDFA_INLINE).
-#define EDFA_INLINE __attribute__((always_inline))
 template <int B, int E, class F>
 __device__ __forceinline__ void static_for(F &&f) {
   if constexpr (B < E) {
@@ -504,14 +542,13 @@ __global__ __launch_bounds__(64) void k_local_reg(LocalArgs<T> A) {
   for (int t = lane; t < LP; t += 64) Lp[t] = 0;
   __syncthreads();
   if (lane < s) {
-    const int r = q[lane];
-    for (int p = A.app_rp[r]; p < A.app_rp[r + 1]; ++p) {
-      const int h = h_find<QH>(qk, A.app_col[p]);
+    row_entries<12>(A.app_rp, A.app_col, A.app_val, q[lane], [&](int c, double v) EDFA_INLINE {
+      const int h = h_find<QH>(qk, c);
       if (h >= 0) {
         const int k = qv[h];
-        if (k <= lane) Lp[pidx(lane, k)] = -(T)A.app_val[p];
+        if (k <= lane) Lp[pidx(lane, k)] = -(T)v;
       }
-    }
+    });
   }
   __syncthreads();
 
@@ -601,14 +638,12 @@ __global__ __launch_bounds__(64) void k_local_reg(LocalArgs<T> A) {
     if (lane == 0) ccount = 0;
     __syncthreads();
     if (lane < s) {
-      const int r = q[lane];
-      for (int p = A.app_rp[r]; p < A.app_rp[r + 1]; ++p) {
-        const int c = A.app_col[p];
+      row_cols<12>(A.app_rp, A.app_col, q[lane], [&](int c) EDFA_INLINE {
         if (h_find<QH>(qk, c) < 0) {
           bool fr;
           if (h_insert<CH>(ck, c, fr) < 0) sflag = 1;
         }
-      }
+      });
     }
     __syncthreads();
     if (sflag) {
@@ -621,12 +656,11 @@ __global__ __launch_bounds__(64) void k_local_reg(LocalArgs<T> A) {
     const int nc = ccount;
     // r_j = (A_pipi R^T g~)_j for j outside Q (a_ppi^(m) vanishes there)
     for (int c = lane; c < nc; c += 64) {
-      const int j = clist[c];
       T acc = 0;
-      for (int p = A.app_rp[j]; p < A.app_rp[j + 1]; ++p) {
-        const int h = h_find<QH>(qk, A.app_col[p]);
-        if (h >= 0) acc += (T)A.app_val[p] * xs[qv[h]];
-      }
+      row_entries<12>(A.app_rp, A.app_col, A.app_val, clist[c], [&](int col, double v) EDFA_INLINE {
+        const int h = h_find<QH>(qk, col);
+        if (h >= 0) acc += (T)v * xs[qv[h]];
+      });
       cr[c] = acc;
     }
     __syncthreads();
@@ -843,15 +877,14 @@ __global__ __launch_bounds__(64) void k_htilde(HArgs<T> A) {
   }
   // support of t = A_pipi R^T g~: A_pipi neighbours of the pattern of g~
   for (int p = g0 + lane; p < g1; p += 64) {
-    const int k = A.g_col[p];
-    for (int q = A.app_rp[k]; q < A.app_rp[k + 1]; ++q) {
+    row_cols<12>(A.app_rp, A.app_col, A.g_col[p], [&](int c) EDFA_INLINE {
       bool fr;
-      const int h = h_insert<TH>(tk, A.app_col[q], fr);
+      const int h = h_insert<TH>(tk, c, fr);
       if (h < 0)
         sflag = 1;
       else if (fr)
         tlist[atomicAdd(&tcount, 1)] = h;
-    }
+    });
   }
   __syncthreads();
   if (A.retry_count && (sflag || tcount > TH / 2)) {
@@ -865,25 +898,23 @@ __global__ __launch_bounds__(64) void k_htilde(HArgs<T> A) {
   const int nt = tcount;
   for (int c = lane; c < nt; c += 64) {
     const int h = tlist[c];
-    const int j = tk[h];
     T acc = 0;
-    for (int q = A.app_rp[j]; q < A.app_rp[j + 1]; ++q) {
-      const int s = h_find<GH>(gk, A.app_col[q]);
-      if (s >= 0) acc += (T)A.app_val[q] * gv[s];
-    }
+    row_entries<12>(A.app_rp, A.app_col, A.app_val, tk[h], [&](int col, double v) EDFA_INLINE {
+      const int s = h_find<GH>(gk, col);
+      if (s >= 0) acc += (T)v * gv[s];
+    });
     tv[h] = acc;
   }
   // candidate cells: all l with F~[j, l] != 0 for j in the support of t
   for (int c = lane; c < nt; c += 64) {
-    const int j = tk[tlist[c]];
-    for (int q = A.ff_rp[j]; q < A.ff_rp[j + 1]; ++q) {
+    row_cols<16>(A.ff_rp, A.ff_col, tk[tlist[c]], [&](int l) EDFA_INLINE {
       bool fr;
-      const int h = h_insert<LH>(lk, A.ff_col[q], fr);
+      const int h = h_insert<LH>(lk, l, fr);
       if (h < 0)
         sflag = 1;
       else if (fr)
-        llist[atomicAdd(&lcount, 1)] = A.ff_col[q];
-    }
+        llist[atomicAdd(&lcount, 1)] = l;
+    });
   }
   __syncthreads();
   const int nl = lcount;
@@ -897,12 +928,11 @@ __global__ __launch_bounds__(64) void k_htilde(HArgs<T> A) {
   }
   // h_ml = sum over the pattern of f~_l of t_j f~_l[j]   (F~^T row l, ascending j)
   for (int c = lane; c < nl; c += 64) {
-    const int l = llist[c];
     T acc = 0;
-    for (int q = A.ft_rp[l]; q < A.ft_rp[l + 1]; ++q) {
-      const int s = h_find<TH>(tk, A.ft_col[q]);
-      if (s >= 0) acc += tv[s] * A.ft_val[q];
-    }
+    row_entries<16>(A.ft_rp, A.ft_col, A.ft_val, llist[c], [&](int col, T v) EDFA_INLINE {
+      const int s = h_find<TH>(tk, col);
+      if (s >= 0) acc += tv[s] * v;
+    });
     hv[c] = acc;
   }
   __syncthreads();

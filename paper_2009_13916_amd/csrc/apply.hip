@@ -64,7 +64,7 @@ static void to_fp32(const Csr<double> &M, Csr<float> &F, hipStream_t s) {
 // a gather and a scatter of the vector.
 template <class T>
 static void sinv(edfa_precond_s &P, PrecData<T> &D, int transpose, const T *y, T *zp,
-                 hipStream_t s) {
+                 hipStream_t s, RowMask cm) {
   const int ne = P.sys->ne;
   const int gb = ceil_div(ne, 256);
   D.w.ensure(ne);
@@ -78,15 +78,16 @@ static void sinv(edfa_precond_s &P, PrecData<T> &D, int transpose, const T *y, T
     const Sell<T> &T2 = transpose ? D.LT_s : D.U_s;
     const double g1 = transpose ? 0.0 : -1.0;   // (I + L) w = L w + w
     const double g2 = transpose ? -1.0 : 0.0;
-    spmv_sell<T, T>(M1, y, D.w.p, 1.0, nullptr, 0.0, s);
+    const int R = SPMV_PRECOND;
+    spmv_sell<T, T>(M1, y, D.w.p, 1.0, nullptr, 0.0, s, 0.0, R, nullptr, nullptr, cm);
     for (int k = 1; k < steps; ++k) {
-      spmv_sell<T, T>(T1, D.w.p, D.res.p, -1.0, y, 1.0, s, g1);
-      spmv_sell<T, T>(M1, D.res.p, D.w.p, 1.0, D.w.p, 1.0, s);
+      spmv_sell<T, T>(T1, D.w.p, D.res.p, -1.0, y, 1.0, s, g1, R, nullptr, nullptr, cm);
+      spmv_sell<T, T>(M1, D.res.p, D.w.p, 1.0, D.w.p, 1.0, s, 0.0, R, nullptr, nullptr, cm);
     }
-    spmv_sell<T, T>(M2, D.w.p, zp, 1.0, nullptr, 0.0, s);
+    spmv_sell<T, T>(M2, D.w.p, zp, 1.0, nullptr, 0.0, s, 0.0, R, nullptr, nullptr, cm);
     for (int k = 1; k < steps; ++k) {
-      spmv_sell<T, T>(T2, zp, D.res.p, -1.0, D.w.p, 1.0, s, g2);
-      spmv_sell<T, T>(M2, D.res.p, zp, 1.0, zp, 1.0, s);
+      spmv_sell<T, T>(T2, zp, D.res.p, -1.0, D.w.p, 1.0, s, g2, R, nullptr, nullptr, cm);
+      spmv_sell<T, T>(M2, D.res.p, zp, 1.0, zp, 1.0, s, 0.0, R, nullptr, nullptr, cm);
     }
     return;
   }
@@ -149,31 +150,36 @@ static void ensure_transposed_factors(edfa_precond_s &P, PrecData<T> &D, hipStre
 }
 
 // z = P^-1 r (or P^-T r) in precision T; c1 = A_ppi (A_pip^T), c2 = A_pip (A_ppi^T).
+// fm / cm: rows of face / cell unknowns to skip (grids of a batch that have converged).
 template <class T>
 static void apply_typed(edfa_precond_s &P, PrecData<T> &D, const T *r, T *z, const Sell<T> &c1,
-                        const Sell<T> &c2, int transpose, hipStream_t s) {
+                        const Sell<T> &c2, int transpose, hipStream_t s, RowMask fm,
+                        RowMask cm) {
   edfa_system_s &S = *P.sys;
   const int nfu = S.nfu, ne = S.ne;
+  const int R = SPMV_PRECOND;
   D.t1.ensure(nfu);
   D.t2.ensure(nfu);
   D.r.ensure(ne);
   const T *rpi = r, *rp = r + nfu;
   T *zpi = z, *zp = z + nfu;
   // t = A~^-1 r_pi = -G_F^T G_F r_pi
-  spmv_sell<T, T>(D.GF_s, rpi, D.t1.p, 1.0, nullptr, 0.0, s);
-  spmv_sell<T, T>(D.GFT_s, D.t1.p, D.t2.p, -1.0, nullptr, 0.0, s);
+  spmv_sell<T, T>(D.GF_s, rpi, D.t1.p, 1.0, nullptr, 0.0, s, 0.0, R, nullptr, nullptr, fm);
+  spmv_sell<T, T>(D.GFT_s, D.t1.p, D.t2.p, -1.0, nullptr, 0.0, s, 0.0, R, nullptr, nullptr, fm);
   // y = r_p - A_ppi t
-  spmv_sell<T, T>(c1, D.t2.p, D.r.p, -1.0, rp, 1.0, s);
+  spmv_sell<T, T>(c1, D.t2.p, D.r.p, -1.0, rp, 1.0, s, 0.0, R, nullptr, nullptr, cm);
   // z_p = S~^-1 y
-  sinv<T>(P, D, transpose, D.r.p, zp, s);
+  sinv<T>(P, D, transpose, D.r.p, zp, s, cm);
   // z_pi = A~^-1 (r_pi - A_pip z_p)
-  spmv_sell<T, T>(c2, zp, D.t1.p, -1.0, rpi, 1.0, s);
-  spmv_sell<T, T>(D.GF_s, D.t1.p, D.t2.p, 1.0, nullptr, 0.0, s);
-  spmv_sell<T, T>(D.GFT_s, D.t2.p, zpi, -1.0, nullptr, 0.0, s);
+  spmv_sell<T, T>(c2, zp, D.t1.p, -1.0, rpi, 1.0, s, 0.0, R, nullptr, nullptr, fm);
+  spmv_sell<T, T>(D.GF_s, D.t1.p, D.t2.p, 1.0, nullptr, 0.0, s, 0.0, R, nullptr, nullptr, fm);
+  spmv_sell<T, T>(D.GFT_s, D.t2.p, zpi, -1.0, nullptr, 0.0, s, 0.0, R, nullptr, nullptr, fm);
 }
 
-void precond_apply(edfa_precond_s &P, int transpose, const double *r, double *z, hipStream_t s) {
+void precond_apply(edfa_precond_s &P, int transpose, const double *r, double *z, hipStream_t s,
+                   RowMask mask) {
   edfa_system_s &S = *P.sys;
+  const RowMask fm = mask, cm = mask.offset(S.nfu);
   if (transpose) {
     if (P.prm.precision == 1)
       ensure_transposed_factors(P, P.f, s);
@@ -183,7 +189,7 @@ void precond_apply(edfa_precond_s &P, int transpose, const double *r, double *z,
   }
   if (P.prm.precision != 1) {
     apply_typed<double>(P, P.d, r, z, transpose ? S.AfcT_s : S.Acf_s,
-                        transpose ? S.AcfT_s : S.Afc_s, transpose, s);
+                        transpose ? S.AcfT_s : S.Afc_s, transpose, s, fm, cm);
     return;
   }
   // FP32 application: convert in, apply, convert out
@@ -208,7 +214,7 @@ void precond_apply(edfa_precond_s &P, int transpose, const double *r, double *z,
                      (long long)n, rin.p);
   EDFA_CHECK_LAUNCH();
   apply_typed<float>(P, D, rin.p, D.z.p, transpose ? cs[2] : cs[0], transpose ? cs[3] : cs[1],
-                     transpose, s);
+                     transpose, s, fm, cm);
   hipLaunchKernelGGL((k_convert<float, double>), dim3(ceil_div(n, 256)), dim3(256), 0, s, D.z.p,
                      (long long)n, z);
   EDFA_CHECK_LAUNCH();

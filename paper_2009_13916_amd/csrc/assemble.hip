@@ -5,6 +5,8 @@
 // eq. fluxes_MHFEM_STRONG (cells), i.e. the entry lists of Appendix A.  Every row is
 // built by one thread from the cell matrices it touches (gather, no atomics), so the
 // result is deterministic.
+#include <algorithm>
+
 #include "system.hpp"
 
 namespace edfa {
@@ -603,6 +605,17 @@ void compute_ranges(edfa_system_s &S, hipStream_t s) {
   S.ranges.ensure(S.ngrid);
   EDFA_HIP(hipMemcpyAsync(S.ranges.p, S.ranges_h.data(), sizeof(GridRange) * S.ngrid,
                           hipMemcpyHostToDevice, s));
+  if (S.ngrid > 1) {
+    // grid of every unknown: face unknowns first, then cells
+    std::vector<int> seg((size_t)S.nfu + S.ne);
+    for (int g = 0; g < S.ngrid; ++g) {
+      const GridRange &R = S.ranges_h[g];
+      std::fill(seg.begin() + R.uf0, seg.begin() + R.uf1, g);
+      std::fill(seg.begin() + S.nfu + R.c0, seg.begin() + S.nfu + R.c1, g);
+    }
+    S.rowseg.ensure(seg.size());
+    EDFA_HIP(hipMemcpyAsync(S.rowseg.p, seg.data(), sizeof(int) * seg.size(), hipMemcpyHostToDevice, s));
+  }
   EDFA_HIP(hipStreamSynchronize(s));
 }
 

@@ -157,6 +157,15 @@ void spmv(const int *rowptr, const int *col, const V *val, int rows, const X *x,
 template <class V>
 void build_sell(const Csr<V> &M, Sell<V> &S, DBuf<int> &tmp, hipStream_t s);
 
+// Rows to skip in a product: row r is computed only if act[seg[r] * stride] != 0 (the
+// activity flag of its grid).  seg == NULL computes every row.
+struct RowMask {
+  const int *seg = nullptr;
+  const int *act = nullptr;
+  int stride = 0;
+  RowMask offset(int rows) const { return seg ? RowMask{seg + rows, act, stride} : RowMask{}; }
+};
+
 // Same contract as spmv() for a SELL-64 matrix.  `role` picks the kernel symbol:
 // SPMV_OPERATOR for products with the system matrix, SPMV_PRECOND for everything else.
 // Non-null events e0/e1 are recorded by the launch itself around the kernel.
@@ -164,6 +173,6 @@ enum { SPMV_OPERATOR = 0, SPMV_PRECOND = 1 };
 template <class V, class X>
 void spmv_sell(const Sell<V> &M, const X *x, X *y, double alpha, const X *b, double beta,
                hipStream_t s, double gamma = 0.0, int role = SPMV_PRECOND,
-               hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+               hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr, RowMask mask = {});
 
 }  // namespace edfa

@@ -37,6 +37,7 @@ struct PrecData {
   DBuf<int> color, perm, iperm;     // perm[new] = old
   DBuf<int> hist, wide;             // colour histograms; wide static patches
   DBuf<int> resume;                 // colouring: where each vertex's neighbour scan stopped
+  DBuf<int> jplist;                 // colouring: vertices still uncoloured
   std::vector<int> cstart;          // host: colour c owns new rows [cstart[c], cstart[c+1])
   Csr<T> B;             // P S~ P^T, factored in place into L\U
   DBuf<int> diag;       // Ne: position of the diagonal in B
@@ -97,7 +98,8 @@ struct edfa_precond_s {
 namespace edfa {
 void precond_stage1(edfa_precond_s &P, hipStream_t s);
 void precond_stage2(edfa_precond_s &P, hipStream_t s);
-void precond_apply(edfa_precond_s &P, int transpose, const double *r, double *z, hipStream_t s);
+void precond_apply(edfa_precond_s &P, int transpose, const double *r, double *z, hipStream_t s,
+                   RowMask mask = {});
 edfa_status gmres(edfa_system_s &S, edfa_precond_s &P, const double *b, double *x,
                   const edfa_solve_params &prm, hipStream_t s, edfa_solve_info *info);
 template <class T>

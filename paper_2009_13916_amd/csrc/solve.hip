@@ -493,24 +493,33 @@ edfa_status gmres(edfa_system_s &S, edfa_precond_s &P, const double *b, double *
   total.start(s);
 
   // profiled system products: the launch records its own events around the kernel
+  // Inside the Arnoldi loop of a batch, the products skip the rows of grids that have
+  // stopped iterating (every matrix is block-diagonal by grid).
+  RowMask live;
+  if (nseg > 1) {
+    if (S.rowseg.n < (size_t)n) fail(EDFA_ERR_ARG, "batch without its row-to-grid map");
+    live = RowMask{S.rowseg.p, &W.st.p->active, (int)(sizeof(SegState) / sizeof(int))};
+  }
   // profiling events are recorded on the caller's stream only (never inside a capture)
-  auto spmvA = [&](const double *in, double *out, const double *bb, hipStream_t cs) {
+  auto spmvA = [&](const double *in, double *out, const double *bb, hipStream_t cs,
+                   RowMask mk) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (prm.profile && cs == s) {
       e0 = prof.get();
       e1 = prof.get();
       ev_spmv.emplace_back(e0, e1);
     }
-    spmv_sell<double, double>(A, in, out, bb ? -1.0 : 1.0, bb, 1.0, cs, 0.0, SPMV_OPERATOR, e0, e1);
+    spmv_sell<double, double>(A, in, out, bb ? -1.0 : 1.0, bb, 1.0, cs, 0.0, SPMV_OPERATOR, e0, e1,
+                              mk);
   };
-  auto applyP = [&](const double *in, double *out, hipStream_t cs) {
+  auto applyP = [&](const double *in, double *out, hipStream_t cs, RowMask mk) {
     const bool pr = prm.profile && cs == s;
     hipEvent_t e0{}, e1{};
     if (pr) {
       e0 = prof.get();
       EDFA_HIP(hipEventRecord(e0, cs));
     }
-    precond_apply(P, tr, in, out, cs);
+    precond_apply(P, tr, in, out, cs, mk);
     if (pr) {
       e1 = prof.get();
       EDFA_HIP(hipEventRecord(e1, cs));
@@ -551,8 +560,8 @@ edfa_status gmres(edfa_system_s &S, edfa_precond_s &P, const double *b, double *
     for (int j = 0; j < m; ++j) {
       double *vj = W.V.p + (size_t)j * n;
       double *zj = prm.flexible ? W.Z.p + (size_t)j * n : W.z.p;
-      applyP(vj, zj, cs);
-      spmvA(zj, W.w.p, nullptr, cs);
+      applyP(vj, zj, cs, live);
+      spmvA(zj, W.w.p, nullptr, cs, live);
       dots(j, vj, W.w.p);
       hipLaunchKernelGGL(k_dcgs_step, dim3(nseg), dim3(64), 0, cs, nseg, m, j, 0, W.st.p, W.h1.p,
                          ld, W.Hb.p, W.R.p, W.cs.p, W.sn.p, W.g.p, W.coef.p, W.scale.p,
@@ -586,12 +595,12 @@ edfa_status gmres(edfa_system_s &S, edfa_precond_s &P, const double *b, double *
     } else {
       hipLaunchKernelGGL(k_combine, dim3(nch), dim3(RT), 0, cs, W.V.p, (long long)n, m, W.chunks.p,
                          W.y.p, W.ran.p, W.w.p, 0);
-      applyP(W.w.p, W.z.p, cs);
+      applyP(W.w.p, W.z.p, cs, RowMask{});
       hipLaunchKernelGGL(k_axpy, dim3(ceil_div(n, 256)), dim3(256), 0, cs, (long long)n, W.z.p, x);
     }
     EDFA_CHECK_LAUNCH();
     // true residual r = b - A x and the next cycle's start
-    spmvA(x, W.r.p, b, cs);
+    spmvA(x, W.r.p, b, cs, RowMask{});
     seg_norms(W.r.p, W.nrm.p, cs);
     hipLaunchKernelGGL(k_seg_start, dim3(sb), dim3(64), 0, cs, nseg, m, W.st.p, W.nrm.p, ld, W.g.p,
                        W.scale.p, prm.max_iter, 0);

@@ -333,10 +333,11 @@ __global__ __launch_bounds__(SPMV_T) void k_spmv_sell(const int *__restrict__ sp
                                                       const V *__restrict__ val, int rows,
                                                       const X *__restrict__ x, X *__restrict__ y,
                                                       double alpha, const X *__restrict__ b,
-                                                      double beta, double gamma) {
+                                                      double beta, double gamma, RowMask mk) {
   using A = typename AccT<V, X>::type;
   const int r = blockIdx.x * SPMV_T + threadIdx.x;
   if (r >= rows) return;
+  if (mk.seg && !mk.act[mk.seg[r] * mk.stride]) return;
   const int n = rlen[r];
   const int base = sptr[r >> 6] + (r & 63);
   A s0 = 0, s1 = 0, s2 = 0, s3 = 0;
@@ -368,11 +369,12 @@ __global__ __launch_bounds__(SPMV_T) void k_spmv_csr_vec(const int *__restrict__
                                                          const V *__restrict__ val, int rows,
                                                          const X *__restrict__ x, X *__restrict__ y,
                                                          double alpha, const X *__restrict__ b,
-                                                         double beta, double gamma) {
+                                                         double beta, double gamma, RowMask mk) {
   using A = typename AccT<V, X>::type;
   const int t = blockIdx.x * SPMV_T + threadIdx.x;
   const int r = t / L, l = t % L;
   if (r >= rows) return;   // all L lanes of a row leave together
+  if (mk.seg && !mk.act[mk.seg[r] * mk.stride]) return;
   const int a = rp[r], e = rp[r + 1];
   A s0 = 0, s1 = 0;
   int p = a + l;
@@ -405,13 +407,14 @@ static void launch_timed(K kern, int blocks, hipStream_t s, hipEvent_t e0, hipEv
 
 template <class V, class X>
 void spmv_sell(const Sell<V> &M, const X *x, X *y, double alpha, const X *b, double beta,
-               hipStream_t s, double gamma, int role, hipEvent_t e0, hipEvent_t e1) {
+               hipStream_t s, double gamma, int role, hipEvent_t e0, hipEvent_t e1,
+               RowMask mk) {
   if (M.rows <= 0) return;
   if (M.lanes > 1) {
     const int nb = ceil_div((long long)M.rows * M.lanes, SPMV_T);
 #define EDFA_VEC(LN)                                                                          \
   launch_timed(k_spmv_csr_vec<V, X, LN>, nb, s, e0, e1, M.csr_rp, M.csr_col, M.csr_val, M.rows, \
-               x, y, alpha, b, beta, gamma)
+               x, y, alpha, b, beta, gamma, mk)
     switch (M.lanes) {
       case 2: EDFA_VEC(2); break;
       case 4: EDFA_VEC(4); break;
@@ -422,19 +425,19 @@ void spmv_sell(const Sell<V> &M, const X *x, X *y, double alpha, const X *b, dou
 #undef EDFA_VEC
   } else if (role == SPMV_OPERATOR) {
     launch_timed(k_spmv_sell<V, X, SPMV_OPERATOR>, ceil_div(M.rows, SPMV_T), s, e0, e1, M.sptr.p,
-                 M.rlen.p, M.col.p, M.val.p, M.rows, x, y, alpha, b, beta, gamma);
+                 M.rlen.p, M.col.p, M.val.p, M.rows, x, y, alpha, b, beta, gamma, mk);
   } else {
     launch_timed(k_spmv_sell<V, X, SPMV_PRECOND>, ceil_div(M.rows, SPMV_T), s, e0, e1, M.sptr.p,
-                 M.rlen.p, M.col.p, M.val.p, M.rows, x, y, alpha, b, beta, gamma);
+                 M.rlen.p, M.col.p, M.val.p, M.rows, x, y, alpha, b, beta, gamma, mk);
   }
   EDFA_CHECK_LAUNCH();
 }
 
 template void spmv_sell<double, double>(const Sell<double> &, const double *, double *, double,
                                         const double *, double, hipStream_t, double, int,
-                                        hipEvent_t, hipEvent_t);
+                                        hipEvent_t, hipEvent_t, RowMask);
 template void spmv_sell<float, float>(const Sell<float> &, const float *, float *, double,
                                       const float *, double, hipStream_t, double, int, hipEvent_t,
-                                      hipEvent_t);
+                                      hipEvent_t, RowMask);
 
 }  // namespace edfa

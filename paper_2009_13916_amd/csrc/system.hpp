@@ -119,6 +119,7 @@ struct edfa_system_s {
   std::vector<edfa::GridRange> ranges_h;
   edfa::DBuf<edfa::GridDesc> grids;
   edfa::DBuf<edfa::GridRange> ranges;
+  edfa::DBuf<int> rowseg;        // batches only: grid of every unknown (faces, then cells)
   // per cell
   edfa::DBuf<double> W;          // Ne x 36
   edfa::DBuf<double> vol;        // Ne

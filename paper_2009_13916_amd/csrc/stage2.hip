@@ -107,12 +107,14 @@ __global__ __launch_bounds__(256) void k_jp_round(const int *__restrict__ srp,
                                                   const int *__restrict__ trp,
                                                   const int *__restrict__ tcol, int ne,
                                                   const GridDesc *__restrict__ grids, int ngrid,
+                                                  const int *__restrict__ list, int nlist,
                                                   int *color, int *resume, int *ncolored,
                                                   int *err) {
   const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int v = (int)(gid / JPG);
+  const int slot = (int)(gid / JPG);
   const int l = (int)(gid % JPG);
-  if (v >= ne) return;
+  if (slot >= (list ? nlist : ne)) return;
+  const int v = list ? list[slot] : slot;
   if (__atomic_load_n(&color[v], __ATOMIC_RELAXED) >= 0) return;
   const int c0 = grids[grid_of(grids, ngrid, v, true)].cell0;
   const unsigned pv = fmix32((unsigned)(v - c0));
@@ -156,6 +158,13 @@ __global__ __launch_bounds__(256) void k_jp_round(const int *__restrict__ srp,
   }
   __atomic_store_n(&color[v], c, __ATOMIC_RELAXED);
   atomicAdd(ncolored, 1);
+}
+
+// Worklist of the vertices still uncoloured (any order: a vertex's colour depends only on
+// its coloured higher-priority neighbours, not on when it is visited).
+__global__ void k_uncolored(const int *__restrict__ color, int n, int *list, int *count) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n && color[v] < 0) list[atomicAdd(count, 1)] = v;
 }
 
 __global__ void k_color_max(const int *__restrict__ color, int n, int *out) {
@@ -256,11 +265,30 @@ __global__ __launch_bounds__(64) void k_ilu_color(const int *__restrict__ rp,
     vi[t] = val[a + t];
   }
   __syncthreads();
-  for (int p = 0; p < d; ++p) {
+  // Software pipeline over the pivots: the next pivot row's diagonal position, end, u_kk and
+  // first 64 upper entries (one per lane, in registers) are requested while this step runs.
+  int dk = 0, ek = 0, qc = -1;
+  T uk = T(1), qv = T(0);
+  auto fetch = [&](int p) {
     const int k = ci[p];
-    const int dk = diag[k];
-    const T lik = vi[p] / val[dk];
-    for (int q = dk + 1 + threadIdx.x; q < rp[k + 1]; q += 64) {
+    dk = diag[k];
+    ek = rp[k + 1];
+    uk = val[dk];
+    const int q = dk + 1 + threadIdx.x;
+    qc = q < ek ? col[q] : -1;
+    qv = q < ek ? val[q] : T(0);
+  };
+  if (d > 0) fetch(0);
+  for (int p = 0; p < d; ++p) {
+    const int cdk = dk, cek = ek, cqc = qc;
+    const T cuk = uk, cqv = qv;
+    if (p + 1 < d) fetch(p + 1);
+    const T lik = vi[p] / cuk;
+    if (cqc >= 0) {
+      const int pos = bsearch_range(ci, p + 1, n, cqc);
+      if (pos >= 0) vi[pos] -= lik * cqv;
+    }
+    for (int q = cdk + 65 + threadIdx.x; q < cek; q += 64) {   // pivot rows past 64 entries
       const int pos = bsearch_range(ci, p + 1, n, col[q]);
       if (pos >= 0) vi[pos] -= lik * val[q];
     }
@@ -456,19 +484,31 @@ static void stage2_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
   D.resume.ensure(ne);
   EDFA_HIP(hipMemsetAsync(D.resume.p, 0, sizeof(int) * (size_t)ne, s));
   int rounds = 0;
+  int nlist = ne;                 // vertices each round visits
+  const int *list = nullptr;      // nullptr: all of them
+  D.jplist.ensure(ne);
   while (true) {
     // a round is cheap (one load per vertex still blocked), so check completion rarely
     const int batch = rounds < 64 ? 16 : 32;
     for (int r = 0; r < batch; ++r)
-      hipLaunchKernelGGL(k_jp_round, dim3(ceil_div((long long)ne * JPG, 256)), dim3(256), 0, s,
-                         D.S.rowptr.p,
-                         D.S.col.p, D.ST.rowptr.p, D.ST.col.p, ne, S.grids.p, S.ngrid, D.color.p,
-                         D.resume.p, P.flags.p + 2, P.flags.p + 1);
+      hipLaunchKernelGGL(k_jp_round, dim3(ceil_div((long long)nlist * JPG, 256)), dim3(256), 0, s,
+                         D.S.rowptr.p, D.S.col.p, D.ST.rowptr.p, D.ST.col.p, ne, S.grids.p,
+                         S.ngrid, list, nlist, D.color.p, D.resume.p, P.flags.p + 2,
+                         P.flags.p + 1);
     EDFA_CHECK_LAUNCH();
     rounds += batch;
     const int done = read_scalar(P.flags.p + 2, s);
     if (done >= ne) break;
     if (rounds > 2 * ne + 64) fail(EDFA_ERR_BREAKDOWN, "colouring did not finish");
+    if (2 * (ne - done) < nlist) {
+      // at most half of the visited vertices are left: visit only those from now on
+      EDFA_HIP(hipMemsetAsync(P.flags.p + 3, 0, sizeof(int), s));
+      hipLaunchKernelGGL(k_uncolored, dim3(ceil_div(ne, 256)), dim3(256), 0, s, D.color.p, ne,
+                         D.jplist.p, P.flags.p + 3);
+      EDFA_CHECK_LAUNCH();
+      nlist = read_scalar(P.flags.p + 3, s);
+      list = D.jplist.p;
+    }
   }
   if (read_scalar(P.flags.p + 1, s) != 0x7fffffff)
     fail(EDFA_ERR_CAPACITY, "more than %d colours needed", MAX_COLORS);

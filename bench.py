@@ -125,6 +125,44 @@ def run_batched(edfa, inputs, steps, warmup):
             "batched_mixed_graph_iterations_max": i32["iterations"]}
 
 
+def run_transient(edfa, inputs, nsteps=10):
+    """128x128x64 distorted hexahedra with binary channels (contrast 1e6, 30% volume); dt
+    doubles from 1e-3 for `nsteps` steps with p_n = the previous step's pressure.  The
+    preconditioner is refreshed by stage 2 only (stage 1 does not depend on dt) or rebuilt
+    fully; FP64 and the FP32-preconditioner FGMRES form.  Times are whole sequences."""
+    import torch
+    prob = inputs.channel_problem(128, 128, 64, contrast=1e6, perturb=0.2, dt=1e-3)
+    out = {"workload": "channels_distorted_128x128x64", "steps": nsteps}
+    for name, prm, flex in (("fp64", edfa.Params("dynamic", n_add=1, n_ent=6, tau=1e-3,
+                                                 filt="post_H"), False),
+                            ("mixed", edfa.Params("dynamic", n_add=1, n_ent=6, tau=1e-3,
+                                                  filt="post_H", precision=1), True)):
+        for refresh in ("stage2", "full"):
+            S = edfa.System(prob)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            P = edfa.Precond(S, prm)
+            iters, ok = [], 0
+            for k in range(nsteps):
+                if k > 0:
+                    S.update_dt(1e-3 * 2.0 ** k, p_prev)
+                    if refresh == "stage2":
+                        P.stage2()
+                    else:
+                        P.resetup()
+                x, info, st = edfa.solve(S, P, S.rhs(), rtol=1e-8, restart=50, flexible=flex)
+                p_prev = x[S.info["nfu"]:].clone()
+                iters.append(info["iterations"])
+                ok += int(st == 0)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            log(f"transient {name} refresh={refresh}: {t:.3f} s for {nsteps} steps, "
+                f"iterations {iters}")
+            out[f"{name}_{refresh}"] = {"s": t, "iterations": iters, "converged_steps": ok}
+            del P, S
+    return out
+
+
 def cpu_baseline(iters_gpu, n_full, ne_full):
     """Time the oracle on a bounded sample: the whole oracle pipeline on the 12^3 member
     of the same workload family, scaled to 64^3 (setup per cell, solve per iteration and
@@ -216,6 +254,8 @@ def main():
                     help="skip the 256-grid batch forms")
     ap.add_argument("--batched-only", action="store_true",
                     help="diagnostic: run only the 256-grid batch forms and print their record")
+    ap.add_argument("--transient", action="store_true",
+                    help="diagnostic: run only the 128x128x64 ten-step transient sequence")
     ap.add_argument("--probe", choices=["spmv", "apply"], default=None,
                     help="run only the launches that PMC passes count: 'spmv' = 20 system "
                          "SpMVs and one plain copy of known size; 'apply' = setup and 20 "
@@ -229,6 +269,10 @@ def main():
     from paper_2009_13916_amd import edfa, inputs
     edfa.load()
     torch.cuda.set_device(0)
+    if args.transient:
+        print(json.dumps({"forms": {"transient_128x128x64": run_transient(edfa, inputs)}}),
+              flush=True)
+        return
     if args.batched_only:
         print(json.dumps({"forms": {"batch_256": run_batched(edfa, inputs, args.steps,
                                                              args.warmup)}}), flush=True)

@@ -23,9 +23,11 @@ __global__ void k_scatter(const T *__restrict__ x, const int *__restrict__ idx, 
 }
 
 template <class A, class B>
-__global__ void k_convert(const A *__restrict__ x, long long n, B *y) {
+__global__ void k_convert(const A *__restrict__ x, long long n, B *y, RowMask mk) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = (B)x[i];
+  if (i >= n) return;
+  if (mk.seg && !mk.act[mk.seg[i] * mk.stride]) return;
+  y[i] = (B)x[i];
 }
 
 // Colour-by-colour substitution on rows [r0, r1): y_i = (b_i - sum_{j != diag} a_ij y_j) / d
@@ -53,7 +55,7 @@ static void to_fp32(const Csr<double> &M, Csr<float> &F, hipStream_t s) {
   if (M.nnz) {
     EDFA_HIP(hipMemcpyAsync(F.col.p, M.col.p, sizeof(int) * M.nnz, hipMemcpyDeviceToDevice, s));
     hipLaunchKernelGGL((k_convert<double, float>), dim3(ceil_div(M.nnz, 256)), dim3(256), 0, s,
-                       M.val.p, (long long)M.nnz, F.val.p);
+                       M.val.p, (long long)M.nnz, F.val.p, RowMask{});
     EDFA_CHECK_LAUNCH();
   }
 }
@@ -211,12 +213,12 @@ void precond_apply(edfa_precond_s &P, int transpose, const double *r, double *z,
   DBuf<float> &rin = P.rin_f;
   rin.ensure(n);
   hipLaunchKernelGGL((k_convert<double, float>), dim3(ceil_div(n, 256)), dim3(256), 0, s, r,
-                     (long long)n, rin.p);
+                     (long long)n, rin.p, mask);
   EDFA_CHECK_LAUNCH();
   apply_typed<float>(P, D, rin.p, D.z.p, transpose ? cs[2] : cs[0], transpose ? cs[3] : cs[1],
                      transpose, s, fm, cm);
   hipLaunchKernelGGL((k_convert<float, double>), dim3(ceil_div(n, 256)), dim3(256), 0, s, D.z.p,
-                     (long long)n, z);
+                     (long long)n, z, mask);
   EDFA_CHECK_LAUNCH();
 }
 

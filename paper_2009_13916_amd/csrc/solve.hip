@@ -31,7 +31,8 @@ constexpr int RT = 256;
 
 // Partial dots tiled over (chunk, group of DG basis vectors): block (c, q) forms Q_i . u and
 // Q_i . w on chunk c for i in [DG q, DG q + DG); blocks with q = 0 also form u . u and u . w.
-// Components per chunk row: [Q^T u (nv) | Q^T w (nv) | u.u | u.w].
+// Components per chunk row: [Q^T u (nv) | Q^T w (nv) | u.u | u.w].  (Groups of 16 vectors,
+// which re-read u and w less, leave too few blocks to keep HBM busy: 4 is faster.)
 constexpr int DG = 4;
 __global__ __launch_bounds__(RT) void k_dots2(const double *__restrict__ Q, long long ldq, int nv,
                                               const double *__restrict__ u,

@@ -591,6 +591,7 @@ __global__ __launch_bounds__(64) void k_local_reg(LocalArgs<T> A) {
 
   const int it_max = A.it_max > 0 ? A.it_max : A.n_ent;
   int n_prog = 0, sweep = 0;
+  int scanned = 0;   // pattern entries whose A_pipi rows are in the candidate set
   bool fin = !A.dynamic;
   T xg = 0, xf = 0;
   for (;;) {
@@ -633,34 +634,42 @@ __global__ __launch_bounds__(64) void k_local_reg(LocalArgs<T> A) {
     ++sweep;
     const int n = min(A.n_add, A.n_ent - n_prog);
     if (lane < s) xs[lane] = xg;
-    // candidate set: A_pipi neighbours of Q outside Q (support of the prolonged residual)
-    for (int h = lane; h < CH; h += 64) ck[h] = -1;
-    if (lane == 0) ccount = 0;
+    // candidate set: A_pipi neighbours of Q outside Q (support of the prolonged residual),
+    // kept across sweeps: only the rows of the entries appended since the last sweep are
+    // scanned, fresh candidates are appended to clist, and candidates that have joined Q
+    // get a zero residual below
+    if (sweep == 1) {
+      for (int h = lane; h < CH; h += 64) ck[h] = -1;
+      if (lane == 0) ccount = 0;
+    }
     __syncthreads();
-    if (lane < s) {
-      row_cols<12>(A.app_rp, A.app_col, q[lane], [&](int c) EDFA_INLINE {
+    for (int t = scanned + lane; t < s; t += 64) {
+      row_cols<12>(A.app_rp, A.app_col, q[t], [&](int c) EDFA_INLINE {
         if (h_find<QH>(qk, c) < 0) {
           bool fr;
-          if (h_insert<CH>(ck, c, fr) < 0) sflag = 1;
+          if (h_insert<CH>(ck, c, fr) < 0)
+            sflag = 1;
+          else if (fr)
+            clist[atomicAdd(&ccount, 1)] = c;
         }
       });
     }
+    scanned = s;
     __syncthreads();
     if (sflag) {
       if (lane == 0) atomicMin(A.err_cap, m);
       return;
     }
-    for (int h = lane; h < CH; h += 64)
-      if (ck[h] >= 0) clist[atomicAdd(&ccount, 1)] = ck[h];
-    __syncthreads();
     const int nc = ccount;
     // r_j = (A_pipi R^T g~)_j for j outside Q (a_ppi^(m) vanishes there)
     for (int c = lane; c < nc; c += 64) {
+      const int j = clist[c];
       T acc = 0;
-      row_entries<12>(A.app_rp, A.app_col, A.app_val, clist[c], [&](int col, double v) EDFA_INLINE {
-        const int h = h_find<QH>(qk, col);
-        if (h >= 0) acc += (T)v * xs[qv[h]];
-      });
+      if (h_find<QH>(qk, j) < 0)
+        row_entries<12>(A.app_rp, A.app_col, A.app_val, j, [&](int col, double v) EDFA_INLINE {
+          const int h = h_find<QH>(qk, col);
+          if (h >= 0) acc += (T)v * xs[qv[h]];
+        });
       cr[c] = acc;
     }
     __syncthreads();

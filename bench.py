@@ -43,10 +43,26 @@ def spmv_bytes(nnz, n):
     return 12 * nnz + 4 * (n + 1) + 8 * n + 8 * n
 
 
+def print_tune_report(rep, tag):
+    """One stderr line per timed matrix: the chosen kernel, its time and its rate on the
+    algorithmic bytes (values and indices once, row pointers once, x and y once)."""
+    for name, r in rep.items():
+        vb = r["value_bytes"]
+        nbytes = (4 + vb) * r["nnz"] + 4 * (r["rows"] + 1) + vb * (r["cols"] + r["rows"])
+        t = r["us"][r["variant"]]
+        alt = " ".join(f"{v}:{u:.1f}" for v, u in r["us"].items())
+        lay = f"pad {r['sell_padding']:.2f}{' sorted' if r['sell_sorted'] else ''}"
+        print(f"[tune {tag}] {name:8s} rows {r['rows']:8d} nnz {r['nnz']:9d} {lay:17s} "
+              f"{r['variant']:8s} {t:7.1f} us {nbytes / t / 1e3:6.0f} GB/s  ({alt})",
+              file=sys.stderr, flush=True)
+
+
 def run_form(edfa, S, b, prm, steps, warmup, flexible):
     import torch
     P = edfa.Precond(S, prm)
-    P.autotune()   # one-off choice of SpMV launch shapes, kept across the timed re-setups
+    # one-off choice of SpMV launch shapes, kept across the timed re-setups
+    rep = P.autotune(report=True)
+    print_tune_report(rep, "fp32" if prm.precision == 1 else "fp64")
     for _ in range(warmup):
         P.resetup()
         edfa.solve(S, P, b, rtol=1e-8, restart=50, flexible=flexible)
@@ -60,7 +76,16 @@ def run_form(edfa, S, b, prm, steps, warmup, flexible):
         pinfos.append(P.info())
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    return (t1 - t0) / steps, infos, pinfos, x
+    return (t1 - t0) / steps, infos, pinfos, x, rep
+
+
+def kernel_label(variant):
+    """Kernel (as traces name it) that runs the system-matrix product for a tuner choice."""
+    kind, depth = variant.split("/")
+    if kind == "sell":
+        return f"k_spmv_sell<double, double, 0, {depth}>: SELL-64 SpMV with the system matrix"
+    return (f"k_spmv_csr_vec<double, double, {kind[3:]}, {depth}>: CSR SpMV with the system "
+            f"matrix, {kind[3:]} lanes per row")
 
 
 def run_batched(edfa, inputs, steps, warmup):
@@ -216,12 +241,12 @@ def probe_spmv(torch, S, b):
 
 
 def spmv_kernel_sha():
-    """SHA-256 of the source of the SELL SpMV kernel: a traffic figure measured on another
-    version of the kernel is not reported."""
+    """SHA-256 of the source of the SpMV kernels (SELL and CSR): a traffic figure measured
+    on another version of them is not reported."""
     import hashlib
     src = open(os.path.join(ROOT, "paper_2009_13916_amd", "csrc", "sparse.hip")).read()
     a = src.index("void k_spmv_sell(")
-    e = src.index("// L lanes per row on the CSR arrays")
+    e = src.index("// Launch helper: the extended launch")
     return hashlib.sha256(src[a:e].encode()).hexdigest()[:16]
 
 
@@ -296,7 +321,8 @@ def main():
     nnz, N, ne = S.info["nnz"], S.info["n"], S.info["ne"]
     log(f"assembled: N={N} nnz={nnz}")
     prm = edfa.Params("dynamic", n_add=1, n_ent=6, tau=1e-3, filt="post_H")
-    t64, infos, pinfos, x = run_form(edfa, S, b, prm, args.steps, args.warmup, flexible=False)
+    t64, infos, pinfos, x, rep64 = run_form(edfa, S, b, prm, args.steps, args.warmup,
+                                            flexible=False)
     info, st = infos[-1]
     log(f"fp64: {t64:.4f} s/step, {info['iterations']} iterations, relres {info['relres_true']:.2e}")
     log("preconditioner: " + ", ".join(f"{k} {v}" for k, v in pinfos[-1].items()))
@@ -307,7 +333,8 @@ def main():
                       "colors": pinfos[-1]["n_colors"]}}
     if not args.no_mixed:
         prm32 = edfa.Params("dynamic", n_add=1, n_ent=6, tau=1e-3, filt="post_H", precision=1)
-        t32, i32, p32, x32 = run_form(edfa, S, b, prm32, args.steps, args.warmup, flexible=True)
+        t32, i32, p32, x32, _ = run_form(edfa, S, b, prm32, args.steps, args.warmup,
+                                         flexible=True)
         inf32, st32 = i32[-1]
         dp = (x32 - x)[S.info["nfu"]:].norm() / x[S.info["nfu"]:].norm()
         log(f"mixed: {t32:.4f} s/step, {inf32['iterations']} iterations")
@@ -331,7 +358,7 @@ def main():
         "iterations": info["iterations"], "relres_true": info["relres_true"],
         "forms": forms,
         "roofline": {"bound": "hbm",
-                     "kernel": "k_spmv_sell<double, double, 0>: SELL-64 SpMV with the system matrix",
+                     "kernel": kernel_label(rep64["A"]["variant"]),
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "bytes_per_launch": ab, "avg_launch_ms": spmv_ms,

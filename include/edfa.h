@@ -249,10 +249,39 @@ edfa_status edfa_grad_logk(edfa_system sys, const double *u, const double *lambd
  * that the solve and the application multiply -- the system matrix (and its transpose once
  * built), the FSAI factor and its transpose, the coupling blocks, the ILU(0) factors and
  * their approximate inverses -- with the one-lane-per-row SELL kernel and with the CSR
- * kernel at 2, 4, 8, 16 and 32 lanes per row, and keeps the fastest for each; the choice
+ * kernel at 2, 4, 8, 16 and 32 lanes per row, each at two load depths, and keeps the
+ * fastest for each; the choice
  * stays with the handle across later setups.  *tuned (host, may be NULL) receives the
- * number of matrices timed.  Synchronises the stream.  Errors: EDFA_ERR_ARG, EDFA_ERR_HIP. */
-edfa_status edfa_autotune(edfa_precond pre, hipStream_t stream, int32_t *tuned /* (host) */);
+ * number of matrices timed; slots (host, may be NULL) the timings of every slot.  Synchronises the stream.  Errors: EDFA_ERR_ARG, EDFA_ERR_HIP. */
+#define EDFA_TUNE_SLOTS 16
+#define EDFA_TUNE_VARIANTS 12
+/* One matrix timed by the autotuner.  Slots: 0 A, 1 A^T, 2 G_F, 3 G_F^T, 4 L, 5 U, 6 M_L,
+ * 7 M_U, 8 L^T, 9 U^T, 10 M_L^T, 11 M_U^T, 12 A_ppi, 13 A_pip, 14 A_pip^T, 15 A_ppi^T
+ * (the FP32 copies for an FP32 preconditioner).  Variants v = 0..11, as (lanes per row,
+ * entries in flight per lane): SELL (1, 4), (1, 8); CSR (2, 2), (2, 4), (4, 2), (4, 4),
+ * (8, 2), (8, 4), (16, 2), (16, 4), (32, 2), (32, 4).  us[v]: best of five launches of
+ * variant v, in microseconds; when some matrix of the handle exceeds 8 MiB, a 512 MiB read
+ * before each timed launch evicts the caches, as a full iteration does in the solve. */
+typedef struct {
+  int32_t rows, cols;   /* 0 rows: the matrix does not exist (yet); nothing was timed */
+  int64_t nnz;
+  int32_t variant;      /* the chosen variant */
+  int32_t value_bytes;  /* 8 (FP64) or 4 (FP32) */
+  int32_t sell_sorted;  /* 1: the SELL copy holds the rows sorted by length in windows */
+  float sell_padding;   /* stored SELL entries / nnz */
+  float us[EDFA_TUNE_VARIANTS];
+} edfa_tune_slot;
+
+edfa_status edfa_autotune(edfa_precond pre, hipStream_t stream, int32_t *tuned /* (host) */,
+                          edfa_tune_slot *slots /* (host) EDFA_TUNE_SLOTS entries, may be NULL */);
+
+/* Pin the sparse-product kernel of one slot (0 .. EDFA_TUNE_SLOTS - 1, numbered as for
+ * edfa_tune_slot) or of every slot (slot = -1) to a variant (0 .. EDFA_TUNE_VARIANTS - 1;
+ * -1 = the default choice at the next setup), as edfa_autotune would keep it: for callers
+ * that want a fixed kernel (and rounding order) instead of a timed choice.  Takes effect
+ * at once and survives later setups.  Host only, nothing is launched.
+ * Errors: EDFA_ERR_ARG (slot or variant out of range). */
+edfa_status edfa_set_variant(edfa_precond pre, int32_t slot, int32_t variant);
 
 const char *edfa_last_error(void);
 

@@ -341,11 +341,23 @@ edfa_status edfa_solve(edfa_system sys, edfa_precond pre, const double *b, doubl
   });
 }
 
-edfa_status edfa_autotune(edfa_precond pre, hipStream_t stream, int32_t *tuned) {
+edfa_status edfa_autotune(edfa_precond pre, hipStream_t stream, int32_t *tuned,
+                          edfa_tune_slot *slots) {
   return guard([&] {
     if (!pre) fail(EDFA_ERR_ARG, "NULL preconditioner");
-    const int n = autotune(*pre, stream);
+    const int n = autotune(*pre, stream, slots);
     if (tuned) *tuned = n;
+    return EDFA_OK;
+  });
+}
+
+edfa_status edfa_set_variant(edfa_precond pre, int32_t slot, int32_t variant) {
+  return guard([&] {
+    if (!pre) fail(EDFA_ERR_ARG, "NULL preconditioner");
+    if (slot < -1 || slot >= EDFA_TUNE_SLOTS) fail(EDFA_ERR_ARG, "slot %d out of range", slot);
+    if (variant < -1 || variant >= EDFA_TUNE_VARIANTS)
+      fail(EDFA_ERR_ARG, "variant %d out of range", variant);
+    set_variant(*pre, slot, variant);
     return EDFA_OK;
   });
 }

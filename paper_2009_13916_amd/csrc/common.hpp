@@ -90,14 +90,22 @@ struct Sell {
   DBuf<int> rlen;   // rows
   DBuf<int> col;
   DBuf<V> val;
+  // sorted layout: position p of the slices holds row perm[p] (rows sorted by length
+  // inside windows); otherwise position p holds row p
+  bool sorted = false;
+  DBuf<int> perm;
   // Kernel choice: lanes <= 1 runs the SELL kernel; lanes = 2..32 runs the CSR kernel with
   // that many lanes per row on the source CSR arrays (which must outlive this copy).
+  // depth: entries in flight per lane and round (SELL 4 or 8, CSR 2 or 4; other values
+  // take 4 and 2).
   int lanes = 0;
+  int depth = 0;
   const int *csr_rp = nullptr, *csr_col = nullptr;
   const V *csr_val = nullptr;
 };
 
 inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
+
 
 // Host read of one device scalar (synchronises the stream).
 template <class T>

@@ -92,7 +92,7 @@ struct edfa_precond_s {
   edfa::DBuf<float> rin_f;         // FP32 copy of the vector being preconditioned
   std::unique_ptr<edfa::SolveWork> ws;
   int tuned[16] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
-                                   // autotuned lanes per row of each product (-1: default)
+                                   // autotuned kernel variant of each product (-1: default)
 };
 
 namespace edfa {
@@ -106,5 +106,7 @@ template <class T>
 void build_hraw(edfa_precond_s &P, PrecData<T> &D, hipStream_t s);
 void grad_logk(edfa_system_s &S, const double *u, const double *lam, double *g, hipStream_t s);
 void apply_tuned(edfa_precond_s &P);
-int autotune(edfa_precond_s &P, hipStream_t s);
+// slot -1: every slot; variant -1: back to the default choice (at the next setup)
+void set_variant(edfa_precond_s &P, int slot, int variant);
+int autotune(edfa_precond_s &P, hipStream_t s, edfa_tune_slot *slots = nullptr);
 }  // namespace edfa

@@ -45,25 +45,41 @@ __global__ __launch_bounds__(RT) void k_dots2(const double *__restrict__ Q, long
   if (!st[c.seg].active) return;
   const int i0 = blockIdx.y * DG;
   const bool self = blockIdx.y == 0;
-  double au[DG], aw[DG], uu = 0.0, uw = 0.0;
-#pragma unroll
-  for (int g = 0; g < DG; ++g) au[g] = aw[g] = 0.0;
+  // Branch-free loads: elements past the chunk end re-read its last element with weight
+  // zero, and basis slots past nv re-read slot nv - 1 (their sums are not stored), so every
+  // load of the block is issued before the first wait.
+  int ek[8];
+  bool ok[8];
+  double ue[8], we[8];
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     const int e = c.start + threadIdx.x + k * RT;
-    if (e < c.end) {
-      const double ue = u[e], we = w[e];
+    ok[k] = e < c.end;
+    ek[k] = ok[k] ? e : c.end - 1;
+    ue[k] = u[ek[k]];
+    we[k] = w[ek[k]];
+  }
+  double au[DG], aw[DG], uu = 0.0, uw = 0.0;
 #pragma unroll
-      for (int g = 0; g < DG; ++g)
-        if (i0 + g < nv) {
-          const double q = Q[(long long)(i0 + g) * ldq + e];
-          au[g] += q * ue;
-          aw[g] += q * we;
-        }
-      if (self) {
-        uu += ue * ue;
-        uw += ue * we;
+  for (int g = 0; g < DG; ++g) au[g] = aw[g] = 0.0;
+  if (nv > 0) {
+#pragma unroll
+    for (int g = 0; g < DG; ++g) {
+      const double *qg = Q + (long long)min(i0 + g, nv - 1) * ldq;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const double q = ok[k] ? qg[ek[k]] : 0.0;
+        au[g] += q * ue[k];
+        aw[g] += q * we[k];
       }
+    }
+  }
+  if (self) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const double uk = ok[k] ? ue[k] : 0.0;
+      uu += uk * uk;
+      uw += uk * we[k];
     }
   }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -255,19 +271,36 @@ __global__ __launch_bounds__(RT) void k_dcgs_update(double *Q, long long ldq, in
   const double cj = cf[2 * j], ir = scale[c.seg];
   double *uj = Q + (long long)j * ldq;
   double *un = Q + (long long)(j + 1) * ldq;
+  // block (c, h) updates half h of the chunk (twice the blocks of one per chunk keep more
+  // loads in flight); basis vectors outermost, each step issuing the UE loads of one vector
+  // without a branch (elements past the chunk end re-read its last element, unstored)
+  constexpr int UE = CHUNK / RT / 2;
+  const int e0 = c.start + blockIdx.y * (UE * RT) + threadIdx.x;
+  int ek[UE];
+  double u[UE], x[UE];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const int e = c.start + threadIdx.x + k * RT;
+  for (int k = 0; k < UE; ++k) {
+    ek[k] = min(e0 + k * RT, c.end - 1);
+    u[k] = uj[ek[k]];
+    x[k] = w[ek[k]];
+  }
+  for (int i = 0; i < j; ++i) {
+    const double a = sa[i], bb = sb[i];
+    const double *qi = Q + (long long)i * ldq;
+#pragma unroll
+    for (int k = 0; k < UE; ++k) {
+      const double q = qi[ek[k]];
+      u[k] -= a * q;
+      x[k] -= bb * q;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < UE; ++k) {
+    const int e = e0 + k * RT;
     if (e < c.end) {
-      double u = uj[e], x = w[e];
-      for (int i = 0; i < j; ++i) {
-        const double q = Q[(long long)i * ldq + e];
-        u -= sa[i] * q;
-        x -= sb[i] * q;
-      }
-      const double qj = u * ir;
+      const double qj = u[k] * ir;
       uj[e] = qj;
-      un[e] = (x - cj * qj) * ir;
+      un[e] = (x[k] - cj * qj) * ir;
     }
   }
 }
@@ -286,15 +319,23 @@ __global__ __launch_bounds__(RT) void k_dcgs_update_z(double *Z, long long ldz, 
   __syncthreads();
   const double ir = scale[c.seg];
   double *zj = Z + (long long)j * ldz;
+  int ek[8];
+  double z[8];
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    const int e = c.start + threadIdx.x + k * RT;
-    if (e < c.end) {
-      double z = zj[e];
-      for (int i = 0; i < j; ++i) z -= sa[i] * Z[(long long)i * ldz + e];
-      zj[e] = z * ir;
-    }
+    ek[k] = min(c.start + (int)threadIdx.x + k * RT, c.end - 1);
+    z[k] = zj[ek[k]];
   }
+#pragma unroll 2
+  for (int i = 0; i < j; ++i) {
+    const double a = sa[i];
+    const double *zi = Z + (long long)i * ldz;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) z[k] -= a * zi[ek[k]];
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if (c.start + (int)threadIdx.x + k * RT < c.end) zj[c.start + threadIdx.x + k * RT] = z[k] * ir;
 }
 
 // V_{j+1} = w * scale[seg] (active segments); with j < 0: V_0 = r / beta for starting ones.
@@ -371,15 +412,23 @@ __global__ __launch_bounds__(RT) void k_combine(const double *__restrict__ B, lo
   const Chunk c = ch[blockIdx.x];
   const int k = ran[c.seg];
   const double *yy = y + (long long)c.seg * m;
+  int ek[8];
+  double s[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
-    const int e = c.start + threadIdx.x + q * RT;
-    if (e < c.end) {
-      double s = accumulate ? out[e] : 0.0;
-      for (int i = 0; i < k; ++i) s += yy[i] * B[(long long)i * ldb + e];
-      out[e] = s;
-    }
+    ek[q] = min(c.start + (int)threadIdx.x + q * RT, c.end - 1);
+    s[q] = accumulate ? out[ek[q]] : 0.0;
   }
+#pragma unroll 2
+  for (int i = 0; i < k; ++i) {
+    const double a = yy[i];
+    const double *bi = B + (long long)i * ldb;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s[q] += a * bi[ek[q]];
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q)
+    if (c.start + (int)threadIdx.x + q * RT < c.end) out[c.start + threadIdx.x + q * RT] = s[q];
 }
 
 __global__ void k_axpy(long long n, const double *__restrict__ x, double *y) {
@@ -567,7 +616,7 @@ edfa_status gmres(edfa_system_s &S, edfa_precond_s &P, const double *b, double *
       hipLaunchKernelGGL(k_dcgs_step, dim3(nseg), dim3(64), 0, cs, nseg, m, j, 0, W.st.p, W.h1.p,
                          ld, W.Hb.p, W.R.p, W.cs.p, W.sn.p, W.g.p, W.coef.p, W.scale.p,
                          prm.max_iter);
-      hipLaunchKernelGGL(k_dcgs_update, dim3(nch), dim3(RT), 0, cs, W.V.p, (long long)n, j, W.w.p,
+      hipLaunchKernelGGL(k_dcgs_update, dim3(nch, 2), dim3(RT), 0, cs, W.V.p, (long long)n, j, W.w.p,
                          W.chunks.p, W.st.p, W.coef.p, 2 * m + 2, W.scale.p);
       if (prm.flexible)
         hipLaunchKernelGGL(k_dcgs_update_z, dim3(nch), dim3(RT), 0, cs, W.Z.p, (long long)n, j,

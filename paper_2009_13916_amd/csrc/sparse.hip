@@ -272,15 +272,65 @@ __global__ void k_sell_width(const int *__restrict__ rowptr, int rows, int nslic
   w64[sl] = w * 64;
 }
 
+// Sorted layout (SELL-C-sigma with C = 64, sigma = SELL_SIGMA): inside each window of
+// SELL_SIGMA rows, positions hold the rows by descending length (ties by row index), so a
+// slice of 64 positions holds rows of similar length.  One block of 256 threads per window:
+// bitonic sort of (length, row) keys in LDS.  perm[position] = row.
+constexpr int SELL_SIGMA = 1024;
+__global__ __launch_bounds__(256) void k_sell_sort(const int *__restrict__ rowptr, int rows,
+                                                   int *perm) {
+  __shared__ unsigned long long key[SELL_SIGMA];
+  const int w0 = blockIdx.x * SELL_SIGMA;
+  for (int t = threadIdx.x; t < SELL_SIGMA; t += 256) {
+    const int r = w0 + t;
+    // ascending keys = descending lengths; rows past the end sort last
+    key[t] = r < rows ? ((unsigned long long)(0x7fffffff - (rowptr[r + 1] - rowptr[r])) << 32) |
+                            (unsigned)r
+                      : ~0ull;
+  }
+  __syncthreads();
+  for (int k = 2; k <= SELL_SIGMA; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int t = threadIdx.x; t < SELL_SIGMA; t += 256) {
+        const int o = t ^ j;
+        if (o > t) {
+          const unsigned long long a = key[t], b = key[o];
+          if (((t & k) == 0) == (a > b)) {
+            key[t] = b;
+            key[o] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  for (int t = threadIdx.x; t < SELL_SIGMA; t += 256)
+    if (w0 + t < rows) perm[w0 + t] = (int)(key[t] & 0xffffffffu);
+}
+
+// slice widths of the sorted layout: the longest row of each slice of 64 positions
+__global__ void k_sell_width_perm(const int *__restrict__ rowptr, const int *__restrict__ perm,
+                                  int rows, int nslice, int *w64) {
+  const int sl = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sl >= nslice) return;
+  int w = 0;
+  for (int p = sl * 64; p < min(rows, sl * 64 + 64); ++p) {
+    const int r = perm[p];
+    w = max(w, rowptr[r + 1] - rowptr[r]);
+  }
+  w64[sl] = w * 64;
+}
+
+// position p holds row perm[p] (perm NULL: row p)
 template <class V>
 __global__ void k_sell_fill(const int *__restrict__ rowptr, const int *__restrict__ col,
-                            const V *__restrict__ val, int rows, const int *__restrict__ sptr,
-                            int *rlen, int *scol, V *sval) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= rows) return;
+                            const V *__restrict__ val, int rows, const int *__restrict__ perm,
+                            const int *__restrict__ sptr, int *rlen, int *scol, V *sval) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= rows) return;
+  const int r = perm ? perm[p] : p;
   const int a = rowptr[r], n = rowptr[r + 1] - a;
-  const int base = sptr[r >> 6] + (r & 63);
-  rlen[r] = n;
+  const int base = sptr[p >> 6] + (p & 63);
+  rlen[p] = n;
   for (int k = 0; k < n; ++k) {
     scol[base + 64 * k] = col[a + k];
     sval[base + 64 * k] = val[a + k];
@@ -290,6 +340,8 @@ __global__ void k_sell_fill(const int *__restrict__ rowptr, const int *__restric
 // Lanes per row for a matrix with the given mean row length: one lane per row (SELL) for
 // short rows, a CSR group of lanes for long ones.
 constexpr double SPMV_VEC_MIN_ROW = 24.0;
+// SELL-64 padding (stored / true entries) above which the rows are sorted by length
+constexpr double SELL_SORT_PAD = 1.2;
 int default_spmv_lanes(double mean_row) { return mean_row < SPMV_VEC_MIN_ROW ? 0 : 8; }
 
 template <class V>
@@ -301,6 +353,7 @@ void build_sell(const Csr<V> &M, Sell<V> &S, DBuf<int> &tmp, hipStream_t s) {
   S.csr_col = M.col.p;
   S.csr_val = M.val.p;
   S.lanes = M.rows > 0 ? default_spmv_lanes((double)M.nnz / M.rows) : 0;
+  S.depth = 0;
   S.nslice = ceil_div(M.rows, 64);
   S.sptr.ensure((size_t)S.nslice + 1);
   S.rlen.ensure((size_t)std::max(M.rows, 1));
@@ -312,58 +365,90 @@ void build_sell(const Csr<V> &M, Sell<V> &S, DBuf<int> &tmp, hipStream_t s) {
                      M.rows, S.nslice, S.sptr.p);
   EDFA_CHECK_LAUNCH();
   S.padded = exclusive_scan(S.sptr.p, S.sptr.p, S.nslice, tmp, s);
+  S.sorted = false;
+  if (S.padded > SELL_SORT_PAD * (double)M.nnz) {
+    // rows of very different lengths side by side: sort them inside windows
+    S.perm.ensure((size_t)M.rows);
+    hipLaunchKernelGGL(k_sell_sort, dim3(ceil_div(M.rows, SELL_SIGMA)), dim3(256), 0, s,
+                       M.rowptr.p, M.rows, S.perm.p);
+    hipLaunchKernelGGL(k_sell_width_perm, dim3(ceil_div(S.nslice, 256)), dim3(256), 0, s,
+                       M.rowptr.p, S.perm.p, M.rows, S.nslice, S.sptr.p);
+    EDFA_CHECK_LAUNCH();
+    S.padded = exclusive_scan(S.sptr.p, S.sptr.p, S.nslice, tmp, s);
+    S.sorted = true;
+  }
   S.col.ensure((size_t)std::max<int64_t>(S.padded, 1));
   S.val.ensure((size_t)std::max<int64_t>(S.padded, 1));
   hipLaunchKernelGGL(k_sell_fill<V>, dim3(ceil_div(M.rows, 256)), dim3(256), 0, s, M.rowptr.p,
-                     M.col.p, M.val.p, M.rows, S.sptr.p, S.rlen.p, S.col.p, S.val.p);
+                     M.col.p, M.val.p, M.rows, S.sorted ? S.perm.p : nullptr, S.sptr.p,
+                     S.rlen.p, S.col.p, S.val.p);
   EDFA_CHECK_LAUNCH();
 }
 
 template void build_sell<double>(const Csr<double> &, Sell<double> &, DBuf<int> &, hipStream_t);
 template void build_sell<float>(const Csr<float> &, Sell<float> &, DBuf<int> &, hipStream_t);
 
-// One lane per row, four entries in flight per lane.  ROLE only separates the
-// system-operator launches (0) from the preconditioner's (1) in kernel traces.
+// One lane per row.  Each round issues the loads of the next U entries of the row at once
+// (predicated past the row's end), so a row of up to U entries costs one dependent chain
+// (column index -> x) instead of one per entry.  ROLE only separates the system-operator
+// launches (0) from the preconditioner's (1) in kernel traces.
 constexpr int SPMV_T = 256;
 
-template <class V, class X, int ROLE>
+template <class V, class X, int ROLE, int U>
 __global__ __launch_bounds__(SPMV_T) void k_spmv_sell(const int *__restrict__ sptr,
                                                       const int *__restrict__ rlen,
                                                       const int *__restrict__ col,
-                                                      const V *__restrict__ val, int rows,
+                                                      const V *__restrict__ val,
+                                                      const int *__restrict__ perm, int rows,
                                                       const X *__restrict__ x, X *__restrict__ y,
                                                       double alpha, const X *__restrict__ b,
                                                       double beta, double gamma, RowMask mk) {
   using A = typename AccT<V, X>::type;
-  const int r = blockIdx.x * SPMV_T + threadIdx.x;
+  const int r = blockIdx.x * SPMV_T + threadIdx.x;   // position in the layout
   if (r >= rows) return;
-  if (mk.seg && !mk.act[mk.seg[r] * mk.stride]) return;
+  const int row = perm ? perm[r] : r;
+  if (mk.seg && !mk.act[mk.seg[row] * mk.stride]) return;
+  // a wavefront holds exactly one slice of 64 rows: its offset is a scalar load, issued
+  // (the empty asm keeps it from sinking below the length test) while the vector load of
+  // the row length is in flight
+  const int sb = sptr[__builtin_amdgcn_readfirstlane(r >> 6)];
   const int n = rlen[r];
-  const int base = sptr[r >> 6] + (r & 63);
-  A s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-  int k = 0;
-  for (; k + 4 <= n; k += 4) {
-    const int p = base + 64 * k;
-    const int c0 = col[p], c1 = col[p + 64], c2 = col[p + 128], c3 = col[p + 192];
-    const V v0 = val[p], v1 = val[p + 64], v2 = val[p + 128], v3 = val[p + 192];
-    s0 += (A)v0 * (A)x[c0];
-    s1 += (A)v1 * (A)x[c1];
-    s2 += (A)v2 * (A)x[c2];
-    s3 += (A)v3 * (A)x[c3];
+  asm volatile("" ::"s"(sb));
+  const int base = sb + (r & 63);
+  A s[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) s[u] = 0;
+  for (int k = 0; k < n; k += U) {
+    // entries past the row's end re-read its last entry (always valid, no branch) and
+    // contribute zero, so every load of the round is issued before the first wait
+    int c[U];
+    V v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int p = base + 64 * min(k + u, n - 1);
+      c[u] = col[p];
+      v[u] = val[p];
+    }
+    X xv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) xv[u] = x[c[u]];
+#pragma unroll
+    for (int u = 0; u < U; ++u) s[u] += (k + u < n ? (A)v[u] : A(0)) * (A)xv[u];
   }
-  for (; k < n; ++k) {
-    const int p = base + 64 * k;
-    s0 += (A)val[p] * (A)x[col[p]];
-  }
-  A out = (A)alpha * ((s0 + s1) + (s2 + s3));
-  if (b) out += (A)beta * (A)b[r];
-  if (gamma != 0.0) out += (A)gamma * (A)x[r];
-  y[r] = (X)out;
+#pragma unroll
+  for (int h = U / 2; h > 0; h >>= 1)
+#pragma unroll
+    for (int u = 0; u < h; ++u) s[u] += s[u + h];
+  A out = (A)alpha * s[0];
+  if (b) out += (A)beta * (A)b[row];
+  if (gamma != 0.0) out += (A)gamma * (A)x[row];
+  y[row] = (X)out;
 }
 
 // L lanes per row on the CSR arrays, for matrices with long rows: the lanes of a row read
-// consecutive entries (coalesced) and a shuffle tree sums their partials.
-template <class V, class X, int L>
+// consecutive entries (coalesced), each round issuing U entries per lane at once
+// (predicated past the row's end), and a shuffle tree sums the lanes' partials.
+template <class V, class X, int L, int U>
 __global__ __launch_bounds__(SPMV_T) void k_spmv_csr_vec(const int *__restrict__ rp,
                                                          const int *__restrict__ col,
                                                          const V *__restrict__ val, int rows,
@@ -376,14 +461,30 @@ __global__ __launch_bounds__(SPMV_T) void k_spmv_csr_vec(const int *__restrict__
   if (r >= rows) return;   // all L lanes of a row leave together
   if (mk.seg && !mk.act[mk.seg[r] * mk.stride]) return;
   const int a = rp[r], e = rp[r + 1];
-  A s0 = 0, s1 = 0;
-  int p = a + l;
-  for (; p + L < e; p += 2 * L) {
-    s0 += (A)val[p] * (A)x[col[p]];
-    s1 += (A)val[p + L] * (A)x[col[p + L]];
+  A s[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) s[u] = 0;
+  for (int p0 = a + l; p0 < e; p0 += L * U) {
+    // entries past the row's end re-read entry p0 (valid, no branch) and contribute zero
+    int c[U];
+    V v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int p = p0 + u * L < e ? p0 + u * L : p0;
+      c[u] = col[p];
+      v[u] = val[p];
+    }
+    X xv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) xv[u] = x[c[u]];
+#pragma unroll
+    for (int u = 0; u < U; ++u) s[u] += (p0 + u * L < e ? (A)v[u] : A(0)) * (A)xv[u];
   }
-  if (p < e) s0 += (A)val[p] * (A)x[col[p]];
-  A sum = s0 + s1;
+#pragma unroll
+  for (int h = U / 2; h > 0; h >>= 1)
+#pragma unroll
+    for (int u = 0; u < h; ++u) s[u] += s[u + h];
+  A sum = s[0];
 #pragma unroll
   for (int o = L / 2; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
   if (l == 0) {
@@ -412,23 +513,33 @@ void spmv_sell(const Sell<V> &M, const X *x, X *y, double alpha, const X *b, dou
   if (M.rows <= 0) return;
   if (M.lanes > 1) {
     const int nb = ceil_div((long long)M.rows * M.lanes, SPMV_T);
-#define EDFA_VEC(LN)                                                                          \
-  launch_timed(k_spmv_csr_vec<V, X, LN>, nb, s, e0, e1, M.csr_rp, M.csr_col, M.csr_val, M.rows, \
-               x, y, alpha, b, beta, gamma, mk)
+    const bool deep = M.depth == 4;
+#define EDFA_VEC(LN, UU)                                                                      \
+  launch_timed(k_spmv_csr_vec<V, X, LN, UU>, nb, s, e0, e1, M.csr_rp, M.csr_col, M.csr_val,    \
+               M.rows, x, y, alpha, b, beta, gamma, mk)
+#define EDFA_VEC2(LN) \
+  if (deep) EDFA_VEC(LN, 4); else EDFA_VEC(LN, 2)
     switch (M.lanes) {
-      case 2: EDFA_VEC(2); break;
-      case 4: EDFA_VEC(4); break;
-      case 8: EDFA_VEC(8); break;
-      case 16: EDFA_VEC(16); break;
-      default: EDFA_VEC(32); break;
+      case 2: EDFA_VEC2(2); break;
+      case 4: EDFA_VEC2(4); break;
+      case 8: EDFA_VEC2(8); break;
+      case 16: EDFA_VEC2(16); break;
+      default: EDFA_VEC2(32); break;
     }
+#undef EDFA_VEC2
 #undef EDFA_VEC
-  } else if (role == SPMV_OPERATOR) {
-    launch_timed(k_spmv_sell<V, X, SPMV_OPERATOR>, ceil_div(M.rows, SPMV_T), s, e0, e1, M.sptr.p,
-                 M.rlen.p, M.col.p, M.val.p, M.rows, x, y, alpha, b, beta, gamma, mk);
   } else {
-    launch_timed(k_spmv_sell<V, X, SPMV_PRECOND>, ceil_div(M.rows, SPMV_T), s, e0, e1, M.sptr.p,
-                 M.rlen.p, M.col.p, M.val.p, M.rows, x, y, alpha, b, beta, gamma, mk);
+    const int nb = ceil_div(M.rows, SPMV_T);
+    const bool deep = M.depth == 8;
+#define EDFA_SELL(RL, UU)                                                                     \
+  launch_timed(k_spmv_sell<V, X, RL, UU>, nb, s, e0, e1, M.sptr.p, M.rlen.p, M.col.p, M.val.p, \
+               M.sorted ? M.perm.p : nullptr, M.rows, x, y, alpha, b, beta, gamma, mk)
+    if (role == SPMV_OPERATOR) {
+      if (deep) EDFA_SELL(SPMV_OPERATOR, 8); else EDFA_SELL(SPMV_OPERATOR, 4);
+    } else {
+      if (deep) EDFA_SELL(SPMV_PRECOND, 8); else EDFA_SELL(SPMV_PRECOND, 4);
+    }
+#undef EDFA_SELL
   }
   EDFA_CHECK_LAUNCH();
 }

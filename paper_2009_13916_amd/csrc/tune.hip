@@ -2,10 +2,11 @@
 //
 // Every matrix the solve multiplies (the system matrix, the FSAI factor and its transpose,
 // the coupling blocks, the ILU(0) factors and their approximate inverses, and their
-// transposes once built) is timed with the SELL kernel (one lane per row) and with the
-// CSR kernel at 2, 4, 8, 16 and 32 lanes per row; the fastest choice is kept in the
-// preconditioner handle and re-applied whenever the copies are rebuilt (the next setup
-// rebuilds them with the default choice).
+// transposes once built) is timed with the SELL kernel (one lane per row, 4 or 8 entries
+// in flight per lane) and with the CSR kernel at 2, 4, 8, 16 and 32 lanes per row (2 or 4
+// entries in flight per lane); the fastest choice is kept in the preconditioner handle
+// and re-applied whenever the copies are rebuilt (the next setup rebuilds them with the
+// default choice).
 #include <hip/hip_ext.h>
 
 #include <algorithm>
@@ -16,7 +17,12 @@ namespace edfa {
 
 namespace {
 
-constexpr int kVariants[] = {0, 2, 4, 8, 16, 32};
+struct Variant {
+  int lanes, depth;
+};
+constexpr Variant kVariants[EDFA_TUNE_VARIANTS] = {{0, 4},  {0, 8},  {2, 2},  {2, 4},
+                                                   {4, 2},  {4, 4},  {8, 2},  {8, 4},
+                                                   {16, 2}, {16, 4}, {32, 2}, {32, 4}};
 
 // Visit every tunable matrix of the active precision path: fn(slot, Sell<V>&, role).
 template <class F>
@@ -48,14 +54,31 @@ void for_each_slot(edfa_precond_s &P, F &&fn) {
   }
 }
 
+// Reads a buffer larger than the last-level cache, so the next launch finds the matrix in
+// HBM as it does inside the solve (where a full iteration streams between two products
+// with the same matrix); the conditional store keeps the loads.
+constexpr long long FLUSH_DOUBLES = 64ll << 20;   // 512 MiB
+__global__ void k_flush(const double *__restrict__ buf, long long n, double *sink) {
+  double acc = 0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    acc += buf[i];
+  if (acc == 1.0) sink[0] = acc;
+}
+
 template <class V>
-float time_lanes(Sell<V> &M, int lanes, int role, DBuf<V> &x, DBuf<V> &y, hipStream_t s,
-                 hipEvent_t e0, hipEvent_t e1) {
-  const int saved = M.lanes;
-  M.lanes = lanes;
+float time_variant(Sell<V> &M, Variant v, int role, DBuf<V> &x, DBuf<V> &y, DBuf<double> &fl,
+                   hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  const int saved = M.lanes, saved_depth = M.depth;
+  M.lanes = v.lanes;
+  M.depth = v.depth;
   spmv_sell<V, V>(M, x.p, y.p, 1.0, nullptr, 0.0, s, 0.0, role);   // warm-up
   float best = 1e30f;
   for (int r = 0; r < 5; ++r) {
+    if (fl.p) {
+      hipLaunchKernelGGL(k_flush, dim3(4096), dim3(256), 0, s, fl.p, FLUSH_DOUBLES, fl.p);
+      EDFA_CHECK_LAUNCH();
+    }
     spmv_sell<V, V>(M, x.p, y.p, 1.0, nullptr, 0.0, s, 0.0, role, e0, e1);
     EDFA_HIP(hipEventSynchronize(e1));
     float ms = 0;
@@ -63,6 +86,7 @@ float time_lanes(Sell<V> &M, int lanes, int role, DBuf<V> &x, DBuf<V> &y, hipStr
     best = std::min(best, ms);
   }
   M.lanes = saved;
+  M.depth = saved_depth;
   return best;
 }
 
@@ -76,12 +100,22 @@ __global__ void k_fill_ones(V *x, long long n) {
 
 void apply_tuned(edfa_precond_s &P) {
   for_each_slot(P, [&](int slot, auto &M, int) {
-    if (P.tuned[slot] >= 0 && M.rows > 0) M.lanes = P.tuned[slot];
+    if (P.tuned[slot] >= 0 && M.rows > 0) {
+      M.lanes = kVariants[P.tuned[slot]].lanes;
+      M.depth = kVariants[P.tuned[slot]].depth;
+    }
   });
+}
+
+void set_variant(edfa_precond_s &P, int slot, int variant) {
+  for (int q = 0; q < EDFA_TUNE_SLOTS; ++q)
+    if (slot < 0 || q == slot) P.tuned[q] = variant;
+  apply_tuned(P);
 }
 
 namespace {
 struct TuneBufs {
+  DBuf<double> flush;   // cache eviction between timed launches (empty: none)
   DBuf<double> xd, yd;
   DBuf<float> xf, yf;
   DBuf<double> &x(double *) { return xd; }
@@ -91,7 +125,8 @@ struct TuneBufs {
 };
 
 template <class V>
-int tune_one(Sell<V> &M, int role, TuneBufs &B, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+int tune_one(Sell<V> &M, int role, TuneBufs &B, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+             float *us) {
   DBuf<V> &x = B.x((V *)nullptr);
   DBuf<V> &y = B.y((V *)nullptr);
   const int nx = std::max(M.cols, 1);
@@ -101,29 +136,52 @@ int tune_one(Sell<V> &M, int role, TuneBufs &B, hipStream_t s, hipEvent_t e0, hi
   EDFA_CHECK_LAUNCH();
   int best = 0;
   float tbest = 1e30f;
-  for (int lanes : kVariants) {
-    const float t = time_lanes(M, lanes, role, x, y, s, e0, e1);
+  for (int v = 0; v < EDFA_TUNE_VARIANTS; ++v) {
+    const float t = time_variant(M, kVariants[v], role, x, y, B.flush, s, e0, e1);
+    us[v] = 1e3f * t;
     if (t < tbest) {
       tbest = t;
-      best = lanes;
+      best = v;
     }
   }
   return best;
 }
 }  // namespace
 
-int autotune(edfa_precond_s &P, hipStream_t s) {
+int autotune(edfa_precond_s &P, hipStream_t s, edfa_tune_slot *slots) {
   hipEvent_t e0, e1;
   EDFA_HIP(hipEventCreate(&e0));
   EDFA_HIP(hipEventCreate(&e1));
   TuneBufs B;
+  // matrices larger than an XCD's L2 are timed cold: a zeroed 512 MiB buffer is read
+  // before every timed launch
+  int64_t biggest = 0;
+  for_each_slot(P, [&](int, auto &M, int) { biggest = std::max<int64_t>(biggest, M.nnz); });
+  if (biggest * 12 > (8ll << 20)) {
+    B.flush.ensure((size_t)FLUSH_DOUBLES);
+    EDFA_HIP(hipMemsetAsync(B.flush.p, 0, sizeof(double) * FLUSH_DOUBLES, s));
+  }
   int tuned = 0;
+  if (slots)
+    for (int q = 0; q < EDFA_TUNE_SLOTS; ++q) slots[q] = edfa_tune_slot{};
   for_each_slot(P, [&](int slot, auto &M, int role) {
     if (M.rows <= 0) return;
-    const int best = tune_one(M, role, B, s, e0, e1);
+    edfa_tune_slot rec{};
+    const int best = tune_one(M, role, B, s, e0, e1, rec.us);
     P.tuned[slot] = best;
-    M.lanes = best;
+    M.lanes = kVariants[best].lanes;
+    M.depth = kVariants[best].depth;
     ++tuned;
+    if (slots) {
+      rec.rows = M.rows;
+      rec.cols = M.cols;
+      rec.nnz = M.nnz;
+      rec.variant = best;
+      rec.value_bytes = (int32_t)sizeof(*M.val.p);
+      rec.sell_sorted = M.sorted ? 1 : 0;
+      rec.sell_padding = M.nnz > 0 ? (float)((double)M.padded / (double)M.nnz) : 1.0f;
+      slots[slot] = rec;
+    }
   });
   EDFA_HIP(hipStreamSynchronize(s));
   (void)hipEventDestroy(e0);

@@ -76,6 +76,25 @@ class _SolveInfo(C.Structure):
                 ("apply_count", C.c_int32)]
 
 
+TUNE_SLOTS = ("A", "A^T", "G_F", "G_F^T", "L", "U", "M_L", "M_U", "L^T", "U^T", "M_L^T",
+              "M_U^T", "A_ppi", "A_pip", "A_pip^T", "A_ppi^T")
+# (lanes per row, entries in flight per lane); lanes 1 = the SELL kernel, else CSR
+TUNE_VARIANTS = ((1, 4), (1, 8), (2, 2), (2, 4), (4, 2), (4, 4), (8, 2), (8, 4), (16, 2),
+                 (16, 4), (32, 2), (32, 4))
+
+
+def variant_name(v):
+    lanes, depth = TUNE_VARIANTS[v]
+    return f"sell/{depth}" if lanes == 1 else f"csr{lanes}/{depth}"
+
+
+class _TuneSlot(C.Structure):
+    _fields_ = [("rows", C.c_int32), ("cols", C.c_int32), ("nnz", C.c_int64),
+                ("variant", C.c_int32), ("value_bytes", C.c_int32),
+                ("sell_sorted", C.c_int32), ("sell_padding", C.c_float),
+                ("us", C.c_float * len(TUNE_VARIANTS))]
+
+
 _lib = None
 
 
@@ -106,7 +125,8 @@ def load():
             "edfa_solve": (C.c_int, [vp, vp, vp, vp, C.POINTER(_SolveParams), vp,
                                      C.POINTER(_SolveInfo)]),
             "edfa_grad_logk": (C.c_int, [vp, vp, vp, vp, vp]),
-            "edfa_autotune": (C.c_int, [vp, vp, C.POINTER(i32)]),
+            "edfa_autotune": (C.c_int, [vp, vp, C.POINTER(i32), C.POINTER(_TuneSlot)]),
+            "edfa_set_variant": (C.c_int, [vp, i32, i32]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name, None)
@@ -125,7 +145,8 @@ def exported_symbols():
                         "edfa_system_get_info", "edfa_update_dt", "edfa_export_block",
                         "edfa_export_rhs", "edfa_spmv", "edfa_setup", "edfa_setup_stage2", "edfa_resetup",
                         "edfa_precond_destroy", "edfa_precond_get_info", "edfa_export_precond",
-                        "edfa_apply", "edfa_solve", "edfa_grad_logk", "edfa_autotune")
+                        "edfa_apply", "edfa_solve", "edfa_grad_logk", "edfa_autotune",
+                        "edfa_set_variant")
             if hasattr(L, n)]
 
 
@@ -274,12 +295,39 @@ class Precond:
         _check(load().edfa_apply(self._h, int(transpose), _ptr(r), _ptr(z), _stream()))
         return z
 
-    def autotune(self):
+    def autotune(self, report=False):
         """Time the sparse-product kernel variants for every matrix of the solve and keep
-        the fastest (returns the number of matrices timed)."""
+        the fastest.  Returns the number of matrices timed, or with report=True a dict
+        {slot name: {rows, cols, nnz, variant, value_bytes, sell_sorted, sell_padding,
+        us: {variant name: microseconds}}} over the matrices that were timed (variant
+        names: variant_name)."""
         n = C.c_int32(0)
-        _check(load().edfa_autotune(self._h, _stream(), C.byref(n)))
-        return n.value
+        rec = (_TuneSlot * len(TUNE_SLOTS))()
+        _check(load().edfa_autotune(self._h, _stream(), C.byref(n), rec))
+        if not report:
+            return n.value
+        out = {}
+        for name, r in zip(TUNE_SLOTS, rec):
+            if r.rows > 0:
+                out[name] = {"rows": r.rows, "cols": r.cols, "nnz": r.nnz,
+                             "variant": variant_name(r.variant), "value_bytes": r.value_bytes,
+                             "sell_sorted": bool(r.sell_sorted),
+                             "sell_padding": float(r.sell_padding),
+                             "us": {variant_name(v): float(t) for v, t in enumerate(r.us)}}
+        return out
+
+    def set_variant(self, variant, slot=None):
+        """Pin the sparse-product kernel of one slot (a name of TUNE_SLOTS or an index;
+        None = every slot) to a variant (a name from variant_name, an index, or None for
+        the default choice)."""
+        s = -1 if slot is None else (TUNE_SLOTS.index(slot) if isinstance(slot, str) else slot)
+        if variant is None:
+            v = -1
+        elif isinstance(variant, str):
+            v = [variant_name(i) for i in range(len(TUNE_VARIANTS))].index(variant)
+        else:
+            v = variant
+        _check(load().edfa_set_variant(self._h, int(s), int(v)))
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:

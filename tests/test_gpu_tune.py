@@ -20,8 +20,14 @@ def test_autotuned_solve_matches_untuned(lib, precision):
     flex = precision == 1
     b = S.rhs()
     x0, i0, s0 = lib.solve(S, P, b, rtol=1e-12, flexible=flex)
-    n = P.autotune()
-    assert n >= 8
+    rep = P.autotune(report=True)
+    assert len(rep) >= 8 and {"A", "G_F", "G_F^T", "M_L", "M_U", "A_ppi", "A_pip"} <= set(rep)
+    for name, r in rep.items():
+        vb = 8 if name in ("A", "A^T") or not flex else 4   # the operator stays FP64
+        assert r["value_bytes"] == vb and len(r["us"]) == len(lib.TUNE_VARIANTS)
+        assert all(t > 0 for t in r["us"].values())
+        assert r["us"][r["variant"]] == min(r["us"].values())
+    assert rep["A"]["rows"] == rep["A"]["cols"] == S.n and rep["A"]["nnz"] == S.info["nnz"]
     x1, i1, s1 = lib.solve(S, P, b, rtol=1e-12, flexible=flex)
     lam, il, sl = lib.solve(S, P, b, rtol=1e-12, flexible=flex, transpose=True)
     P.resetup()

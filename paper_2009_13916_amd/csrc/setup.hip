@@ -829,6 +829,55 @@ __global__ void k_vec_write(const int *__restrict__ Q, const int *__restrict__ q
   }
 }
 
+// Patterns of at most 64 entries: one wavefront per cell (four per block), lane t holding
+// entry t; the pre-filtration norm is a fixed butterfly sum (the count and the write pass
+// compute it the same way), and each kept entry's slot is its rank by column.
+template <class T>
+__device__ inline bool vec_keep(T xv, bool in, int pre, double tau) {
+  if (!pre) return in;
+  const double thr = tau * sqrt(wave_sum((double)xv * (double)xv));
+  return in && fabs((double)xv) >= thr;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_vec_count_w(const int *__restrict__ qlen,
+                                                     const T *__restrict__ v, int ne, int smax,
+                                                     int pre, double tau, int *len) {
+  const int m = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (m >= ne) return;
+  const int s = qlen[m];
+  const bool in = lane < s;
+  const T xv = in ? v[(size_t)m * smax + lane] : T(0);
+  const bool keep = vec_keep(xv, in, pre, tau);
+  const int k = __popcll(__ballot(keep));
+  if (lane == 0) len[m] = k;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_vec_write_w(const int *__restrict__ Q,
+                                                     const int *__restrict__ qlen,
+                                                     const T *__restrict__ v, int ne, int smax,
+                                                     int pre, double tau,
+                                                     const int *__restrict__ rp, int *col, T *val) {
+  const int m = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (m >= ne) return;
+  const int s = qlen[m];
+  const bool in = lane < s;
+  const T xv = in ? v[(size_t)m * smax + lane] : T(0);
+  const int c = in ? Q[(size_t)m * smax + lane] : 0x7fffffff;
+  const bool keep = vec_keep(xv, in, pre, tau);
+  int rank = 0;
+  for (int j = 0; j < s; ++j) {
+    const int cj = __shfl(c, j);
+    const int kj = __shfl((int)keep, j);
+    rank += kj && cj < c;
+  }
+  if (keep) {
+    col[rp[m] + rank] = c;
+    val[rp[m] + rank] = xv;
+  }
+}
+
 // ------------------------------------------------------------------------------------
 // H~ rows: h_m = (A_pipi R^T g~_m)^T F~, one wavefront per cell
 // ------------------------------------------------------------------------------------
@@ -850,14 +899,20 @@ struct HArgs {
   int *retry_list;       //   instead of computed (first pass with small tables)
 };
 
+// Tables: g~ (GH slots), the support of t (TH slots, listed in tlist: TH/2 entries for the
+// small tables, a first-pass row that fills them past half retries; TH for the large ones)
+// and the candidate cells (LH slots; at most LH/2 candidates are kept, listed in llist
+// with their values in hv).
 template <class T, int GH, int TH, int LH>
 __global__ __launch_bounds__(64) void k_htilde(HArgs<T> A) {
+  constexpr int CL = LH / 2;
+  constexpr int TL = TH <= 512 ? TH / 2 : TH;
   __shared__ int gk[GH];
   __shared__ T gv[GH];
-  __shared__ int tk[TH], tlist[TH];
+  __shared__ int tk[TH], tlist[TL];
   __shared__ T tv[TH];
-  __shared__ int lk[LH], llist[LH];
-  __shared__ T hv[LH];
+  __shared__ int lk[LH], llist[CL];
+  __shared__ T hv[CL];
   __shared__ int tcount, lcount, sflag;
   const int m = A.cells ? A.cells[blockIdx.x] : blockIdx.x;
   const int lane = threadIdx.x;
@@ -889,10 +944,12 @@ __global__ __launch_bounds__(64) void k_htilde(HArgs<T> A) {
     row_cols<12>(A.app_rp, A.app_col, A.g_col[p], [&](int c) EDFA_INLINE {
       bool fr;
       const int h = h_insert<TH>(tk, c, fr);
-      if (h < 0)
+      if (h < 0) {
         sflag = 1;
-      else if (fr)
-        tlist[atomicAdd(&tcount, 1)] = h;
+      } else if (fr) {
+        const int i = atomicAdd(&tcount, 1);
+        if (i < TL) tlist[i] = h;
+      }
     });
   }
   __syncthreads();
@@ -900,7 +957,7 @@ __global__ __launch_bounds__(64) void k_htilde(HArgs<T> A) {
     retry();
     return;
   }
-  if (sflag) {
+  if (sflag || tcount > TL) {
     if (lane == 0) atomicMin(A.err_cap, m);
     return;
   }
@@ -918,20 +975,22 @@ __global__ __launch_bounds__(64) void k_htilde(HArgs<T> A) {
   for (int c = lane; c < nt; c += 64) {
     row_cols<16>(A.ff_rp, A.ff_col, tk[tlist[c]], [&](int l) EDFA_INLINE {
       bool fr;
-      const int h = h_insert<LH>(lk, l, fr);
-      if (h < 0)
+      const int q = h_insert<LH>(lk, l, fr);
+      if (q < 0) {
         sflag = 1;
-      else if (fr)
-        llist[atomicAdd(&lcount, 1)] = l;
+      } else if (fr) {
+        const int i = atomicAdd(&lcount, 1);
+        if (i < CL) llist[i] = l;
+      }
     });
   }
   __syncthreads();
   const int nl = lcount;
-  if (A.retry_count && (sflag || nl > LH / 2)) {
+  if (A.retry_count && (sflag || nl > CL)) {
     retry();
     return;
   }
-  if (sflag || nl > HMAX) {
+  if (sflag || nl > CL || nl > HMAX) {
     if (lane == 0) atomicMin(A.err_cap, m);
     return;
   }
@@ -956,48 +1015,61 @@ __global__ __launch_bounds__(64) void k_htilde(HArgs<T> A) {
   if (lane == 0) A.Hlen[m] = nl;
 }
 
-// Post-filtration on H~ (row norm before dropping, diagonal kept) and compaction.
+// Post-filtration on H~ (row norm before dropping, diagonal kept) and compaction: one
+// wavefront per row (four rows per block of 256), lanes across the row's entries; the
+// norm is a fixed butterfly sum, and the kept entries keep their order (ballot prefix).
 template <class T>
-__global__ void k_hcount(const int *__restrict__ Hcol, const T *__restrict__ Hval,
-                         const int *__restrict__ Hlen, int ne, int filt, double tau, int *len) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= ne) return;
-  const int n = Hlen[m];
-  if (!filt) {
-    len[m] = n;
-    return;
-  }
-  const T *v = Hval + (size_t)m * HMAX;
-  const int *c = Hcol + (size_t)m * HMAX;
+__device__ inline double hrow_threshold(const T *v, int n, int lane, int filt, double tau) {
+  if (!filt) return -1.0;
   double nrm = 0;
-  for (int t = 0; t < n; ++t) nrm += (double)v[t] * (double)v[t];
-  const double thr = tau * sqrt(nrm);
-  int k = 0;
-  for (int t = 0; t < n; ++t) k += (fabs((double)v[t]) >= thr) || c[t] == m;
-  len[m] = k;
+  for (int t = lane; t < n; t += 64) nrm += (double)v[t] * (double)v[t];
+  return tau * sqrt(wave_sum(nrm));
 }
 
 template <class T>
-__global__ void k_hwrite(const int *__restrict__ Hcol, const T *__restrict__ Hval,
-                         const int *__restrict__ Hlen, int ne, int filt, double tau,
-                         const int *__restrict__ rp, int *col, T *val) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_hcount(const int *__restrict__ Hcol,
+                                                const T *__restrict__ Hval,
+                                                const int *__restrict__ Hlen, int ne, int filt,
+                                                double tau, int *len) {
+  const int m = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (m >= ne) return;
   const int n = Hlen[m];
   const T *v = Hval + (size_t)m * HMAX;
   const int *c = Hcol + (size_t)m * HMAX;
-  double thr = -1.0;
-  if (filt) {
-    double nrm = 0;
-    for (int t = 0; t < n; ++t) nrm += (double)v[t] * (double)v[t];
-    thr = tau * sqrt(nrm);
+  const double thr = hrow_threshold(v, n, lane, filt, tau);
+  int k = 0;
+  for (int t0 = 0; t0 < n; t0 += 64) {
+    const int t = t0 + lane;
+    const bool keep = t < n && (!filt || fabs((double)v[t]) >= thr || c[t] == m);
+    k += __popcll(__ballot(keep));
   }
+  if (lane == 0) len[m] = k;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_hwrite(const int *__restrict__ Hcol,
+                                                const T *__restrict__ Hval,
+                                                const int *__restrict__ Hlen, int ne, int filt,
+                                                double tau, const int *__restrict__ rp, int *col,
+                                                T *val) {
+  const int m = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (m >= ne) return;
+  const int n = Hlen[m];
+  const T *v = Hval + (size_t)m * HMAX;
+  const int *c = Hcol + (size_t)m * HMAX;
+  const double thr = hrow_threshold(v, n, lane, filt, tau);
+  const unsigned long long below = (1ull << lane) - 1;
   int o = rp[m];
-  for (int t = 0; t < n; ++t) {
-    if (filt && !((fabs((double)v[t]) >= thr) || c[t] == m)) continue;
-    col[o] = c[t];
-    val[o] = v[t];
-    ++o;
+  for (int t0 = 0; t0 < n; t0 += 64) {
+    const int t = t0 + lane;
+    const bool keep = t < n && (!filt || fabs((double)v[t]) >= thr || c[t] == m);
+    const unsigned long long mask = __ballot(keep);
+    if (keep) {
+      const int q = o + __popcll(mask & below);
+      col[q] = c[t];
+      val[q] = v[t];
+    }
+    o += __popcll(mask);
   }
 }
 
@@ -1079,8 +1151,15 @@ static void build_vec_csr(edfa_system_s &S, PrecData<T> &D, const DBuf<T> &v, in
                           double tau, Csr<T> &out, hipStream_t s) {
   const int ne = S.ne;
   out.rowptr.ensure((size_t)ne + 1);
-  hipLaunchKernelGGL(k_vec_count<T>, dim3(ceil_div(ne, 256)), dim3(256), 0, s, D.qlen.p, v.p, ne,
-                     smax, pre, tau, out.rowptr.p);
+  // patterns of up to 64 entries: wavefront kernels (the count and the write pass must
+  // share the way the filtration norm is summed)
+  const bool wave = smax <= 64;
+  if (wave)
+    hipLaunchKernelGGL(k_vec_count_w<T>, dim3(ceil_div(ne, 4)), dim3(256), 0, s, D.qlen.p, v.p,
+                       ne, smax, pre, tau, out.rowptr.p);
+  else
+    hipLaunchKernelGGL(k_vec_count<T>, dim3(ceil_div(ne, 256)), dim3(256), 0, s, D.qlen.p, v.p,
+                       ne, smax, pre, tau, out.rowptr.p);
   EDFA_CHECK_LAUNCH();
   const int64_t nnz = exclusive_scan(out.rowptr.p, out.rowptr.p, ne, S.tmp, s);
   out.rows = ne;
@@ -1093,13 +1172,11 @@ static void build_vec_csr(edfa_system_s &S, PrecData<T> &D, const DBuf<T> &v, in
                        pre, tau, out.rowptr.p, out.col.p, out.val.p);
     EDFA_CHECK_LAUNCH();
   };
-  if (smax <= 16)
-    launch(k_vec_write<T, 16>);
-  else if (smax <= 32)
-    launch(k_vec_write<T, 32>);
-  else if (smax <= 64)
-    launch(k_vec_write<T, 64>);
-  else if (smax <= 128)
+  if (wave) {
+    hipLaunchKernelGGL(k_vec_write_w<T>, dim3(ceil_div(ne, 4)), dim3(256), 0, s, D.Q.p, D.qlen.p,
+                       v.p, ne, smax, pre, tau, out.rowptr.p, out.col.p, out.val.p);
+    EDFA_CHECK_LAUNCH();
+  } else if (smax <= 128)
     launch(k_vec_write<T, 128>);
   else
     launch(k_vec_write<T, PATCH_MAX>);
@@ -1270,8 +1347,8 @@ static void stage1_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
     EDFA_CHECK_LAUNCH();
   };
   if (ne > 0 && P.max_pattern <= 64) {
-    // first pass with half-size tables (twice the occupancy); rows that fill them past half
-    // are listed and recomputed with the large tables
+    // first pass with small tables (about twice the occupancy); rows that fill them past
+    // their limits are listed and recomputed with the large tables
     D.hretry.ensure(ne);
     EDFA_HIP(hipMemsetAsync(P.flags.p + 3, 0, sizeof(int), s));
     ha.retry_count = P.flags.p + 3;
@@ -1293,7 +1370,7 @@ static void stage1_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
   check_flags(P, s, "H~ rows");
   const int postH = prm.filt_mode == EDFA_FILT_POST_H;
   D.H.rowptr.ensure((size_t)ne + 1);
-  hipLaunchKernelGGL(k_hcount<T>, dim3(ceil_div(ne, 256)), dim3(256), 0, s, D.Hcol.p, D.Hval.p,
+  hipLaunchKernelGGL(k_hcount<T>, dim3(ceil_div(ne, 4)), dim3(256), 0, s, D.Hcol.p, D.Hval.p,
                      D.Hlen.p, ne, postH, prm.tau_filt, D.H.rowptr.p);
   EDFA_CHECK_LAUNCH();
   const int64_t hnnz = exclusive_scan(D.H.rowptr.p, D.H.rowptr.p, ne, S.tmp, s);
@@ -1301,7 +1378,7 @@ static void stage1_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
   D.H.nnz = hnnz;
   D.H.col.ensure(hnnz);
   D.H.val.ensure(hnnz);
-  hipLaunchKernelGGL(k_hwrite<T>, dim3(ceil_div(ne, 256)), dim3(256), 0, s, D.Hcol.p, D.Hval.p,
+  hipLaunchKernelGGL(k_hwrite<T>, dim3(ceil_div(ne, 4)), dim3(256), 0, s, D.Hcol.p, D.Hval.p,
                      D.Hlen.p, ne, postH, prm.tau_filt, D.H.rowptr.p, D.H.col.p, D.H.val.p);
   EDFA_CHECK_LAUNCH();
 
@@ -1333,14 +1410,14 @@ void build_hraw(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
   edfa_system_s &S = *P.sys;
   const int ne = S.ne;
   D.Hraw.rowptr.ensure((size_t)ne + 1);
-  hipLaunchKernelGGL(k_hcount<T>, dim3(ceil_div(ne, 256)), dim3(256), 0, s, D.Hcol.p, D.Hval.p,
+  hipLaunchKernelGGL(k_hcount<T>, dim3(ceil_div(ne, 4)), dim3(256), 0, s, D.Hcol.p, D.Hval.p,
                      D.Hlen.p, ne, 0, 0.0, D.Hraw.rowptr.p);
   const int64_t nnz = exclusive_scan(D.Hraw.rowptr.p, D.Hraw.rowptr.p, ne, S.tmp, s);
   D.Hraw.rows = D.Hraw.cols = ne;
   D.Hraw.nnz = nnz;
   D.Hraw.col.ensure(nnz);
   D.Hraw.val.ensure(nnz);
-  hipLaunchKernelGGL(k_hwrite<T>, dim3(ceil_div(ne, 256)), dim3(256), 0, s, D.Hcol.p, D.Hval.p,
+  hipLaunchKernelGGL(k_hwrite<T>, dim3(ceil_div(ne, 4)), dim3(256), 0, s, D.Hcol.p, D.Hval.p,
                      D.Hlen.p, ne, 0, 0.0, D.Hraw.rowptr.p, D.Hraw.col.p, D.Hraw.val.p);
   EDFA_CHECK_LAUNCH();
 }

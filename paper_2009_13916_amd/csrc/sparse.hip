@@ -93,14 +93,19 @@ __global__ void k_count_cols(const int *__restrict__ col, int64_t nnz, int *cnt)
   if (k < nnz) atomicAdd(&cnt[col[k]], 1);
 }
 
-template <class V>
-__global__ void k_transpose_fill(const int *__restrict__ rowptr, const int *__restrict__ col,
-                                 const V *__restrict__ val, int rows, int *cursor, int *colT,
-                                 V *valT) {
-  int r = blockIdx.x * blockDim.x + threadIdx.x;
+// L lanes per source row, across its entries (the order inside a target row is fixed by the
+// sort that follows)
+template <class V, int L>
+__global__ __launch_bounds__(256) void k_transpose_fill(const int *__restrict__ rowptr,
+                                                        const int *__restrict__ col,
+                                                        const V *__restrict__ val, int rows,
+                                                        int *cursor, int *colT, V *valT) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  const int r = t / L;
   if (r >= rows) return;
-  for (int k = rowptr[r]; k < rowptr[r + 1]; ++k) {
-    int pos = atomicAdd(&cursor[col[k]], 1);
+  const int e = rowptr[r + 1];
+  for (int k = rowptr[r] + t % L; k < e; k += L) {
+    const int pos = atomicAdd(&cursor[col[k]], 1);
     colT[pos] = r;
     valT[pos] = val[k];
   }
@@ -172,9 +177,14 @@ void csr_transpose(const Csr<V> &src, Csr<V> &dst, DBuf<int> &tmp, DBuf<int> &cu
   EDFA_HIP(hipMemcpyAsync(cursor.p, dst.rowptr.p, sizeof(int) * ((size_t)src.cols + 1),
                           hipMemcpyDeviceToDevice, s));
   if (src.rows > 0) {
-    hipLaunchKernelGGL(k_transpose_fill<V>, dim3(ceil_div(src.rows, 256)), dim3(256), 0, s,
-                       src.rowptr.p, src.col.p, src.val.p, src.rows, cursor.p, dst.col.p,
-                       dst.val.p);
+    if ((double)src.nnz > 16.0 * src.rows)
+      hipLaunchKernelGGL((k_transpose_fill<V, 16>), dim3(ceil_div((long long)src.rows * 16, 256)),
+                         dim3(256), 0, s, src.rowptr.p, src.col.p, src.val.p, src.rows, cursor.p,
+                         dst.col.p, dst.val.p);
+    else
+      hipLaunchKernelGGL((k_transpose_fill<V, 4>), dim3(ceil_div((long long)src.rows * 4, 256)),
+                         dim3(256), 0, s, src.rowptr.p, src.col.p, src.val.p, src.rows, cursor.p,
+                         dst.col.p, dst.val.p);
     EDFA_CHECK_LAUNCH();
   }
   if (src.cols > 0 && sort) {

@@ -92,6 +92,90 @@ __global__ void k_merge_write(const int *arp, const int *acol, const double *ava
   merge_row<T, true>(arp, acol, aval, hrp, hcol, hval, i, filt, tau, ocol + orp[i], oval + orp[i]);
 }
 
+// Without post-filtration on S~: one wavefront per row (four per block of 256).  Lane j holds
+// entry j of the A_pp row (rows of up to 64 entries; a longer row is merged by lane 0 with
+// merge_row); the H~ row streams through in chunks of 64.  Pass 1 finds, for each A_pp
+// entry, whether H~ holds its column and how many H~ columns are smaller; pass 2 places
+// each H~ entry at its index plus the number of smaller A_pp-only columns, and each
+// A_pp-only entry after the smaller H~ columns and the A_pp-only entries before it: the
+// union sorted by column, with the same values as merge_row.
+template <class T, bool WRITE>
+__device__ int merge_row_wave(const int *arp, const int *acol, const double *aval, const int *hrp,
+                              const int *hcol, const T *hval, int i, int lane, int *ocol,
+                              T *oval) {
+  const int a0 = arp[i], na = arp[i + 1] - a0, h0 = hrp[i], nh = hrp[i + 1] - h0;
+  if (na > 64) {   // uniform
+    int n = 0;
+    if (lane == 0) n = merge_row<T, WRITE>(arp, acol, aval, hrp, hcol, hval, i, 0, 0.0, ocol, oval);
+    return __shfl(n, 0);
+  }
+  const bool ina = lane < na;
+  const int ac = ina ? acol[a0 + lane] : 0x7fffffff;
+  const T av = ina ? (T)aval[a0 + lane] : T(0);
+  int lessH = 0;      // for this lane's A_pp entry: H~ entries with smaller columns
+  bool inH = false;   // ... and whether H~ holds its column
+  for (int q0 = 0; q0 < nh; q0 += 64) {
+    const int q = q0 + lane;
+    const bool inh = q < nh;
+    const int hc = inh ? hcol[h0 + q] : 0x7fffffff;
+    for (int j = 0; j < na; ++j) {
+      const int cj = __shfl(ac, j);
+      const unsigned long long lt = __ballot(inh && hc < cj), eq = __ballot(inh && hc == cj);
+      if (lane == j) {
+        lessH += __popcll(lt);
+        inH = inH || eq != 0;
+      }
+    }
+  }
+  const bool aonly = ina && !inH;
+  const unsigned long long amask = __ballot(aonly);
+  if (!WRITE) return nh + __popcll(amask);
+  if (aonly) {
+    const int o = lessH + __popcll(amask & ((1ull << lane) - 1));
+    ocol[o] = ac;
+    oval[o] = av;
+  }
+  for (int q0 = 0; q0 < nh; q0 += 64) {
+    const int q = q0 + lane;
+    const bool inh = q < nh;
+    const int hc = inh ? hcol[h0 + q] : 0x7fffffff;
+    const T hv = inh ? hval[h0 + q] : T(0);
+    int less = 0, match = -1;
+    for (int j = 0; j < na; ++j) {
+      const int cj = __shfl(ac, j);
+      less += ((amask >> j) & 1) && cj < hc;
+      if (cj == hc) match = j;
+    }
+    const T am = __shfl(av, match < 0 ? 0 : match);
+    if (inh) {
+      ocol[q + less] = hc;
+      oval[q + less] = match >= 0 ? am - hv : -hv;
+    }
+  }
+  return nh + __popcll(amask);
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_merge_count_w(const int *arp, const int *acol,
+                                                       const double *aval, const int *hrp,
+                                                       const int *hcol, const T *hval, int ne,
+                                                       int *len) {
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (i >= ne) return;
+  const int n = merge_row_wave<T, false>(arp, acol, aval, hrp, hcol, hval, i, lane, nullptr, nullptr);
+  if (lane == 0) len[i] = n;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_merge_write_w(const int *arp, const int *acol,
+                                                       const double *aval, const int *hrp,
+                                                       const int *hcol, const T *hval, int ne,
+                                                       const int *orp, int *ocol, T *oval) {
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (i >= ne) return;
+  merge_row_wave<T, true>(arp, acol, aval, hrp, hcol, hval, i, lane, ocol + orp[i], oval + orp[i]);
+}
+
 // ---------------------------------------------------------------------------------------
 // Colouring
 // ---------------------------------------------------------------------------------------
@@ -250,13 +334,17 @@ __device__ inline int bsearch_range(const int *a, int lo, int hi, int key) {
 // LDS; for each pivot column k (ascending) the lanes stream the U part of row k and update
 // the matching entries of the row (found by binary search), so row i's updates keep the
 // IKJ order exactly.
+// Dynamic LDS of the per-row kernels below, `cap` entries per array (cap = the longest row
+// of S~): the T arrays first, then the int arrays.
+extern __shared__ __align__(16) unsigned char row_lds[];
+
 template <class T>
 __global__ __launch_bounds__(64) void k_ilu_color(const int *__restrict__ rp,
                                                   const int *__restrict__ col, T *val,
                                                   const int *__restrict__ diag, int r0, int r1,
-                                                  int *err) {
-  __shared__ int ci[HMAX + 64];
-  __shared__ T vi[HMAX + 64];
+                                                  int cap, int *err) {
+  T *vi = (T *)row_lds;
+  int *ci = (int *)(vi + cap), *sdk = ci + cap, *sek = sdk + cap;
   const int i = r0 + blockIdx.x;
   if (i >= r1) return;
   const int a = rp[i], n = rp[i + 1] - a, d = diag[i] - a;
@@ -265,24 +353,32 @@ __global__ __launch_bounds__(64) void k_ilu_color(const int *__restrict__ rp,
     vi[t] = val[a + t];
   }
   __syncthreads();
-  // Software pipeline over the pivots: the next pivot row's diagonal position, end, u_kk and
-  // first 64 upper entries (one per lane, in registers) are requested while this step runs.
-  int dk = 0, ek = 0, qc = -1;
-  T uk = T(1), qv = T(0);
-  auto fetch = [&](int p) {
-    const int k = ci[p];
-    dk = diag[k];
-    ek = rp[k + 1];
+  // diagonal position and end of every pivot row, all at once
+  for (int t = threadIdx.x; t < d; t += 64) {
+    const int k = ci[t];
+    sdk[t] = diag[k];
+    sek[t] = rp[k + 1];
+  }
+  __syncthreads();
+  // Software pipeline over the pivots: u_kk and the first 64 upper entries of pivot rows
+  // p + 1 and p + 2 (one entry per lane, in registers) are in flight while step p runs.
+  int qc0 = -1, qc1 = -1, qc2 = -1;
+  T uk0 = T(1), uk1 = T(1), uk2 = T(1), qv0 = T(0), qv1 = T(0), qv2 = T(0);
+  auto fetch = [&](int p, T &uk, int &qc, T &qv) {
+    const int dk = sdk[p], ek = sek[p];
     uk = val[dk];
     const int q = dk + 1 + threadIdx.x;
     qc = q < ek ? col[q] : -1;
     qv = q < ek ? val[q] : T(0);
   };
-  if (d > 0) fetch(0);
+  if (d > 0) fetch(0, uk1, qc1, qv1);
+  if (d > 1) fetch(1, uk2, qc2, qv2);
   for (int p = 0; p < d; ++p) {
-    const int cdk = dk, cek = ek, cqc = qc;
-    const T cuk = uk, cqv = qv;
-    if (p + 1 < d) fetch(p + 1);
+    uk0 = uk1, qc0 = qc1, qv0 = qv1;
+    uk1 = uk2, qc1 = qc2, qv1 = qv2;
+    if (p + 2 < d) fetch(p + 2, uk2, qc2, qv2);
+    const int cdk = sdk[p], cek = sek[p], cqc = qc0;
+    const T cuk = uk0, cqv = qv0;
     const T lik = vi[p] / cuk;
     if (cqc >= 0) {
       const int pos = bsearch_range(ci, p + 1, n, cqc);
@@ -316,22 +412,26 @@ __global__ void k_split_len(const int *__restrict__ rp, const int *__restrict__ 
   ulen[i] = rp[i + 1] - diag[i];
 }
 
+// L and U parts of each row (one wavefront per row, four rows per block of 256)
 template <class T>
-__global__ void k_split(const int *__restrict__ rp, const int *__restrict__ col,
-                        const T *__restrict__ val, const int *__restrict__ diag, int n,
-                        const int *__restrict__ lrp, int *lcol, T *lval, const int *__restrict__ urp,
-                        int *ucol, T *uval) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_split(const int *__restrict__ rp,
+                                               const int *__restrict__ col,
+                                               const T *__restrict__ val,
+                                               const int *__restrict__ diag, int n,
+                                               const int *__restrict__ lrp, int *lcol, T *lval,
+                                               const int *__restrict__ urp, int *ucol, T *uval) {
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (i >= n) return;
-  int o = lrp[i];
-  for (int p = rp[i]; p < diag[i]; ++p, ++o) {
-    lcol[o] = col[p];
-    lval[o] = val[p];
-  }
-  o = urp[i];
-  for (int p = diag[i]; p < rp[i + 1]; ++p, ++o) {
-    ucol[o] = col[p];
-    uval[o] = val[p];
+  const int a = rp[i], e = rp[i + 1], d = diag[i];
+  const int lo = lrp[i] - a, uo = urp[i] - d;
+  for (int p = a + lane; p < e; p += 64) {
+    if (p < d) {
+      lcol[lo + p] = col[p];
+      lval[lo + p] = val[p];
+    } else {
+      ucol[uo + p] = col[p];
+      uval[uo + p] = val[p];
+    }
   }
 }
 
@@ -351,30 +451,55 @@ __device__ inline int bsearch_lds(const int *a, int n, int key) {
 
 // ISAI of the unit lower factor (I + L): row i on P = cols(L row i) + {i}.
 // (T[P,P])^T m = e_i, solved from the last index down: m_k = delta_ik - sum_{j>k} T[j,k] m_j.
+// The extents of all rows k in P are read at once; the first 64 entries of the rows of the
+// next two steps are in flight (one per lane, in registers) while a step runs, and rows
+// past 64 entries read their remainder in the step.  The order of the updates of each
+// acc entry is the order of the steps, as without the prefetch.
 template <class T>
 __global__ __launch_bounds__(64) void k_isai_lower(const int *__restrict__ lrp,
                                                    const int *__restrict__ lcol,
-                                                   const T *__restrict__ lval, int n,
+                                                   const T *__restrict__ lval, int n, int cap,
                                                    const int *__restrict__ mrp, int *mcol, T *mval) {
-  __shared__ int P[HMAX + 64];
-  __shared__ T acc[HMAX + 64];
+  T *acc = (T *)row_lds;
+  int *P = (int *)(acc + cap), *rb = P + cap, *re = rb + cap;
   const int i = blockIdx.x;
   if (i >= n) return;
   const int a = lrp[i], nl = lrp[i + 1] - a, np = nl + 1;
   for (int t = threadIdx.x; t < np; t += 64) {
-    P[t] = t < nl ? lcol[a + t] : i;
+    const int k = t < nl ? lcol[a + t] : i;
+    P[t] = k;
+    rb[t] = lrp[k];
+    re[t] = lrp[k + 1];
     acc[t] = 0;
   }
   __syncthreads();
   const int o = mrp[i];
+  int c1 = -1, c2 = -1;
+  T v1 = T(0), v2 = T(0);
+  auto fetch = [&](int idx, int &c, T &v) {
+    const int q = rb[idx] + threadIdx.x;
+    c = q < re[idx] ? lcol[q] : -1;
+    v = q < re[idx] ? lval[q] : T(0);
+  };
+  fetch(np - 1, c1, v1);
+  if (np > 1) fetch(np - 2, c2, v2);
   for (int idx = np - 1; idx >= 0; --idx) {
+    const int c0 = c1;
+    const T v0 = v1;
+    c1 = c2;
+    v1 = v2;
+    if (idx >= 2) fetch(idx - 2, c2, v2);
     const int k = P[idx];
     const T mk = (k == i ? T(1) : T(0)) - acc[idx];
     if (threadIdx.x == 0) {
       mcol[o + idx] = k;
       mval[o + idx] = mk;
     }
-    for (int p = lrp[k] + threadIdx.x; p < lrp[k + 1]; p += 64) {
+    if (c0 >= 0) {
+      const int pos = bsearch_lds(P, idx, c0);
+      if (pos >= 0) acc[pos] += v0 * mk;
+    }
+    for (int p = rb[idx] + 64 + threadIdx.x; p < re[idx]; p += 64) {
       const int pos = bsearch_lds(P, idx, lcol[p]);
       if (pos >= 0) acc[pos] += lval[p] * mk;
     }
@@ -384,30 +509,54 @@ __global__ __launch_bounds__(64) void k_isai_lower(const int *__restrict__ lrp,
 
 // ISAI of U (diagonal first in each row): row i on P = cols(U row i).
 // (U[P,P])^T m = e_i, solved upward: m_k = (delta_ik - sum_{j<k} U[j,k] m_j) / U[k,k].
+// Same prefetch scheme as the lower factor (rows k start with their diagonal, read with the
+// extents).
 template <class T>
 __global__ __launch_bounds__(64) void k_isai_upper(const int *__restrict__ urp,
                                                    const int *__restrict__ ucol,
-                                                   const T *__restrict__ uval, int n, int *mcol,
-                                                   T *mval) {
-  __shared__ int P[HMAX + 64];
-  __shared__ T acc[HMAX + 64];
+                                                   const T *__restrict__ uval, int n, int cap,
+                                                   int *mcol, T *mval) {
+  T *acc = (T *)row_lds, *ud = acc + cap;
+  int *P = (int *)(ud + cap), *rb = P + cap, *re = rb + cap;
   const int i = blockIdx.x;
   if (i >= n) return;
   const int a = urp[i], np = urp[i + 1] - a;
   for (int t = threadIdx.x; t < np; t += 64) {
-    P[t] = ucol[a + t];
+    const int k = ucol[a + t];
+    P[t] = k;
+    const int kb = urp[k];
+    rb[t] = kb + 1;
+    re[t] = urp[k + 1];
+    ud[t] = uval[kb];
     acc[t] = 0;
   }
   __syncthreads();
+  int c1 = -1, c2 = -1;
+  T v1 = T(0), v2 = T(0);
+  auto fetch = [&](int idx, int &c, T &v) {
+    const int q = rb[idx] + threadIdx.x;
+    c = q < re[idx] ? ucol[q] : -1;
+    v = q < re[idx] ? uval[q] : T(0);
+  };
+  if (np > 0) fetch(0, c1, v1);
+  if (np > 1) fetch(1, c2, v2);
   for (int idx = 0; idx < np; ++idx) {
+    const int c0 = c1;
+    const T v0 = v1;
+    c1 = c2;
+    v1 = v2;
+    if (idx + 2 < np) fetch(idx + 2, c2, v2);
     const int k = P[idx];
-    const int kb = urp[k];
-    const T mk = ((k == i ? T(1) : T(0)) - acc[idx]) / uval[kb];
+    const T mk = ((k == i ? T(1) : T(0)) - acc[idx]) / ud[idx];
     if (threadIdx.x == 0) {
       mcol[a + idx] = k;
       mval[a + idx] = mk;
     }
-    for (int p = kb + 1 + threadIdx.x; p < urp[k + 1]; p += 64) {
+    if (c0 >= 0) {
+      const int pos = bsearch_lds(P + idx + 1, np - idx - 1, c0);
+      if (pos >= 0) acc[idx + 1 + pos] += v0 * mk;
+    }
+    for (int p = rb[idx] + 64 + threadIdx.x; p < re[idx]; p += 64) {
       const int pos = bsearch_lds(P + idx + 1, np - idx - 1, ucol[p]);
       if (pos >= 0) acc[idx + 1 + pos] += uval[p] * mk;
     }
@@ -456,18 +605,28 @@ static void stage2_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
   // S~ = A_pp - H~, post-filtration on S~
   const int postS = prm.filt_mode == EDFA_FILT_POST_S;
   D.S.rowptr.ensure((size_t)ne + 1);
-  hipLaunchKernelGGL(k_merge_count<T>, dim3(ceil_div(ne, 256)), dim3(256), 0, s, S.Acc.rowptr.p,
-                     S.Acc.col.p, S.Acc.val.p, D.H.rowptr.p, D.H.col.p, D.H.val.p, ne, postS,
-                     prm.tau_filt, D.S.rowptr.p);
+  if (postS)
+    hipLaunchKernelGGL(k_merge_count<T>, dim3(ceil_div(ne, 256)), dim3(256), 0, s,
+                       S.Acc.rowptr.p, S.Acc.col.p, S.Acc.val.p, D.H.rowptr.p, D.H.col.p,
+                       D.H.val.p, ne, postS, prm.tau_filt, D.S.rowptr.p);
+  else
+    hipLaunchKernelGGL(k_merge_count_w<T>, dim3(ceil_div(ne, 4)), dim3(256), 0, s,
+                       S.Acc.rowptr.p, S.Acc.col.p, S.Acc.val.p, D.H.rowptr.p, D.H.col.p,
+                       D.H.val.p, ne, D.S.rowptr.p);
   EDFA_CHECK_LAUNCH();
   const int64_t snnz = exclusive_scan(D.S.rowptr.p, D.S.rowptr.p, ne, S.tmp, s);
   D.S.rows = D.S.cols = ne;
   D.S.nnz = snnz;
   D.S.col.ensure(snnz);
   D.S.val.ensure(snnz);
-  hipLaunchKernelGGL(k_merge_write<T>, dim3(ceil_div(ne, 256)), dim3(256), 0, s, S.Acc.rowptr.p,
-                     S.Acc.col.p, S.Acc.val.p, D.H.rowptr.p, D.H.col.p, D.H.val.p, ne, postS,
-                     prm.tau_filt, D.S.rowptr.p, D.S.col.p, D.S.val.p);
+  if (postS)
+    hipLaunchKernelGGL(k_merge_write<T>, dim3(ceil_div(ne, 256)), dim3(256), 0, s,
+                       S.Acc.rowptr.p, S.Acc.col.p, S.Acc.val.p, D.H.rowptr.p, D.H.col.p,
+                       D.H.val.p, ne, postS, prm.tau_filt, D.S.rowptr.p, D.S.col.p, D.S.val.p);
+  else
+    hipLaunchKernelGGL(k_merge_write_w<T>, dim3(ceil_div(ne, 4)), dim3(256), 0, s,
+                       S.Acc.rowptr.p, S.Acc.col.p, S.Acc.val.p, D.H.rowptr.p, D.H.col.p,
+                       D.H.val.p, ne, D.S.rowptr.p, D.S.col.p, D.S.val.p);
   EDFA_CHECK_LAUNCH();
   EDFA_HIP(hipMemsetAsync(P.flags.p + 2, 0, sizeof(int), s));
   hipLaunchKernelGGL(k_row_len_max, dim3(ceil_div(ne, 256)), dim3(256), 0, s, D.S.rowptr.p, ne,
@@ -565,12 +724,14 @@ static void stage2_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
   EDFA_CHECK_LAUNCH();
   if (read_scalar(P.flags.p + 1, s) != 0x7fffffff)
     fail(EDFA_ERR_BREAKDOWN, "S~ row %d has no diagonal entry", read_scalar(P.flags.p + 1, s));
-  // ILU(0) colour by colour
+  // ILU(0) colour by colour; the per-row kernels size their LDS by the longest row
+  const int cap = std::max(smaxrow, 1);
+  const size_t lds_ilu = (size_t)cap * (sizeof(T) + 3 * sizeof(int));
   for (int c = 0; c < ncol; ++c) {
     const int r0 = D.cstart[c], r1 = D.cstart[c + 1];
     if (r1 > r0)
-      hipLaunchKernelGGL(k_ilu_color<T>, dim3(r1 - r0), dim3(64), 0, s, D.B.rowptr.p, D.B.col.p,
-                         D.B.val.p, D.diag.p, r0, r1, P.flags.p);
+      hipLaunchKernelGGL(k_ilu_color<T>, dim3(r1 - r0), dim3(64), lds_ilu, s, D.B.rowptr.p,
+                         D.B.col.p, D.B.val.p, D.diag.p, r0, r1, cap, P.flags.p);
   }
   EDFA_CHECK_LAUNCH();
   if (read_scalar(P.flags.p, s) != 0x7fffffff)
@@ -591,7 +752,7 @@ static void stage2_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
   D.L.val.ensure(lnnz);
   D.U.col.ensure(unnz);
   D.U.val.ensure(unnz);
-  hipLaunchKernelGGL(k_split<T>, dim3(ceil_div(ne, 256)), dim3(256), 0, s, D.B.rowptr.p, D.B.col.p,
+  hipLaunchKernelGGL(k_split<T>, dim3(ceil_div(ne, 4)), dim3(256), 0, s, D.B.rowptr.p, D.B.col.p,
                      D.B.val.p, D.diag.p, ne, D.L.rowptr.p, D.L.col.p, D.L.val.p, D.U.rowptr.p,
                      D.U.col.p, D.U.val.p);
   EDFA_CHECK_LAUNCH();
@@ -605,11 +766,13 @@ static void stage2_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
     EDFA_HIP(hipMemcpyAsync(D.MU.rowptr.p, D.U.rowptr.p, sizeof(int) * ((size_t)ne + 1),
                             hipMemcpyDeviceToDevice, s));
     if (ne) {
-      hipLaunchKernelGGL(k_isai_lower<T>, dim3(ne), dim3(64), 0, s, D.L.rowptr.p, D.L.col.p,
-                         D.L.val.p, ne, D.ML.rowptr.p, D.ML.col.p, D.ML.val.p);
+      hipLaunchKernelGGL(k_isai_lower<T>, dim3(ne), dim3(64),
+                         (size_t)cap * (sizeof(T) + 3 * sizeof(int)), s, D.L.rowptr.p,
+                         D.L.col.p, D.L.val.p, ne, cap, D.ML.rowptr.p, D.ML.col.p, D.ML.val.p);
       EDFA_CHECK_LAUNCH();
-      hipLaunchKernelGGL(k_isai_upper<T>, dim3(ne), dim3(64), 0, s, D.U.rowptr.p, D.U.col.p,
-                         D.U.val.p, ne, D.MU.col.p, D.MU.val.p);
+      hipLaunchKernelGGL(k_isai_upper<T>, dim3(ne), dim3(64),
+                         (size_t)cap * (2 * sizeof(T) + 3 * sizeof(int)), s, D.U.rowptr.p,
+                         D.U.col.p, D.U.val.p, ne, cap, D.MU.col.p, D.MU.val.p);
       EDFA_CHECK_LAUNCH();
     }
   }

@@ -76,7 +76,7 @@ def test_set_variant_rejects_out_of_range(lib):
     S = lib.System(prob)
     P = lib.Precond(S, lib.Params(variant="dynamic", n_add=1, n_ent=4))
     with pytest.raises(lib.EdfaError):
-        P.set_variant(12)
+        P.set_variant(len(lib.TUNE_VARIANTS))
     with pytest.raises(lib.EdfaError):
         P.set_variant(0, slot=16)
     P.set_variant(None)   # back to the defaults

@@ -164,6 +164,8 @@ void spmv(const int *rowptr, const int *col, const V *val, int rows, const X *x,
 // SELL-64 copy of a CSR matrix (device-side conversion; synchronises to size the storage).
 template <class V>
 void build_sell(const Csr<V> &M, Sell<V> &S, DBuf<int> &tmp, hipStream_t s);
+// Default lanes per row for a mean row length (0: the SELL kernel).
+int default_spmv_lanes(double mean_row);
 
 // Rows to skip in a product: row r is computed only if act[seg[r] * stride] != 0 (the
 // activity flag of its grid).  seg == NULL computes every row.

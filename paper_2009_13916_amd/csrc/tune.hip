@@ -24,6 +24,12 @@ constexpr Variant kVariants[EDFA_TUNE_VARIANTS] = {{0, 4},  {0, 8},  {2, 2},  {2
                                                    {4, 2},  {4, 4},  {8, 2},  {8, 4},
                                                    {16, 2}, {16, 4}, {32, 2}, {32, 4}};
 
+template <class M_>
+void set_kernel(M_ &M, const Variant &v) {
+  M.lanes = v.lanes;
+  M.depth = v.depth;
+}
+
 // Visit every tunable matrix of the active precision path: fn(slot, Sell<V>&, role).
 template <class F>
 void for_each_slot(edfa_precond_s &P, F &&fn) {
@@ -70,8 +76,7 @@ template <class V>
 float time_variant(Sell<V> &M, Variant v, int role, DBuf<V> &x, DBuf<V> &y, DBuf<double> &fl,
                    hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   const int saved = M.lanes, saved_depth = M.depth;
-  M.lanes = v.lanes;
-  M.depth = v.depth;
+  set_kernel(M, v);
   spmv_sell<V, V>(M, x.p, y.p, 1.0, nullptr, 0.0, s, 0.0, role);   // warm-up
   float best = 1e30f;
   for (int r = 0; r < 5; ++r) {
@@ -100,10 +105,7 @@ __global__ void k_fill_ones(V *x, long long n) {
 
 void apply_tuned(edfa_precond_s &P) {
   for_each_slot(P, [&](int slot, auto &M, int) {
-    if (P.tuned[slot] >= 0 && M.rows > 0) {
-      M.lanes = kVariants[P.tuned[slot]].lanes;
-      M.depth = kVariants[P.tuned[slot]].depth;
-    }
+    if (P.tuned[slot] >= 0 && M.rows > 0) set_kernel(M, kVariants[P.tuned[slot]]);
   });
 }
 
@@ -124,6 +126,8 @@ struct TuneBufs {
   DBuf<float> &y(float *) { return yf; }
 };
 
+constexpr float TUNE_MARGIN = 0.03f;
+
 template <class V>
 int tune_one(Sell<V> &M, int role, TuneBufs &B, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
              float *us) {
@@ -134,16 +138,15 @@ int tune_one(Sell<V> &M, int role, TuneBufs &B, hipStream_t s, hipEvent_t e0, hi
   y.ensure(std::max(M.rows, 1));
   hipLaunchKernelGGL(k_fill_ones<V>, dim3(ceil_div(nx, 256)), dim3(256), 0, s, x.p, (long long)nx);
   EDFA_CHECK_LAUNCH();
-  int best = 0;
-  float tbest = 1e30f;
-  for (int v = 0; v < EDFA_TUNE_VARIANTS; ++v) {
-    const float t = time_variant(M, kVariants[v], role, x, y, B.flush, s, e0, e1);
-    us[v] = 1e3f * t;
-    if (t < tbest) {
-      tbest = t;
-      best = v;
-    }
-  }
+  // the default kernel (SELL, 4 in flight, for short rows; CSR with 8 lanes, 2 in flight,
+  // for long ones) is kept unless another variant is at least TUNE_MARGIN faster, so timing
+  // noise does not flip the choice between equivalent kernels
+  const int dflt = M.rows > 0 && default_spmv_lanes((double)M.nnz / M.rows) > 1 ? 6 : 0;
+  for (int v = 0; v < EDFA_TUNE_VARIANTS; ++v)
+    us[v] = 1e3f * time_variant(M, kVariants[v], role, x, y, B.flush, s, e0, e1);
+  int best = dflt;
+  for (int v = 0; v < EDFA_TUNE_VARIANTS; ++v)
+    if (us[v] < us[best] * (1.0f - TUNE_MARGIN)) best = v;
   return best;
 }
 }  // namespace
@@ -169,8 +172,7 @@ int autotune(edfa_precond_s &P, hipStream_t s, edfa_tune_slot *slots) {
     edfa_tune_slot rec{};
     const int best = tune_one(M, role, B, s, e0, e1, rec.us);
     P.tuned[slot] = best;
-    M.lanes = kVariants[best].lanes;
-    M.depth = kVariants[best].depth;
+    set_kernel(M, kVariants[best]);
     ++tuned;
     if (slots) {
       rec.rows = M.rows;

@@ -26,7 +26,8 @@ def test_autotuned_solve_matches_untuned(lib, precision):
         vb = 8 if name in ("A", "A^T") or not flex else 4   # the operator stays FP64
         assert r["value_bytes"] == vb and len(r["us"]) == len(lib.TUNE_VARIANTS)
         assert all(t > 0 for t in r["us"].values())
-        assert r["us"][r["variant"]] == min(r["us"].values())
+        # the default kernel stays unless another is at least 3% faster
+        assert r["us"][r["variant"]] * 0.97 <= min(r["us"].values()) * (1 + 1e-6)
     assert rep["A"]["rows"] == rep["A"]["cols"] == S.n and rep["A"]["nnz"] == S.info["nnz"]
     x1, i1, s1 = lib.solve(S, P, b, rtol=1e-12, flexible=flex)
     lam, il, sl = lib.solve(S, P, b, rtol=1e-12, flexible=flex, transpose=True)

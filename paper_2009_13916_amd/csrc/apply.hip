@@ -133,13 +133,18 @@ static void sinv(edfa_precond_s &P, PrecData<T> &D, int transpose, const T *y, T
 template <class T>
 static void ensure_transposed_factors(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
   edfa_system_s &S = *P.sys;
-  if (D.UT.rows == 0 && S.ne) {
-    // ISAI: transposes of the natural-order copies; exact substitution: colour order
+  if (D.MUT.rows == 0 && D.UT.rows == 0 && S.ne) {
+    // ISAI: transposes of the natural-order copies (of the factors only for refinement
+    // steps); exact substitution: colour order
     const bool isai = P.prm.schur_solver == EDFA_SCHUR_ISAI;
-    csr_transpose(isai ? D.Un : D.U, D.UT, S.tmp, S.tmp2, s);
-    csr_transpose(isai ? D.Ln : D.L, D.LT, S.tmp, S.tmp2, s);
-    build_sell(D.UT, D.UT_s, S.tmp, s);
-    build_sell(D.LT, D.LT_s, S.tmp, s);
+    if (!isai || P.prm.isai_steps > 1) {
+      csr_transpose(isai ? D.Un : D.U, D.UT, S.tmp, S.tmp2, s);
+      csr_transpose(isai ? D.Ln : D.L, D.LT, S.tmp, S.tmp2, s);
+      build_sell(D.UT, D.UT_s, S.tmp, s);
+      build_sell(D.LT, D.LT_s, S.tmp, s);
+    } else {
+      D.UT_s.rows = D.LT_s.rows = 0;
+    }
     if (isai) {
       csr_transpose(D.MLn, D.MLT, S.tmp, S.tmp2, s);
       csr_transpose(D.MUn, D.MUT, S.tmp, S.tmp2, s);

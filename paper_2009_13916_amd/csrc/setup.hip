@@ -901,8 +901,7 @@ struct HArgs {
 
 // Tables: g~ (GH slots), the support of t (TH slots, listed in tlist: TH/2 entries for the
 // small tables, a first-pass row that fills them past half retries; TH for the large ones)
-// and the candidate cells (LH slots; at most LH/2 candidates are kept, listed in llist
-// with their values in hv).
+// and the candidate cells (LH slots; at most LH/2 candidates are kept, listed in llist).
 template <class T, int GH, int TH, int LH>
 __global__ __launch_bounds__(64) void k_htilde(HArgs<T> A) {
   constexpr int CL = LH / 2;
@@ -912,7 +911,6 @@ __global__ __launch_bounds__(64) void k_htilde(HArgs<T> A) {
   __shared__ int tk[TH], tlist[TL];
   __shared__ T tv[TH];
   __shared__ int lk[LH], llist[CL];
-  __shared__ T hv[CL];
   __shared__ int tcount, lcount, sflag;
   const int m = A.cells ? A.cells[blockIdx.x] : blockIdx.x;
   const int lane = threadIdx.x;
@@ -994,23 +992,19 @@ __global__ __launch_bounds__(64) void k_htilde(HArgs<T> A) {
     if (lane == 0) atomicMin(A.err_cap, m);
     return;
   }
-  // h_ml = sum over the pattern of f~_l of t_j f~_l[j]   (F~^T row l, ascending j)
+  // h_ml = sum over the pattern of f~_l of t_j f~_l[j] (F~^T row l, ascending j), written
+  // sorted by column: slot = number of smaller candidate cells
   for (int c = lane; c < nl; c += 64) {
+    const int l = llist[c];
     T acc = 0;
-    row_entries<16>(A.ft_rp, A.ft_col, A.ft_val, llist[c], [&](int col, T v) EDFA_INLINE {
+    row_entries<16>(A.ft_rp, A.ft_col, A.ft_val, l, [&](int col, T v) EDFA_INLINE {
       const int s = h_find<TH>(tk, col);
       if (s >= 0) acc += tv[s] * v;
     });
-    hv[c] = acc;
-  }
-  __syncthreads();
-  // write sorted by column: rank = number of smaller candidate cells
-  for (int c = lane; c < nl; c += 64) {
-    const int l = llist[c];
     int rank = 0;
     for (int c2 = 0; c2 < nl; ++c2) rank += llist[c2] < l;
     A.Hcol[(size_t)m * HMAX + rank] = l;
-    A.Hval[(size_t)m * HMAX + rank] = hv[c];
+    A.Hval[(size_t)m * HMAX + rank] = acc;
   }
   if (lane == 0) A.Hlen[m] = nl;
 }

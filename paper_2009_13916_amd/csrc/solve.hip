@@ -240,17 +240,10 @@ __global__ __launch_bounds__(64) void k_dcgs_step(int nseg, int m, int j, int fi
   if (lane == 0) cc[j] = (beta - ab) / rho;
   __syncthreads();
   double *hn = H + (long long)j * (m + 1);
-  // column by column (each column's rows 0..k+1 are read by consecutive lanes, and the
-  // loads of successive columns are independent); row i still sums k = i-1, i, ..., j-1 in
-  // ascending order
-  for (int i0 = 0; i0 <= j; i0 += 64) {
-    const int i = i0 + lane;
-    double t = i <= j ? cc[i] : 0.0;
-    for (int k = max(i0 - 1, 0); k < j; ++k) {
-      const double h = H[(long long)k * (m + 1) + min(i, k + 1)];   // rows 0..k+1 stored
-      if (i <= j && k >= i - 1) t -= h * a[k];
-    }
-    if (i <= j) hn[i] = t / rho;
+  for (int i = lane; i <= j; i += 64) {
+    double t = cc[i];
+    for (int k = (i > 0 ? i - 1 : 0); k < j; ++k) t -= H[(long long)k * (m + 1) + i] * a[k];
+    hn[i] = t / rho;
   }
   double *cf = coef + (long long)g * (2 * m + 2);
   for (int i = lane; i < j; i += 64) cf[i] = a[i];

@@ -360,31 +360,39 @@ __global__ __launch_bounds__(64) void k_ilu_color(const int *__restrict__ rp,
     sek[t] = rp[k + 1];
   }
   __syncthreads();
-  // Software pipeline over the pivots: u_kk and the first 64 upper entries of pivot rows
-  // p + 1 and p + 2 (one entry per lane, in registers) are in flight while step p runs.
-  int qc0 = -1, qc1 = -1, qc2 = -1;
-  T uk0 = T(1), uk1 = T(1), uk2 = T(1), qv0 = T(0), qv1 = T(0), qv2 = T(0);
-  auto fetch = [&](int p, T &uk, int &qc, T &qv) {
-    const int dk = sdk[p], ek = sek[p];
-    uk = val[dk];
-    const int q = dk + 1 + threadIdx.x;
-    qc = q < ek ? col[q] : -1;
-    qv = q < ek ? val[q] : T(0);
+  // Software pipeline over the pivots: u_kk and the first 128 upper entries of pivot rows
+  // p + 1 and p + 2 (two entries per lane, in registers) are in flight while step p runs.
+  struct Piv {
+    T uk, v0, v1;
+    int c0, c1;
   };
-  if (d > 0) fetch(0, uk1, qc1, qv1);
-  if (d > 1) fetch(1, uk2, qc2, qv2);
+  Piv f0{T(1), T(0), T(0), -1, -1}, f1 = f0, f2 = f0;
+  auto fetch = [&](int p, Piv &f) {
+    const int dk = sdk[p], ek = sek[p];
+    f.uk = val[dk];
+    const int q = dk + 1 + threadIdx.x;
+    f.c0 = q < ek ? col[q] : -1;
+    f.v0 = q < ek ? val[q] : T(0);
+    f.c1 = q + 64 < ek ? col[q + 64] : -1;
+    f.v1 = q + 64 < ek ? val[q + 64] : T(0);
+  };
+  if (d > 0) fetch(0, f1);
+  if (d > 1) fetch(1, f2);
   for (int p = 0; p < d; ++p) {
-    uk0 = uk1, qc0 = qc1, qv0 = qv1;
-    uk1 = uk2, qc1 = qc2, qv1 = qv2;
-    if (p + 2 < d) fetch(p + 2, uk2, qc2, qv2);
-    const int cdk = sdk[p], cek = sek[p], cqc = qc0;
-    const T cuk = uk0, cqv = qv0;
-    const T lik = vi[p] / cuk;
-    if (cqc >= 0) {
-      const int pos = bsearch_range(ci, p + 1, n, cqc);
-      if (pos >= 0) vi[pos] -= lik * cqv;
+    f0 = f1;
+    f1 = f2;
+    if (p + 2 < d) fetch(p + 2, f2);
+    const int cdk = sdk[p], cek = sek[p];
+    const T lik = vi[p] / f0.uk;
+    if (f0.c0 >= 0) {
+      const int pos = bsearch_range(ci, p + 1, n, f0.c0);
+      if (pos >= 0) vi[pos] -= lik * f0.v0;
     }
-    for (int q = cdk + 65 + threadIdx.x; q < cek; q += 64) {   // pivot rows past 64 entries
+    if (f0.c1 >= 0) {
+      const int pos = bsearch_range(ci, p + 1, n, f0.c1);
+      if (pos >= 0) vi[pos] -= lik * f0.v1;
+    }
+    for (int q = cdk + 129 + threadIdx.x; q < cek; q += 64) {   // pivot rows past 128 entries
       const int pos = bsearch_range(ci, p + 1, n, col[q]);
       if (pos >= 0) vi[pos] -= lik * val[q];
     }
@@ -778,12 +786,17 @@ static void stage2_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
   }
   if (prm.schur_solver == EDFA_SCHUR_ISAI) {
     // the application works in the natural cell order: P^T M P for every factor it uses
-    to_natural_order(D.L, D.Ln, D, S, s);
-    to_natural_order(D.U, D.Un, D, S, s);
+    // (the factors themselves only in the refinement steps)
+    if (prm.isai_steps > 1) {
+      to_natural_order(D.L, D.Ln, D, S, s);
+      to_natural_order(D.U, D.Un, D, S, s);
+      build_sell(D.Ln, D.L_s, S.tmp, s);
+      build_sell(D.Un, D.U_s, S.tmp, s);
+    } else {
+      D.L_s.rows = D.U_s.rows = 0;
+    }
     to_natural_order(D.ML, D.MLn, D, S, s);
     to_natural_order(D.MU, D.MUn, D, S, s);
-    build_sell(D.Ln, D.L_s, S.tmp, s);
-    build_sell(D.Un, D.U_s, S.tmp, s);
     build_sell(D.MLn, D.ML_s, S.tmp, s);
     build_sell(D.MUn, D.MU_s, S.tmp, s);
   } else {

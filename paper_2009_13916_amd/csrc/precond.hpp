@@ -37,6 +37,7 @@ struct PrecData {
   DBuf<int> color, perm, iperm;     // perm[new] = old
   DBuf<int> hist, wide;             // colour histograms; wide static patches
   DBuf<int> resume;                 // colouring: where each vertex's neighbour scan stopped
+  DBuf<int> blocker;                // colouring: the uncoloured neighbour found there (-1: none)
   DBuf<int> jplist;                 // colouring: vertices still uncoloured
   std::vector<int> cstart;          // host: colour c owns new rows [cstart[c], cstart[c+1])
   Csr<T> B;             // P S~ P^T, factored in place into L\U

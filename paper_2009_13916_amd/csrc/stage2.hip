@@ -192,14 +192,17 @@ __global__ __launch_bounds__(256) void k_jp_round(const int *__restrict__ srp,
                                                   const int *__restrict__ tcol, int ne,
                                                   const GridDesc *__restrict__ grids, int ngrid,
                                                   const int *__restrict__ list, int nlist,
-                                                  int *color, int *resume, int *ncolored,
-                                                  int *err) {
+                                                  int *color, int *resume, int *blocker,
+                                                  int *ncolored, int *err) {
   const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int slot = (int)(gid / JPG);
   const int l = (int)(gid % JPG);
   if (slot >= (list ? nlist : ne)) return;
   const int v = list ? list[slot] : slot;
+  // a vertex whose recorded blocker is still uncoloured stays blocked: two loads
+  const int bv = blocker[v];
   if (__atomic_load_n(&color[v], __ATOMIC_RELAXED) >= 0) return;
+  if (bv >= 0 && __atomic_load_n(&color[bv], __ATOMIC_RELAXED) < 0) return;
   const int c0 = grids[grid_of(grids, ngrid, v, true)].cell0;
   const unsigned pv = fmix32((unsigned)(v - c0));
   const int s0 = srp[v], ls = srp[v + 1] - s0, t0 = trp[v], lt = trp[v + 1] - t0;
@@ -215,7 +218,11 @@ __global__ __launch_bounds__(256) void k_jp_round(const int *__restrict__ srp,
     }
     const unsigned gm = (unsigned)((__ballot(blk) >> shift) & ((1ull << JPG) - 1));
     if (gm) {
-      if (l == 0) resume[v] = base + __ffs(gm) - 1;
+      const int first = __ffs(gm) - 1;
+      if (l == first) {
+        resume[v] = p;
+        blocker[v] = p < ls ? scol[s0 + p] : tcol[t0 + p - ls];
+      }
       return;
     }
   }
@@ -650,6 +657,8 @@ static void stage2_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
   EDFA_HIP(hipMemsetAsync(P.flags.p + 2, 0, sizeof(int), s));
   D.resume.ensure(ne);
   EDFA_HIP(hipMemsetAsync(D.resume.p, 0, sizeof(int) * (size_t)ne, s));
+  D.blocker.ensure(ne);
+  EDFA_HIP(hipMemsetAsync(D.blocker.p, 0xff, sizeof(int) * (size_t)ne, s));
   int rounds = 0;
   int nlist = ne;                 // vertices each round visits
   const int *list = nullptr;      // nullptr: all of them
@@ -660,8 +669,8 @@ static void stage2_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
     for (int r = 0; r < batch; ++r)
       hipLaunchKernelGGL(k_jp_round, dim3(ceil_div((long long)nlist * JPG, 256)), dim3(256), 0, s,
                          D.S.rowptr.p, D.S.col.p, D.ST.rowptr.p, D.ST.col.p, ne, S.grids.p,
-                         S.ngrid, list, nlist, D.color.p, D.resume.p, P.flags.p + 2,
-                         P.flags.p + 1);
+                         S.ngrid, list, nlist, D.color.p, D.resume.p, D.blocker.p,
+                         P.flags.p + 2, P.flags.p + 1);
     EDFA_CHECK_LAUNCH();
     rounds += batch;
     const int done = read_scalar(P.flags.p + 2, s);

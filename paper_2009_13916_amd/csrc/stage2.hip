@@ -253,9 +253,18 @@ __global__ __launch_bounds__(256) void k_jp_round(const int *__restrict__ srp,
 
 // Worklist of the vertices still uncoloured (any order: a vertex's colour depends only on
 // its coloured higher-priority neighbours, not on when it is visited).
-__global__ void k_uncolored(const int *__restrict__ color, int n, int *list, int *count) {
+__global__ __launch_bounds__(256) void k_uncolored(const int *__restrict__ color, int n, int *list,
+                                                   int *count) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < n && color[v] < 0) list[atomicAdd(count, 1)] = v;
+  const bool keep = v < n && color[v] < 0;
+  // one atomic per wavefront: lanes take consecutive slots after the wavefront's base
+  const unsigned long long mask = __ballot(keep);
+  if (!mask) return;
+  const int lane = threadIdx.x & 63, leader = __ffsll((long long)mask) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(count, __popcll(mask));
+  base = __shfl(base, leader);
+  if (keep) list[base + __popcll(mask & ((1ull << lane) - 1))] = v;
 }
 
 __global__ void k_color_max(const int *__restrict__ color, int n, int *out) {
@@ -323,18 +332,19 @@ __global__ __launch_bounds__(64) void k_permute_rows(const int *__restrict__ srp
   }
 }
 
-__device__ inline int bsearch_range(const int *a, int lo, int hi, int key) {
-  hi -= 1;
-  while (lo <= hi) {
-    const int mid = (lo + hi) >> 1;
-    const int v = a[mid];
-    if (v == key) return mid;
-    if (v < key)
-      lo = mid + 1;
-    else
-      hi = mid - 1;
+// Column -> position table of one row in LDS (open addressing, `bits` = log2 of its size,
+// at least twice the row length): each lookup is one or two probes instead of a binary
+// search's chain of dependent reads.
+__device__ inline unsigned row_slot(int key, int bits) {
+  return ((unsigned)key * 2654435761u) >> (32 - bits);
+}
+__device__ inline int row_find(const int *keys, const int *pos, int bits, int key) {
+  const unsigned mask = (1u << bits) - 1;
+  for (unsigned h = row_slot(key, bits);; h = (h + 1) & mask) {
+    const int k = keys[h];
+    if (k == key) return pos[h];
+    if (k == -1) return -1;
   }
-  return -1;
 }
 
 // ILU(0), IKJ form, rows [r0, r1) of one colour; one wavefront per row.  The row lives in
@@ -349,17 +359,25 @@ template <class T>
 __global__ __launch_bounds__(64) void k_ilu_color(const int *__restrict__ rp,
                                                   const int *__restrict__ col, T *val,
                                                   const int *__restrict__ diag, int r0, int r1,
-                                                  int cap, int *err) {
+                                                  int cap, int hbits, int *err) {
   T *vi = (T *)row_lds;
   int *ci = (int *)(vi + cap), *sdk = ci + cap, *sek = sdk + cap;
+  int *hk = sek + cap, *hp = hk + (1 << hbits);   // column -> position of row i
   const int i = r0 + blockIdx.x;
   if (i >= r1) return;
   const int a = rp[i], n = rp[i + 1] - a, d = diag[i] - a;
+  for (int t = threadIdx.x; t < (1 << hbits); t += 64) hk[t] = -1;
   for (int t = threadIdx.x; t < n; t += 64) {
     ci[t] = col[a + t];
     vi[t] = val[a + t];
   }
   __syncthreads();
+  for (int t = threadIdx.x; t < n; t += 64) {   // columns of a row are distinct
+    const unsigned mask = (1u << hbits) - 1;
+    unsigned h = row_slot(ci[t], hbits);
+    while (atomicCAS(&hk[h], -1, ci[t]) != -1) h = (h + 1) & mask;
+    hp[h] = t;
+  }
   // diagonal position and end of every pivot row, all at once
   for (int t = threadIdx.x; t < d; t += 64) {
     const int k = ci[t];
@@ -368,43 +386,59 @@ __global__ __launch_bounds__(64) void k_ilu_color(const int *__restrict__ rp,
   }
   __syncthreads();
   // Software pipeline over the pivots: u_kk and the first 128 upper entries of pivot rows
-  // p + 1 and p + 2 (two entries per lane, in registers) are in flight while step p runs.
+  // (two entries per lane, in registers) are loaded three steps ahead.  The loop is
+  // unrolled over three register slots used in place: moving a register whose load is in
+  // flight would wait for that load.
+  // Every step issues the same loads without a branch (entries past the row's end read
+  // its diagonal; a clamped step index re-reads the last pivot), so the compiler can wait
+  // for exactly the oldest slot's loads.
   struct Piv {
     T uk, v0, v1;
     int c0, c1;
+    bool ok0, ok1;
   };
-  Piv f0{T(1), T(0), T(0), -1, -1}, f1 = f0, f2 = f0;
-  auto fetch = [&](int p, Piv &f) {
+  auto fetch = [&](int p, Piv &g) {
     const int dk = sdk[p], ek = sek[p];
-    f.uk = val[dk];
     const int q = dk + 1 + threadIdx.x;
-    f.c0 = q < ek ? col[q] : -1;
-    f.v0 = q < ek ? val[q] : T(0);
-    f.c1 = q + 64 < ek ? col[q + 64] : -1;
-    f.v1 = q + 64 < ek ? val[q + 64] : T(0);
+    g.ok0 = q < ek;
+    g.ok1 = q + 64 < ek;
+    const int q0 = g.ok0 ? q : dk, q1 = g.ok1 ? q + 64 : dk;
+    g.uk = val[dk];
+    g.c0 = col[q0];
+    g.v0 = val[q0];
+    g.c1 = col[q1];
+    g.v1 = val[q1];
   };
-  if (d > 0) fetch(0, f1);
-  if (d > 1) fetch(1, f2);
-  for (int p = 0; p < d; ++p) {
-    f0 = f1;
-    f1 = f2;
-    if (p + 2 < d) fetch(p + 2, f2);
+  auto step = [&](int p, Piv &f) {
     const int cdk = sdk[p], cek = sek[p];
-    const T lik = vi[p] / f0.uk;
-    if (f0.c0 >= 0) {
-      const int pos = bsearch_range(ci, p + 1, n, f0.c0);
-      if (pos >= 0) vi[pos] -= lik * f0.v0;
+    const T lik = vi[p] / f.uk;
+    // a pivot row's columns exceed k = ci[p], so the positions found lie past p
+    if (f.ok0) {
+      const int pos = row_find(hk, hp, hbits, f.c0);
+      if (pos >= 0) vi[pos] -= lik * f.v0;
     }
-    if (f0.c1 >= 0) {
-      const int pos = bsearch_range(ci, p + 1, n, f0.c1);
-      if (pos >= 0) vi[pos] -= lik * f0.v1;
+    if (f.ok1) {
+      const int pos = row_find(hk, hp, hbits, f.c1);
+      if (pos >= 0) vi[pos] -= lik * f.v1;
     }
     for (int q = cdk + 129 + threadIdx.x; q < cek; q += 64) {   // pivot rows past 128 entries
-      const int pos = bsearch_range(ci, p + 1, n, col[q]);
+      const int pos = row_find(hk, hp, hbits, col[q]);
       if (pos >= 0) vi[pos] -= lik * val[q];
     }
     __syncthreads();
     if (threadIdx.x == 0) vi[p] = lik;
+    fetch(min(p + 3, d - 1), f);   // this slot serves step p + 3
+  };
+  Piv fa, fb, fc;
+  if (d > 0) {
+    fetch(0, fa);
+    fetch(min(1, d - 1), fb);
+    fetch(min(2, d - 1), fc);
+  }
+  for (int p = 0; p < d; p += 3) {
+    step(p, fa);
+    if (p + 1 < d) step(p + 1, fb);
+    if (p + 2 < d) step(p + 2, fc);
   }
   __syncthreads();
   for (int t = threadIdx.x; t < n; t += 64) val[a + t] = vi[t];
@@ -450,20 +484,6 @@ __global__ __launch_bounds__(256) void k_split(const int *__restrict__ rp,
   }
 }
 
-__device__ inline int bsearch_lds(const int *a, int n, int key) {
-  int lo = 0, hi = n - 1;
-  while (lo <= hi) {
-    const int mid = (lo + hi) >> 1;
-    const int v = a[mid];
-    if (v == key) return mid;
-    if (v < key)
-      lo = mid + 1;
-    else
-      hi = mid - 1;
-  }
-  return -1;
-}
-
 // ISAI of the unit lower factor (I + L): row i on P = cols(L row i) + {i}.
 // (T[P,P])^T m = e_i, solved from the last index down: m_k = delta_ik - sum_{j>k} T[j,k] m_j.
 // The extents of all rows k in P are read at once; the first 64 entries of the rows of the
@@ -474,51 +494,68 @@ template <class T>
 __global__ __launch_bounds__(64) void k_isai_lower(const int *__restrict__ lrp,
                                                    const int *__restrict__ lcol,
                                                    const T *__restrict__ lval, int n, int cap,
-                                                   const int *__restrict__ mrp, int *mcol, T *mval) {
+                                                   int hbits, const int *__restrict__ mrp,
+                                                   int *mcol, T *mval) {
   T *acc = (T *)row_lds;
   int *P = (int *)(acc + cap), *rb = P + cap, *re = rb + cap;
+  int *hk = re + cap, *hp = hk + (1 << hbits);   // column -> index in P
   const int i = blockIdx.x;
   if (i >= n) return;
   const int a = lrp[i], nl = lrp[i + 1] - a, np = nl + 1;
+  for (int t = threadIdx.x; t < (1 << hbits); t += 64) hk[t] = -1;
+  __syncthreads();
   for (int t = threadIdx.x; t < np; t += 64) {
     const int k = t < nl ? lcol[a + t] : i;
     P[t] = k;
     rb[t] = lrp[k];
     re[t] = lrp[k + 1];
     acc[t] = 0;
+    unsigned h = row_slot(k, hbits);
+    while (atomicCAS(&hk[h], -1, k) != -1) h = (h + 1) & ((1u << hbits) - 1);
+    hp[h] = t;
   }
   __syncthreads();
   const int o = mrp[i];
-  int c1 = -1, c2 = -1;
-  T v1 = T(0), v2 = T(0);
+  // branch-free loads (an entry past the row's end reads entry 0, unused), so every step
+  // issues the same loads and the compiler waits for exactly the oldest slot's
   auto fetch = [&](int idx, int &c, T &v) {
     const int q = rb[idx] + threadIdx.x;
-    c = q < re[idx] ? lcol[q] : -1;
-    v = q < re[idx] ? lval[q] : T(0);
+    const int qc = q < re[idx] ? q : 0;
+    c = lcol[qc];
+    v = lval[qc];
   };
-  fetch(np - 1, c1, v1);
-  if (np > 1) fetch(np - 2, c2, v2);
-  for (int idx = np - 1; idx >= 0; --idx) {
-    const int c0 = c1;
-    const T v0 = v1;
-    c1 = c2;
-    v1 = v2;
-    if (idx >= 2) fetch(idx - 2, c2, v2);
+  // three register slots used in place (see k_ilu_color), loaded three steps ahead
+  auto step = [&](int idx, int &c0, T &v0) {
     const int k = P[idx];
     const T mk = (k == i ? T(1) : T(0)) - acc[idx];
-    if (threadIdx.x == 0) {
-      mcol[o + idx] = k;
-      mval[o + idx] = mk;
-    }
-    if (c0 >= 0) {
-      const int pos = bsearch_lds(P, idx, c0);
+    // acc[idx] is final once read: it keeps m_k until the row is written out at the end
+    // (no global store inside the loop, so the barrier waits for no memory operation)
+    if (threadIdx.x == 0) acc[idx] = mk;
+    // row k's columns are below k = P[idx], so the indices found lie before idx
+    if (rb[idx] + (int)threadIdx.x < re[idx]) {
+      const int pos = row_find(hk, hp, hbits, c0);
       if (pos >= 0) acc[pos] += v0 * mk;
     }
     for (int p = rb[idx] + 64 + threadIdx.x; p < re[idx]; p += 64) {
-      const int pos = bsearch_lds(P, idx, lcol[p]);
+      const int pos = row_find(hk, hp, hbits, lcol[p]);
       if (pos >= 0) acc[pos] += lval[p] * mk;
     }
     __syncthreads();
+    fetch(max(idx - 3, 0), c0, v0);
+  };
+  int ca, cb, cc;
+  T va, vb, vc;
+  fetch(np - 1, ca, va);
+  fetch(max(np - 2, 0), cb, vb);
+  fetch(max(np - 3, 0), cc, vc);
+  for (int idx = np - 1; idx >= 0; idx -= 3) {
+    step(idx, ca, va);
+    if (idx >= 1) step(idx - 1, cb, vb);
+    if (idx >= 2) step(idx - 2, cc, vc);
+  }
+  for (int t = threadIdx.x; t < np; t += 64) {
+    mcol[o + t] = P[t];
+    mval[o + t] = acc[t];
   }
 }
 
@@ -530,12 +567,15 @@ template <class T>
 __global__ __launch_bounds__(64) void k_isai_upper(const int *__restrict__ urp,
                                                    const int *__restrict__ ucol,
                                                    const T *__restrict__ uval, int n, int cap,
-                                                   int *mcol, T *mval) {
+                                                   int hbits, int *mcol, T *mval) {
   T *acc = (T *)row_lds, *ud = acc + cap;
   int *P = (int *)(ud + cap), *rb = P + cap, *re = rb + cap;
+  int *hk = re + cap, *hp = hk + (1 << hbits);   // column -> index in P
   const int i = blockIdx.x;
   if (i >= n) return;
   const int a = urp[i], np = urp[i + 1] - a;
+  for (int t = threadIdx.x; t < (1 << hbits); t += 64) hk[t] = -1;
+  __syncthreads();
   for (int t = threadIdx.x; t < np; t += 64) {
     const int k = ucol[a + t];
     P[t] = k;
@@ -544,38 +584,48 @@ __global__ __launch_bounds__(64) void k_isai_upper(const int *__restrict__ urp,
     re[t] = urp[k + 1];
     ud[t] = uval[kb];
     acc[t] = 0;
+    unsigned h = row_slot(k, hbits);
+    while (atomicCAS(&hk[h], -1, k) != -1) h = (h + 1) & ((1u << hbits) - 1);
+    hp[h] = t;
   }
   __syncthreads();
-  int c1 = -1, c2 = -1;
-  T v1 = T(0), v2 = T(0);
-  auto fetch = [&](int idx, int &c, T &v) {
+  auto fetch = [&](int idx, int &c, T &v) {   // as in k_isai_lower
     const int q = rb[idx] + threadIdx.x;
-    c = q < re[idx] ? ucol[q] : -1;
-    v = q < re[idx] ? uval[q] : T(0);
+    const int qc = q < re[idx] ? q : 0;
+    c = ucol[qc];
+    v = uval[qc];
   };
-  if (np > 0) fetch(0, c1, v1);
-  if (np > 1) fetch(1, c2, v2);
-  for (int idx = 0; idx < np; ++idx) {
-    const int c0 = c1;
-    const T v0 = v1;
-    c1 = c2;
-    v1 = v2;
-    if (idx + 2 < np) fetch(idx + 2, c2, v2);
+  // three register slots used in place (see k_ilu_color), loaded three steps ahead
+  auto step = [&](int idx, int &c0, T &v0) {
     const int k = P[idx];
     const T mk = ((k == i ? T(1) : T(0)) - acc[idx]) / ud[idx];
-    if (threadIdx.x == 0) {
-      mcol[a + idx] = k;
-      mval[a + idx] = mk;
-    }
-    if (c0 >= 0) {
-      const int pos = bsearch_lds(P + idx + 1, np - idx - 1, c0);
-      if (pos >= 0) acc[idx + 1 + pos] += v0 * mk;
+    if (threadIdx.x == 0) acc[idx] = mk;   // kept until the row is written out
+    // row k's columns past its diagonal exceed k = P[idx]: the indices found lie past idx
+    if (rb[idx] + (int)threadIdx.x < re[idx]) {
+      const int pos = row_find(hk, hp, hbits, c0);
+      if (pos >= 0) acc[pos] += v0 * mk;
     }
     for (int p = rb[idx] + 64 + threadIdx.x; p < re[idx]; p += 64) {
-      const int pos = bsearch_lds(P + idx + 1, np - idx - 1, ucol[p]);
-      if (pos >= 0) acc[idx + 1 + pos] += uval[p] * mk;
+      const int pos = row_find(hk, hp, hbits, ucol[p]);
+      if (pos >= 0) acc[pos] += uval[p] * mk;
     }
     __syncthreads();
+    fetch(min(idx + 3, np - 1), c0, v0);
+  };
+  if (np <= 0) return;
+  int ca, cb, cc;
+  T va, vb, vc;
+  fetch(0, ca, va);
+  fetch(min(1, np - 1), cb, vb);
+  fetch(min(2, np - 1), cc, vc);
+  for (int idx = 0; idx < np; idx += 3) {
+    step(idx, ca, va);
+    if (idx + 1 < np) step(idx + 1, cb, vb);
+    if (idx + 2 < np) step(idx + 2, cc, vc);
+  }
+  for (int t = threadIdx.x; t < np; t += 64) {
+    mcol[a + t] = P[t];
+    mval[a + t] = acc[t];
   }
 }
 
@@ -676,8 +726,8 @@ static void stage2_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
     const int done = read_scalar(P.flags.p + 2, s);
     if (done >= ne) break;
     if (rounds > 2 * ne + 64) fail(EDFA_ERR_BREAKDOWN, "colouring did not finish");
-    if (2 * (ne - done) < nlist) {
-      // at most half of the visited vertices are left: visit only those from now on
+    if (10 * (ne - done) < 7 * nlist) {
+      // under 70% of the visited vertices are left: visit only those from now on
       EDFA_HIP(hipMemsetAsync(P.flags.p + 3, 0, sizeof(int), s));
       hipLaunchKernelGGL(k_uncolored, dim3(ceil_div(ne, 256)), dim3(256), 0, s, D.color.p, ne,
                          D.jplist.p, P.flags.p + 3);
@@ -743,12 +793,14 @@ static void stage2_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
     fail(EDFA_ERR_BREAKDOWN, "S~ row %d has no diagonal entry", read_scalar(P.flags.p + 1, s));
   // ILU(0) colour by colour; the per-row kernels size their LDS by the longest row
   const int cap = std::max(smaxrow, 1);
-  const size_t lds_ilu = (size_t)cap * (sizeof(T) + 3 * sizeof(int));
+  int hbits = 1;
+  while ((1 << hbits) < 2 * cap) ++hbits;
+  const size_t lds_ilu = (size_t)cap * (sizeof(T) + 3 * sizeof(int)) + sizeof(int) * (2u << hbits);
   for (int c = 0; c < ncol; ++c) {
     const int r0 = D.cstart[c], r1 = D.cstart[c + 1];
     if (r1 > r0)
       hipLaunchKernelGGL(k_ilu_color<T>, dim3(r1 - r0), dim3(64), lds_ilu, s, D.B.rowptr.p,
-                         D.B.col.p, D.B.val.p, D.diag.p, r0, r1, cap, P.flags.p);
+                         D.B.col.p, D.B.val.p, D.diag.p, r0, r1, cap, hbits, P.flags.p);
   }
   EDFA_CHECK_LAUNCH();
   if (read_scalar(P.flags.p, s) != 0x7fffffff)
@@ -783,13 +835,16 @@ static void stage2_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
     EDFA_HIP(hipMemcpyAsync(D.MU.rowptr.p, D.U.rowptr.p, sizeof(int) * ((size_t)ne + 1),
                             hipMemcpyDeviceToDevice, s));
     if (ne) {
+      const size_t lds_tab = sizeof(int) * (2u << hbits);
       hipLaunchKernelGGL(k_isai_lower<T>, dim3(ne), dim3(64),
-                         (size_t)cap * (sizeof(T) + 3 * sizeof(int)), s, D.L.rowptr.p,
-                         D.L.col.p, D.L.val.p, ne, cap, D.ML.rowptr.p, D.ML.col.p, D.ML.val.p);
+                         (size_t)cap * (sizeof(T) + 3 * sizeof(int)) + lds_tab, s, D.L.rowptr.p,
+                         D.L.col.p, D.L.val.p, ne, cap, hbits, D.ML.rowptr.p, D.ML.col.p,
+                         D.ML.val.p);
       EDFA_CHECK_LAUNCH();
       hipLaunchKernelGGL(k_isai_upper<T>, dim3(ne), dim3(64),
-                         (size_t)cap * (2 * sizeof(T) + 3 * sizeof(int)), s, D.U.rowptr.p,
-                         D.U.col.p, D.U.val.p, ne, cap, D.MU.col.p, D.MU.val.p);
+                         (size_t)cap * (2 * sizeof(T) + 3 * sizeof(int)) + lds_tab, s,
+                         D.U.rowptr.p, D.U.col.p, D.U.val.p, ne, cap, hbits, D.MU.col.p,
+                         D.MU.val.p);
       EDFA_CHECK_LAUNCH();
     }
   }

@@ -1194,7 +1194,10 @@ static void reset_flags(edfa_precond_s &P, hipStream_t s) {
 
 // Compiled pattern capacities: the smallest that holds `need` entries, 0 if none does.
 static int pattern_stride(int need) {
-  for (int c : {16, 32, 48, 64, 128})
+  // 40 and 44 keep the register kernel (its code grows with the square of the stride) close
+  // to the patterns of the usual hexahedral grids (a base pattern of 36 faces plus a few
+  // dynamic entries)
+  for (int c : {16, 32, 40, 44, 48, 64, 128})
     if (need <= c) return c;
   return 0;
 }
@@ -1279,6 +1282,8 @@ static void stage1_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
     switch (smax) {
       case 16: hipLaunchKernelGGL((k_local_reg<T, 16>), dim3(ne), dim3(64), 0, s, la); break;
       case 32: hipLaunchKernelGGL((k_local_reg<T, 32>), dim3(ne), dim3(64), 0, s, la); break;
+      case 40: hipLaunchKernelGGL((k_local_reg<T, 40>), dim3(ne), dim3(64), 0, s, la); break;
+      case 44: hipLaunchKernelGGL((k_local_reg<T, 44>), dim3(ne), dim3(64), 0, s, la); break;
       case 48: hipLaunchKernelGGL((k_local_reg<T, 48>), dim3(ne), dim3(64), 0, s, la); break;
       case 64: hipLaunchKernelGGL((k_local<T, 64>), dim3(ne), dim3(64), 0, s, la); break;
       case 128: hipLaunchKernelGGL((k_local<T, 128>), dim3(ne), dim3(64), 0, s, la); break;

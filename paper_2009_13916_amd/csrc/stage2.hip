@@ -435,11 +435,16 @@ __global__ __launch_bounds__(64) void k_ilu_color(const int *__restrict__ rp,
     fetch(min(1, d - 1), fb);
     fetch(min(2, d - 1), fc);
   }
-  for (int p = 0; p < d; p += 3) {
+  // whole groups of three steps, then the tail: every path around the loop issues the
+  // same loads, so the wait before a step covers only its own slot
+  int p = 0;
+  for (; p + 3 <= d; p += 3) {
     step(p, fa);
-    if (p + 1 < d) step(p + 1, fb);
-    if (p + 2 < d) step(p + 2, fc);
+    step(p + 1, fb);
+    step(p + 2, fc);
   }
+  if (p < d) step(p, fa);
+  if (p + 1 < d) step(p + 1, fb);
   __syncthreads();
   for (int t = threadIdx.x; t < n; t += 64) val[a + t] = vi[t];
   if (threadIdx.x == 0) {
@@ -548,11 +553,14 @@ __global__ __launch_bounds__(64) void k_isai_lower(const int *__restrict__ lrp,
   fetch(np - 1, ca, va);
   fetch(max(np - 2, 0), cb, vb);
   fetch(max(np - 3, 0), cc, vc);
-  for (int idx = np - 1; idx >= 0; idx -= 3) {
+  int idx = np - 1;   // whole groups of three, then the tail (see k_ilu_color)
+  for (; idx >= 2; idx -= 3) {
     step(idx, ca, va);
-    if (idx >= 1) step(idx - 1, cb, vb);
-    if (idx >= 2) step(idx - 2, cc, vc);
+    step(idx - 1, cb, vb);
+    step(idx - 2, cc, vc);
   }
+  if (idx >= 0) step(idx, ca, va);
+  if (idx >= 1) step(idx - 1, cb, vb);
   for (int t = threadIdx.x; t < np; t += 64) {
     mcol[o + t] = P[t];
     mval[o + t] = acc[t];
@@ -618,11 +626,14 @@ __global__ __launch_bounds__(64) void k_isai_upper(const int *__restrict__ urp,
   fetch(0, ca, va);
   fetch(min(1, np - 1), cb, vb);
   fetch(min(2, np - 1), cc, vc);
-  for (int idx = 0; idx < np; idx += 3) {
+  int idx = 0;   // whole groups of three, then the tail (see k_ilu_color)
+  for (; idx + 3 <= np; idx += 3) {
     step(idx, ca, va);
-    if (idx + 1 < np) step(idx + 1, cb, vb);
-    if (idx + 2 < np) step(idx + 2, cc, vc);
+    step(idx + 1, cb, vb);
+    step(idx + 2, cc, vc);
   }
+  if (idx < np) step(idx, ca, va);
+  if (idx + 1 < np) step(idx + 1, cb, vb);
   for (int t = threadIdx.x; t < np; t += 64) {
     mcol[a + t] = P[t];
     mval[a + t] = acc[t];

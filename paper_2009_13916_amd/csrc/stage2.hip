@@ -333,18 +333,38 @@ __global__ __launch_bounds__(64) void k_permute_rows(const int *__restrict__ srp
 }
 
 // Column -> position table of one row in LDS (open addressing, `bits` = log2 of its size,
-// at least twice the row length): each lookup is one or two probes instead of a binary
-// search's chain of dependent reads.
+// at least twice the row length).  A slot holds the key in its low and the position in its
+// high 32 bits, so a probe is one LDS read; most lookups end at the first probe.  It sits at
+// the start of the dynamic LDS (8-byte slots).
+using RowSlot = unsigned long long;
+constexpr RowSlot ROW_EMPTY = ~0ull;
 __device__ inline unsigned row_slot(int key, int bits) {
   return ((unsigned)key * 2654435761u) >> (32 - bits);
 }
-__device__ inline int row_find(const int *keys, const int *pos, int bits, int key) {
+__device__ inline void row_clear(RowSlot *tab, int bits) {
+  for (int t = threadIdx.x; t < (1 << bits); t += blockDim.x) tab[t] = ROW_EMPTY;
+}
+__device__ inline void row_insert(RowSlot *tab, int bits, int key, int pos) {   // distinct keys
   const unsigned mask = (1u << bits) - 1;
-  for (unsigned h = row_slot(key, bits);; h = (h + 1) & mask) {
-    const int k = keys[h];
-    if (k == key) return pos[h];
+  const RowSlot e = ((RowSlot)(unsigned)pos << 32) | (unsigned)key;
+  unsigned h = row_slot(key, bits);
+  while (atomicCAS(&tab[h], ROW_EMPTY, e) != ROW_EMPTY) h = (h + 1) & mask;
+}
+// Position of key (-1 when absent), given the content e of its first slot h: the first
+// probe can then be issued early, beside other reads.
+__device__ inline int row_resolve(const RowSlot *tab, int bits, int key, unsigned h, RowSlot e) {
+  const unsigned mask = (1u << bits) - 1;
+  for (;;) {
+    const int k = (int)(unsigned)e;
+    if (k == key) return (int)(e >> 32);
     if (k == -1) return -1;
+    h = (h + 1) & mask;
+    e = tab[h];
   }
+}
+__device__ inline int row_find(const RowSlot *tab, int bits, int key) {
+  const unsigned h = row_slot(key, bits);
+  return row_resolve(tab, bits, key, h, tab[h]);
 }
 
 // ILU(0), IKJ form, rows [r0, r1) of one colour; one wavefront per row.  The row lives in
@@ -360,24 +380,19 @@ __global__ __launch_bounds__(64) void k_ilu_color(const int *__restrict__ rp,
                                                   const int *__restrict__ col, T *val,
                                                   const int *__restrict__ diag, int r0, int r1,
                                                   int cap, int hbits, int *err) {
-  T *vi = (T *)row_lds;
+  RowSlot *tab = (RowSlot *)row_lds;   // column -> position of row i
+  T *vi = (T *)(tab + (1 << hbits));
   int *ci = (int *)(vi + cap), *sdk = ci + cap, *sek = sdk + cap;
-  int *hk = sek + cap, *hp = hk + (1 << hbits);   // column -> position of row i
   const int i = r0 + blockIdx.x;
   if (i >= r1) return;
   const int a = rp[i], n = rp[i + 1] - a, d = diag[i] - a;
-  for (int t = threadIdx.x; t < (1 << hbits); t += 64) hk[t] = -1;
+  row_clear(tab, hbits);
   for (int t = threadIdx.x; t < n; t += 64) {
     ci[t] = col[a + t];
     vi[t] = val[a + t];
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < n; t += 64) {   // columns of a row are distinct
-    const unsigned mask = (1u << hbits) - 1;
-    unsigned h = row_slot(ci[t], hbits);
-    while (atomicCAS(&hk[h], -1, ci[t]) != -1) h = (h + 1) & mask;
-    hp[h] = t;
-  }
+  for (int t = threadIdx.x; t < n; t += 64) row_insert(tab, hbits, ci[t], t);
   // diagonal position and end of every pivot row, all at once
   for (int t = threadIdx.x; t < d; t += 64) {
     const int k = ci[t];
@@ -411,18 +426,20 @@ __global__ __launch_bounds__(64) void k_ilu_color(const int *__restrict__ rp,
   };
   auto step = [&](int p, Piv &f) {
     const int cdk = sdk[p], cek = sek[p];
+    // the first probes of both entries issue with the read of the row's entry p, so the
+    // chain of a step is one LDS read, the division and one read-modify-write
+    const unsigned h0 = row_slot(f.c0, hbits), h1 = row_slot(f.c1, hbits);
+    const RowSlot e0 = tab[h0], e1 = tab[h1];
     const T lik = vi[p] / f.uk;
-    // a pivot row's columns exceed k = ci[p], so the positions found lie past p
-    if (f.ok0) {
-      const int pos = row_find(hk, hp, hbits, f.c0);
-      if (pos >= 0) vi[pos] -= lik * f.v0;
-    }
-    if (f.ok1) {
-      const int pos = row_find(hk, hp, hbits, f.c1);
-      if (pos >= 0) vi[pos] -= lik * f.v1;
-    }
+    // a pivot row's columns exceed k = ci[p], so the positions found lie past p; its
+    // columns are distinct, so are the two positions, and both reads may go first
+    const int pos0 = f.ok0 ? row_resolve(tab, hbits, f.c0, h0, e0) : -1;
+    const int pos1 = f.ok1 ? row_resolve(tab, hbits, f.c1, h1, e1) : -1;
+    const T a0 = vi[pos0 >= 0 ? pos0 : p], a1 = vi[pos1 >= 0 ? pos1 : p];
+    if (pos0 >= 0) vi[pos0] = a0 - lik * f.v0;
+    if (pos1 >= 0) vi[pos1] = a1 - lik * f.v1;
     for (int q = cdk + 129 + threadIdx.x; q < cek; q += 64) {   // pivot rows past 128 entries
-      const int pos = row_find(hk, hp, hbits, col[q]);
+      const int pos = row_find(tab, hbits, col[q]);
       if (pos >= 0) vi[pos] -= lik * val[q];
     }
     __syncthreads();
@@ -501,13 +518,13 @@ __global__ __launch_bounds__(64) void k_isai_lower(const int *__restrict__ lrp,
                                                    const T *__restrict__ lval, int n, int cap,
                                                    int hbits, const int *__restrict__ mrp,
                                                    int *mcol, T *mval) {
-  T *acc = (T *)row_lds;
+  RowSlot *tab = (RowSlot *)row_lds;   // column -> index in P
+  T *acc = (T *)(tab + (1 << hbits));
   int *P = (int *)(acc + cap), *rb = P + cap, *re = rb + cap;
-  int *hk = re + cap, *hp = hk + (1 << hbits);   // column -> index in P
   const int i = blockIdx.x;
   if (i >= n) return;
   const int a = lrp[i], nl = lrp[i + 1] - a, np = nl + 1;
-  for (int t = threadIdx.x; t < (1 << hbits); t += 64) hk[t] = -1;
+  row_clear(tab, hbits);
   __syncthreads();
   for (int t = threadIdx.x; t < np; t += 64) {
     const int k = t < nl ? lcol[a + t] : i;
@@ -515,9 +532,7 @@ __global__ __launch_bounds__(64) void k_isai_lower(const int *__restrict__ lrp,
     rb[t] = lrp[k];
     re[t] = lrp[k + 1];
     acc[t] = 0;
-    unsigned h = row_slot(k, hbits);
-    while (atomicCAS(&hk[h], -1, k) != -1) h = (h + 1) & ((1u << hbits) - 1);
-    hp[h] = t;
+    row_insert(tab, hbits, k, t);
   }
   __syncthreads();
   const int o = mrp[i];
@@ -531,6 +546,8 @@ __global__ __launch_bounds__(64) void k_isai_lower(const int *__restrict__ lrp,
   };
   // three register slots used in place (see k_ilu_color), loaded three steps ahead
   auto step = [&](int idx, int &c0, T &v0) {
+    const unsigned h0 = row_slot(c0, hbits);
+    const RowSlot e0 = tab[h0];   // first probe, beside the reads below
     const int k = P[idx];
     const T mk = (k == i ? T(1) : T(0)) - acc[idx];
     // acc[idx] is final once read: it keeps m_k until the row is written out at the end
@@ -538,11 +555,11 @@ __global__ __launch_bounds__(64) void k_isai_lower(const int *__restrict__ lrp,
     if (threadIdx.x == 0) acc[idx] = mk;
     // row k's columns are below k = P[idx], so the indices found lie before idx
     if (rb[idx] + (int)threadIdx.x < re[idx]) {
-      const int pos = row_find(hk, hp, hbits, c0);
+      const int pos = row_resolve(tab, hbits, c0, h0, e0);
       if (pos >= 0) acc[pos] += v0 * mk;
     }
     for (int p = rb[idx] + 64 + threadIdx.x; p < re[idx]; p += 64) {
-      const int pos = row_find(hk, hp, hbits, lcol[p]);
+      const int pos = row_find(tab, hbits, lcol[p]);
       if (pos >= 0) acc[pos] += lval[p] * mk;
     }
     __syncthreads();
@@ -576,13 +593,13 @@ __global__ __launch_bounds__(64) void k_isai_upper(const int *__restrict__ urp,
                                                    const int *__restrict__ ucol,
                                                    const T *__restrict__ uval, int n, int cap,
                                                    int hbits, int *mcol, T *mval) {
-  T *acc = (T *)row_lds, *ud = acc + cap;
+  RowSlot *tab = (RowSlot *)row_lds;   // column -> index in P
+  T *acc = (T *)(tab + (1 << hbits)), *ud = acc + cap;
   int *P = (int *)(ud + cap), *rb = P + cap, *re = rb + cap;
-  int *hk = re + cap, *hp = hk + (1 << hbits);   // column -> index in P
   const int i = blockIdx.x;
   if (i >= n) return;
   const int a = urp[i], np = urp[i + 1] - a;
-  for (int t = threadIdx.x; t < (1 << hbits); t += 64) hk[t] = -1;
+  row_clear(tab, hbits);
   __syncthreads();
   for (int t = threadIdx.x; t < np; t += 64) {
     const int k = ucol[a + t];
@@ -592,9 +609,7 @@ __global__ __launch_bounds__(64) void k_isai_upper(const int *__restrict__ urp,
     re[t] = urp[k + 1];
     ud[t] = uval[kb];
     acc[t] = 0;
-    unsigned h = row_slot(k, hbits);
-    while (atomicCAS(&hk[h], -1, k) != -1) h = (h + 1) & ((1u << hbits) - 1);
-    hp[h] = t;
+    row_insert(tab, hbits, k, t);
   }
   __syncthreads();
   auto fetch = [&](int idx, int &c, T &v) {   // as in k_isai_lower
@@ -605,16 +620,18 @@ __global__ __launch_bounds__(64) void k_isai_upper(const int *__restrict__ urp,
   };
   // three register slots used in place (see k_ilu_color), loaded three steps ahead
   auto step = [&](int idx, int &c0, T &v0) {
+    const unsigned h0 = row_slot(c0, hbits);
+    const RowSlot e0 = tab[h0];   // first probe, beside the reads below
     const int k = P[idx];
     const T mk = ((k == i ? T(1) : T(0)) - acc[idx]) / ud[idx];
     if (threadIdx.x == 0) acc[idx] = mk;   // kept until the row is written out
     // row k's columns past its diagonal exceed k = P[idx]: the indices found lie past idx
     if (rb[idx] + (int)threadIdx.x < re[idx]) {
-      const int pos = row_find(hk, hp, hbits, c0);
+      const int pos = row_resolve(tab, hbits, c0, h0, e0);
       if (pos >= 0) acc[pos] += v0 * mk;
     }
     for (int p = rb[idx] + 64 + threadIdx.x; p < re[idx]; p += 64) {
-      const int pos = row_find(hk, hp, hbits, ucol[p]);
+      const int pos = row_find(tab, hbits, ucol[p]);
       if (pos >= 0) acc[pos] += uval[p] * mk;
     }
     __syncthreads();

@@ -36,7 +36,6 @@ struct PrecData {
   Csr<T> ST;            // pattern of S~^T (colouring)
   DBuf<int> color, perm, iperm;     // perm[new] = old
   DBuf<int> hist, wide;             // colour histograms; wide static patches
-  DBuf<int> resume;                 // colouring: where each vertex's neighbour scan stopped
   DBuf<int> blocker;                // colouring: the uncoloured neighbour found there (-1: none)
   DBuf<int> jplist;                 // colouring: vertices still uncoloured
   std::vector<int> cstart;          // host: colour c owns new rows [cstart[c], cstart[c+1])

@@ -458,6 +458,36 @@ __global__ __launch_bounds__(64) void k_local(LocalArgs<T> A) {
   if (lane == 0) A.qlen[m] = s;
 }
 
+// Pattern table of the register kernel: a slot holds a column in its low and its index in
+// Q in its high 32 bits, so a lookup is one LDS read per probe.  Columns are inserted once.
+constexpr unsigned long long Q_EMPTY = ~0ull;
+template <int SIZE>
+__device__ inline int q_resolve(const unsigned long long *tab, int key, unsigned h,
+                                unsigned long long e) {   // e = tab[h], h = hslot(key)
+  for (int p = 0; p < SIZE; ++p) {
+    const int k = (int)(unsigned)e;
+    if (k == key) return (int)(e >> 32);
+    if (k == -1) return -1;
+    h = (h + 1) & (SIZE - 1);
+    e = tab[h];
+  }
+  return -1;
+}
+template <int SIZE>
+__device__ inline int q_find(const unsigned long long *tab, int key) {
+  const unsigned h = hslot<SIZE>(key);
+  return q_resolve<SIZE>(tab, key, h, tab[h]);
+}
+template <int SIZE>
+__device__ inline void q_insert(unsigned long long *tab, int key, int pos) {
+  const unsigned long long e = ((unsigned long long)(unsigned)pos << 32) | (unsigned)key;
+  unsigned h = hslot<SIZE>(key);
+  for (int p = 0; p < SIZE; ++p) {
+    if (atomicCAS(&tab[h], Q_EMPTY, e) == Q_EMPTY) return;
+    h = (h + 1) & (SIZE - 1);
+  }
+}
+
 // ------------------------------------------------------------------------------------
 // Restricted local solves with the factor held in registers (patterns of at most 48).
 //
@@ -501,7 +531,7 @@ __global__ __launch_bounds__(64) void k_local_reg(LocalArgs<T> A) {
   constexpr int LP = SMAX * (SMAX + 1) / 2;
   __shared__ T Lp[LP];
   __shared__ int q[SMAX];
-  __shared__ int qk[QH], qv[QH];
+  __shared__ unsigned long long qt[QH];   // column -> index in Q (q_find)
   __shared__ T bg[SMAX], bf[SMAX], rowt[SMAX], xs[SMAX];
   __shared__ int ck[CH], clist[CH];
   __shared__ T cr[CH];
@@ -520,34 +550,27 @@ __global__ __launch_bounds__(64) void k_local_reg(LocalArgs<T> A) {
     bg[t] = 0;
     bf[t] = 0;
   }
-  for (int h = lane; h < QH; h += 64) qk[h] = -1;
+  for (int h = lane; h < QH; h += 64) qt[h] = Q_EMPTY;
   if (lane == 0) sflag = 0;
   __syncthreads();
-  for (int t = lane; t < s; t += 64) {
-    bool fr;
-    const int h = h_insert<QH>(qk, q[t], fr);
-    qv[h] = t;
-  }
+  for (int t = lane; t < s; t += 64) q_insert<QH>(qt, q[t], t);
   __syncthreads();
   // right-hand sides: a_ppi^(m) (row m of A_ppi) and a_pip^(m) (column m of A_pip)
   for (int p = A.acf_rp[m] + lane; p < A.acf_rp[m + 1]; p += 64) {
-    const int h = h_find<QH>(qk, A.acf_col[p]);
-    if (h >= 0) bg[qv[h]] = (T)A.acf_val[p];
+    const int k = q_find<QH>(qt, A.acf_col[p]);
+    if (k >= 0) bg[k] = (T)A.acf_val[p];
   }
   for (int p = A.afcT_rp[m] + lane; p < A.afcT_rp[m + 1]; p += 64) {
-    const int h = h_find<QH>(qk, A.afcT_col[p]);
-    if (h >= 0) bf[qv[h]] = (T)A.afcT_val[p];
+    const int k = q_find<QH>(qt, A.afcT_col[p]);
+    if (k >= 0) bf[k] = (T)A.afcT_val[p];
   }
   // restricted matrix -R A_pipi R^T, lower part in Q order
   for (int t = lane; t < LP; t += 64) Lp[t] = 0;
   __syncthreads();
   if (lane < s) {
     row_entries<12>(A.app_rp, A.app_col, A.app_val, q[lane], [&](int c, double v) EDFA_INLINE {
-      const int h = h_find<QH>(qk, c);
-      if (h >= 0) {
-        const int k = qv[h];
-        if (k <= lane) Lp[pidx(lane, k)] = -(T)v;
-      }
+      const int k = q_find<QH>(qt, c);
+      if (k >= 0 && k <= lane) Lp[pidx(lane, k)] = -(T)v;
     });
   }
   __syncthreads();
@@ -645,7 +668,7 @@ __global__ __launch_bounds__(64) void k_local_reg(LocalArgs<T> A) {
     __syncthreads();
     for (int t = scanned + lane; t < s; t += 64) {
       row_cols<12>(A.app_rp, A.app_col, q[t], [&](int c) EDFA_INLINE {
-        if (h_find<QH>(qk, c) < 0) {
+        if (q_find<QH>(qt, c) < 0) {
           bool fr;
           if (h_insert<CH>(ck, c, fr) < 0)
             sflag = 1;
@@ -661,15 +684,43 @@ __global__ __launch_bounds__(64) void k_local_reg(LocalArgs<T> A) {
       return;
     }
     const int nc = ccount;
-    // r_j = (A_pipi R^T g~)_j for j outside Q (a_ppi^(m) vanishes there)
+    // r_j = (A_pipi R^T g~)_j for j outside Q (a_ppi^(m) vanishes there).  A block of a
+    // row's entries is looked up at once: the first table probes of all of them, then the
+    // reads of x~ at the entries found, each a batch of independent LDS reads; the sum
+    // runs in the row's order.
     for (int c = lane; c < nc; c += 64) {
       const int j = clist[c];
       T acc = 0;
-      if (h_find<QH>(qk, j) < 0)
-        row_entries<12>(A.app_rp, A.app_col, A.app_val, j, [&](int col, double v) EDFA_INLINE {
-          const int h = h_find<QH>(qk, col);
-          if (h >= 0) acc += (T)v * xs[qv[h]];
-        });
+      if (q_find<QH>(qt, j) < 0) {
+        constexpr int RB = 12;
+        const int p0 = A.app_rp[j], p1 = A.app_rp[j + 1];
+        for (int b = p0; b < p1; b += RB) {
+          int cc[RB], kq[RB];
+          double vv[RB];
+          unsigned hh[RB];
+          unsigned long long ee[RB];
+          T xv[RB];
+#pragma unroll
+          for (int u = 0; u < RB; ++u) {
+            const int pp = min(b + u, p1 - 1);
+            cc[u] = A.app_col[pp];
+            vv[u] = A.app_val[pp];
+          }
+#pragma unroll
+          for (int u = 0; u < RB; ++u) {
+            hh[u] = hslot<QH>(cc[u]);
+            ee[u] = qt[hh[u]];
+          }
+#pragma unroll
+          for (int u = 0; u < RB; ++u)
+            kq[u] = b + u < p1 ? q_resolve<QH>(qt, cc[u], hh[u], ee[u]) : -1;
+#pragma unroll
+          for (int u = 0; u < RB; ++u) xv[u] = xs[kq[u] >= 0 ? kq[u] : 0];
+#pragma unroll
+          for (int u = 0; u < RB; ++u)
+            if (kq[u] >= 0) acc += (T)vv[u] * xv[u];
+        }
+      }
       cr[c] = acc;
     }
     __syncthreads();
@@ -708,16 +759,14 @@ __global__ __launch_bounds__(64) void k_local_reg(LocalArgs<T> A) {
       if (lane == 0) {
         cr[bc] = 0;
         q[t] = bj;
-        bool fr;
-        const int h = h_insert<QH>(qk, bj, fr);
-        qv[h] = t;
+        q_insert<QH>(qt, bj, t);
       }
       if (lane <= t) rowt[lane] = 0;
       __syncthreads();
       // bordering: column of -A_pipi[Q, j] and its diagonal, L l = a, l_tt^2 = a_tt - l.l
       for (int p = A.app_rp[bj] + lane; p < A.app_rp[bj + 1]; p += 64) {
-        const int h = h_find<QH>(qk, A.app_col[p]);
-        if (h >= 0) rowt[qv[h]] = -(T)A.app_val[p];
+        const int k = q_find<QH>(qt, A.app_col[p]);
+        if (k >= 0) rowt[k] = -(T)A.app_val[p];
       }
       __syncthreads();
       T a = lane <= t ? rowt[lane] : T(0);

@@ -180,75 +180,96 @@ __global__ __launch_bounds__(256) void k_merge_write_w(const int *arp, const int
 // Colouring
 // ---------------------------------------------------------------------------------------
 // Priorities use the cell index local to its grid, so a batch of grids is coloured exactly
-// as each grid alone (neighbours never cross grids).  One group of JPG lanes per vertex:
-// the group checks JPG neighbour entries at a time (S~ row, then S~^T row) starting where
-// the previous round stopped; an uncoloured higher-priority neighbour blocks the vertex
-// for this round (and becomes the resume point).  A vertex with no blocker takes the
-// smallest colour unused by its neighbours (all coloured ones have higher priority).
-constexpr int JPG = 16;
+// as each grid alone (neighbours never cross grids).  One lane per vertex checks the common
+// case: a vertex whose recorded blocker is still uncoloured stays blocked (two loads).  The
+// wavefront then takes its other uncoloured vertices four at a time (16 lanes each), reading
+// all neighbour entries (S~ row, then S~^T row) and their colours at once; the first uncoloured
+// higher-priority neighbour blocks the vertex for this round and is recorded.  A vertex
+// with no blocker takes the smallest colour unused by its neighbours (all coloured ones have
+// higher priority), so the colouring does not depend on the order in which a round visits
+// the vertices.
+constexpr int JP_BATCH = 14;
 __global__ __launch_bounds__(256) void k_jp_round(const int *__restrict__ srp,
                                                   const int *__restrict__ scol,
                                                   const int *__restrict__ trp,
                                                   const int *__restrict__ tcol, int ne,
                                                   const GridDesc *__restrict__ grids, int ngrid,
                                                   const int *__restrict__ list, int nlist,
-                                                  int *color, int *resume, int *blocker,
+                                                  int *color, int *blocker,
                                                   int *ncolored, int *err) {
-  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int slot = (int)(gid / JPG);
-  const int l = (int)(gid % JPG);
-  if (slot >= (list ? nlist : ne)) return;
-  const int v = list ? list[slot] : slot;
-  // a vertex whose recorded blocker is still uncoloured stays blocked: two loads
-  const int bv = blocker[v];
-  if (__atomic_load_n(&color[v], __ATOMIC_RELAXED) >= 0) return;
-  if (bv >= 0 && __atomic_load_n(&color[bv], __ATOMIC_RELAXED) < 0) return;
-  const int c0 = grids[grid_of(grids, ngrid, v, true)].cell0;
-  const unsigned pv = fmix32((unsigned)(v - c0));
-  const int s0 = srp[v], ls = srp[v + 1] - s0, t0 = trp[v], lt = trp[v + 1] - t0;
-  const int tot = ls + lt;
-  const int shift = ((threadIdx.x & 63) / JPG) * JPG;
-  for (int base = resume[v]; base < tot; base += JPG) {
-    const int p = base + l;
-    bool blk = false;
-    if (p < tot) {
-      const int u = p < ls ? scol[s0 + p] : tcol[t0 + p - ls];
-      blk = u != v && fmix32((unsigned)(u - c0)) > pv &&
-            __atomic_load_n(&color[u], __ATOMIC_RELAXED) < 0;
+  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  int v = -1;
+  bool need = false;
+  if (slot < (list ? nlist : ne)) {
+    v = list ? list[slot] : slot;
+    if (__atomic_load_n(&color[v], __ATOMIC_RELAXED) < 0) {
+      const int bv = blocker[v];
+      need = !(bv >= 0 && __atomic_load_n(&color[bv], __ATOMIC_RELAXED) < 0);
     }
-    const unsigned gm = (unsigned)((__ballot(blk) >> shift) & ((1ull << JPG) - 1));
-    if (gm) {
-      const int first = __ffs(gm) - 1;
-      if (l == first) {
-        resume[v] = p;
-        blocker[v] = p < ls ? scol[s0 + p] : tcol[t0 + p - ls];
+  }
+  unsigned long long work = __ballot(need);
+  const int g = lane >> 4, l = lane & 15;   // four groups of 16 lanes
+  while (work) {   // uniform: the same mask in every lane
+    // the next four vertices of the wavefront's list, one per group
+    int mine = -1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (work) {
+        if (q == g) mine = __ffsll((long long)work) - 1;
+        work &= work - 1;
       }
-      return;
+    }
+    const int w = __shfl(v, mine >= 0 ? mine : 0);
+    if (mine < 0) continue;
+    const int c0 = grids[grid_of(grids, ngrid, w, true)].cell0;
+    const unsigned pw = fmix32((unsigned)(w - c0));
+    const int s0 = srp[w], ls = srp[w + 1] - s0, t0 = trp[w], lt = trp[w + 1] - t0;
+    const int tot = ls + lt;
+    // JP_BATCH entries per lane: the neighbour indices, then their colours, are each one
+    // batch of independent loads; the same colours serve the blocking test and the choice
+    // of colour (a coloured neighbour always has the higher priority)
+    unsigned used[MAX_COLORS / 32];
+#pragma unroll
+    for (int q = 0; q < MAX_COLORS / 32; ++q) used[q] = 0;
+    int first = -1;   // position of the first blocking entry (the same in the group)
+    for (int base = 0; base < tot && first < 0; base += 16 * JP_BATCH) {
+      int u[JP_BATCH], cu[JP_BATCH];
+#pragma unroll
+      for (int k = 0; k < JP_BATCH; ++k) {
+        const int p = base + 16 * k + l;
+        u[k] = p < tot ? (p < ls ? scol[s0 + p] : tcol[t0 + p - ls]) : w;
+      }
+#pragma unroll
+      for (int k = 0; k < JP_BATCH; ++k) cu[k] = __atomic_load_n(&color[u[k]], __ATOMIC_RELAXED);
+#pragma unroll
+      for (int k = 0; k < JP_BATCH; ++k) {
+        const bool blk = u[k] != w && cu[k] < 0 && fmix32((unsigned)(u[k] - c0)) > pw;
+        const unsigned gm = (unsigned)(__ballot(blk) >> (16 * g)) & 0xffffu;
+        if (first < 0 && gm) first = base + 16 * k + __ffs(gm) - 1;
+        if (u[k] != w && cu[k] >= 0) used[cu[k] >> 5] |= 1u << (cu[k] & 31);
+      }
+    }
+    if (first >= 0) {   // blocked for this round
+      if (l == (first & 15)) blocker[w] = first < ls ? scol[s0 + first] : tcol[t0 + first - ls];
+      continue;
+    }
+#pragma unroll
+    for (int q = 0; q < MAX_COLORS / 32; ++q)
+#pragma unroll
+      for (int o = 8; o > 0; o >>= 1) used[q] |= __shfl_xor(used[q], o, 16);
+    if (l == 0) {
+      int c = -1;
+      for (int q = 0; q < MAX_COLORS / 32 && c < 0; ++q)
+        if (~used[q]) c = q * 32 + __ffs(~used[q]) - 1;
+      if (c < 0) {
+        atomicMin(err, w);
+        c = MAX_COLORS - 1;
+      }
+      __atomic_store_n(&color[w], c, __ATOMIC_RELAXED);
+      atomicAdd(ncolored, 1);
     }
   }
-  unsigned used[MAX_COLORS / 32];
-#pragma unroll
-  for (int w = 0; w < MAX_COLORS / 32; ++w) used[w] = 0;
-  for (int p = l; p < tot; p += JPG) {
-    const int u = p < ls ? scol[s0 + p] : tcol[t0 + p - ls];
-    if (u == v) continue;
-    const int cu = __atomic_load_n(&color[u], __ATOMIC_RELAXED);
-    if (cu >= 0) used[cu >> 5] |= 1u << (cu & 31);
-  }
-#pragma unroll
-  for (int w = 0; w < MAX_COLORS / 32; ++w)
-#pragma unroll
-    for (int o = JPG / 2; o > 0; o >>= 1) used[w] |= __shfl_xor(used[w], o, JPG);
-  if (l != 0) return;
-  int c = -1;
-  for (int w = 0; w < MAX_COLORS / 32 && c < 0; ++w)
-    if (~used[w]) c = w * 32 + __ffs(~used[w]) - 1;
-  if (c < 0) {
-    atomicMin(err, v);
-    c = MAX_COLORS - 1;
-  }
-  __atomic_store_n(&color[v], c, __ATOMIC_RELAXED);
-  atomicAdd(ncolored, 1);
 }
 
 // Worklist of the vertices still uncoloured (any order: a vertex's colour depends only on
@@ -733,8 +754,6 @@ static void stage2_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
   D.color.ensure(ne);
   EDFA_HIP(hipMemsetAsync(D.color.p, 0xff, sizeof(int) * ne, s));
   EDFA_HIP(hipMemsetAsync(P.flags.p + 2, 0, sizeof(int), s));
-  D.resume.ensure(ne);
-  EDFA_HIP(hipMemsetAsync(D.resume.p, 0, sizeof(int) * (size_t)ne, s));
   D.blocker.ensure(ne);
   EDFA_HIP(hipMemsetAsync(D.blocker.p, 0xff, sizeof(int) * (size_t)ne, s));
   int rounds = 0;
@@ -745,9 +764,9 @@ static void stage2_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
     // a round is cheap (one load per vertex still blocked), so check completion rarely
     const int batch = rounds < 64 ? 16 : 32;
     for (int r = 0; r < batch; ++r)
-      hipLaunchKernelGGL(k_jp_round, dim3(ceil_div((long long)nlist * JPG, 256)), dim3(256), 0, s,
+      hipLaunchKernelGGL(k_jp_round, dim3(ceil_div(nlist, 256)), dim3(256), 0, s,
                          D.S.rowptr.p, D.S.col.p, D.ST.rowptr.p, D.ST.col.p, ne, S.grids.p,
-                         S.ngrid, list, nlist, D.color.p, D.resume.p, D.blocker.p,
+                         S.ngrid, list, nlist, D.color.p, D.blocker.p,
                          P.flags.p + 2, P.flags.p + 1);
     EDFA_CHECK_LAUNCH();
     rounds += batch;

@@ -20,6 +20,8 @@ struct PrecData {
   DBuf<int> Q;          // Ne x smax final patterns (base order, then appended)
   DBuf<int> qlen;       // Ne
   DBuf<T> gbuf, fbuf;   // Ne x smax restricted solutions
+  DBuf<int> ell_col;    // A_pipi rows padded to ELL_W entries (column -1 past a row's end)
+  DBuf<double> ell_val;
   Csr<T> G;             // G~   (Ne x Nfu)
   Csr<T> FT;            // F~^T (Ne x Nfu): row m = column m of F~
   Csr<T> Fface;         // F~   (Nfu x Ne)

@@ -193,6 +193,21 @@ __global__ void k_row_max(const int *__restrict__ rp, int rows, int *out) {
   atomicMax(out, rp[r + 1] - rp[r]);
 }
 
+// A_pipi rows padded to ELL_W entries, for the candidate residuals of k_local_reg: a row's
+// entries then load from its index alone, in a few wide loads.  A face couples to the
+// faces of its one or two hexahedra, at most 11 entries.
+constexpr int ELL_W = 12;
+__global__ void k_ell_fill(const int *__restrict__ rp, const int *__restrict__ col,
+                           const double *__restrict__ val, int rows, int *ecol, double *eval) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)rows * ELL_W) return;
+  const int r = (int)(t / ELL_W), k = (int)(t % ELL_W);
+  const int p = rp[r] + k;
+  const bool in = p < rp[r + 1];
+  ecol[t] = in ? col[p] : -1;
+  eval[t] = in ? val[p] : 0.0;
+}
+
 // ------------------------------------------------------------------------------------
 // Restricted local solves, one 64-lane wavefront per cell
 // ------------------------------------------------------------------------------------
@@ -201,6 +216,8 @@ struct LocalArgs {
   int ne;
   const int *app_rp, *app_col;
   const double *app_val;
+  const int *ell_col;   // A_pipi as ELL_W-entry rows (k_local_reg)
+  const double *ell_val;
   const int *acf_rp, *acf_col;
   const double *acf_val;
   const int *afcT_rp, *afcT_col;
@@ -575,7 +592,10 @@ __global__ __launch_bounds__(64) void k_local_reg(LocalArgs<T> A) {
   }
   __syncthreads();
 
-  // row `lane` into registers and right-looking Cholesky
+  // row `lane` into registers and right-looking Cholesky.  Lane i keeps row i of L strictly
+  // below the diagonal, and L_ii and 1/L_ii apart; the updates of a step also touch the
+  // slots at and past the diagonal, which no later step reads, so they are cleared at the
+  // end.  The triangular solves below then need no per-step selects.
   T Lr[SMAX];
   static_for<0, SMAX>([&](auto K) EDFA_INLINE {
     constexpr int k = K;
@@ -605,10 +625,14 @@ __global__ __launch_bounds__(64) void k_local_reg(LocalArgs<T> A) {
     return;
   }
   T invd = T(1) / dg;
+  static_for<0, SMAX>([&](auto K) EDFA_INLINE {
+    constexpr int k = K;
+    Lr[k] = k < lane ? Lr[k] : T(0);
+  });
   __syncthreads();
   static_for<0, SMAX>([&](auto K) EDFA_INLINE {
     constexpr int k = K;
-    if (lane < s && k <= lane) Lp[pidx(lane, k)] = Lr[k];
+    if (lane < s && k < lane) Lp[pidx(lane, k)] = Lr[k];
   });
   __syncthreads();
 
@@ -619,39 +643,45 @@ __global__ __launch_bounds__(64) void k_local_reg(LocalArgs<T> A) {
   T xg = 0, xf = 0;
   for (;;) {
     const bool last = fin || !(n_prog < A.n_ent && sweep < it_max);
-    // forward L y = b (g, and f on the last pass), then backward L^T x = y
+    // forward L y = b, then backward L^T x = y (g~, and f~ on the last pass).  Lane k's
+    // entry is final when step k reads it (its row has no entry at or past k), so each lane
+    // ends holding its own entry and divides it by L_kk there: the same operations, on the
+    // same operands, as dividing at step k.
     {
       T b1 = lane < s ? bg[lane] : T(0);
-      T b2 = (last && lane < s) ? bf[lane] : T(0);
-      T y1 = 0, y2 = 0;
-      static_for<0, SMAX>([&](auto K) EDFA_INLINE {
-        constexpr int k = K;
-        if (k >= s) return;
-        const T ik = lane_value(invd, k);
-        const T a1 = lane_value(b1, k) * ik;
-        const T a2 = lane_value(b2, k) * ik;
-        b1 -= Lr[k] * a1;
-        b2 -= Lr[k] * a2;
-        if (lane == k) {
-          y1 = a1;
-          y2 = a2;
+      if (!last) {
+        static_for<0, SMAX>([&](auto K) EDFA_INLINE {
+          constexpr int k = K;
+          if (k < s) b1 -= Lr[k] * (lane_value(b1, k) * lane_value(invd, k));
+        });
+        b1 *= invd;
+        for (int k = s - 1; k >= 0; --k) {   // uniform k: lane reads and LDS only
+          const T l = lane < k ? Lp[pidx(k, lane)] : T(0);
+          b1 -= l * (lane_value(b1, k) * lane_value(invd, k));
         }
-      });
-      T x1 = 0, x2 = 0;
-      for (int k = s - 1; k >= 0; --k) {   // uniform k: lane reads and LDS only
-        const T ik = lane_value(invd, k);
-        const T c1 = lane_value(y1, k) * ik;
-        const T c2 = lane_value(y2, k) * ik;
-        const T l = lane < k ? Lp[pidx(k, lane)] : T(0);
-        y1 -= l * c1;
-        y2 -= l * c2;
-        if (lane == k) {
-          x1 = c1;
-          x2 = c2;
+        b1 *= invd;
+      } else {
+        T b2 = lane < s ? bf[lane] : T(0);
+        static_for<0, SMAX>([&](auto K) EDFA_INLINE {
+          constexpr int k = K;
+          if (k >= s) return;
+          const T ik = lane_value(invd, k);
+          b1 -= Lr[k] * (lane_value(b1, k) * ik);
+          b2 -= Lr[k] * (lane_value(b2, k) * ik);
+        });
+        b1 *= invd;
+        b2 *= invd;
+        for (int k = s - 1; k >= 0; --k) {
+          const T ik = lane_value(invd, k);
+          const T l = lane < k ? Lp[pidx(k, lane)] : T(0);
+          b1 -= l * (lane_value(b1, k) * ik);
+          b2 -= l * (lane_value(b2, k) * ik);
         }
+        b1 *= invd;
+        b2 *= invd;
+        xf = b2;
       }
-      xg = x1;
-      if (last) xf = x2;
+      xg = b1;
     }
     if (last) break;
     ++sweep;
@@ -684,44 +714,69 @@ __global__ __launch_bounds__(64) void k_local_reg(LocalArgs<T> A) {
       return;
     }
     const int nc = ccount;
-    // r_j = (A_pipi R^T g~)_j for j outside Q (a_ppi^(m) vanishes there).  A block of a
-    // row's entries is looked up at once: the first table probes of all of them, then the
-    // reads of x~ at the entries found, each a batch of independent LDS reads; the sum
-    // runs in the row's order.
-    for (int c = lane; c < nc; c += 64) {
+    // r_j = (A_pipi R^T g~)_j for j outside Q (a_ppi^(m) vanishes there).  Lane l takes the
+    // candidates l, l + 64, ...; the ELL row of its next candidate is in flight while the
+    // current one is looked up (two register slots used in place; the loads are issued
+    // without branches, past the list's end re-reading its last candidate).  A row's
+    // entries are looked up as one batch of first table probes, then one batch of x~
+    // reads at the entries found; the sum runs in the row's order.
+    struct EllRow {
+      int4 c[ELL_W / 4];
+      double2 v[ELL_W / 2];
+    };
+    auto rfetch = [&](int c, EllRow &r) EDFA_INLINE {
+      const int j = clist[min(c, nc - 1)];
+      const int4 *pc = reinterpret_cast<const int4 *>(A.ell_col + (size_t)j * ELL_W);
+      const double2 *pv = reinterpret_cast<const double2 *>(A.ell_val + (size_t)j * ELL_W);
+#pragma unroll
+      for (int u = 0; u < ELL_W / 4; ++u) r.c[u] = pc[u];
+#pragma unroll
+      for (int u = 0; u < ELL_W / 2; ++u) r.v[u] = pv[u];
+    };
+    auto residual = [&](int c, const EllRow &r) EDFA_INLINE {
+      if (c >= nc) return;
       const int j = clist[c];
       T acc = 0;
       if (q_find<QH>(qt, j) < 0) {
-        constexpr int RB = 12;
-        const int p0 = A.app_rp[j], p1 = A.app_rp[j + 1];
-        for (int b = p0; b < p1; b += RB) {
-          int cc[RB], kq[RB];
-          double vv[RB];
-          unsigned hh[RB];
-          unsigned long long ee[RB];
-          T xv[RB];
+        int cc[ELL_W], kq[ELL_W];
+        double vv[ELL_W];
+        unsigned long long ee[ELL_W];
+        T xv[ELL_W];
 #pragma unroll
-          for (int u = 0; u < RB; ++u) {
-            const int pp = min(b + u, p1 - 1);
-            cc[u] = A.app_col[pp];
-            vv[u] = A.app_val[pp];
-          }
-#pragma unroll
-          for (int u = 0; u < RB; ++u) {
-            hh[u] = hslot<QH>(cc[u]);
-            ee[u] = qt[hh[u]];
-          }
-#pragma unroll
-          for (int u = 0; u < RB; ++u)
-            kq[u] = b + u < p1 ? q_resolve<QH>(qt, cc[u], hh[u], ee[u]) : -1;
-#pragma unroll
-          for (int u = 0; u < RB; ++u) xv[u] = xs[kq[u] >= 0 ? kq[u] : 0];
-#pragma unroll
-          for (int u = 0; u < RB; ++u)
-            if (kq[u] >= 0) acc += (T)vv[u] * xv[u];
+        for (int u = 0; u < ELL_W / 4; ++u) {
+          cc[4 * u] = r.c[u].x;
+          cc[4 * u + 1] = r.c[u].y;
+          cc[4 * u + 2] = r.c[u].z;
+          cc[4 * u + 3] = r.c[u].w;
         }
+#pragma unroll
+        for (int u = 0; u < ELL_W / 2; ++u) {
+          vv[2 * u] = r.v[u].x;
+          vv[2 * u + 1] = r.v[u].y;
+        }
+#pragma unroll
+        for (int u = 0; u < ELL_W; ++u) ee[u] = qt[hslot<QH>(cc[u])];
+#pragma unroll
+        for (int u = 0; u < ELL_W; ++u)
+          kq[u] = cc[u] >= 0 ? q_resolve<QH>(qt, cc[u], hslot<QH>(cc[u]), ee[u]) : -1;
+#pragma unroll
+        for (int u = 0; u < ELL_W; ++u) xv[u] = xs[kq[u] >= 0 ? kq[u] : 0];
+#pragma unroll
+        for (int u = 0; u < ELL_W; ++u)
+          if (kq[u] >= 0) acc += (T)vv[u] * xv[u];
       }
       cr[c] = acc;
+    };
+    if (nc > 0) {
+      EllRow ra, rb;
+      rfetch(lane, ra);
+      rfetch(lane + 64, rb);
+      for (int base = 0; base < nc; base += 128) {
+        residual(base + lane, ra);
+        rfetch(base + lane + 128, ra);
+        residual(base + lane + 64, rb);
+        rfetch(base + lane + 192, rb);
+      }
     }
     __syncthreads();
     int added = 0;
@@ -787,16 +842,11 @@ __global__ __launch_bounds__(64) void k_local_reg(LocalArgs<T> A) {
         return;
       }
       const T ltt = sqrt(d);
-      static_for<0, SMAX>([&](auto K) EDFA_INLINE {
-        constexpr int k = K;
-        Lr[k] = (k == t && lane == t) ? ltt : Lr[k];
-      });
       if (lane == t) {
         dg = ltt;
         invd = T(1) / ltt;
       }
       if (lane == 0) {
-        Lp[pidx(t, t)] = ltt;
         bg[t] = 0;
         bf[t] = 0;
       }
@@ -1265,10 +1315,17 @@ static void stage1_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
                      P.flags.p + 2);
   EDFA_CHECK_LAUNCH();
   const int maxbase = read_scalar(P.flags.p + 2, s);
+  // the register kernel reads A_pipi as ELL_W-entry rows; longer rows take the LDS kernel
+  EDFA_HIP(hipMemsetAsync(P.flags.p + 2, 0, sizeof(int), s));
+  hipLaunchKernelGGL(k_row_max, dim3(ceil_div(nfu, 256)), dim3(256), 0, s, S.Afp.rowptr.p, nfu,
+                     P.flags.p + 2);
+  EDFA_CHECK_LAUNCH();
+  const bool ell_ok = read_scalar(P.flags.p + 2, s) <= ELL_W;
+  const auto reg_stride = [&](int sm) { return sm > 0 && sm <= 48 && !ell_ok ? 64 : sm; };
   const bool dynamic = prm.variant == EDFA_DYNAMIC;
   int need = maxbase;
   if (dynamic) need = maxbase + std::max(0, prm.n_ent);
-  int smax = pattern_stride(need);
+  int smax = reg_stride(pattern_stride(need));
   if (!smax && (dynamic || prm.static_level == 0))
     fail(EDFA_ERR_CAPACITY, "patterns of up to %d entries exceed 128", need);
   D.qlen.ensure(ne);
@@ -1289,6 +1346,7 @@ static void stage1_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
     need = read_scalar(P.flags.p + 2, s);
     smax = pattern_stride(need);
     if (!smax) fail(EDFA_ERR_CAPACITY, "static patches of %d entries exceed 128", need);
+    smax = reg_stride(smax);
     D.Q.ensure((size_t)ne * smax);
     hipLaunchKernelGGL(k_repack, dim3(ceil_div(ne, 256)), dim3(256), 0, s, D.wide.p, D.qlen.p, ne,
                        PATCH_MAX, smax, D.Q.p);
@@ -1306,6 +1364,17 @@ static void stage1_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
   la.app_rp = S.Afp.rowptr.p;
   la.app_col = S.Afp.col.p;
   la.app_val = S.Afp.val.p;
+  la.ell_col = nullptr;
+  la.ell_val = nullptr;
+  if (smax <= 48 && nfu > 0) {
+    D.ell_col.ensure((size_t)nfu * ELL_W);
+    D.ell_val.ensure((size_t)nfu * ELL_W);
+    hipLaunchKernelGGL(k_ell_fill, dim3(ceil_div((long long)nfu * ELL_W, 256)), dim3(256), 0, s,
+                       S.Afp.rowptr.p, S.Afp.col.p, S.Afp.val.p, nfu, D.ell_col.p, D.ell_val.p);
+    EDFA_CHECK_LAUNCH();
+    la.ell_col = D.ell_col.p;
+    la.ell_val = D.ell_val.p;
+  }
   la.acf_rp = S.Acf.rowptr.p;
   la.acf_col = S.Acf.col.p;
   la.acf_val = S.Acf.val.p;

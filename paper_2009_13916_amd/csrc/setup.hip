@@ -655,10 +655,13 @@ __global__ __launch_bounds__(64) void k_local_reg(LocalArgs<T> A) {
           if (k < s) b1 -= Lr[k] * (lane_value(b1, k) * lane_value(invd, k));
         });
         b1 *= invd;
-        for (int k = s - 1; k >= 0; --k) {   // uniform k: lane reads and LDS only
+        // all SMAX steps, without branches, so the LDS reads of later steps issue early:
+        // the entries past s are zero and so are their updates
+        static_for<0, SMAX>([&](auto K) EDFA_INLINE {
+          constexpr int k = SMAX - 1 - K;
           const T l = lane < k ? Lp[pidx(k, lane)] : T(0);
           b1 -= l * (lane_value(b1, k) * lane_value(invd, k));
-        }
+        });
         b1 *= invd;
       } else {
         T b2 = lane < s ? bf[lane] : T(0);
@@ -671,12 +674,13 @@ __global__ __launch_bounds__(64) void k_local_reg(LocalArgs<T> A) {
         });
         b1 *= invd;
         b2 *= invd;
-        for (int k = s - 1; k >= 0; --k) {
+        static_for<0, SMAX>([&](auto K) EDFA_INLINE {
+          constexpr int k = SMAX - 1 - K;
           const T ik = lane_value(invd, k);
           const T l = lane < k ? Lp[pidx(k, lane)] : T(0);
           b1 -= l * (lane_value(b1, k) * ik);
           b2 -= l * (lane_value(b2, k) * ik);
-        }
+        });
         b1 *= invd;
         b2 *= invd;
         xf = b2;

@@ -650,13 +650,13 @@ __global__ __launch_bounds__(64) void k_local_reg(LocalArgs<T> A) {
     {
       T b1 = lane < s ? bg[lane] : T(0);
       if (!last) {
+        // both substitutions run all SMAX steps without branches, so the reads of later
+        // steps issue early: the entries past s are zero and so are their updates
         static_for<0, SMAX>([&](auto K) EDFA_INLINE {
           constexpr int k = K;
-          if (k < s) b1 -= Lr[k] * (lane_value(b1, k) * lane_value(invd, k));
+          b1 -= Lr[k] * (lane_value(b1, k) * lane_value(invd, k));
         });
         b1 *= invd;
-        // all SMAX steps, without branches, so the LDS reads of later steps issue early:
-        // the entries past s are zero and so are their updates
         static_for<0, SMAX>([&](auto K) EDFA_INLINE {
           constexpr int k = SMAX - 1 - K;
           const T l = lane < k ? Lp[pidx(k, lane)] : T(0);
@@ -667,7 +667,6 @@ __global__ __launch_bounds__(64) void k_local_reg(LocalArgs<T> A) {
         T b2 = lane < s ? bf[lane] : T(0);
         static_for<0, SMAX>([&](auto K) EDFA_INLINE {
           constexpr int k = K;
-          if (k >= s) return;
           const T ik = lane_value(invd, k);
           b1 -= Lr[k] * (lane_value(b1, k) * ik);
           b2 -= Lr[k] * (lane_value(b2, k) * ik);

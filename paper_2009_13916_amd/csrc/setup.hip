@@ -505,6 +505,39 @@ __device__ inline void q_insert(unsigned long long *tab, int key, int pos) {
   }
 }
 
+// Visit the entries of row r of an ELL_W-entry copy in order (column -1 ends a row): the
+// row is requested in a few wide loads before f runs on any entry.  val may be null.
+template <class F>
+__device__ __forceinline__ void ell_row(const int *__restrict__ ecol,
+                                        const double *__restrict__ eval, int r, F &&f) {
+  const int4 *pc = reinterpret_cast<const int4 *>(ecol + (size_t)r * ELL_W);
+  int c[ELL_W];
+  double v[ELL_W];
+#pragma unroll
+  for (int u = 0; u < ELL_W / 4; ++u) {
+    const int4 w = pc[u];
+    c[4 * u] = w.x;
+    c[4 * u + 1] = w.y;
+    c[4 * u + 2] = w.z;
+    c[4 * u + 3] = w.w;
+  }
+  if (eval) {
+    const double2 *pv = reinterpret_cast<const double2 *>(eval + (size_t)r * ELL_W);
+#pragma unroll
+    for (int u = 0; u < ELL_W / 2; ++u) {
+      const double2 w = pv[u];
+      v[2 * u] = w.x;
+      v[2 * u + 1] = w.y;
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < ELL_W; ++u) v[u] = 0;
+  }
+#pragma unroll
+  for (int u = 0; u < ELL_W; ++u)
+    if (c[u] >= 0) f(c[u], v[u]);
+}
+
 // ------------------------------------------------------------------------------------
 // Restricted local solves with the factor held in registers (patterns of at most 48).
 //
@@ -585,7 +618,7 @@ __global__ __launch_bounds__(64) void k_local_reg(LocalArgs<T> A) {
   for (int t = lane; t < LP; t += 64) Lp[t] = 0;
   __syncthreads();
   if (lane < s) {
-    row_entries<12>(A.app_rp, A.app_col, A.app_val, q[lane], [&](int c, double v) EDFA_INLINE {
+    ell_row(A.ell_col, A.ell_val, q[lane], [&](int c, double v) EDFA_INLINE {
       const int k = q_find<QH>(qt, c);
       if (k >= 0 && k <= lane) Lp[pidx(lane, k)] = -(T)v;
     });
@@ -700,7 +733,7 @@ __global__ __launch_bounds__(64) void k_local_reg(LocalArgs<T> A) {
     }
     __syncthreads();
     for (int t = scanned + lane; t < s; t += 64) {
-      row_cols<12>(A.app_rp, A.app_col, q[t], [&](int c) EDFA_INLINE {
+      ell_row(A.ell_col, nullptr, q[t], [&](int c, double) EDFA_INLINE {
         if (q_find<QH>(qt, c) < 0) {
           bool fr;
           if (h_insert<CH>(ck, c, fr) < 0)
@@ -822,9 +855,10 @@ __global__ __launch_bounds__(64) void k_local_reg(LocalArgs<T> A) {
       if (lane <= t) rowt[lane] = 0;
       __syncthreads();
       // bordering: column of -A_pipi[Q, j] and its diagonal, L l = a, l_tt^2 = a_tt - l.l
-      for (int p = A.app_rp[bj] + lane; p < A.app_rp[bj + 1]; p += 64) {
-        const int k = q_find<QH>(qt, A.app_col[p]);
-        if (k >= 0) rowt[k] = -(T)A.app_val[p];
+      if (lane < ELL_W) {
+        const int c = A.ell_col[(size_t)bj * ELL_W + lane];
+        const int k = c >= 0 ? q_find<QH>(qt, c) : -1;
+        if (k >= 0) rowt[k] = -(T)A.ell_val[(size_t)bj * ELL_W + lane];
       }
       __syncthreads();
       T a = lane <= t ? rowt[lane] : T(0);

@@ -1024,6 +1024,8 @@ struct HArgs {
   const T *g_val;
   const int *app_rp, *app_col;
   const double *app_val;
+  const int *ell_col;   // A_pipi as ELL_W-entry rows, or null (then the CSR arrays)
+  const double *ell_val;
   const int *ff_rp, *ff_col;   // F~ by face rows (cells)
   const int *ft_rp, *ft_col;   // F~^T by cell rows (faces)
   const T *ft_val;
@@ -1074,17 +1076,21 @@ __global__ __launch_bounds__(64) void k_htilde(HArgs<T> A) {
       gv[h] = A.g_val[p];
   }
   // support of t = A_pipi R^T g~: A_pipi neighbours of the pattern of g~
+  auto add_t = [&](int c, double) EDFA_INLINE {
+    bool fr;
+    const int h = h_insert<TH>(tk, c, fr);
+    if (h < 0) {
+      sflag = 1;
+    } else if (fr) {
+      const int i = atomicAdd(&tcount, 1);
+      if (i < TL) tlist[i] = h;
+    }
+  };
   for (int p = g0 + lane; p < g1; p += 64) {
-    row_cols<12>(A.app_rp, A.app_col, A.g_col[p], [&](int c) EDFA_INLINE {
-      bool fr;
-      const int h = h_insert<TH>(tk, c, fr);
-      if (h < 0) {
-        sflag = 1;
-      } else if (fr) {
-        const int i = atomicAdd(&tcount, 1);
-        if (i < TL) tlist[i] = h;
-      }
-    });
+    if (A.ell_col)
+      ell_row(A.ell_col, nullptr, A.g_col[p], add_t);
+    else
+      row_cols<12>(A.app_rp, A.app_col, A.g_col[p], [&](int c) EDFA_INLINE { add_t(c, 0.0); });
   }
   __syncthreads();
   if (A.retry_count && (sflag || tcount > TH / 2)) {
@@ -1099,10 +1105,14 @@ __global__ __launch_bounds__(64) void k_htilde(HArgs<T> A) {
   for (int c = lane; c < nt; c += 64) {
     const int h = tlist[c];
     T acc = 0;
-    row_entries<12>(A.app_rp, A.app_col, A.app_val, tk[h], [&](int col, double v) EDFA_INLINE {
+    auto add = [&](int col, double v) EDFA_INLINE {
       const int s = h_find<GH>(gk, col);
       if (s >= 0) acc += (T)v * gv[s];
-    });
+    };
+    if (A.ell_col)
+      ell_row(A.ell_col, A.ell_val, tk[h], add);
+    else
+      row_entries<12>(A.app_rp, A.app_col, A.app_val, tk[h], add);
     tv[h] = acc;
   }
   // candidate cells: all l with F~[j, l] != 0 for j in the support of t
@@ -1403,7 +1413,7 @@ static void stage1_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
   la.app_val = S.Afp.val.p;
   la.ell_col = nullptr;
   la.ell_val = nullptr;
-  if (smax <= 48 && nfu > 0) {
+  if (ell_ok && nfu > 0) {   // the register kernel and the rows of H~ read it
     D.ell_col.ensure((size_t)nfu * ELL_W);
     D.ell_val.ensure((size_t)nfu * ELL_W);
     hipLaunchKernelGGL(k_ell_fill, dim3(ceil_div((long long)nfu * ELL_W, 256)), dim3(256), 0, s,
@@ -1476,6 +1486,8 @@ static void stage1_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
   ha.app_rp = S.Afp.rowptr.p;
   ha.app_col = S.Afp.col.p;
   ha.app_val = S.Afp.val.p;
+  ha.ell_col = la.ell_col;
+  ha.ell_val = la.ell_val;
   ha.ff_rp = D.Fface.rowptr.p;
   ha.ff_col = D.Fface.col.p;
   ha.ft_rp = D.FT.rowptr.p;

@@ -37,6 +37,19 @@ __device__ inline int h_find(const int *keys, int key) {
   return -1;
 }
 
+// h_find given the key k0 read at the key's first slot h: the first probe can be issued
+// early, beside other reads.
+template <int SIZE>
+__device__ inline int h_resolve(const int *keys, int key, unsigned h, int k0) {
+  for (int p = 0; p < SIZE; ++p) {
+    if (k0 == key) return (int)h;
+    if (k0 == -1) return -1;
+    h = (h + 1) & (SIZE - 1);
+    k0 = keys[h];
+  }
+  return -1;
+}
+
 // Insert key (idempotent); returns the slot, or -1 when the table is full.  fresh tells
 // whether this call inserted it.
 template <int SIZE>
@@ -1143,10 +1156,30 @@ __global__ __launch_bounds__(64) void k_htilde(HArgs<T> A) {
   for (int c = lane; c < nl; c += 64) {
     const int l = llist[c];
     T acc = 0;
-    row_entries<16>(A.ft_rp, A.ft_col, A.ft_val, l, [&](int col, T v) EDFA_INLINE {
-      const int s = h_find<TH>(tk, col);
-      if (s >= 0) acc += tv[s] * v;
-    });
+    // a block of the row is looked up at once: the first table probes of all its entries,
+    // then the reads of t at the entries found, each one batch of LDS reads; the sum runs
+    // in the row's order
+    const int p0 = A.ft_rp[l], p1 = A.ft_rp[l + 1];
+    for (int b = p0; b < p1; b += 16) {
+      int cc[16], kk[16], sl[16];
+      T vv[16], xv[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int p = min(b + u, p1 - 1);
+        cc[u] = A.ft_col[p];
+        vv[u] = A.ft_val[p];
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) kk[u] = tk[hslot<TH>(cc[u])];
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        sl[u] = b + u < p1 ? h_resolve<TH>(tk, cc[u], hslot<TH>(cc[u]), kk[u]) : -1;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) xv[u] = tv[sl[u] >= 0 ? sl[u] : 0];
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (sl[u] >= 0) acc += xv[u] * vv[u];
+    }
     int rank = 0;
     for (int c2 = 0; c2 < nl; ++c2) rank += llist[c2] < l;
     A.Hcol[(size_t)m * HMAX + rank] = l;

@@ -1118,14 +1118,45 @@ __global__ __launch_bounds__(64) void k_htilde(HArgs<T> A) {
   for (int c = lane; c < nt; c += 64) {
     const int h = tlist[c];
     T acc = 0;
-    auto add = [&](int col, double v) EDFA_INLINE {
-      const int s = h_find<GH>(gk, col);
-      if (s >= 0) acc += (T)v * gv[s];
-    };
-    if (A.ell_col)
-      ell_row(A.ell_col, A.ell_val, tk[h], add);
-    else
-      row_entries<12>(A.app_rp, A.app_col, A.app_val, tk[h], add);
+    if (A.ell_col) {
+      // the row's first table probes as one batch of LDS reads, then the reads of g~ at
+      // the entries found; the sum runs in the row's order
+      const int r = tk[h];
+      const int4 *pc = reinterpret_cast<const int4 *>(A.ell_col + (size_t)r * ELL_W);
+      const double2 *pv = reinterpret_cast<const double2 *>(A.ell_val + (size_t)r * ELL_W);
+      int cc[ELL_W], kk[ELL_W], sl[ELL_W];
+      double vv[ELL_W];
+      T xv[ELL_W];
+#pragma unroll
+      for (int u = 0; u < ELL_W / 4; ++u) {
+        const int4 w = pc[u];
+        cc[4 * u] = w.x;
+        cc[4 * u + 1] = w.y;
+        cc[4 * u + 2] = w.z;
+        cc[4 * u + 3] = w.w;
+      }
+#pragma unroll
+      for (int u = 0; u < ELL_W / 2; ++u) {
+        const double2 w = pv[u];
+        vv[2 * u] = w.x;
+        vv[2 * u + 1] = w.y;
+      }
+#pragma unroll
+      for (int u = 0; u < ELL_W; ++u) kk[u] = gk[hslot<GH>(cc[u])];
+#pragma unroll
+      for (int u = 0; u < ELL_W; ++u)
+        sl[u] = cc[u] >= 0 ? h_resolve<GH>(gk, cc[u], hslot<GH>(cc[u]), kk[u]) : -1;
+#pragma unroll
+      for (int u = 0; u < ELL_W; ++u) xv[u] = gv[sl[u] >= 0 ? sl[u] : 0];
+#pragma unroll
+      for (int u = 0; u < ELL_W; ++u)
+        if (sl[u] >= 0) acc += (T)vv[u] * xv[u];
+    } else {
+      row_entries<12>(A.app_rp, A.app_col, A.app_val, tk[h], [&](int col, double v) EDFA_INLINE {
+        const int s = h_find<GH>(gk, col);
+        if (s >= 0) acc += (T)v * gv[s];
+      });
+    }
     tv[h] = acc;
   }
   // candidate cells: all l with F~[j, l] != 0 for j in the support of t

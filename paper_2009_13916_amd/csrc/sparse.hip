@@ -341,9 +341,22 @@ __global__ void k_sell_fill(const int *__restrict__ rowptr, const int *__restric
   const int a = rowptr[r], n = rowptr[r + 1] - a;
   const int base = sptr[p >> 6] + (p & 63);
   rlen[p] = n;
-  for (int k = 0; k < n; ++k) {
-    scol[base + 64 * k] = col[a + k];
-    sval[base + 64 * k] = val[a + k];
+  // eight entries of the row in flight at once (clamped reads, guarded stores)
+  for (int k0 = 0; k0 < n; k0 += 8) {
+    int c[8];
+    V v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int k = min(k0 + u, n - 1);
+      c[u] = col[a + k];
+      v[u] = val[a + k];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (k0 + u < n) {
+        scol[base + 64 * (k0 + u)] = c[u];
+        sval[base + 64 * (k0 + u)] = v[u];
+      }
   }
 }
 

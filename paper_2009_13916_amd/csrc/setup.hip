@@ -82,7 +82,7 @@ __device__ inline int pidx(int i, int j) { return i * (i + 1) / 2 + j; }   // pa
 
 #define EDFA_INLINE __attribute__((always_inline))
 
-// Visit the entries of CSR row r in blocks of RB: every index (and value) of a block is
+// Visit the column indices of CSR row r in blocks of RB: every index of a block is
 // requested before f runs on any of them, so a row's loads are in flight together instead
 // of one behind each hash lookup.  Positions past the row's end re-read its last entry
 // (always in bounds) and are not passed to f.
@@ -97,25 +97,6 @@ __device__ __forceinline__ void row_cols(const int *__restrict__ rp, const int *
 #pragma unroll
     for (int k = 0; k < RB; ++k)
       if (b + k < p1) f(c[k]);
-  }
-}
-
-template <int RB, class V, class F>
-__device__ __forceinline__ void row_entries(const int *__restrict__ rp, const int *__restrict__ col,
-                                            const V *__restrict__ val, int r, F &&f) {
-  const int p0 = rp[r], p1 = rp[r + 1];
-  for (int b = p0; b < p1; b += RB) {
-    int c[RB];
-    V v[RB];
-#pragma unroll
-    for (int k = 0; k < RB; ++k) {
-      const int p = min(b + k, p1 - 1);
-      c[k] = col[p];
-      v[k] = val[p];
-    }
-#pragma unroll
-    for (int k = 0; k < RB; ++k)
-      if (b + k < p1) f(c[k], v[k]);
   }
 }
 
@@ -1035,9 +1016,7 @@ struct HArgs {
   int ne;
   const int *g_rp, *g_col;
   const T *g_val;
-  const int *app_rp, *app_col;
-  const double *app_val;
-  const int *ell_col;   // A_pipi as ELL_W-entry rows, or null (then the CSR arrays)
+  const int *ell_col;   // A_pipi as ELL_W-entry rows
   const double *ell_val;
   const int *ff_rp, *ff_col;   // F~ by face rows (cells)
   const int *ft_rp, *ft_col;   // F~^T by cell rows (faces)
@@ -1099,12 +1078,7 @@ __global__ __launch_bounds__(64) void k_htilde(HArgs<T> A) {
       if (i < TL) tlist[i] = h;
     }
   };
-  for (int p = g0 + lane; p < g1; p += 64) {
-    if (A.ell_col)
-      ell_row(A.ell_col, nullptr, A.g_col[p], add_t);
-    else
-      row_cols<12>(A.app_rp, A.app_col, A.g_col[p], [&](int c) EDFA_INLINE { add_t(c, 0.0); });
-  }
+  for (int p = g0 + lane; p < g1; p += 64) ell_row(A.ell_col, nullptr, A.g_col[p], add_t);
   __syncthreads();
   if (A.retry_count && (sflag || tcount > TH / 2)) {
     retry();
@@ -1118,7 +1092,7 @@ __global__ __launch_bounds__(64) void k_htilde(HArgs<T> A) {
   for (int c = lane; c < nt; c += 64) {
     const int h = tlist[c];
     T acc = 0;
-    if (A.ell_col) {
+    {
       // the row's first table probes as one batch of LDS reads, then the reads of g~ at
       // the entries found; the sum runs in the row's order
       const int r = tk[h];
@@ -1151,11 +1125,6 @@ __global__ __launch_bounds__(64) void k_htilde(HArgs<T> A) {
 #pragma unroll
       for (int u = 0; u < ELL_W; ++u)
         if (sl[u] >= 0) acc += (T)vv[u] * xv[u];
-    } else {
-      row_entries<12>(A.app_rp, A.app_col, A.app_val, tk[h], [&](int col, double v) EDFA_INLINE {
-        const int s = h_find<GH>(gk, col);
-        if (s >= 0) acc += (T)v * gv[s];
-      });
     }
     tv[h] = acc;
   }
@@ -1426,17 +1395,19 @@ static void stage1_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
                      P.flags.p + 2);
   EDFA_CHECK_LAUNCH();
   const int maxbase = read_scalar(P.flags.p + 2, s);
-  // the register kernel reads A_pipi as ELL_W-entry rows; longer rows take the LDS kernel
+  // the register kernel and the rows of H~ read A_pipi as ELL_W-entry rows
   EDFA_HIP(hipMemsetAsync(P.flags.p + 2, 0, sizeof(int), s));
   hipLaunchKernelGGL(k_row_max, dim3(ceil_div(nfu, 256)), dim3(256), 0, s, S.Afp.rowptr.p, nfu,
                      P.flags.p + 2);
   EDFA_CHECK_LAUNCH();
-  const bool ell_ok = read_scalar(P.flags.p + 2, s) <= ELL_W;
-  const auto reg_stride = [&](int sm) { return sm > 0 && sm <= 48 && !ell_ok ? 64 : sm; };
+  const int afp_max = read_scalar(P.flags.p + 2, s);
+  if (afp_max > ELL_W)
+    fail(EDFA_ERR_CAPACITY, "a row of A_pipi has %d > %d entries (hexahedra give at most 11)",
+         afp_max, ELL_W);
   const bool dynamic = prm.variant == EDFA_DYNAMIC;
   int need = maxbase;
   if (dynamic) need = maxbase + std::max(0, prm.n_ent);
-  int smax = reg_stride(pattern_stride(need));
+  int smax = pattern_stride(need);
   if (!smax && (dynamic || prm.static_level == 0))
     fail(EDFA_ERR_CAPACITY, "patterns of up to %d entries exceed 128", need);
   D.qlen.ensure(ne);
@@ -1457,7 +1428,6 @@ static void stage1_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
     need = read_scalar(P.flags.p + 2, s);
     smax = pattern_stride(need);
     if (!smax) fail(EDFA_ERR_CAPACITY, "static patches of %d entries exceed 128", need);
-    smax = reg_stride(smax);
     D.Q.ensure((size_t)ne * smax);
     hipLaunchKernelGGL(k_repack, dim3(ceil_div(ne, 256)), dim3(256), 0, s, D.wide.p, D.qlen.p, ne,
                        PATCH_MAX, smax, D.Q.p);
@@ -1477,7 +1447,7 @@ static void stage1_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
   la.app_val = S.Afp.val.p;
   la.ell_col = nullptr;
   la.ell_val = nullptr;
-  if (ell_ok && nfu > 0) {   // the register kernel and the rows of H~ read it
+  if (nfu > 0) {
     D.ell_col.ensure((size_t)nfu * ELL_W);
     D.ell_val.ensure((size_t)nfu * ELL_W);
     hipLaunchKernelGGL(k_ell_fill, dim3(ceil_div((long long)nfu * ELL_W, 256)), dim3(256), 0, s,
@@ -1547,9 +1517,6 @@ static void stage1_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
   ha.g_rp = D.G.rowptr.p;
   ha.g_col = D.G.col.p;
   ha.g_val = D.G.val.p;
-  ha.app_rp = S.Afp.rowptr.p;
-  ha.app_col = S.Afp.col.p;
-  ha.app_val = S.Afp.val.p;
   ha.ell_col = la.ell_col;
   ha.ell_val = la.ell_val;
   ha.ff_rp = D.Fface.rowptr.p;

@@ -287,8 +287,8 @@ def main():
                          "preconditioner applications")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is "
-              "described in DESIGN.md but not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the solver does not "
+              "shard a system over several GPUs.", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2009_13916_amd import edfa, inputs

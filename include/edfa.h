@@ -162,8 +162,11 @@ typedef struct {
   int64_t nnz_G, nnz_F, nnz_H, nnz_S, nnz_GF, nnz_L, nnz_U, nnz_ML, nnz_MU;
   int32_t n_colors;
   int32_t max_pattern;      /* largest |Q^(m)| */
-  double  mu;               /* preconditioner density of Section 4 (nnz of the inner
-                               inverses counted as stored: 2 nnz(G_F), L, U and the ISAI) */
+  double  mu;               /* preconditioner density of Section 4, nnz() counting what the
+                               application stores and reads: 2 nnz(G_F) for A~_pipi^-1, the
+                               coupling blocks, and for S~^-1 nnz(M_L) + nnz(M_U) (plus
+                               nnz(L) + nnz(U) when isai_steps > 1) or nnz(L) + nnz(U) with
+                               exact substitution */
   double  t_stage1_ms, t_stage2_ms;   /* device time of the last setup */
 } edfa_precond_info;
 

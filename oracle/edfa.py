@@ -47,6 +47,10 @@ exact G, F, S and a one-step solve; exact factor identities G = C - F^T and S
 symmetric SPD; ILU(0) defining property; FSAI defining property; colouring
 validity and agreement with a brute-force greedy; homogeneous media give
 translation-invariant dynamic patterns (Test 1 discussion).
+tests/test_oracle_pins.py: dynamic selection against a dense brute-force
+prolonged residual per sweep, selection tie and rounding rules, pre-filtration
+thresholds, Patch(k) face counts by hand and by a face-graph search, density
+mu counted by hand on a one-cell grid.
 """
 from __future__ import annotations
 
@@ -191,6 +195,7 @@ class CellResult:
     g: np.ndarray
     f: np.ndarray
     sweeps: int = 0
+    added: tuple = ()       # number of indices appended by each dynamic sweep
 
 
 def local_cell(s: System, m, prm: Params, base_rows=None) -> CellResult:
@@ -214,6 +219,7 @@ def local_cell(s: System, m, prm: Params, base_rows=None) -> CellResult:
     r_idx, r_val = prolonged_residual(s, a_idx, a_val, Q, g)
     it_max = prm.n_ent if prm.it_max is None else prm.it_max
     n_prog, k = 0, 0
+    added = []
     while n_prog < prm.n_ent and k < it_max:
         k += 1
         n = min(prm.n_add, prm.n_ent - n_prog)
@@ -221,11 +227,12 @@ def local_cell(s: System, m, prm: Params, base_rows=None) -> CellResult:
         if new.size == 0:
             break
         Q = np.concatenate([Q, new])
+        added.append(int(new.size))
         n_prog += new.size
         g = _chol_solve(restricted_matrix(s, Q), rhs_g(Q), m)
         r_idx, r_val = prolonged_residual(s, a_idx, a_val, Q, g)
     f = _chol_solve(restricted_matrix(s, Q), rhs_f(Q), m)
-    return CellResult(Q, g, f, k)
+    return CellResult(Q, g, f, k, tuple(added))
 
 
 @dataclass
@@ -576,11 +583,22 @@ class Edfa:
         return np.concatenate([z_pi, z_p])
 
     def density(self):
-        """mu of the paper (preconditioner density), with nnz(A~^-1) = nnz(G_F) + nnz(G_F^T)."""
+        """Preconditioner density mu (Section 4).
+
+        nnz() counts the entries stored for the application: the FSAI factor and its
+        transpose for A~_pipi^-1, the two coupling blocks, and for S~^-1 the matrices the
+        triangular solves read: M_L and M_U (ISAI, one step), plus the factors L and U when
+        refinement steps use them, or L and U alone (exact substitution).
+        """
         s = self.sys
-        num = 2 * self.st1.GF.nnz + s.Apc.nnz + s.Acp.nnz + self.st2.L.nnz + self.st2.U.nnz
+        st2 = self.st2
         if self.prm.schur == "isai":
-            num += self.st2.ML.nnz + self.st2.MU.nnz
+            ns = st2.ML.nnz + st2.MU.nnz
+            if self.prm.isai_steps > 1:
+                ns += st2.L.nnz + st2.U.nnz
+        else:
+            ns = st2.L.nnz + st2.U.nnz
+        num = 2 * self.st1.GF.nnz + s.Apc.nnz + s.Acp.nnz + ns
         den = s.App.nnz + s.Apc.nnz + s.Acp.nnz + s.Acc.nnz
         return num / den
 

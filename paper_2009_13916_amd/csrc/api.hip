@@ -216,9 +216,13 @@ static void fill_info(edfa_precond_s &P, PrecData<T> &D, edfa_precond_info *info
   info->nnz_MU = isai ? D.MU.nnz : 0;
   info->n_colors = P.n_colors;
   info->max_pattern = P.max_pattern;
+  // mu of Section 4 with nnz() counting what the application stores and reads: G_F and
+  // G_F^T for A~_pipi^-1, the coupling blocks, and for S~^-1 the approximate inverses M_L,
+  // M_U (plus L and U when refinement steps multiply by them) or L and U (substitution)
   const double den = (double)(S.Afp.nnz + S.Afc.nnz + S.Acf.nnz + S.Acc.nnz);
-  const double num = 2.0 * D.GF.nnz + S.Afc.nnz + S.Acf.nnz + D.L.nnz + D.U.nnz +
-                     (isai ? (double)(D.ML.nnz + D.MU.nnz) : 0.0);
+  double ns = (double)(D.L.nnz + D.U.nnz);
+  if (isai) ns = (double)(D.ML.nnz + D.MU.nnz) + (P.prm.isai_steps > 1 ? ns : 0.0);
+  const double num = 2.0 * D.GF.nnz + S.Afc.nnz + S.Acf.nnz + ns;
   info->mu = den > 0 ? num / den : 0.0;
   info->t_stage1_ms = P.t_stage1_ms;
   info->t_stage2_ms = P.t_stage2_ms;

@@ -324,10 +324,42 @@ def fsai(s: System):
     return GF
 
 
-def stage1(s: System, prm: Params, base_rows=None) -> Stage1:
+# ----------------------------------------------------------------------------
+# Independent per-cell work over a process pool: the restricted solves of
+# Algorithm 1 are independent by construction (Remark 5), as the paper's parfor uses.
+# The pool only distributes calls; every call is the serial function unchanged.
+# ----------------------------------------------------------------------------
+_POOL_CTX = None
+
+
+def _pool_init(ctx):
+    global _POOL_CTX
+    _POOL_CTX = ctx
+
+
+def _pool_cells(rng):
+    s, prm, base_rows = _POOL_CTX
+    return [local_cell(s, m, prm, base_rows) for m in range(*rng)]
+
+
+def _pool_map(fn, ctx, n, workers):
+    """[fn over ranges of [0, n)] concatenated in order; serial when workers <= 1 or when the
+    work is too small to pay for starting the pool."""
+    if workers <= 1 or n < 2000:
+        _pool_init(ctx)
+        return fn((0, n))
+    import multiprocessing as mp
+    step = -(-n // (4 * workers))
+    ranges = [(a, min(a + step, n)) for a in range(0, n, step)]
+    with mp.get_context("spawn").Pool(workers, initializer=_pool_init, initargs=(ctx,)) as pool:
+        parts = pool.map(fn, ranges)
+    return [x for part in parts for x in part]
+
+
+def stage1(s: System, prm: Params, base_rows=None, workers=1) -> Stage1:
     _ensure_apct(s)
     ne, nfu = s.ne, s.nfu
-    res = [local_cell(s, m, prm, base_rows) for m in range(ne)]
+    res = _pool_map(_pool_cells, (s, prm, base_rows), ne, workers)
     gr, gc, gv, fr, fc, fv = [], [], [], [], [], []
     for m, cr in enumerate(res):
         kg = filter_keep(cr.g, prm.tau) if prm.filt == "pre" else np.ones(len(cr.Q), bool)
@@ -411,6 +443,14 @@ def unit_lower(L: sp.csr_matrix):
     return M
 
 
+def _isai_row(T: sp.csr_matrix, i):
+    P = T.indices[T.indptr[i]:T.indptr[i + 1]]
+    sub = T[P][:, P].toarray()
+    e = np.zeros(len(P))
+    e[np.searchsorted(P, i)] = 1.0
+    return P, np.linalg.solve(sub.T, e)
+
+
 def isai(T: sp.csr_matrix):
     """Incomplete sparse approximate inverse of a triangular factor on its own pattern.
 
@@ -421,11 +461,7 @@ def isai(T: sp.csr_matrix):
     T.sort_indices()
     rows, cols, vals = [], [], []
     for i in range(T.shape[0]):
-        P = T.indices[T.indptr[i]:T.indptr[i + 1]]
-        sub = T[P][:, P].toarray()
-        e = np.zeros(len(P))
-        e[np.searchsorted(P, i)] = 1.0
-        m = np.linalg.solve(sub.T, e)
+        P, m = _isai_row(T, i)
         rows.append(np.full(len(P), i)); cols.append(P); vals.append(m)
     M = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                       shape=T.shape)
@@ -603,7 +639,9 @@ class Edfa:
         return num / den
 
 
-def build(s: System, prm: Params) -> Edfa:
-    st1 = stage1(s, prm)
+def build(s: System, prm: Params, workers=1) -> Edfa:
+    """Stage 1 and stage 2; workers > 1 spreads the per-cell solves of stage 1 over a
+    process pool (same results)."""
+    st1 = stage1(s, prm, workers=workers)
     st2 = stage2(s, st1, prm)
     return Edfa(s, prm, st1, st2)

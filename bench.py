@@ -10,9 +10,13 @@ device before timing (assembly is not part of the metric).
 One step = EDFA stage 1 + stage 2 (dynamic patterns, n_add = 1, n_ent = 6,
 post-filtration on H~ with tau = 1e-3) followed by right-preconditioned GMRES(50)
 from x0 = 0 to a true relative residual <= 1e-8.  The launch-shape autotuner runs once
-per preconditioner before the timed steps (its choices persist across re-setups).  ``value`` is the mean wall time of
-one step in seconds for the FP64 path; the FP32-preconditioner / FP64 flexible GMRES
-form is timed the same way and reported under ``forms``.
+per preconditioner before the timed steps (its choices persist across re-setups).
+``value`` is the mean wall time of one step in seconds for the FP64 path.  ``forms``
+holds the same step with the FP32 preconditioner inside FP64 flexible GMRES and with
+Bi-CGStab (the paper's solver), the 256-grid batch, and the 128x128x64 distorted-channel
+sequence of 10 steps with dt doubling from 1e-3 (FP64 and mixed; stage-2 refresh per step
+and full re-setup per step).  ``roofline`` is the dominant sparse-product kernel of the
+64^3 step, timed live with HIP events inside the solve; ``families`` lists every product.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -57,21 +61,23 @@ def print_tune_report(rep, tag):
               file=sys.stderr, flush=True)
 
 
-def run_form(edfa, S, b, prm, steps, warmup, flexible):
+def run_form(edfa, S, b, prm, steps, warmup, flexible, method="gmres", P=None):
     import torch
-    P = edfa.Precond(S, prm)
+    if P is None:
+        P = edfa.Precond(S, prm)
     # one-off choice of SpMV launch shapes, kept across the timed re-setups
     rep = P.autotune(report=True)
-    print_tune_report(rep, "fp32" if prm.precision == 1 else "fp64")
+    print_tune_report(rep, ("fp32" if prm.precision == 1 else "fp64") + f" {method}")
+    kw = dict(rtol=1e-8, restart=50, flexible=flexible, method=method, max_iter=5000)
     for _ in range(warmup):
         P.resetup()
-        edfa.solve(S, P, b, rtol=1e-8, restart=50, flexible=flexible)
+        edfa.solve(S, P, b, **kw)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos, pinfos = [], []
     for k in range(steps):
         P.resetup()
-        x, info, st = edfa.solve(S, P, b, rtol=1e-8, restart=50, flexible=flexible, profile=True)
+        x, info, st = edfa.solve(S, P, b, profile=True, **kw)
         infos.append((info, st))
         pinfos.append(P.info())
     torch.cuda.synchronize()
@@ -79,13 +85,15 @@ def run_form(edfa, S, b, prm, steps, warmup, flexible):
     return (t1 - t0) / steps, infos, pinfos, x, rep
 
 
-def kernel_label(variant):
-    """Kernel (as traces name it) that runs the system-matrix product for a tuner choice."""
+def kernel_label(variant, what="the system matrix", role=0):
+    """Kernel (as traces name it) that runs a product for a tuner choice."""
     kind, depth = variant.split("/")
     if kind == "sell":
-        return f"k_spmv_sell<double, double, 0, {depth}>: SELL-64 SpMV with the system matrix"
-    return (f"k_spmv_csr_vec<double, double, {kind[3:]}, {depth}>: CSR SpMV with the system "
-            f"matrix, {kind[3:]} lanes per row")
+        return f"k_spmv_sell<double, double, {role}, {depth}>: SELL-64 SpMV with {what}"
+    if kind == "chunk":
+        return f"k_spmv_chunk<double, double, {depth}>: row-chunk SpMV with {what}"
+    return (f"k_spmv_csr_vec<double, double, {kind[3:]}, {depth}>: CSR SpMV with {what}, "
+            f"{kind[3:]} lanes per row")
 
 
 def run_batched(edfa, inputs, steps, warmup):
@@ -151,98 +159,114 @@ def run_batched(edfa, inputs, steps, warmup):
 
 
 def run_transient(edfa, inputs, nsteps=10):
-    """128x128x64 distorted hexahedra with binary channels (contrast 1e6, 30% volume); dt
-    doubles from 1e-3 for `nsteps` steps with p_n = the previous step's pressure.  The
+    """128x128x64 distorted hexahedra with binary channels (contrast 1e6, 30% volume): a
+    sequence of `nsteps` steps with dt doubling from 1e-3 (eq. delta_t_dyn with dt_mult = 2
+    and no pressure goal), p_n the previous step's pressure, through edfa_transient.  The
     preconditioner is refreshed by stage 2 only (stage 1 does not depend on dt) or rebuilt
-    fully; FP64 and the FP32-preconditioner FGMRES form.  Times are whole sequences."""
+    fully every step; FP64 GMRES and the FP32-preconditioner FGMRES form.  Times are whole
+    sequences (setup included); chi_inf per step and its mean are reported."""
     import torch
     prob = inputs.channel_problem(128, 128, 64, contrast=1e6, perturb=0.2, dt=1e-3)
-    out = {"workload": "channels_distorted_128x128x64", "steps": nsteps}
-    for name, prm, flex in (("fp64", edfa.Params("dynamic", n_add=1, n_ent=6, tau=1e-3,
-                                                 filt="post_H"), False),
-                            ("mixed", edfa.Params("dynamic", n_add=1, n_ent=6, tau=1e-3,
-                                                  filt="post_H", precision=1), True)):
-        for refresh in ("stage2", "full"):
+    out = {"workload": "channels_distorted_128x128x64", "cells": prob.n_cells, "steps": nsteps,
+           "channel_fraction": prob.meta.get("channel_fraction")}
+    for name, prec, flex in (("fp64", 0, False), ("mixed", 1, True)):
+        prm = edfa.Params("dynamic", n_add=1, n_ent=6, tau=1e-3, filt="post_H", precision=prec)
+        for refresh, every in (("stage2", 0), ("full", 1)):
             S = edfa.System(prob)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             P = edfa.Precond(S, prm)
-            iters, ok = [], 0
-            for k in range(nsteps):
-                if k > 0:
-                    S.update_dt(1e-3 * 2.0 ** k, p_prev)
-                    if refresh == "stage2":
-                        P.stage2()
-                    else:
-                        P.resetup()
-                x, info, st = edfa.solve(S, P, S.rhs(), rtol=1e-8, restart=50, flexible=flex)
-                p_prev = x[S.info["nfu"]:].clone()
-                iters.append(info["iterations"])
-                ok += int(st == 0)
+            u, steps, st = edfa.transient(S, P, n_steps=nsteps, dt0=1e-3, dt_mult=2.0,
+                                          porosity=inputs.PHI, stage1_every=every,
+                                          flexible=flex)
             torch.cuda.synchronize()
             t = time.perf_counter() - t0
-            log(f"transient {name} refresh={refresh}: {t:.3f} s for {nsteps} steps, "
+            iters = [r["iterations"] for r in steps]
+            chi = [r["chi_inf"] for r in steps]
+            log(f"transient {name} refresh={refresh}: {t:.3f} s for {len(steps)} steps, "
                 f"iterations {iters}")
-            out[f"{name}_{refresh}"] = {"s": t, "iterations": iters, "converged_steps": ok}
+            out[f"{name}_{refresh}"] = {
+                "s": t, "iterations": iters, "converged_steps": sum(r["converged"] for r in steps),
+                "dt": [r["dt"] for r in steps], "chi_inf": chi,
+                "chi_inf_mean": sum(chi) / len(chi) if chi else 0.0,
+                "setup_ms": [round(r["t_setup_ms"], 3) for r in steps],
+                "solve_ms": [round(r["t_solve_ms"], 3) for r in steps]}
             del P, S
     return out
 
 
-def cpu_baseline(iters_gpu, n_full, ne_full):
-    """Time the oracle on a bounded sample: the whole oracle pipeline on the 12^3 member
-    of the same workload family, scaled to 64^3 (setup per cell, solve per iteration and
-    unknown, at the GPU's iteration count).  Runs single-threaded in a child process."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(iters_gpu, n_full, ne_full, n_sample=16):
+    """Time the oracle on a bounded sample of the workload family: the whole oracle pipeline
+    on the n_sample^3 member (same field statistics, correlation length scaled with the
+    grid), with the per-cell restricted solves of stage 1 spread over every core this
+    process may run on (a process pool, the paper's parfor); stage 2 and GMRES as the oracle
+    runs them.  The measured rates are scaled to the 64^3 step: setup per cell, solve per
+    iteration and unknown at the GPU iteration count."""
+    cores = len(os.sched_getaffinity(0))
     code = r"""
 import json, sys, time
 sys.path.insert(0, %r)
 from paper_2009_13916_amd import inputs
 from oracle import edfa, krylov, mhfe
-p = inputs.full_tensor_problem(12, sigma=2.0, corr=8.0 * 12 / 64)
-s = mhfe.assemble(p)
-prm = edfa.Params("dynamic", n_add=1, n_ent=6, tau=1e-3, filt="post_H")
-t0 = time.perf_counter(); st1 = edfa.stage1(s, prm); t1 = time.perf_counter()
-st2 = edfa.stage2(s, st1, prm); t2 = time.perf_counter()
-E = edfa.Edfa(s, prm, st1, st2); A = s.matrix()
-t3 = time.perf_counter(); r = krylov.gmres(lambda v: A @ v, E.apply, s.b, 1e-8, 50); t4 = time.perf_counter()
-print(json.dumps({"setup": t2 - t0, "solve": t4 - t3, "iters": r.iterations, "n": s.n, "ne": s.ne}))
-""" % ROOT
-    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
-    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
-                         timeout=600)
+if __name__ == "__main__":
+    n = %d
+    p = inputs.full_tensor_problem(n, sigma=2.0, corr=8.0 * n / 64)
+    s = mhfe.assemble(p)
+    prm = edfa.Params("dynamic", n_add=1, n_ent=6, tau=1e-3, filt="post_H")
+    t0 = time.perf_counter(); st1 = edfa.stage1(s, prm, workers=%d); t1 = time.perf_counter()
+    st2 = edfa.stage2(s, st1, prm); t2 = time.perf_counter()
+    E = edfa.Edfa(s, prm, st1, st2); A = s.matrix()
+    t3 = time.perf_counter(); r = krylov.gmres(lambda v: A @ v, E.apply, s.b, 1e-8, 50); t4 = time.perf_counter()
+    print(json.dumps({"stage1": t1 - t0, "stage2": t2 - t1, "solve": t4 - t3,
+                      "iters": r.iterations, "n": s.n, "ne": s.ne}))
+""" % (ROOT, n_sample, cores)
+    path = os.path.join("/tmp", f"edfa_cpu_baseline_{os.getpid()}.py")
+    with open(path, "w") as f:
+        f.write(code)
+    try:
+        out = subprocess.run([sys.executable, path], capture_output=True, text=True, timeout=900)
+    finally:
+        os.unlink(path)
     if out.returncode != 0:
         log("cpu baseline failed: " + out.stderr[-500:])
         return None
     d = json.loads(out.stdout.strip().splitlines()[-1])
-    setup = d["setup"] * ne_full / d["ne"]
+    setup = (d["stage1"] + d["stage2"]) * ne_full / d["ne"]
     solve = d["solve"] / (d["iters"] * d["n"]) * iters_gpu * n_full
-    return {"value": setup + solve, "unit": "s", "cores": 1, "kind": "oracle",
-            "sample": (f"full oracle pipeline on the 12^3 member of the workload family "
-                       f"({d['ne']} cells, setup {d['setup']:.2f} s, {d['iters']} GMRES iterations "
-                       f"in {d['solve']:.2f} s), setup scaled per cell and solve per iteration and "
-                       f"unknown to 64^3 at the GPU iteration count ({iters_gpu})")}
+    return {"value": setup + solve, "unit": "s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": (f"oracle pipeline on the {n_sample}^3 member of the workload family "
+                       f"({d['ne']} cells; stage 1 {d['stage1']:.2f} s over a pool of {cores} "
+                       f"processes, stage 2 {d['stage2']:.2f} s and {d['iters']} GMRES "
+                       f"iterations in {d['solve']:.2f} s in one process), setup scaled per "
+                       f"cell and solve per iteration and unknown to 64^3 at the GPU iteration "
+                       f"count ({iters_gpu})")}
 
 
 COPY_BYTES = 1 << 30   # bytes read (and written) by the calibration copy
+TRAFFIC = os.path.join(ROOT, "profiles", "spmv_kernels_full_tensor_64cubed_traffic.md")
 
 
-def probe_spmv(torch, S, b):
-    """Launches counted by the FETCH_SIZE / WRITE_SIZE passes: 20 products with the
-    system matrix, then one device copy of COPY_BYTES (reads and writes COPY_BYTES)."""
-    for _ in range(20):
-        S.spmv(b)
-    src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
-    dst = torch.empty_like(src)
-    torch.cuda.synchronize()
-    dst.copy_(src)
-    torch.cuda.synchronize()
-    nnz, N = S.info["nnz"], S.info["n"]
-    print(json.dumps({"probe": "spmv", "launches": 20, "spmv_bytes": spmv_bytes(nnz, N),
-                      "copy_bytes": COPY_BYTES, "kernel_sha": spmv_kernel_sha()}), flush=True)
+def slot_bytes(r):
+    """Algorithmic bytes of one product with a tuned matrix (values and indices once, row
+    pointers once, x and y once)."""
+    vb = r["value_bytes"]
+    return (4 + vb) * r["nnz"] + 4 * (r["rows"] + 1) + vb * (r["cols"] + r["rows"])
 
 
 def spmv_kernel_sha():
-    """SHA-256 of the source of the SpMV kernels (SELL and CSR): a traffic figure measured
-    on another version of them is not reported."""
+    """SHA-256 of the source of the sparse-product kernels (SELL, CSR and chunk kernels): a
+    traffic figure measured on another version of them is not reported."""
     import hashlib
     src = open(os.path.join(ROOT, "paper_2009_13916_amd", "csrc", "sparse.hip")).read()
     a = src.index("void k_spmv_sell(")
@@ -250,13 +274,12 @@ def spmv_kernel_sha():
     return hashlib.sha256(src[a:e].encode()).hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per system-SpMV launch from the committed PMC summary, or None when it
-    is absent or was taken on another version of the kernel."""
-    path = os.path.join(ROOT, "profiles", "spmv_sell_operator_full_tensor_64cubed_traffic.md")
-    if not os.path.exists(path):
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` (its trace name) from the committed PMC summary, or
+    None when absent or taken on another version of the kernels."""
+    if not os.path.exists(TRAFFIC):
         return None
-    txt = open(path).read()
+    txt = open(TRAFFIC).read()
     try:
         blob = txt[txt.index("```json") + 7:]
         d = json.loads(blob[:blob.index("```")])
@@ -264,7 +287,63 @@ def measured_traffic():
         return None
     if d.get("kernel_sha") != spmv_kernel_sha():
         return None
-    return d.get("hbm_bytes_per_launch")
+    return d.get("kernels", {}).get(kernel, {}).get("hbm_bytes_per_launch")
+
+
+def probe(torch, edfa, S, b, what):
+    """Launches counted by the FETCH_SIZE / WRITE_SIZE passes.  'spmv': 20 products with the
+    system matrix; 'apply': the workload's preconditioner (autotuned as in the timed steps)
+    and 20 applications.  Then one device copy of COPY_BYTES (reads and writes COPY_BYTES)
+    that calibrates the counters.  Prints the algorithmic bytes of every product."""
+    rec = {"probe": what, "launches": 20, "copy_bytes": COPY_BYTES, "kernel_sha": spmv_kernel_sha()}
+    if what == "spmv":
+        for _ in range(20):
+            S.spmv(b)
+        rec["products"] = {"A": {"bytes": spmv_bytes(S.info["nnz"], S.info["n"]),
+                                 "kernel": "k_spmv_sell<double, double, 0, 4>"}}
+    else:
+        P = edfa.Precond(S, edfa.Params("dynamic", n_add=1, n_ent=6, tau=1e-3, filt="post_H"))
+        rep = P.autotune(report=True)
+        torch.cuda.synchronize()
+        for _ in range(20):
+            P.apply(b)
+        rec["products"] = {k: {"bytes": slot_bytes(r), "rows": r["rows"],
+                               "kernel": kernel_label(r["variant"], k, 0 if k in ("A", "A^T") else 1)
+                               .split(":")[0]}
+                           for k, r in rep.items()}
+    src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps(rec), flush=True)
+
+
+def families(info, rep, apply_count):
+    """Per matrix of a profiled solve: its kernel, algorithmic bytes, mean launch time (HIP
+    events on the solve stream), rate and fraction of peak, and time per step; per kernel
+    symbol: the totals.  Returns (per-matrix list, per-kernel dict)."""
+    rows, kern = [], {}
+    for name, ms in info["slot_ms"].items():
+        if name not in rep:
+            continue
+        r = rep[name]
+        n = info["slot_launches"][name]
+        by = slot_bytes(r)
+        label = kernel_label(r["variant"], name, 0 if name in ("A", "A^T") else 1)
+        sym = label.split(":")[0]
+        gbs = by / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+        rows.append({"matrix": name, "kernel": sym, "bytes_per_launch": by,
+                     "avg_launch_us": round(ms * 1e3, 2), "launches": n,
+                     "per_apply": round(n / apply_count, 3) if apply_count else None,
+                     "GB_s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "ms_per_step": round(ms * n, 3)})
+        k = kern.setdefault(sym, {"bytes": 0.0, "ms": 0.0, "launches": 0, "matrices": []})
+        k["bytes"] += by * n
+        k["ms"] += ms * n
+        k["launches"] += n
+        k["matrices"].append(name)
+    return rows, kern
 
 
 def main():
@@ -275,16 +354,18 @@ def main():
     ap.add_argument("--n", type=int, default=64, help="grid side (64 = the benchmark workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--no-batched", action="store_true",
-                    help="skip the 256-grid batch forms")
+    ap.add_argument("--no-bicgstab", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 256-grid batch forms")
+    ap.add_argument("--no-transient", action="store_true",
+                    help="skip the 128x128x64 ten-step sequence")
     ap.add_argument("--batched-only", action="store_true",
                     help="diagnostic: run only the 256-grid batch forms and print their record")
-    ap.add_argument("--transient", action="store_true",
-                    help="diagnostic: run only the 128x128x64 ten-step transient sequence")
+    ap.add_argument("--transient-only", action="store_true",
+                    help="diagnostic: run only the 128x128x64 ten-step sequence")
     ap.add_argument("--probe", choices=["spmv", "apply"], default=None,
                     help="run only the launches that PMC passes count: 'spmv' = 20 system "
-                         "SpMVs and one plain copy of known size; 'apply' = setup and 20 "
-                         "preconditioner applications")
+                         "products, 'apply' = setup and 20 preconditioner applications; "
+                         "each then one plain copy of known size")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the solver does not "
@@ -294,7 +375,7 @@ def main():
     from paper_2009_13916_amd import edfa, inputs
     edfa.load()
     torch.cuda.set_device(0)
-    if args.transient:
+    if args.transient_only:
         print(json.dumps({"forms": {"transient_128x128x64": run_transient(edfa, inputs)}}),
               flush=True)
         return
@@ -308,15 +389,8 @@ def main():
     S = edfa.System(prob)
     b = S.rhs()
     torch.cuda.synchronize()
-    if args.probe == "spmv":
-        probe_spmv(torch, S, b)
-        return
-    if args.probe == "apply":
-        P = edfa.Precond(S, edfa.Params("dynamic", n_add=1, n_ent=6, tau=1e-3, filt="post_H"))
-        for _ in range(20):
-            P.apply(b)
-        torch.cuda.synchronize()
-        print(json.dumps({"probe": "apply", "launches": 20, **P.info()}), flush=True)
+    if args.probe:
+        probe(torch, edfa, S, b, args.probe)
         return
     nnz, N, ne = S.info["nnz"], S.info["n"], S.info["ne"]
     log(f"assembled: N={N} nnz={nnz}")
@@ -324,13 +398,15 @@ def main():
     t64, infos, pinfos, x, rep64 = run_form(edfa, S, b, prm, args.steps, args.warmup,
                                             flexible=False)
     info, st = infos[-1]
+    pi = pinfos[-1]
     log(f"fp64: {t64:.4f} s/step, {info['iterations']} iterations, relres {info['relres_true']:.2e}")
-    log("preconditioner: " + ", ".join(f"{k} {v}" for k, v in pinfos[-1].items()))
+    log("preconditioner: " + ", ".join(f"{k} {v}" for k, v in pi.items()))
     forms = {"fp64": {"s_per_step": t64, "iterations": info["iterations"],
                       "relres_true": info["relres_true"], "converged": st == 0,
-                      "stage1_ms": pinfos[-1]["t_stage1_ms"], "stage2_ms": pinfos[-1]["t_stage2_ms"],
-                      "solve_ms": info["t_solve_ms"], "mu": pinfos[-1]["mu"],
-                      "colors": pinfos[-1]["n_colors"]}}
+                      "stage1_ms": pi["t_stage1_ms"], "stage2_ms": pi["t_stage2_ms"],
+                      "solve_ms": info["t_solve_ms"], "mu": pi["mu"], "colors": pi["n_colors"],
+                      "nnz_H_raw": pi["nnz_H_raw"], "nnz_H": pi["nnz_H"],
+                      "apply_avg_us": round(info["apply_avg_ms"] * 1e3, 2)}}
     if not args.no_mixed:
         prm32 = edfa.Params("dynamic", n_add=1, n_ent=6, tau=1e-3, filt="post_H", precision=1)
         t32, i32, p32, x32, _ = run_form(edfa, S, b, prm32, args.steps, args.warmup,
@@ -342,12 +418,36 @@ def main():
             "s_per_step": t32, "iterations": inf32["iterations"], "relres_true": inf32["relres_true"],
             "converged": st32 == 0, "stage1_ms": p32[-1]["t_stage1_ms"],
             "stage2_ms": p32[-1]["t_stage2_ms"], "solve_ms": inf32["t_solve_ms"],
+            "apply_avg_us": round(inf32["apply_avg_ms"] * 1e3, 2),
             "pressure_rel_diff_vs_fp64": float(dp)}
+    if not args.no_bicgstab:
+        tb, ib, pb, xb, _ = run_form(edfa, S, b, prm, args.steps, args.warmup, flexible=False,
+                                     method="bicgstab")
+        infb, stb = ib[-1]
+        dpb = (xb - x)[S.info["nfu"]:].norm() / x[S.info["nfu"]:].norm()
+        log(f"bicgstab: {tb:.4f} s/step, {infb['iterations']} iterations")
+        forms["fp64_bicgstab"] = {
+            "s_per_step": tb, "iterations": infb["iterations"], "relres_true": infb["relres_true"],
+            "converged": stb == 0, "solve_ms": infb["t_solve_ms"],
+            "pressure_rel_diff_vs_gmres": float(dpb)}
     if not args.no_batched:
         forms["batch_256"] = run_batched(edfa, inputs, args.steps, args.warmup)
+    if not args.no_transient:
+        forms["transient_128x128x64"] = run_transient(edfa, inputs)
+
+    # per-matrix product timings of the last profiled FP64 step and the dominant kernel
+    fam, kern = families(info, rep64, info["apply_count"])
+    dom = max(kern, key=lambda k: kern[k]["ms"])
+    K = kern[dom]
+    achieved = K["bytes"] / (K["ms"] * 1e-3) / 1e9
+    for f in sorted(fam, key=lambda r: -r["ms_per_step"]):
+        log(f"product {f['matrix']:8s} {f['kernel']:40s} {f['avg_launch_us']:8.2f} us "
+            f"{f['GB_s']:7.1f} GB/s ({f['frac']:.3f})  x{f['launches']}  {f['ms_per_step']:.2f} ms/step")
+    apply_bytes = sum(f["bytes_per_launch"] * f["launches"] for f in fam
+                      if f["matrix"] not in ("A", "A^T")) / max(1, info["apply_count"])
+    apply_gbs = apply_bytes / (info["apply_avg_ms"] * 1e-3) / 1e9 if info["apply_avg_ms"] else 0.0
     spmv_ms = info["spmv_avg_ms"]
     ab = spmv_bytes(nnz, N)
-    achieved = ab / (spmv_ms * 1e-3) / 1e9 if spmv_ms > 0 else 0.0
     out = {
         "metric": METRIC, "value": t64, "unit": "s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": t64 * 1e3, "higher_is_better": False,
@@ -357,12 +457,18 @@ def main():
                    "krylov": "GMRES(50), x0 = 0", "rtol": 1e-8},
         "iterations": info["iterations"], "relres_true": info["relres_true"],
         "forms": forms,
-        "roofline": {"bound": "hbm",
-                     "kernel": kernel_label(rep64["A"]["variant"]),
+        "roofline": {"bound": "hbm", "kernel": dom,
+                     "matrices": K["matrices"],
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "bytes_per_launch": ab, "avg_launch_ms": spmv_ms,
-                     "launches": info["spmv_count"]},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
+                     "bytes_per_launch": K["bytes"] / K["launches"],
+                     "avg_launch_ms": K["ms"] / K["launches"], "launches": K["launches"]},
+        "families": fam,
+        "apply": {"bytes": apply_bytes, "avg_us": round(info["apply_avg_ms"] * 1e3, 2),
+                  "GB_s": round(apply_gbs, 1), "frac": round(apply_gbs / HBM_PEAK_GBS, 4),
+                  "launches": info["apply_count"]},
+        "system_spmv": {"bytes": ab, "avg_us": round(spmv_ms * 1e3, 2),
+                        "GB_s": round(ab / (spmv_ms * 1e-3) / 1e9, 1) if spmv_ms else 0.0},
     }
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample")

@@ -109,8 +109,10 @@ typedef struct {
  *    the faces of each face neighbour coupled to the shared face.
  * count >= 1 grids (a batch is one block-diagonal system).  Input arrays are
  * read during the call only.  Synchronises the stream.
- * Errors: EDFA_ERR_ARG (sizes), EDFA_ERR_NOT_SPD (K or a Jacobian not
- * positive: cell index in the message), EDFA_ERR_NOMEM. */
+ * Errors: EDFA_ERR_ARG (sizes), EDFA_ERR_NAN (a non-finite entry in nodes, K, c,
+ * bc_value, p_prev or source, or a non-finite c_scalar: grid, array and index in the
+ * message), EDFA_ERR_NOT_SPD (K or a Jacobian not positive: cell index in the message),
+ * EDFA_ERR_NOMEM. */
 edfa_status edfa_assemble(const edfa_problem *grids /* (host) array */, int32_t count,
                           hipStream_t stream, edfa_system *out);
 void edfa_system_destroy(edfa_system sys);
@@ -155,6 +157,10 @@ typedef struct {
   int32_t precision;        /* 0: FP64 preconditioner; 1: FP32 setup and application */
   int32_t schur_solver;     /* EDFA_SCHUR_* */
   int32_t isai_steps;       /* ISAI applications per factor (>= 1) */
+  int32_t htilde_retry;     /* performance knob of the rows of H~ (patterns of up to 64): a
+                               row whose support of t = A_pipi R^T g~ exceeds this many faces
+                               is recomputed in a second pass with large hash tables (1..256;
+                               0: 256, half the small table); results do not depend on it */
 } edfa_params;
 
 /* Preconditioner sizes and diagnostics (host struct). */
@@ -168,6 +174,11 @@ typedef struct {
                                nnz(L) + nnz(U) when isai_steps > 1) or nnz(L) + nnz(U) with
                                exact substitution */
   double  t_stage1_ms, t_stage2_ms;   /* device time of the last setup */
+  int64_t nnz_H_raw;        /* entries of H~ before the post-filtration */
+  int32_t htilde_retry_rows;/* rows of H~ whose first pass (small hash tables) overflowed and
+                               were recomputed with large tables */
+  int32_t color_rounds;     /* parallel colouring rounds of the last stage 2 ... */
+  int32_t color_list_rounds;/* ... of which visited only a worklist of the uncoloured cells */
 } edfa_precond_info;
 
 /* Build the preconditioner: stage 1 (Algorithm 1: restricted SPD solves on static or
@@ -215,12 +226,18 @@ typedef struct {
   int32_t profile;          /* 1: time every launch of the dominant kernels with events
                                (eagerly run cycles only) */
   double  rtol;             /* stop when ||b - A x|| <= rtol ||b|| (x0 = 0, Section 4) */
+  int32_t method;           /* EDFA_GMRES (restart, flexible, use_graph apply) or
+                               EDFA_BICGSTAB (the paper's solver, Section 4; restart,
+                               flexible ignored, use_graph must be 0) */
 } edfa_solve_params;
+#define EDFA_GMRES    0
+#define EDFA_BICGSTAB 1
 
 typedef struct {
-  int32_t iterations;       /* max over grids of the total inner iterations */
+  int32_t iterations;       /* max over grids of the total inner iterations (Bi-CGStab: full
+                               iterations, each with two products and two applications) */
   int32_t converged;        /* number of grids converged */
-  int32_t cycles;
+  int32_t cycles;           /* GMRES restart cycles / Bi-CGStab (re)starts */
   double  relres_est;       /* max over grids of the Arnoldi estimate / ||b|| */
   double  relres_true;      /* max over grids of the FP64 ||b - A x|| / ||b|| */
   double  t_solve_ms;       /* device time of the solve */
@@ -228,15 +245,73 @@ typedef struct {
   int32_t spmv_count;
   double  apply_avg_ms;     /* profile = 1: mean duration of one preconditioner application */
   int32_t apply_count;
+  double  slot_ms[16];      /* profile = 1: mean duration of one product with each matrix,
+                               numbered as the slots of edfa_tune_slot (0 / 1: the system
+                               matrix or its transpose) */
+  int32_t slot_launches[16];/* profile = 1: products timed per slot */
 } edfa_solve_info;
 
-/* Solve A x = b (or A^T x = b) by restarted right-preconditioned GMRES, x0 = 0, each grid
- * of a batch to its own rtol.  b, x: N-vectors (x output only).  Synchronises the stream
- * once per restart cycle.  Returns EDFA_OK when every grid converged on its true FP64
- * residual, EDFA_NOT_CONVERGED otherwise (x = last iterate). */
+/* Solve A x = b (or A^T x = b), x0 = 0, each grid of a batch to its own rtol, with
+ *  - EDFA_GMRES: restarted right-preconditioned GMRES(restart) (flexible: FGMRES).
+ *    Synchronises the stream at the start of every restart cycle and, inside an eagerly
+ *    run cycle, after every 8 iterations (16 for a batch) to stop the cycle once every
+ *    grid has converged; a graph-replayed cycle synchronises only at its start.
+ *  - EDFA_BICGSTAB: right-preconditioned Bi-CGStab (Section 4: x0 = 0, exit on
+ *    ||r_k|| <= rtol ||r_0||).  Synchronises every 4 iterations; when every grid has
+ *    stopped, the true residual confirms convergence, and a grid whose recurrence drifted
+ *    or broke down restarts from its iterate with the shadow residual r^ = r.
+ * b, x: N-vectors (x output only).  Returns EDFA_OK when every grid converged on its
+ * true FP64 residual, EDFA_NOT_CONVERGED (the paper's "NC") when max_iter ends a grid
+ * first (x = last iterate).  Errors: EDFA_ERR_NAN (b has a non-finite entry: ||b|| is
+ * not finite; nothing is iterated), EDFA_ERR_ARG. */
 edfa_status edfa_solve(edfa_system sys, edfa_precond pre, const double *b, double *x,
                        const edfa_solve_params *prm /* (host) */, hipStream_t stream,
                        edfa_solve_info *info /* (host), may be NULL */);
+
+/* Transient sequence (Section 4).  Starting from the system's p_prev, each step
+ *  - sets dt (edfa_update_dt: A_pp's diagonal and f_p; the previous step's pressure becomes
+ *    p_prev), rebuilds stage 2 of `pre` on its recycled stage 1 (stage 1 depends only on
+ *    A_pipi, A_pip and A_ppi, which dt does not change; Section 3, implementation details)
+ *    and, when stage1_every > 0, stage 1 too on every stage1_every-th step (k = 0, k, 2k..);
+ *  - solves from x0 = 0 with `solve` (GMRES or Bi-CGStab);
+ *  - measures dp_max = max_E |p^E - p_prev^E| and the largest Courant number of
+ *    eq. CFL_number, chi_inf = max_E Q^E dt / (Omega^E porosity), Q^E = sum_i |q_i^E| / 2
+ *    with the local fluxes q^E = W^E (p^E 1 - pi^E) (eq. fluxes_MHFEM_3);
+ *  - takes the next step dt = min(dt min(dt_mult, dp_target / dp_max), dt_max)
+ *    (eq. delta_t_dyn; dp_max = 0 grows dt by dt_mult).
+ * The sequence ends after n_steps steps, once the simulated time reaches t_end (> 0), or at
+ * the first step that does not converge (its status is returned).  u (N, device) holds the
+ * last step's solution; steps (host, n_steps entries, may be NULL) one record per step;
+ * *taken (host, may be NULL) the number of steps.  On return the system holds the last
+ * step's dt and p_prev, and `pre` the last step's stage 2.  Synchronises every step.
+ * Errors: EDFA_ERR_ARG (n_steps < 1, dt0, dt_max, dp_target or porosity not > 0, dt_mult < 1),
+ * and those of edfa_solve and edfa_setup_stage2. */
+typedef struct {
+  int32_t n_steps;          /* largest number of steps */
+  double  t_end;            /* stop once the simulated time reaches it (<= 0: no limit) */
+  double  dt0;              /* first step */
+  double  dt_mult;          /* largest growth factor of dt per step (>= 1) */
+  double  dt_max;           /* largest step (> 0; may be +infinity) */
+  double  dp_target;        /* pressure change goal Delta p_T (> 0; +infinity: no goal) */
+  double  porosity;         /* phi of the Courant number (> 0) */
+  int32_t stage1_every;     /* 0: stage 1 built once (by edfa_setup); k > 0: rebuilt every k steps */
+  edfa_solve_params solve;  /* per-step solve (rtol, method, restart, ...) */
+} edfa_transient_params;
+
+typedef struct {
+  double  t;                /* simulated time at the end of the step */
+  double  dt;               /* the step */
+  double  dp_max;           /* max_E |p^E - p_prev^E| */
+  double  chi_inf;          /* max_E chi^E (eq. CFL_number) */
+  int32_t iterations;       /* Krylov iterations of the step */
+  int32_t converged;        /* 1: the step's solve converged */
+  double  t_setup_ms;       /* device time of the step's preconditioner refresh */
+  double  t_solve_ms;       /* device time of the step's solve */
+} edfa_step_info;
+
+edfa_status edfa_transient(edfa_system sys, edfa_precond pre, const edfa_transient_params *prm,
+                           double *u, hipStream_t stream, edfa_step_info *steps /* (host) */,
+                           int32_t *taken /* (host) */);
 
 /* Per-cell gradient of a scalar loss L(u) with respect to theta_E = ln(multiplier of K^E),
  * given the forward solution u and the adjoint lambda solving A^T lambda = dL/du:
@@ -257,14 +332,17 @@ edfa_status edfa_grad_logk(edfa_system sys, const double *u, const double *lambd
  * stays with the handle across later setups.  *tuned (host, may be NULL) receives the
  * number of matrices timed; slots (host, may be NULL) the timings of every slot.  Synchronises the stream.  Errors: EDFA_ERR_ARG, EDFA_ERR_HIP. */
 #define EDFA_TUNE_SLOTS 16
-#define EDFA_TUNE_VARIANTS 12
+#define EDFA_TUNE_VARIANTS 13
 /* One matrix timed by the autotuner.  Slots: 0 A, 1 A^T, 2 G_F, 3 G_F^T, 4 L, 5 U, 6 M_L,
  * 7 M_U, 8 L^T, 9 U^T, 10 M_L^T, 11 M_U^T, 12 A_ppi, 13 A_pip, 14 A_pip^T, 15 A_ppi^T
- * (the FP32 copies for an FP32 preconditioner).  Variants v = 0..11, as (lanes per row,
+ * (the FP32 copies for an FP32 preconditioner).  Variants v = 0..12, as (lanes per row,
  * entries in flight per lane): SELL (1, 4), (1, 8); CSR (2, 2), (2, 4), (4, 2), (4, 4),
- * (8, 2), (8, 4), (16, 2), (16, 4), (32, 2), (32, 4).  us[v]: best of five launches of
- * variant v, in microseconds; when some matrix of the handle exceeds 8 MiB, a 512 MiB read
- * before each timed launch evicts the caches, as a full iteration does in the solve. */
+ * (8, 2), (8, 4), (16, 2), (16, 4), (32, 2), (32, 4); 12: the chunk kernel (row-aligned
+ * chunks of up to 768 entries, one wavefront each, 12 entries in flight per lane), only
+ * for matrices whose mean row exceeds 24 entries (their default; us[12] = infinity
+ * elsewhere).  us[v]: best of five launches of variant v, in microseconds; when some
+ * matrix of the handle exceeds 8 MiB, a 512 MiB read before each timed launch evicts the
+ * caches, as a full iteration does in the solve. */
 typedef struct {
   int32_t rows, cols;   /* 0 rows: the matrix does not exist (yet); nothing was timed */
   int64_t nnz;
@@ -282,7 +360,8 @@ edfa_status edfa_autotune(edfa_precond pre, hipStream_t stream, int32_t *tuned /
  * edfa_tune_slot) or of every slot (slot = -1) to a variant (0 .. EDFA_TUNE_VARIANTS - 1;
  * -1 = the default choice at the next setup), as edfa_autotune would keep it: for callers
  * that want a fixed kernel (and rounding order) instead of a timed choice.  Takes effect
- * at once and survives later setups.  Host only, nothing is launched.
+ * at once and survives later setups; the chunk variant applies only to matrices with long
+ * rows (the others keep their kernel).  Host only, nothing is launched.
  * Errors: EDFA_ERR_ARG (slot or variant out of range). */
 edfa_status edfa_set_variant(edfa_precond pre, int32_t slot, int32_t variant);
 

@@ -226,6 +226,10 @@ static void fill_info(edfa_precond_s &P, PrecData<T> &D, edfa_precond_info *info
   info->mu = den > 0 ? num / den : 0.0;
   info->t_stage1_ms = P.t_stage1_ms;
   info->t_stage2_ms = P.t_stage2_ms;
+  info->nnz_H_raw = P.nnz_h_raw;
+  info->htilde_retry_rows = P.htilde_retry_rows;
+  info->color_rounds = P.color_rounds;
+  info->color_list_rounds = P.color_list_rounds;
 }
 }  // namespace edfa
 
@@ -248,6 +252,8 @@ edfa_status edfa_setup(edfa_system sys, const edfa_params *prm, hipStream_t stre
     if (prm->schur_solver != EDFA_SCHUR_ISAI && prm->schur_solver != EDFA_SCHUR_EXACT)
       fail(EDFA_ERR_ARG, "schur_solver out of range");
     if (prm->isai_steps < 1) fail(EDFA_ERR_ARG, "isai_steps must be >= 1");
+    if (prm->htilde_retry < 0 || prm->htilde_retry > 256)
+      fail(EDFA_ERR_ARG, "htilde_retry must be in 0..256");
     auto *P = new edfa_precond_s();
     P->sys = sys;
     P->prm = *prm;
@@ -341,7 +347,20 @@ edfa_status edfa_solve(edfa_system sys, edfa_precond pre, const double *b, doubl
     if (pre->sys != sys) fail(EDFA_ERR_ARG, "preconditioner built for another system");
     if (b == x) fail(EDFA_ERR_ARG, "b and x must not alias");
     if (prm->max_iter < 1) fail(EDFA_ERR_ARG, "max_iter must be >= 1");
+    if (prm->method == EDFA_BICGSTAB) return bicgstab(*sys, *pre, b, x, *prm, stream, info);
+    if (prm->method != EDFA_GMRES) fail(EDFA_ERR_ARG, "method must be EDFA_GMRES or EDFA_BICGSTAB");
     return gmres(*sys, *pre, b, x, *prm, stream, info);
+  });
+}
+
+edfa_status edfa_transient(edfa_system sys, edfa_precond pre, const edfa_transient_params *prm,
+                           double *u, hipStream_t stream, edfa_step_info *steps, int32_t *taken) {
+  return guard([&] {
+    if (!sys || !pre || !prm || !u) fail(EDFA_ERR_ARG, "NULL argument");
+    int k = 0;
+    const edfa_status st = transient(*sys, *pre, *prm, u, stream, steps, &k);
+    if (taken) *taken = k;
+    return st;
   });
 }
 

@@ -60,17 +60,37 @@ static void to_fp32(const Csr<double> &M, Csr<float> &F, hipStream_t s) {
   }
 }
 
+// Events of one product of a profiled solve (none otherwise).
+struct Ev {
+  hipEvent_t a = nullptr, b = nullptr;
+};
+static Ev prod_events(edfa_precond_s &P, int slot) {
+  if (!P.prof) return {};
+  Ev e{P.prof->get(), P.prof->get()};
+  P.prof->rec.emplace_back(slot, e.a, e.b);
+  return e;
+}
+
+// Workspace vectors of one application: t1, t2 (N_f^u), r, w, res, y, zq (N_e).
+template <class T>
+struct ApplyWork {
+  T *t1, *t2, *r, *w, *res, *y, *zq;
+};
+template <class T>
+static ApplyWork<T> handle_work(PrecData<T> &D, int nfu, int ne) {
+  return {D.t1.ensure(nfu), D.t2.ensure(nfu), D.r.ensure(ne), D.w.ensure(ne),
+          D.res.ensure(ne),  D.y.ensure(ne),   D.zq.ensure(ne)};
+}
+
 // z_p = S~^-1 y.  ISAI: products with the approximate inverses of (I + L) and U (and
 // Richardson steps with the factors), all stored in the natural cell order, so y and z_p
 // are used as they are.  Exact: colour-by-colour substitution in the colour order, between
 // a gather and a scatter of the vector.
 template <class T>
-static void sinv(edfa_precond_s &P, PrecData<T> &D, int transpose, const T *y, T *zp,
-                 hipStream_t s, RowMask cm) {
+static void sinv(edfa_precond_s &P, PrecData<T> &D, const ApplyWork<T> &W, int transpose,
+                 const T *y, T *zp, hipStream_t s, RowMask cm) {
   const int ne = P.sys->ne;
   const int gb = ceil_div(ne, 256);
-  D.w.ensure(ne);
-  D.res.ensure(ne);
   const int steps = std::max(1, P.prm.isai_steps);
   if (P.prm.schur_solver == EDFA_SCHUR_ISAI) {
     // first factor (L, or U^T for the transpose), then the second
@@ -80,22 +100,28 @@ static void sinv(edfa_precond_s &P, PrecData<T> &D, int transpose, const T *y, T
     const Sell<T> &T2 = transpose ? D.LT_s : D.U_s;
     const double g1 = transpose ? 0.0 : -1.0;   // (I + L) w = L w + w
     const double g2 = transpose ? -1.0 : 0.0;
+    // tuner slots of M1, T1, M2, T2
+    const int sM1 = transpose ? 11 : 6, sT1 = transpose ? 9 : 4;
+    const int sM2 = transpose ? 10 : 7, sT2 = transpose ? 8 : 5;
     const int R = SPMV_PRECOND;
-    spmv_sell<T, T>(M1, y, D.w.p, 1.0, nullptr, 0.0, s, 0.0, R, nullptr, nullptr, cm);
+    auto prod = [&](const Sell<T> &M, int slot, const T *in, T *out, double alpha, const T *bb,
+                    double beta, double gamma) {
+      const Ev e = prod_events(P, slot);
+      spmv_sell<T, T>(M, in, out, alpha, bb, beta, s, gamma, R, e.a, e.b, cm);
+    };
+    prod(M1, sM1, y, W.w, 1.0, nullptr, 0.0, 0.0);
     for (int k = 1; k < steps; ++k) {
-      spmv_sell<T, T>(T1, D.w.p, D.res.p, -1.0, y, 1.0, s, g1, R, nullptr, nullptr, cm);
-      spmv_sell<T, T>(M1, D.res.p, D.w.p, 1.0, D.w.p, 1.0, s, 0.0, R, nullptr, nullptr, cm);
+      prod(T1, sT1, W.w, W.res, -1.0, y, 1.0, g1);
+      prod(M1, sM1, W.res, W.w, 1.0, W.w, 1.0, 0.0);
     }
-    spmv_sell<T, T>(M2, D.w.p, zp, 1.0, nullptr, 0.0, s, 0.0, R, nullptr, nullptr, cm);
+    prod(M2, sM2, W.w, zp, 1.0, nullptr, 0.0, 0.0);
     for (int k = 1; k < steps; ++k) {
-      spmv_sell<T, T>(T2, zp, D.res.p, -1.0, D.w.p, 1.0, s, g2, R, nullptr, nullptr, cm);
-      spmv_sell<T, T>(M2, D.res.p, zp, 1.0, zp, 1.0, s, 0.0, R, nullptr, nullptr, cm);
+      prod(T2, sT2, zp, W.res, -1.0, W.w, 1.0, g2);
+      prod(M2, sM2, W.res, zp, 1.0, zp, 1.0, 0.0);
     }
     return;
   }
-  D.y.ensure(ne);
-  D.zq.ensure(ne);
-  hipLaunchKernelGGL(k_gather<T>, dim3(gb), dim3(256), 0, s, y, D.perm.p, ne, D.y.p);
+  hipLaunchKernelGGL(k_gather<T>, dim3(gb), dim3(256), 0, s, y, D.perm.p, ne, W.y);
   EDFA_CHECK_LAUNCH();
   const int nc = P.n_colors;
   if (!transpose) {
@@ -103,30 +129,30 @@ static void sinv(edfa_precond_s &P, PrecData<T> &D, int transpose, const T *y, T
       const int r0 = D.cstart[c], r1 = D.cstart[c + 1];
       if (r1 > r0)
         hipLaunchKernelGGL(k_sweep<T>, dim3(ceil_div(r1 - r0, 64)), dim3(64), 0, s, D.L.rowptr.p,
-                           D.L.col.p, D.L.val.p, r0, r1, 0, D.y.p, D.w.p);
+                           D.L.col.p, D.L.val.p, r0, r1, 0, W.y, W.w);
     }
     for (int c = nc - 1; c >= 0; --c) {
       const int r0 = D.cstart[c], r1 = D.cstart[c + 1];
       if (r1 > r0)
         hipLaunchKernelGGL(k_sweep<T>, dim3(ceil_div(r1 - r0, 64)), dim3(64), 0, s, D.U.rowptr.p,
-                           D.U.col.p, D.U.val.p, r0, r1, 1, D.w.p, D.zq.p);
+                           D.U.col.p, D.U.val.p, r0, r1, 1, W.w, W.zq);
     }
   } else {
     for (int c = 0; c < nc; ++c) {
       const int r0 = D.cstart[c], r1 = D.cstart[c + 1];
       if (r1 > r0)
         hipLaunchKernelGGL(k_sweep<T>, dim3(ceil_div(r1 - r0, 64)), dim3(64), 0, s, D.UT.rowptr.p,
-                           D.UT.col.p, D.UT.val.p, r0, r1, 2, D.y.p, D.w.p);
+                           D.UT.col.p, D.UT.val.p, r0, r1, 2, W.y, W.w);
     }
     for (int c = nc - 1; c >= 0; --c) {
       const int r0 = D.cstart[c], r1 = D.cstart[c + 1];
       if (r1 > r0)
         hipLaunchKernelGGL(k_sweep<T>, dim3(ceil_div(r1 - r0, 64)), dim3(64), 0, s, D.LT.rowptr.p,
-                           D.LT.col.p, D.LT.val.p, r0, r1, 0, D.w.p, D.zq.p);
+                           D.LT.col.p, D.LT.val.p, r0, r1, 0, W.w, W.zq);
     }
   }
   EDFA_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_scatter<T>, dim3(gb), dim3(256), 0, s, D.zq.p, D.perm.p, ne, zp);
+  hipLaunchKernelGGL(k_scatter<T>, dim3(gb), dim3(256), 0, s, W.zq, D.perm.p, ne, zp);
   EDFA_CHECK_LAUNCH();
 }
 
@@ -159,28 +185,32 @@ static void ensure_transposed_factors(edfa_precond_s &P, PrecData<T> &D, hipStre
 // z = P^-1 r (or P^-T r) in precision T; c1 = A_ppi (A_pip^T), c2 = A_pip (A_ppi^T).
 // fm / cm: rows of face / cell unknowns to skip (grids of a batch that have converged).
 template <class T>
-static void apply_typed(edfa_precond_s &P, PrecData<T> &D, const T *r, T *z, const Sell<T> &c1,
-                        const Sell<T> &c2, int transpose, hipStream_t s, RowMask fm,
-                        RowMask cm) {
+static void apply_typed(edfa_precond_s &P, PrecData<T> &D, const ApplyWork<T> &W, const T *r,
+                        T *z, const Sell<T> &c1, const Sell<T> &c2, int transpose,
+                        hipStream_t s, RowMask fm, RowMask cm) {
   edfa_system_s &S = *P.sys;
-  const int nfu = S.nfu, ne = S.ne;
+  const int nfu = S.nfu;
   const int R = SPMV_PRECOND;
-  D.t1.ensure(nfu);
-  D.t2.ensure(nfu);
-  D.r.ensure(ne);
   const T *rpi = r, *rp = r + nfu;
   T *zpi = z, *zp = z + nfu;
+  // tuner slots of the coupling products
+  const int s1 = transpose ? 14 : 12, s2 = transpose ? 15 : 13;
+  auto prod = [&](const Sell<T> &M, int slot, const T *in, T *out, double alpha, const T *bb,
+                  double beta, RowMask mk) {
+    const Ev e = prod_events(P, slot);
+    spmv_sell<T, T>(M, in, out, alpha, bb, beta, s, 0.0, R, e.a, e.b, mk);
+  };
   // t = A~^-1 r_pi = -G_F^T G_F r_pi
-  spmv_sell<T, T>(D.GF_s, rpi, D.t1.p, 1.0, nullptr, 0.0, s, 0.0, R, nullptr, nullptr, fm);
-  spmv_sell<T, T>(D.GFT_s, D.t1.p, D.t2.p, -1.0, nullptr, 0.0, s, 0.0, R, nullptr, nullptr, fm);
+  prod(D.GF_s, 2, rpi, W.t1, 1.0, nullptr, 0.0, fm);
+  prod(D.GFT_s, 3, W.t1, W.t2, -1.0, nullptr, 0.0, fm);
   // y = r_p - A_ppi t
-  spmv_sell<T, T>(c1, D.t2.p, D.r.p, -1.0, rp, 1.0, s, 0.0, R, nullptr, nullptr, cm);
+  prod(c1, s1, W.t2, W.r, -1.0, rp, 1.0, cm);
   // z_p = S~^-1 y
-  sinv<T>(P, D, transpose, D.r.p, zp, s, cm);
+  sinv<T>(P, D, W, transpose, W.r, zp, s, cm);
   // z_pi = A~^-1 (r_pi - A_pip z_p)
-  spmv_sell<T, T>(c2, zp, D.t1.p, -1.0, rpi, 1.0, s, 0.0, R, nullptr, nullptr, fm);
-  spmv_sell<T, T>(D.GF_s, D.t1.p, D.t2.p, 1.0, nullptr, 0.0, s, 0.0, R, nullptr, nullptr, fm);
-  spmv_sell<T, T>(D.GFT_s, D.t2.p, zpi, -1.0, nullptr, 0.0, s, 0.0, R, nullptr, nullptr, fm);
+  prod(c2, s2, zp, W.t1, -1.0, rpi, 1.0, fm);
+  prod(D.GF_s, 2, W.t1, W.t2, 1.0, nullptr, 0.0, fm);
+  prod(D.GFT_s, 3, W.t2, zpi, -1.0, nullptr, 0.0, fm);
 }
 
 void precond_apply(edfa_precond_s &P, int transpose, const double *r, double *z, hipStream_t s,
@@ -195,7 +225,8 @@ void precond_apply(edfa_precond_s &P, int transpose, const double *r, double *z,
     apply_tuned(P);
   }
   if (P.prm.precision != 1) {
-    apply_typed<double>(P, P.d, r, z, transpose ? S.AfcT_s : S.Acf_s,
+    const ApplyWork<double> W = handle_work(P.d, S.nfu, S.ne);
+    apply_typed<double>(P, P.d, W, r, z, transpose ? S.AfcT_s : S.Acf_s,
                         transpose ? S.AcfT_s : S.Afc_s, transpose, s, fm, cm);
     return;
   }
@@ -214,15 +245,14 @@ void precond_apply(edfa_precond_s &P, int transpose, const double *r, double *z,
   }
   if (rebuilt) apply_tuned(P);
   const int n = S.n;
-  D.z.ensure(n);
-  DBuf<float> &rin = P.rin_f;
-  rin.ensure(n);
+  const ApplyWork<float> W = handle_work(D, S.nfu, S.ne);
+  float *rin = P.rin_f.ensure(n), *zf = D.z.ensure(n);
   hipLaunchKernelGGL((k_convert<double, float>), dim3(ceil_div(n, 256)), dim3(256), 0, s, r,
-                     (long long)n, rin.p, mask);
+                     (long long)n, rin, mask);
   EDFA_CHECK_LAUNCH();
-  apply_typed<float>(P, D, rin.p, D.z.p, transpose ? cs[2] : cs[0], transpose ? cs[3] : cs[1],
+  apply_typed<float>(P, D, W, rin, zf, transpose ? cs[2] : cs[0], transpose ? cs[3] : cs[1],
                      transpose, s, fm, cm);
-  hipLaunchKernelGGL((k_convert<float, double>), dim3(ceil_div(n, 256)), dim3(256), 0, s, D.z.p,
+  hipLaunchKernelGGL((k_convert<float, double>), dim3(ceil_div(n, 256)), dim3(256), 0, s, zf,
                      (long long)n, z, mask);
   EDFA_CHECK_LAUNCH();
 }

@@ -6,6 +6,7 @@
 // built by one thread from the cell matrices it touches (gather, no atomics), so the
 // result is deterministic.
 #include <algorithm>
+#include <cmath>
 
 #include "system.hpp"
 
@@ -60,6 +61,14 @@ __device__ inline void chol_inverse(const double (&L)[N][N], double (&out)[N][N]
 // Per cell: B^E by quadrature, volume, W^E = (B^E)^-1, the storage coefficient and the
 // previous pressure; clears *axis when the cell is not an axis-aligned brick with
 // diagonal K; records the first bad cell.
+// Smallest tag + index of a non-finite entry of a[0, n) (tag in the bits above 40).
+__global__ void k_first_nonfinite(const double *__restrict__ a, long long n, long long tag,
+                                  long long *first) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    if (!isfinite(a[i])) atomicMin((unsigned long long *)first, (unsigned long long)(tag | i));
+}
+
 __global__ void k_element(const GridDesc *__restrict__ grids, int ngrid, int ne, double *W,
                           double *vol, double *cstore, double *p_prev, int *axis, int *bad) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -501,6 +510,42 @@ void assemble_system(edfa_system_s &S, const edfa_problem *probs, int count, hip
   S.grids.ensure(count);
   EDFA_HIP(hipMemcpyAsync(S.grids.p, S.grids_h.data(), sizeof(GridDesc) * count,
                           hipMemcpyHostToDevice, s));
+
+  // non-finite inputs: the first offending entry of each array (per grid) is reported
+  {
+    DBuf<long long> bad;
+    bad.ensure(1);
+    const long long none = 0x7fffffffffffffffLL;
+    EDFA_HIP(hipMemcpyAsync(bad.p, &none, sizeof(none), hipMemcpyHostToDevice, s));
+    struct Arr {
+      const double *p;
+      long long n;
+    };
+    const char *names[6] = {"nodes", "K", "c", "bc_value", "p_prev", "source"};
+    for (int g = 0; g < count; ++g) {
+      const GridDesc &G = S.grids_h[g];
+      const long long nn = (long long)(G.nx + 1) * (G.ny + 1) * (G.nz + 1);
+      const Arr arrs[6] = {{G.nodes, 3 * nn}, {G.K, 6ll * G.ncell}, {G.c, G.c ? G.ncell : 0},
+                           {G.bc_value, G.nface}, {G.p_prev, G.p_prev ? G.ncell : 0},
+                           {G.source, G.source ? G.ncell : 0}};
+      for (int a = 0; a < 6; ++a)
+        if (arrs[a].n > 0) {
+          hipLaunchKernelGGL(k_first_nonfinite, dim3(std::min<long long>(ceil_div(arrs[a].n, 256), 4096)),
+                             dim3(256), 0, s, arrs[a].p, arrs[a].n, (long long)(g * 6 + a) << 40,
+                             bad.p);
+          EDFA_CHECK_LAUNCH();
+        }
+    }
+    const long long fb = read_scalar(bad.p, s);
+    if (fb != none) {
+      const int ga = (int)(fb >> 40);
+      fail(EDFA_ERR_NAN, "grid %d: %s[%lld] is not finite", ga / 6, names[ga % 6],
+           fb & ((1ll << 40) - 1));
+    }
+    for (int g = 0; g < count; ++g)
+      if (!probs[g].c && !std::isfinite(probs[g].c_scalar))
+        fail(EDFA_ERR_NAN, "grid %d: c_scalar is not finite", g);
+  }
 
   // element matrices
   S.W.ensure(36 * (size_t)ne);

@@ -94,15 +94,25 @@ struct Sell {
   // inside windows); otherwise position p holds row p
   bool sorted = false;
   DBuf<int> perm;
-  // Kernel choice: lanes <= 1 runs the SELL kernel; lanes = 2..32 runs the CSR kernel with
-  // that many lanes per row on the source CSR arrays (which must outlive this copy).
+  // Kernel choice: lanes = 0 or 1 runs the SELL kernel; lanes = 2..32 runs the CSR kernel
+  // with that many lanes per row on the source CSR arrays (which must outlive this copy);
+  // lanes = SPMV_CHUNKED runs the chunk kernel on the CSR arrays (below).
   // depth: entries in flight per lane and round (SELL 4 or 8, CSR 2 or 4; other values
-  // take 4 and 2).
+  // take 4 and 2; the chunk kernel always has CHUNK_K).
   int lanes = 0;
   int depth = 0;
   const int *csr_rp = nullptr, *csr_col = nullptr;
   const V *csr_val = nullptr;
+  // Row-aligned chunks of the CSR arrays for the chunk kernel: chunk c holds rows
+  // [chunk[c].x, chunk[c+1].x) and entries [chunk[c].y, chunk[c+1].y), at most 64 * chunk_k
+  // entries unless it is a single longer row (chunk_k = 0: not built).  Built with the
+  // copy for matrices whose rows are long (the kernel's default there).
+  DBuf<int2> chunk;
+  int nchunk = 0;
+  int chunk_k = 0;
 };
+constexpr int SPMV_CHUNKED = -1;
+constexpr int CHUNK_K = 12;   // chunk kernel: 12 entries in flight per lane, 768 per chunk
 
 inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
 
@@ -162,8 +172,13 @@ void spmv(const int *rowptr, const int *col, const V *val, int rows, const X *x,
           double gamma = 0.0);
 
 // SELL-64 copy of a CSR matrix (device-side conversion; synchronises to size the storage).
+// Matrices with long rows also get the chunk descriptors of the default chunk kernel.
 template <class V>
 void build_sell(const Csr<V> &M, Sell<V> &S, DBuf<int> &tmp, hipStream_t s);
+// Chunk descriptors of S's CSR arrays for chunks of at most 64 * k entries (greedy over
+// the rows on the host; synchronises).  No-op when they exist for this k.
+template <class V>
+void build_row_chunks(Sell<V> &S, int k, hipStream_t s);
 // Default lanes per row for a mean row length (0: the SELL kernel).
 int default_spmv_lanes(double mean_row);
 

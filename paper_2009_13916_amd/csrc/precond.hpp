@@ -2,6 +2,8 @@
 #pragma once
 
 #include <memory>
+#include <tuple>
+#include <vector>
 
 #include "system.hpp"
 
@@ -56,6 +58,27 @@ struct PrecData {
   DBuf<T> r, z, t1, t2, y, w, zq, res;
 };
 
+// Events around individual sparse products of a profiled solve: rec holds (tuner slot,
+// start, stop) per launch; events are created on demand and reused.
+struct ProdProfile {
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> rec;
+  hipEvent_t get() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      EDFA_HIP(hipEventCreate(&e));
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  ~ProdProfile() {
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+  // per-slot mean launch time (ms) and launch count
+  void summarise(double *ms, int32_t *count, int nslot) const;
+};
+
 // GMRES state: chunks of the unknown vector that never straddle a grid of a batch, and
 // the per-grid (segment) iteration state.
 constexpr int MAXV = 130;        // restart <= MAXV - 2
@@ -66,6 +89,11 @@ struct SegState {
   double rtol, bnorm, tol, beta, est, relres;
   int active, done, converged, j, total, pad;
 };
+// Bi-CGStab state of one segment (grid).
+struct BiSeg {
+  double bnorm, tol, rho, alpha, omega, beta, rnorm, relres;
+  int active, done, converged, total, half, first, breakdown, pad;
+};
 struct SolveWork {
   int nchunk = 0, n = 0;
   DBuf<Chunk> chunks;
@@ -73,9 +101,16 @@ struct SolveWork {
   DBuf<double> V, Z, w, r, z, part, h1, nrm, R, cs, sn, g, y, scale;
   DBuf<double> Hb;     // unrotated Hessenberg columns per segment, m x (m + 1)
   DBuf<double> coef;   // per segment: update coefficients [a | b | c_j] of the current step
+  DBuf<double> Tz;     // FGMRES, per segment m x m: column j = [a_j; rho_j], u_j = Q T e_j
   DBuf<int> ran;
   DBuf<SegState> st;
+  // Bi-CGStab vectors and state
+  DBuf<double> rhat, p, v, ph, sv, sh, t;
+  DBuf<BiSeg> bst;
 };
+// Chunks of CHUNK unknowns that never straddle a grid (built once per system).
+constexpr int SOLVE_CHUNK = 2048;
+void build_chunks(edfa_system_s &S, SolveWork &W, hipStream_t s);
 
 }  // namespace edfa
 
@@ -85,6 +120,11 @@ struct edfa_precond_s {
   int smax = 0;
   int n_colors = 0;
   int max_pattern = 0;
+  int htilde_retry_rows = 0;       // rows of H~ recomputed with the large hash tables
+  int64_t nnz_h_raw = 0;           // entries of H~ before the post-filtration
+  int color_rounds = 0;            // Jones-Plassmann rounds of the last colouring
+  int color_list_rounds = 0;       //   of which over the worklist of uncoloured vertices
+  edfa::DBuf<unsigned long long> counter;
   double t_stage1_ms = 0, t_stage2_ms = 0;
   edfa::PrecData<double> d;
   edfa::PrecData<float> f;
@@ -95,6 +135,7 @@ struct edfa_precond_s {
   std::unique_ptr<edfa::SolveWork> ws;
   int tuned[16] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
                                    // autotuned kernel variant of each product (-1: default)
+  edfa::ProdProfile *prof = nullptr;   // set while a profiled solve runs eagerly
 };
 
 namespace edfa {
@@ -104,6 +145,10 @@ void precond_apply(edfa_precond_s &P, int transpose, const double *r, double *z,
                    RowMask mask = {});
 edfa_status gmres(edfa_system_s &S, edfa_precond_s &P, const double *b, double *x,
                   const edfa_solve_params &prm, hipStream_t s, edfa_solve_info *info);
+edfa_status bicgstab(edfa_system_s &S, edfa_precond_s &P, const double *b, double *x,
+                     const edfa_solve_params &prm, hipStream_t s, edfa_solve_info *info);
+edfa_status transient(edfa_system_s &S, edfa_precond_s &P, const edfa_transient_params &prm,
+                      double *u, hipStream_t s, edfa_step_info *steps, int *taken);
 template <class T>
 void build_hraw(edfa_precond_s &P, PrecData<T> &D, hipStream_t s);
 void grad_logk(edfa_system_s &S, const double *u, const double *lam, double *g, hipStream_t s);

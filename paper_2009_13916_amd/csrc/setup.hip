@@ -174,6 +174,15 @@ __global__ void k_len_max(const int *__restrict__ len, int n, int *out) {
   atomicMax(out, len[r]);
 }
 
+// total of n int32 lengths (64-bit accumulator)
+__global__ void k_len_sum(const int *__restrict__ len, int n, unsigned long long *out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long v = r < n ? (unsigned long long)len[r] : 0ull;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if ((threadIdx.x & 63) == 0 && v) atomicAdd(out, v);
+}
+
 __global__ void k_repack(const int *__restrict__ src, const int *__restrict__ len, int n, int s0,
                          int s1, int *dst) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1027,6 +1036,7 @@ struct HArgs {
   const int *cells;      // rows to compute (NULL: row = block index)
   int *retry_count;      // non-NULL: a row whose tables pass half full is listed here
   int *retry_list;       //   instead of computed (first pass with small tables)
+  int t_retry;           // first pass: a support of t over this many faces retries
 };
 
 // Tables: g~ (GH slots), the support of t (TH slots, listed in tlist: TH/2 entries for the
@@ -1080,7 +1090,7 @@ __global__ __launch_bounds__(64) void k_htilde(HArgs<T> A) {
   };
   for (int p = g0 + lane; p < g1; p += 64) ell_row(A.ell_col, nullptr, A.g_col[p], add_t);
   __syncthreads();
-  if (A.retry_count && (sflag || tcount > TH / 2)) {
+  if (A.retry_count && (sflag || tcount > A.t_retry)) {
     retry();
     return;
   }
@@ -1532,6 +1542,8 @@ static void stage1_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
   ha.cells = nullptr;
   ha.retry_count = nullptr;
   ha.retry_list = nullptr;
+  // half of the small table of t (its hash probes stay short) unless the caller asks for less
+  ha.t_retry = prm.htilde_retry > 0 ? std::min(prm.htilde_retry, 256) : 256;
   // large-table pass over `rows` rows (all cells, or the listed ones)
   auto large_pass = [&](int rows) {
     if (rows <= 0) return;
@@ -1556,15 +1568,28 @@ static void stage1_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
       hipLaunchKernelGGL((k_htilde<T, 128, 512, 512>), dim3(ne), dim3(64), 0, s, ha);
     EDFA_CHECK_LAUNCH();
     const int nretry = read_scalar(P.flags.p + 3, s);
+    P.htilde_retry_rows = nretry;
     ha.retry_count = nullptr;
     ha.retry_list = nullptr;
     ha.cells = D.hretry.p;
     large_pass(nretry);
     ha.cells = nullptr;
   } else {
+    P.htilde_retry_rows = 0;
     large_pass(ne);
   }
   check_flags(P, s, "H~ rows");
+  {
+    // entries of H~ before the post-filtration (diagnostic of what the filter drops)
+    DBuf<unsigned long long> &acc = P.counter;
+    acc.ensure(1);
+    EDFA_HIP(hipMemsetAsync(acc.p, 0, sizeof(unsigned long long), s));
+    if (ne > 0) {
+      hipLaunchKernelGGL(k_len_sum, dim3(ceil_div(ne, 256)), dim3(256), 0, s, D.Hlen.p, ne, acc.p);
+      EDFA_CHECK_LAUNCH();
+    }
+    P.nnz_h_raw = (int64_t)read_scalar(acc.p, s);
+  }
   const int postH = prm.filt_mode == EDFA_FILT_POST_H;
   D.H.rowptr.ensure((size_t)ne + 1);
   hipLaunchKernelGGL(k_hcount<T>, dim3(ceil_div(ne, 4)), dim3(256), 0, s, D.Hcol.p, D.Hval.p,

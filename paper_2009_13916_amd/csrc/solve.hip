@@ -17,16 +17,18 @@
 //                rho) and gets its Givens rotation; c = [b; (beta - a.b)/rho] = [Q q_j]^T w;
 //                the provisional column j is (c - Hbar a)/rho
 //   one pass     q_j = (u_j - Q a)/rho,  u_{j+1} = (w - Q b - q_j c_j)/rho
-// (w = rho A M^-1 q_j + A M^-1 Q a and A M^-1 Q = Q_{j+1} Hbar give these).  FGMRES also
-// corrects z_j = M^-1 u_j into M^-1 q_j.  The last column of a cycle is finalised by one
-// more pass of dots.
+// (w = rho A M^-1 q_j + A M^-1 Q a and A M^-1 Q = Q_{j+1} Hbar give these).  FGMRES keeps
+// z_j = M^-1 u_j as applied: with u_j = rho_j q_j + Q a_j, the columns M^-1 q_j are
+// Z T^-1 for the upper triangular T with columns [a_j; rho_j], so the end of a cycle adds
+// Z (T^-1 y) instead of correcting every z_j with a pass over Z.  The last column of a
+// cycle is finalised by one more pass of dots.
 #include <cmath>
 
 #include "precond.hpp"
 
 namespace edfa {
 
-constexpr int CHUNK = 2048;   // elements per chunk: 256 threads x 8
+constexpr int CHUNK = SOLVE_CHUNK;   // elements per chunk: 256 threads x 8
 constexpr int RT = 256;
 
 // Partial dots tiled over (chunk, group of DG basis vectors): block (c, q) forms Q_i . u and
@@ -155,7 +157,7 @@ __global__ __launch_bounds__(64) void k_dcgs_step(int nseg, int m, int j, int fi
                                                   const double *__restrict__ d, int ldd,
                                                   double *Hb, double *R, double *cs, double *sn,
                                                   double *gv, double *coef, double *scale,
-                                                  int max_iter) {
+                                                  int max_iter, double *Tz) {
   __shared__ double a[MAXV], b[MAXV], col[MAXV], cc[MAXV], c_[MAXV], s_[MAXV];
   __shared__ double sh_rho;
   __shared__ int sh_live;
@@ -249,6 +251,12 @@ __global__ __launch_bounds__(64) void k_dcgs_step(int nseg, int m, int j, int fi
   for (int i = lane; i < j; i += 64) cf[i] = a[i];
   for (int i = lane; i <= j; i += 64) cf[j + i] = cc[i];
   if (lane == 0) scale[g] = 1.0 / rho;
+  if (Tz && j < m) {
+    // column j of T: u_j = rho q_j + Q a (FGMRES)
+    double *T = Tz + (long long)g * m * m;
+    for (int i = lane; i < j; i += 64) T[(long long)i * m + j] = a[i];
+    if (lane == 0) T[(long long)j * m + j] = rho;
+  }
 }
 
 // q_j = (u_j - Q a) / rho (in place in slot j) and u_{j+1} = (w - Q b - q_j c_j) / rho
@@ -305,39 +313,6 @@ __global__ __launch_bounds__(RT) void k_dcgs_update(double *Q, long long ldq, in
   }
 }
 
-// FGMRES: z_j = (z_j - Z a) / rho turns M^-1 u_j into M^-1 q_j.
-__global__ __launch_bounds__(RT) void k_dcgs_update_z(double *Z, long long ldz, int j,
-                                                      const Chunk *__restrict__ ch,
-                                                      const SegState *__restrict__ st,
-                                                      const double *__restrict__ coef, int ldc,
-                                                      const double *__restrict__ scale) {
-  __shared__ double sa[MAXV];
-  const Chunk c = ch[blockIdx.x];
-  if (!st[c.seg].active) return;
-  const double *cf = coef + (long long)c.seg * ldc;
-  for (int i = threadIdx.x; i < j; i += RT) sa[i] = cf[i];
-  __syncthreads();
-  const double ir = scale[c.seg];
-  double *zj = Z + (long long)j * ldz;
-  int ek[8];
-  double z[8];
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    ek[k] = min(c.start + (int)threadIdx.x + k * RT, c.end - 1);
-    z[k] = zj[ek[k]];
-  }
-#pragma unroll 2
-  for (int i = 0; i < j; ++i) {
-    const double a = sa[i];
-    const double *zi = Z + (long long)i * ldz;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) z[k] -= a * zi[ek[k]];
-  }
-#pragma unroll
-  for (int k = 0; k < 8; ++k)
-    if (c.start + (int)threadIdx.x + k * RT < c.end) zj[c.start + threadIdx.x + k * RT] = z[k] * ir;
-}
-
 // V_{j+1} = w * scale[seg] (active segments); with j < 0: V_0 = r / beta for starting ones.
 __global__ __launch_bounds__(RT) void k_scale(const double *__restrict__ w, double *v,
                                               const Chunk *__restrict__ ch,
@@ -388,9 +363,11 @@ __global__ void k_seg_start(int nseg, int m, SegState *st, const double *__restr
   st[g] = S;
 }
 
-// Least squares of the cycle: R y = g (upper triangular, size j of the segment).
+// Least squares of the cycle: R y = g (upper triangular, size j of the segment); FGMRES
+// (Tz non-null) then replaces y by T^-1 y, the coefficients of the stored z_j.
 __global__ void k_lsq(int nseg, int m, const SegState *__restrict__ st, const double *__restrict__ R,
-                      const double *__restrict__ gv, double *y, int *ran) {
+                      const double *__restrict__ gv, double *y, int *ran,
+                      const double *__restrict__ Tz) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= nseg) return;
   const int k = ran[g];
@@ -401,6 +378,14 @@ __global__ void k_lsq(int nseg, int m, const SegState *__restrict__ st, const do
     double s = gg[i];
     for (int l = i + 1; l < k; ++l) s -= R[((long long)g * m + i) * m + l] * yy[l];
     yy[i] = s / R[((long long)g * m + i) * m + i];
+  }
+  if (Tz) {
+    const double *T = Tz + (long long)g * m * m;
+    for (int i = k - 1; i >= 0; --i) {
+      double s = yy[i];
+      for (int l = i + 1; l < k; ++l) s -= T[(long long)i * m + l] * yy[l];
+      yy[i] = s / T[(long long)i * m + i];
+    }
   }
 }
 
@@ -442,7 +427,24 @@ __global__ void k_record_ran(int nseg, const SegState *__restrict__ st, int *ran
 }
 
 // ---------------------------------------------------------------------------------------
-static void build_chunks(edfa_system_s &S, SolveWork &W, hipStream_t s) {
+void ProdProfile::summarise(double *ms, int32_t *count, int nslot) const {
+  std::vector<double> tot(nslot, 0.0);
+  std::vector<int> cnt(nslot, 0);
+  for (const auto &r : rec) {
+    const int q = std::get<0>(r);
+    if (q < 0 || q >= nslot) continue;
+    float t = 0;
+    EDFA_HIP(hipEventElapsedTime(&t, std::get<1>(r), std::get<2>(r)));
+    tot[q] += t;
+    ++cnt[q];
+  }
+  for (int q = 0; q < nslot; ++q) {
+    ms[q] = cnt[q] ? tot[q] / cnt[q] : 0.0;
+    count[q] = cnt[q];
+  }
+}
+
+void build_chunks(edfa_system_s &S, SolveWork &W, hipStream_t s) {
   if (W.nchunk > 0 && W.n == S.n) return;
   std::vector<Chunk> ch;
   std::vector<int> ptr(S.ngrid + 1, 0);
@@ -509,7 +511,11 @@ edfa_status gmres(edfa_system_s &S, edfa_precond_s &P, const double *b, double *
   const int nch = W.nchunk;
   const int ld = 2 * m + 4;   // per-chunk / per-segment rows of dot products (2j + 2 used)
   W.V.ensure((size_t)(m + 1) * n);
-  if (prm.flexible) W.Z.ensure((size_t)m * n);
+  if (prm.flexible) {
+    W.Z.ensure((size_t)m * n);
+    W.Tz.ensure((size_t)nseg * m * m);
+  }
+  double *Tz = prm.flexible ? W.Tz.p : nullptr;
   W.w.ensure(n);
   W.r.ensure(n);
   W.z.ensure(n);
@@ -562,14 +568,17 @@ edfa_status gmres(edfa_system_s &S, edfa_precond_s &P, const double *b, double *
     spmv_sell<double, double>(A, in, out, bb ? -1.0 : 1.0, bb, 1.0, cs, 0.0, SPMV_OPERATOR, e0, e1,
                               mk);
   };
+  ProdProfile pp;
   auto applyP = [&](const double *in, double *out, hipStream_t cs, RowMask mk) {
     const bool pr = prm.profile && cs == s;
     hipEvent_t e0{}, e1{};
     if (pr) {
       e0 = prof.get();
       EDFA_HIP(hipEventRecord(e0, cs));
+      P.prof = &pp;
     }
     precond_apply(P, tr, in, out, cs, mk);
+    P.prof = nullptr;
     if (pr) {
       e1 = prof.get();
       EDFA_HIP(hipEventRecord(e1, cs));
@@ -615,12 +624,9 @@ edfa_status gmres(edfa_system_s &S, edfa_precond_s &P, const double *b, double *
       dots(j, vj, W.w.p);
       hipLaunchKernelGGL(k_dcgs_step, dim3(nseg), dim3(64), 0, cs, nseg, m, j, 0, W.st.p, W.h1.p,
                          ld, W.Hb.p, W.R.p, W.cs.p, W.sn.p, W.g.p, W.coef.p, W.scale.p,
-                         prm.max_iter);
+                         prm.max_iter, Tz);
       hipLaunchKernelGGL(k_dcgs_update, dim3(nch, 2), dim3(RT), 0, cs, W.V.p, (long long)n, j, W.w.p,
                          W.chunks.p, W.st.p, W.coef.p, 2 * m + 2, W.scale.p);
-      if (prm.flexible)
-        hipLaunchKernelGGL(k_dcgs_update_z, dim3(nch), dim3(RT), 0, cs, W.Z.p, (long long)n, j,
-                           W.chunks.p, W.st.p, W.coef.p, 2 * m + 2, W.scale.p);
       EDFA_CHECK_LAUNCH();
       if (host_checks && (j + 1) % check_every == 0 && j + 1 < m) {
         EDFA_HIP(hipMemcpyAsync(hst.data(), W.st.p, sizeof(SegState) * nseg, hipMemcpyDeviceToHost, cs));
@@ -634,11 +640,12 @@ edfa_status gmres(edfa_system_s &S, edfa_precond_s &P, const double *b, double *
     dots(m, W.V.p + (size_t)m * n, W.V.p + (size_t)m * n);
     hipLaunchKernelGGL(k_dcgs_step, dim3(nseg), dim3(64), 0, cs, nseg, m, m, 1, W.st.p, W.h1.p,
                        ld, W.Hb.p, W.R.p, W.cs.p, W.sn.p, W.g.p, W.coef.p, W.scale.p,
-                       prm.max_iter);
+                       prm.max_iter, Tz);
     EDFA_CHECK_LAUNCH();
     // end of cycle: y = R^-1 g, x += Z y (flexible) or x += P^-1 (V y)
     hipLaunchKernelGGL(k_record_ran, dim3(sb), dim3(64), 0, cs, nseg, W.st.p, W.ran.p);
-    hipLaunchKernelGGL(k_lsq, dim3(sb), dim3(64), 0, cs, nseg, m, W.st.p, W.R.p, W.g.p, W.y.p, W.ran.p);
+    hipLaunchKernelGGL(k_lsq, dim3(sb), dim3(64), 0, cs, nseg, m, W.st.p, W.R.p, W.g.p, W.y.p,
+                       W.ran.p, Tz);
     if (prm.flexible) {
       hipLaunchKernelGGL(k_combine, dim3(nch), dim3(RT), 0, cs, W.Z.p, (long long)n, m, W.chunks.p,
                          W.y.p, W.ran.p, x, 1);
@@ -664,6 +671,10 @@ edfa_status gmres(edfa_system_s &S, edfa_precond_s &P, const double *b, double *
   while (true) {
     EDFA_HIP(hipMemcpyAsync(hst.data(), W.st.p, sizeof(SegState) * nseg, hipMemcpyDeviceToHost, s));
     EDFA_HIP(hipStreamSynchronize(s));
+    if (cycles == 0)
+      for (int g = 0; g < nseg; ++g)
+        if (!std::isfinite(hst[g].bnorm))
+          fail(EDFA_ERR_NAN, "grid %d: the right-hand side has a non-finite entry", g);
     int nact = 0;
     for (auto &q : hst) nact += q.active;
     if (!nact) break;
@@ -716,6 +727,9 @@ edfa_status gmres(edfa_system_s &S, edfa_precond_s &P, const double *b, double *
     info->spmv_count = (int)ev_spmv.size();
     info->apply_avg_ms = prm.profile ? avg(ev_apply) : 0.0;
     info->apply_count = (int)ev_apply.size();
+    pp.summarise(info->slot_ms, info->slot_launches, EDFA_TUNE_SLOTS);
+    info->slot_ms[tr] = info->spmv_avg_ms;
+    info->slot_launches[tr] = info->spmv_count;
   }
   return conv == nseg ? EDFA_OK : EDFA_NOT_CONVERGED;
 }

@@ -1,5 +1,8 @@
 // Primitive device algorithms: prefix sums, CSR transpose, CSR SpMV.
 #include <hip/hip_ext.h>
+
+#include <vector>
+
 #include "common.hpp"
 
 namespace edfa {
@@ -365,7 +368,9 @@ __global__ void k_sell_fill(const int *__restrict__ rowptr, const int *__restric
 constexpr double SPMV_VEC_MIN_ROW = 24.0;
 // SELL-64 padding (stored / true entries) above which the rows are sorted by length
 constexpr double SELL_SORT_PAD = 1.2;
-int default_spmv_lanes(double mean_row) { return mean_row < SPMV_VEC_MIN_ROW ? 0 : 8; }
+int default_spmv_lanes(double mean_row) {
+  return mean_row < SPMV_VEC_MIN_ROW ? 0 : SPMV_CHUNKED;
+}
 
 template <class V>
 void build_sell(const Csr<V> &M, Sell<V> &S, DBuf<int> &tmp, hipStream_t s) {
@@ -377,6 +382,8 @@ void build_sell(const Csr<V> &M, Sell<V> &S, DBuf<int> &tmp, hipStream_t s) {
   S.csr_val = M.val.p;
   S.lanes = M.rows > 0 ? default_spmv_lanes((double)M.nnz / M.rows) : 0;
   S.depth = 0;
+  S.chunk_k = 0;   // the CSR arrays may have changed: descriptors are rebuilt on demand
+  if (S.lanes == SPMV_CHUNKED) build_row_chunks(S, CHUNK_K, s);
   S.nslice = ceil_div(M.rows, 64);
   S.sptr.ensure((size_t)S.nslice + 1);
   S.rlen.ensure((size_t)std::max(M.rows, 1));
@@ -518,6 +525,130 @@ __global__ __launch_bounds__(SPMV_T) void k_spmv_csr_vec(const int *__restrict__
   }
 }
 
+// ----------------------------------------------------------------------------------
+// Chunk kernel for matrices whose rows are long and of uneven length (the approximate
+// inverses of the ILU(0) factors: 1 to ~160 entries, in the natural order).  The CSR arrays
+// are cut, on the host, into chunks of whole consecutive rows holding at most 64 K entries.
+// One wavefront per chunk: its lanes load the chunk's entries with unit stride, K loads of
+// column index and value in flight per lane, gather x, and leave the products in LDS;
+// then G lanes per row sum each row's products (strided, then a shuffle tree).  Every load
+// is useful (no lane idles on a short row) and the x gathers keep the natural order's
+// locality.  A row longer than 64 K entries forms a chunk of its own, summed by the whole
+// wavefront.
+// ----------------------------------------------------------------------------------
+template <class V>
+void build_row_chunks(Sell<V> &S, int k, hipStream_t s) {
+  if (S.chunk_k == k || S.rows <= 0) return;
+  const int cap = 64 * k;
+  std::vector<int> rp((size_t)S.rows + 1);
+  EDFA_HIP(hipMemcpyAsync(rp.data(), S.csr_rp, sizeof(int) * rp.size(), hipMemcpyDeviceToHost, s));
+  EDFA_HIP(hipStreamSynchronize(s));
+  std::vector<int2> d;
+  d.reserve(rp.back() / std::max(1, cap / 2) + 2);
+  int r0 = 0;
+  d.push_back(make_int2(0, rp[0]));
+  for (int r = 0; r < S.rows; ++r) {
+    // close the current chunk before row r when r would overflow it
+    if (r > r0 && rp[r + 1] - rp[r0] > cap) {
+      d.push_back(make_int2(r, rp[r]));
+      r0 = r;
+    }
+  }
+  d.push_back(make_int2(S.rows, rp[S.rows]));
+  S.nchunk = (int)d.size() - 1;
+  S.chunk.ensure(d.size());
+  EDFA_HIP(hipMemcpyAsync(S.chunk.p, d.data(), sizeof(int2) * d.size(), hipMemcpyHostToDevice, s));
+  EDFA_HIP(hipStreamSynchronize(s));
+  S.chunk_k = k;
+}
+template void build_row_chunks<double>(Sell<double> &, int, hipStream_t);
+template void build_row_chunks<float>(Sell<float> &, int, hipStream_t);
+
+constexpr int CHUNK_G = 8;   // lanes per row in the sums
+
+template <class V, class X, int K>
+__global__ __launch_bounds__(SPMV_T) void k_spmv_chunk(const int *__restrict__ rp,
+                                                       const int *__restrict__ col,
+                                                       const V *__restrict__ val,
+                                                       const int2 *__restrict__ desc,
+                                                       int nchunk, const X *__restrict__ x,
+                                                       X *__restrict__ y, double alpha,
+                                                       const X *__restrict__ b, double beta,
+                                                       double gamma, RowMask mk) {
+  using A = typename AccT<V, X>::type;
+  constexpr int CAP = 64 * K;
+  __shared__ A buf[SPMV_T / 64][CAP];
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int c = blockIdx.x * (SPMV_T / 64) + wv;
+  if (c >= nchunk) return;
+  const int2 d0 = desc[c], d1 = desc[c + 1];
+  const int r0 = d0.x, r1 = d1.x, e0 = d0.y, e1 = d1.y;
+  if (mk.seg) {
+    const int s0 = mk.seg[r0], s1 = mk.seg[r1 - 1];
+    if (s0 == s1 && !mk.act[s0 * mk.stride]) return;
+  }
+  auto finish = [&](int row, A sum) {
+    if (mk.seg && !mk.act[mk.seg[row] * mk.stride]) return;
+    A out = (A)alpha * sum;
+    if (b) out += (A)beta * (A)b[row];
+    if (gamma != 0.0) out += (A)gamma * (A)x[row];
+    y[row] = (X)out;
+  };
+  if (e1 - e0 > CAP) {
+    // one long row: the wavefront strides over it, K entries in flight per lane
+    A s = 0;
+    for (int p0 = e0 + lane; p0 < e1; p0 += 64 * K) {
+      int cc[K];
+      V v[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int p = min(p0 + 64 * k, e1 - 1);
+        cc[k] = col[p];
+        v[k] = val[p];
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) s += (p0 + 64 * k < e1 ? (A)v[k] : A(0)) * (A)x[cc[k]];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) finish(r0, s);
+    return;
+  }
+  // row starts of the chunk's first 64 rows (one load per lane, beside the entry loads)
+  const int rpl = rp[min(r0 + lane, r1)];
+  int cc[K];
+  V v[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    // past the chunk's end: re-read its last entry (valid, weight zero)
+    const int p = max(min(e0 + 64 * k + lane, e1 - 1), 0);
+    cc[k] = col[p];
+    v[k] = val[p];
+  }
+  A *mine = buf[wv];
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    mine[64 * k + lane] = (e0 + 64 * k + lane < e1 ? (A)v[k] : A(0)) * (A)x[cc[k]];
+  // the products of other lanes of this wavefront are read below
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const int nr = r1 - r0;
+  const int g = lane / CHUNK_G, gl = lane % CHUNK_G;
+  for (int q = 0; q < nr; q += 64 / CHUNK_G) {   // uniform trip count
+    const int ri = q + g;
+    int a = __shfl(rpl, min(ri, 63)), e = __shfl(rpl, min(ri + 1, 63));
+    if (ri >= 64) a = rp[min(r0 + ri, r1)];
+    if (ri + 1 >= 64) e = rp[min(r0 + ri + 1, r1)];
+    A s = 0;
+    if (ri < nr)
+      for (int p = a - e0 + gl; p < e - e0; p += CHUNK_G) s += mine[p];
+#pragma unroll
+    for (int o = CHUNK_G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, CHUNK_G);
+    if (gl == 0 && ri < nr) finish(r0 + ri, s);
+  }
+}
+
 // Launch helper: the extended launch records e0/e1 around the kernel when given; plain
 // launches otherwise (the form stream capture records).
 template <class K, class... Args>
@@ -534,7 +665,13 @@ void spmv_sell(const Sell<V> &M, const X *x, X *y, double alpha, const X *b, dou
                hipStream_t s, double gamma, int role, hipEvent_t e0, hipEvent_t e1,
                RowMask mk) {
   if (M.rows <= 0) return;
-  if (M.lanes > 1) {
+  if (M.lanes == SPMV_CHUNKED) {
+    if (M.chunk_k != CHUNK_K)
+      fail(EDFA_ERR_ARG, "the chunk kernel needs the chunk descriptors of its matrix");
+    const int nb = ceil_div(M.nchunk, SPMV_T / 64);
+    launch_timed(k_spmv_chunk<V, X, CHUNK_K>, nb, s, e0, e1, M.csr_rp, M.csr_col, M.csr_val,
+                 (const int2 *)M.chunk.p, M.nchunk, x, y, alpha, b, beta, gamma, mk);
+  } else if (M.lanes > 1) {
     const int nb = ceil_div((long long)M.rows * M.lanes, SPMV_T);
     const bool deep = M.depth == 4;
 #define EDFA_VEC(LN, UU)                                                                      \

@@ -756,7 +756,7 @@ static void stage2_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
   EDFA_HIP(hipMemsetAsync(P.flags.p + 2, 0, sizeof(int), s));
   D.blocker.ensure(ne);
   EDFA_HIP(hipMemsetAsync(D.blocker.p, 0xff, sizeof(int) * (size_t)ne, s));
-  int rounds = 0;
+  int rounds = 0, list_rounds = 0;
   int nlist = ne;                 // vertices each round visits
   const int *list = nullptr;      // nullptr: all of them
   D.jplist.ensure(ne);
@@ -770,6 +770,7 @@ static void stage2_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
                          P.flags.p + 2, P.flags.p + 1);
     EDFA_CHECK_LAUNCH();
     rounds += batch;
+    if (list) list_rounds += batch;
     const int done = read_scalar(P.flags.p + 2, s);
     if (done >= ne) break;
     if (rounds > 2 * ne + 64) fail(EDFA_ERR_BREAKDOWN, "colouring did not finish");
@@ -783,6 +784,8 @@ static void stage2_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
       list = D.jplist.p;
     }
   }
+  P.color_rounds = rounds;
+  P.color_list_rounds = list_rounds;
   if (read_scalar(P.flags.p + 1, s) != 0x7fffffff)
     fail(EDFA_ERR_CAPACITY, "more than %d colours needed", MAX_COLORS);
   EDFA_HIP(hipMemsetAsync(P.flags.p + 3, 0, sizeof(int), s));

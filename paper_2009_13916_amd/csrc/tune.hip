@@ -3,13 +3,14 @@
 // Every matrix the solve multiplies (the system matrix, the FSAI factor and its transpose,
 // the coupling blocks, the ILU(0) factors and their approximate inverses, and their
 // transposes once built) is timed with the SELL kernel (one lane per row, 4 or 8 entries
-// in flight per lane) and with the CSR kernel at 2, 4, 8, 16 and 32 lanes per row (2 or 4
-// entries in flight per lane); the fastest choice is kept in the preconditioner handle
-// and re-applied whenever the copies are rebuilt (the next setup rebuilds them with the
-// default choice).
+// in flight per lane), with the CSR kernel at 2, 4, 8, 16 and 32 lanes per row (2 or 4
+// entries in flight per lane) and, for matrices with long rows, with the chunk kernel; the
+// fastest choice is kept in the preconditioner handle and re-applied whenever the copies
+// are rebuilt (the next setup rebuilds them with the default choice).
 #include <hip/hip_ext.h>
 
 #include <algorithm>
+#include <cmath>
 
 #include "precond.hpp"
 
@@ -20,12 +21,21 @@ namespace {
 struct Variant {
   int lanes, depth;
 };
-constexpr Variant kVariants[EDFA_TUNE_VARIANTS] = {{0, 4},  {0, 8},  {2, 2},  {2, 4},
-                                                   {4, 2},  {4, 4},  {8, 2},  {8, 4},
-                                                   {16, 2}, {16, 4}, {32, 2}, {32, 4}};
+constexpr Variant kVariants[EDFA_TUNE_VARIANTS] = {
+    {0, 4},  {0, 8},  {2, 2},  {2, 4},  {4, 2},  {4, 4},           {8, 2},
+    {8, 4},  {16, 2}, {16, 4}, {32, 2}, {32, 4}, {SPMV_CHUNKED, CHUNK_K}};
+constexpr int CHUNK_VARIANT = 12;
+
+// The chunk kernel runs only on matrices that carry chunk descriptors (long rows); others
+// keep their kernel.
+template <class M_>
+bool can_run(const M_ &M, const Variant &v) {
+  return v.lanes != SPMV_CHUNKED || M.chunk_k == CHUNK_K;
+}
 
 template <class M_>
 void set_kernel(M_ &M, const Variant &v) {
+  if (!can_run(M, v)) return;
   M.lanes = v.lanes;
   M.depth = v.depth;
 }
@@ -138,12 +148,15 @@ int tune_one(Sell<V> &M, int role, TuneBufs &B, hipStream_t s, hipEvent_t e0, hi
   y.ensure(std::max(M.rows, 1));
   hipLaunchKernelGGL(k_fill_ones<V>, dim3(ceil_div(nx, 256)), dim3(256), 0, s, x.p, (long long)nx);
   EDFA_CHECK_LAUNCH();
-  // the default kernel (SELL, 4 in flight, for short rows; CSR with 8 lanes, 2 in flight,
-  // for long ones) is kept unless another variant is at least TUNE_MARGIN faster, so timing
-  // noise does not flip the choice between equivalent kernels
-  const int dflt = M.rows > 0 && default_spmv_lanes((double)M.nnz / M.rows) > 1 ? 6 : 0;
+  // the default kernel (SELL, 4 in flight, for short rows; the chunk kernel for long ones)
+  // is kept unless another variant is at least TUNE_MARGIN faster, so timing noise does not
+  // flip the choice between equivalent kernels
+  const int dflt =
+      M.rows > 0 && default_spmv_lanes((double)M.nnz / M.rows) == SPMV_CHUNKED ? CHUNK_VARIANT : 0;
   for (int v = 0; v < EDFA_TUNE_VARIANTS; ++v)
-    us[v] = 1e3f * time_variant(M, kVariants[v], role, x, y, B.flush, s, e0, e1);
+    us[v] = can_run(M, kVariants[v])
+                ? 1e3f * time_variant(M, kVariants[v], role, x, y, B.flush, s, e0, e1)
+                : INFINITY;
   int best = dflt;
   for (int v = 0; v < EDFA_TUNE_VARIANTS; ++v)
     if (us[v] < us[best] * (1.0f - TUNE_MARGIN)) best = v;

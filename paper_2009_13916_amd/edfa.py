@@ -51,7 +51,8 @@ class _Params(C.Structure):
     _fields_ = [("variant", C.c_int32), ("static_level", C.c_int32), ("n_add", C.c_int32),
                 ("n_ent", C.c_int32), ("it_max", C.c_int32), ("tau_filt", C.c_double),
                 ("filt_mode", C.c_int32), ("precision", C.c_int32),
-                ("schur_solver", C.c_int32), ("isai_steps", C.c_int32)]
+                ("schur_solver", C.c_int32), ("isai_steps", C.c_int32),
+                ("htilde_retry", C.c_int32)]
 
 
 class _PrecondInfo(C.Structure):
@@ -59,13 +60,29 @@ class _PrecondInfo(C.Structure):
                 ("nnz_S", C.c_int64), ("nnz_GF", C.c_int64), ("nnz_L", C.c_int64),
                 ("nnz_U", C.c_int64), ("nnz_ML", C.c_int64), ("nnz_MU", C.c_int64),
                 ("n_colors", C.c_int32), ("max_pattern", C.c_int32), ("mu", C.c_double),
-                ("t_stage1_ms", C.c_double), ("t_stage2_ms", C.c_double)]
+                ("t_stage1_ms", C.c_double), ("t_stage2_ms", C.c_double),
+                ("nnz_H_raw", C.c_int64), ("htilde_retry_rows", C.c_int32),
+                ("color_rounds", C.c_int32), ("color_list_rounds", C.c_int32)]
 
 
 class _SolveParams(C.Structure):
     _fields_ = [("restart", C.c_int32), ("max_iter", C.c_int32), ("flexible", C.c_int32),
                 ("transpose", C.c_int32), ("use_graph", C.c_int32), ("profile", C.c_int32),
-                ("rtol", C.c_double)]
+                ("rtol", C.c_double), ("method", C.c_int32)]
+
+METHOD = {"gmres": 0, "bicgstab": 1}
+
+
+class _TransientParams(C.Structure):
+    _fields_ = [("n_steps", C.c_int32), ("t_end", C.c_double), ("dt0", C.c_double),
+                ("dt_mult", C.c_double), ("dt_max", C.c_double), ("dp_target", C.c_double),
+                ("porosity", C.c_double), ("stage1_every", C.c_int32), ("solve", _SolveParams)]
+
+
+class _StepInfo(C.Structure):
+    _fields_ = [("t", C.c_double), ("dt", C.c_double), ("dp_max", C.c_double),
+                ("chi_inf", C.c_double), ("iterations", C.c_int32), ("converged", C.c_int32),
+                ("t_setup_ms", C.c_double), ("t_solve_ms", C.c_double)]
 
 
 class _SolveInfo(C.Structure):
@@ -73,18 +90,22 @@ class _SolveInfo(C.Structure):
                 ("relres_est", C.c_double), ("relres_true", C.c_double),
                 ("t_solve_ms", C.c_double), ("spmv_avg_ms", C.c_double),
                 ("spmv_count", C.c_int32), ("apply_avg_ms", C.c_double),
-                ("apply_count", C.c_int32)]
+                ("apply_count", C.c_int32), ("slot_ms", C.c_double * 16),
+                ("slot_launches", C.c_int32 * 16)]
 
 
 TUNE_SLOTS = ("A", "A^T", "G_F", "G_F^T", "L", "U", "M_L", "M_U", "L^T", "U^T", "M_L^T",
               "M_U^T", "A_ppi", "A_pip", "A_pip^T", "A_ppi^T")
-# (lanes per row, entries in flight per lane); lanes 1 = the SELL kernel, else CSR
+# (lanes per row, entries in flight per lane); lanes 1 = the SELL kernel, -1 = the chunk
+# kernel (long rows only), else CSR
 TUNE_VARIANTS = ((1, 4), (1, 8), (2, 2), (2, 4), (4, 2), (4, 4), (8, 2), (8, 4), (16, 2),
-                 (16, 4), (32, 2), (32, 4))
+                 (16, 4), (32, 2), (32, 4), (-1, 12))
 
 
 def variant_name(v):
     lanes, depth = TUNE_VARIANTS[v]
+    if lanes == -1:
+        return f"chunk/{depth}"
     return f"sell/{depth}" if lanes == 1 else f"csr{lanes}/{depth}"
 
 
@@ -125,6 +146,8 @@ def load():
             "edfa_solve": (C.c_int, [vp, vp, vp, vp, C.POINTER(_SolveParams), vp,
                                      C.POINTER(_SolveInfo)]),
             "edfa_grad_logk": (C.c_int, [vp, vp, vp, vp, vp]),
+            "edfa_transient": (C.c_int, [vp, vp, C.POINTER(_TransientParams), vp, vp,
+                                         C.POINTER(_StepInfo), C.POINTER(i32)]),
             "edfa_autotune": (C.c_int, [vp, vp, C.POINTER(i32), C.POINTER(_TuneSlot)]),
             "edfa_set_variant": (C.c_int, [vp, i32, i32]),
         }
@@ -146,7 +169,7 @@ def exported_symbols():
                         "edfa_export_rhs", "edfa_spmv", "edfa_setup", "edfa_setup_stage2", "edfa_resetup",
                         "edfa_precond_destroy", "edfa_precond_get_info", "edfa_export_precond",
                         "edfa_apply", "edfa_solve", "edfa_grad_logk", "edfa_autotune",
-                        "edfa_set_variant")
+                        "edfa_set_variant", "edfa_transient")
             if hasattr(L, n)]
 
 
@@ -249,11 +272,12 @@ class Params:
     precision: int = 0          # 0 FP64, 1 FP32 setup + application
     schur: str = "isai"
     isai_steps: int = 1
+    htilde_retry: int = 0       # rows of H~ with a wider support of t take the second pass
 
     def c(self):
         return _Params(STATIC if self.variant == "static" else DYNAMIC, self.static_level,
                        self.n_add, self.n_ent, self.it_max, float(self.tau), FILT[self.filt],
-                       self.precision, SCHUR[self.schur], self.isai_steps)
+                       self.precision, SCHUR[self.schur], self.isai_steps, self.htilde_retry)
 
 
 class Precond:
@@ -336,15 +360,38 @@ class Precond:
 
 
 def solve(system: System, pre: Precond, b, rtol=1e-8, restart=50, max_iter=5000, flexible=False,
-          transpose=False, use_graph=False, profile=False):
-    """Right-preconditioned (F)GMRES(restart), x0 = 0.  Returns (x, info dict, status)."""
+          transpose=False, use_graph=False, profile=False, method="gmres"):
+    """Right-preconditioned (F)GMRES(restart) or Bi-CGStab (method="bicgstab"), x0 = 0.
+    Returns (x, info dict, status)."""
     x = torch.zeros_like(b)
     prm = _SolveParams(restart, max_iter, int(flexible), int(transpose), int(use_graph),
-                       int(profile), float(rtol))
+                       int(profile), float(rtol), METHOD[method])
     inf = _SolveInfo()
     st = _check(load().edfa_solve(system._h, pre._h, _ptr(b), _ptr(x), C.byref(prm), _stream(),
                                   C.byref(inf)))
-    return x, {f: getattr(inf, f) for f, _ in _SolveInfo._fields_}, st
+    out = {f: getattr(inf, f) for f, _ in _SolveInfo._fields_}
+    # per-matrix product timings of a profiled solve, by tuner slot name
+    out["slot_ms"] = {TUNE_SLOTS[q]: inf.slot_ms[q] for q in range(16) if inf.slot_launches[q]}
+    out["slot_launches"] = {TUNE_SLOTS[q]: inf.slot_launches[q] for q in range(16)
+                            if inf.slot_launches[q]}
+    return x, out, st
+
+
+def transient(system: System, pre: Precond, n_steps, dt0, dt_mult=2.0, dt_max=float("inf"),
+              dp_target=float("inf"), porosity=0.2, t_end=0.0, stage1_every=0, rtol=1e-8,
+              restart=50, max_iter=5000, flexible=False, method="gmres"):
+    """Adaptive transient sequence (eq. delta_t_dyn, eq. CFL_number) from the system's p_prev.
+    Returns (u of the last step, list of per-step dicts, status)."""
+    u = torch.zeros(system.info["n"], dtype=torch.float64, device="cuda")
+    sp = _SolveParams(restart, max_iter, int(flexible), 0, 0, 0, float(rtol), METHOD[method])
+    prm = _TransientParams(int(n_steps), float(t_end), float(dt0), float(dt_mult), float(dt_max),
+                           float(dp_target), float(porosity), int(stage1_every), sp)
+    recs = (_StepInfo * int(n_steps))()
+    taken = C.c_int32(0)
+    st = _check(load().edfa_transient(system._h, pre._h, C.byref(prm), _ptr(u), _stream(), recs,
+                                      C.byref(taken)))
+    steps = [{f: getattr(recs[k], f) for f, _ in _StepInfo._fields_} for k in range(taken.value)]
+    return u, steps, st
 
 
 def grad_logk(system: System, u, lam):

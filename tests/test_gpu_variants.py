@@ -1,7 +1,8 @@
 """Every sparse-product kernel variant (SELL with 4 or 8 entries in flight, on the plain or the
-length-sorted layout; CSR with 2..32 lanes per row and 2 or 4 entries in flight) computes the
-same products: pinned on every matrix, the EDFA application, its transpose and a GMRES solve
-match the oracle, for one grid and for a batch whose converged grids are masked."""
+length-sorted layout; CSR with 2..32 lanes per row and 2 or 4 entries in flight; the chunk
+kernel on matrices with long rows) computes the same products: pinned on every matrix, the
+EDFA application, its transpose and a GMRES solve match the oracle, for one grid and for a
+batch whose converged grids are masked."""
 import numpy as np
 import pytest
 import torch
@@ -22,14 +23,17 @@ def case():
     return prob, o, E, mhfe.direct_solve(o)
 
 
-@pytest.mark.parametrize("v", range(12))
+@pytest.mark.parametrize("v", range(13))
 def test_pinned_variant_matches_oracle(lib, case, v):
     prob, o, E, u = case
     S = lib.System(prob)
     P = lib.Precond(S, lib.Params(**PRM))
     rep = P.autotune(report=True)
-    # rows of very different lengths (the ISAI factors): the SELL copies are sorted
+    # rows of very different lengths (the ISAI factors): the SELL copies are sorted, and the
+    # chunk kernel (their default) runs on them
     assert rep["M_L"]["sell_sorted"] and rep["M_U"]["sell_sorted"]
+    assert np.isfinite(rep["M_L"]["us"]["chunk/12"]) and np.isfinite(rep["M_U"]["us"]["chunk/12"])
+    assert not np.isfinite(rep["G_F"]["us"]["chunk/12"])
     P.set_variant(v)
     r = np.random.default_rng(v).standard_normal(o.n)
     rt = torch.tensor(r, device="cuda")
@@ -57,6 +61,32 @@ def test_pinned_variant_batch_with_masks(lib, name):
     S = lib.System(probs)
     P = lib.Precond(S, lib.Params(**kw))
     P.set_variant(name)
+    x, info, st = lib.solve(S, P, S.rhs(), rtol=1e-10)
+    assert st == 0 and info["converged"] == 3
+    xg = x.cpu().numpy()
+    nfu = S.info["nfu"]
+    f0 = c0 = 0
+    for p in probs:
+        o = mhfe.assemble(p)
+        u = mhfe.direct_solve(o)
+        xs = np.concatenate([xg[f0:f0 + o.nfu], xg[nfu + c0:nfu + c0 + o.ne]])
+        assert np.linalg.norm(xs - u) <= 1e-8 * np.linalg.norm(u)
+        f0 += o.nfu
+        c0 += o.ne
+
+
+def test_chunk_kernel_batch_with_masks(lib):
+    """The chunk kernel on the long rows of a full-tensor batch whose easy grids converge
+    first: chunks of whole rows can straddle two grids, and the masked rows are skipped."""
+    probs = [inputs.full_tensor_problem(4, sigma=0.3, corr=1.0, config_id=78),
+             inputs.full_tensor_problem(7, sigma=2.5, corr=2.0, config_id=75),
+             inputs.full_tensor_problem(5, sigma=0.5, corr=1.0, config_id=79)]
+    kw = dict(variant="dynamic", n_add=1, n_ent=6)
+    S = lib.System(probs)
+    P = lib.Precond(S, lib.Params(**kw))
+    rep = P.autotune(report=True)
+    assert np.isfinite(rep["M_L"]["us"]["chunk/12"])
+    P.set_variant("chunk/12")
     x, info, st = lib.solve(S, P, S.rhs(), rtol=1e-10)
     assert st == 0 and info["converged"] == 3
     xg = x.cpu().numpy()

@@ -91,12 +91,25 @@ def test_bench_helpers(tmp_path):
     sys.path.insert(0, ROOT)
     import bench
     assert bench.spmv_bytes(10, 4) == 12 * 10 + 4 * 5 + 8 * 4 + 8 * 4
+    r = {"value_bytes": 8, "nnz": 10, "rows": 4, "cols": 4}
+    assert bench.slot_bytes(r) == bench.spmv_bytes(10, 4)
+    assert bench.kernel_label("chunk/12", "M_L", 1).startswith("k_spmv_chunk<double, double, 12>")
+    assert bench.kernel_label("sell/4", "G_F", 1).startswith("k_spmv_sell<double, double, 1, 4>")
+    # per-kernel totals of a profiled solve: two matrices on one kernel are summed
+    info = {"slot_ms": {"M_L": 0.04, "M_U": 0.04, "G_F": 0.016},
+            "slot_launches": {"M_L": 10, "M_U": 10, "G_F": 20}}
+    rep = {k: {"variant": v, "value_bytes": 8, "nnz": 1000, "rows": 100, "cols": 100}
+           for k, v in (("M_L", "chunk/12"), ("M_U", "chunk/12"), ("G_F", "sell/4"))}
+    fam, kern = bench.families(info, rep, 10)
+    k = kern["k_spmv_chunk<double, double, 12>"]
+    assert k["launches"] == 20 and abs(k["ms"] - 0.8) < 1e-12 and k["matrices"] == ["M_L", "M_U"]
+    assert {f["matrix"] for f in fam} == {"M_L", "M_U", "G_F"}
     # the committed traffic record is read only for the kernel source it was taken on
-    t = bench.measured_traffic()
-    sha = bench.spmv_kernel_sha()
-    path = os.path.join(ROOT, "profiles", "spmv_sell_operator_full_tensor_64cubed_traffic.md")
-    rec = json.loads(open(path).read().split("```json")[1].split("```")[0])
-    assert (t is not None) == (rec["kernel_sha"] == sha)
+    if os.path.exists(bench.TRAFFIC):
+        rec = json.loads(open(bench.TRAFFIC).read().split("```json")[1].split("```")[0])
+        for name in rec["kernels"]:
+            t = bench.measured_traffic(name)
+            assert (t is not None) == (rec["kernel_sha"] == bench.spmv_kernel_sha())
 
 
 def test_bench_refuses_more_than_one_gpu():

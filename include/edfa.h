@@ -213,6 +213,21 @@ edfa_status edfa_export_precond(edfa_precond pre, int32_t what, int32_t *rowptr,
 edfa_status edfa_apply(edfa_precond pre, int32_t transpose, const double *r, double *z,
                        hipStream_t stream);
 
+/* edfa_apply without any device allocation, for callers that cannot allocate (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation).  Its workspace
+ * -- 2 N_f^u + 5 N_e values in the preconditioner's precision, plus two N-vectors of floats
+ * for an FP32 preconditioner, each rounded up to 256 bytes -- lives in one static device
+ * array of EDFA_NOALLOC_SCRATCH_BYTES per GPU (held until the process ends; its address is
+ * looked up on the first call on each device).  Every call on a GPU shares that array:
+ * calls that overlap on one GPU race (serialise them, e.g. on one stream).  Results equal
+ * edfa_apply's.  Errors: EDFA_ERR_ARG when the workspace exceeds the array (the message
+ * gives both sizes), or when what the application reads does not exist yet and would have
+ * to be allocated: the transposed factors (transpose = 1) and the FP32 coupling blocks are
+ * built by a first edfa_apply of the same kind (or a solve); EDFA_ERR_HIP.  Asynchronous. */
+#define EDFA_NOALLOC_SCRATCH_BYTES (64u << 20)
+edfa_status edfa_apply_noalloc(edfa_precond pre, int32_t transpose, const double *r, double *z,
+                               hipStream_t stream);
+
 typedef struct {
   int32_t restart;          /* Krylov dimension per cycle (GMRES(m)), 1..128 */
   int32_t max_iter;         /* total iterations over all cycles */

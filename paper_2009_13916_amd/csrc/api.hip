@@ -340,6 +340,16 @@ edfa_status edfa_apply(edfa_precond pre, int32_t transpose, const double *r, dou
   });
 }
 
+edfa_status edfa_apply_noalloc(edfa_precond pre, int32_t transpose, const double *r, double *z,
+                               hipStream_t stream) {
+  return guard([&] {
+    if (!pre || !r || !z) fail(EDFA_ERR_ARG, "NULL argument");
+    if (r == z) fail(EDFA_ERR_ARG, "r and z must not alias");
+    precond_apply_noalloc(*pre, transpose ? 1 : 0, r, z, stream);
+    return EDFA_OK;
+  });
+}
+
 edfa_status edfa_solve(edfa_system sys, edfa_precond pre, const double *b, double *x,
                        const edfa_solve_params *prm, hipStream_t stream, edfa_solve_info *info) {
   return guard([&] {

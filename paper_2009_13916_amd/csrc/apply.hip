@@ -6,6 +6,8 @@
 //                               the natural cell order, or colour-by-colour substitution
 //   z_pi = A~^-1 (r_pi - A_pip z_p)
 // The transpose swaps A_ppi <-> A_pip^T and uses (LU)^-T.
+#include <mutex>
+
 #include "precond.hpp"
 
 namespace edfa {
@@ -213,19 +215,98 @@ static void apply_typed(edfa_precond_s &P, PrecData<T> &D, const ApplyWork<T> &W
   prod(D.GFT_s, 3, W.t2, zpi, -1.0, nullptr, 0.0, fm);
 }
 
-void precond_apply(edfa_precond_s &P, int transpose, const double *r, double *z, hipStream_t s,
-                   RowMask mask) {
+// Device memory for the allocation-free application: a static array per GPU, its
+// address looked up once per device.  Every call on a device uses the same bytes, so calls
+// that overlap on one GPU race.
+constexpr size_t SCRATCH_BYTES = EDFA_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[MAX_DEVICES];
+
+static void *scratch_ptr() {
+  int dev = 0;
+  EDFA_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) fail(EDFA_ERR_ARG, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    EDFA_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+
+// Carves aligned vectors out of a fixed region.
+struct Carver {
+  unsigned char *base;
+  size_t cap, used = 0;
+  template <class T>
+  T *take(size_t n) {
+    const size_t bytes = ((n * sizeof(T) + 255) / 256) * 256;
+    T *p = reinterpret_cast<T *>(base + used);
+    used += bytes;
+    return p;
+  }
+};
+
+template <class T>
+static ApplyWork<T> carve_work(Carver &C, int nfu, int ne) {
+  ApplyWork<T> W;
+  W.t1 = C.take<T>(nfu);
+  W.t2 = C.take<T>(nfu);
+  W.r = C.take<T>(ne);
+  W.w = C.take<T>(ne);
+  W.res = C.take<T>(ne);
+  W.y = C.take<T>(ne);
+  W.zq = C.take<T>(ne);
+  return W;
+}
+
+// Bytes of scratch an application needs (the layout of carve_work, plus the FP32 copies
+// of the vector in and out).
+static size_t scratch_need(const edfa_precond_s &P) {
+  const edfa_system_s &S = *P.sys;
+  auto al = [](size_t b) { return ((b + 255) / 256) * 256; };
+  const size_t vb = P.prm.precision == 1 ? sizeof(float) : sizeof(double);
+  size_t need = 2 * al(vb * S.nfu) + 5 * al(vb * S.ne);
+  if (P.prm.precision == 1) need += 2 * al(sizeof(float) * (size_t)S.n);
+  return need;
+}
+
+static bool transposed_ready(const edfa_precond_s &P) {
+  const edfa_system_s &S = *P.sys;
+  auto ready = [&](const auto &D) {
+    const bool isai = P.prm.schur_solver == EDFA_SCHUR_ISAI;
+    if (isai && (D.MUT_s.rows != S.ne || D.MLT_s.rows != S.ne)) return false;
+    if ((!isai || P.prm.isai_steps > 1) && (D.UT_s.rows != S.ne || D.LT_s.rows != S.ne))
+      return false;
+    return true;
+  };
+  if (S.nfu && S.AcfT_s.rows != S.nfu) return false;
+  return S.ne == 0 || (P.prm.precision == 1 ? ready(P.f) : ready(P.d));
+}
+
+static void apply_impl(edfa_precond_s &P, int transpose, const double *r, double *z,
+                       hipStream_t s, RowMask mask, void *scr) {
   edfa_system_s &S = *P.sys;
   const RowMask fm = mask, cm = mask.offset(S.nfu);
+  Carver C{static_cast<unsigned char *>(scr), SCRATCH_BYTES};
   if (transpose) {
-    if (P.prm.precision == 1)
-      ensure_transposed_factors(P, P.f, s);
-    else
-      ensure_transposed_factors(P, P.d, s);
+    if (!scr) {
+      if (P.prm.precision == 1)
+        ensure_transposed_factors(P, P.f, s);
+      else
+        ensure_transposed_factors(P, P.d, s);
+    } else if (!transposed_ready(P)) {
+      fail(EDFA_ERR_ARG, "the transposed factors do not exist yet: build them with one "
+                         "edfa_apply(transpose = 1) or transposed solve first");
+    }
     apply_tuned(P);
   }
   if (P.prm.precision != 1) {
-    const ApplyWork<double> W = handle_work(P.d, S.nfu, S.ne);
+    const ApplyWork<double> W = scr ? carve_work<double>(C, S.nfu, S.ne)
+                                    : handle_work(P.d, S.nfu, S.ne);
     apply_typed<double>(P, P.d, W, r, z, transpose ? S.AfcT_s : S.Acf_s,
                         transpose ? S.AcfT_s : S.Afc_s, transpose, s, fm, cm);
     return;
@@ -238,6 +319,9 @@ void precond_apply(edfa_precond_s &P, int transpose, const double *r, double *z,
   bool rebuilt = false;
   for (int q = 0; q < (transpose ? 4 : 2); ++q) {
     if (cf[q].rows != src[q]->rows || cf[q].nnz != src[q]->nnz) {
+      if (scr)
+        fail(EDFA_ERR_ARG, "the FP32 coupling blocks do not exist yet: build them with one "
+                           "edfa_apply (of the same transpose) first");
       to_fp32(*src[q], cf[q], s);
       build_sell(cf[q], cs[q], S.tmp, s);
       rebuilt = true;
@@ -245,8 +329,17 @@ void precond_apply(edfa_precond_s &P, int transpose, const double *r, double *z,
   }
   if (rebuilt) apply_tuned(P);
   const int n = S.n;
-  const ApplyWork<float> W = handle_work(D, S.nfu, S.ne);
-  float *rin = P.rin_f.ensure(n), *zf = D.z.ensure(n);
+  float *rin, *zf;
+  ApplyWork<float> W;
+  if (scr) {
+    W = carve_work<float>(C, S.nfu, S.ne);
+    rin = C.take<float>(n);
+    zf = C.take<float>(n);
+  } else {
+    W = handle_work(D, S.nfu, S.ne);
+    rin = P.rin_f.ensure(n);
+    zf = D.z.ensure(n);
+  }
   hipLaunchKernelGGL((k_convert<double, float>), dim3(ceil_div(n, 256)), dim3(256), 0, s, r,
                      (long long)n, rin, mask);
   EDFA_CHECK_LAUNCH();
@@ -255,6 +348,23 @@ void precond_apply(edfa_precond_s &P, int transpose, const double *r, double *z,
   hipLaunchKernelGGL((k_convert<float, double>), dim3(ceil_div(n, 256)), dim3(256), 0, s, zf,
                      (long long)n, z, mask);
   EDFA_CHECK_LAUNCH();
+}
+
+void precond_apply(edfa_precond_s &P, int transpose, const double *r, double *z, hipStream_t s,
+                   RowMask mask) {
+  apply_impl(P, transpose, r, z, s, mask, nullptr);
+}
+
+void precond_apply_noalloc(edfa_precond_s &P, int transpose, const double *r, double *z,
+                           hipStream_t s) {
+  const size_t need = scratch_need(P);
+  if (need > SCRATCH_BYTES)
+    fail(EDFA_ERR_ARG,
+         "the allocation-free application needs %zu bytes of workspace for this system "
+         "(2 N_f^u + 5 N_e preconditioner values, plus 2 N floats in FP32); its static "
+         "array holds %zu",
+         need, SCRATCH_BYTES);
+  apply_impl(P, transpose, r, z, s, RowMask{}, scratch_ptr());
 }
 
 }  // namespace edfa

@@ -143,6 +143,8 @@ void precond_stage1(edfa_precond_s &P, hipStream_t s);
 void precond_stage2(edfa_precond_s &P, hipStream_t s);
 void precond_apply(edfa_precond_s &P, int transpose, const double *r, double *z, hipStream_t s,
                    RowMask mask = {});
+void precond_apply_noalloc(edfa_precond_s &P, int transpose, const double *r, double *z,
+                           hipStream_t s);
 edfa_status gmres(edfa_system_s &S, edfa_precond_s &P, const double *b, double *x,
                   const edfa_solve_params &prm, hipStream_t s, edfa_solve_info *info);
 edfa_status bicgstab(edfa_system_s &S, edfa_precond_s &P, const double *b, double *x,

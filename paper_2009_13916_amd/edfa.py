@@ -143,6 +143,7 @@ def load():
             "edfa_export_precond": (C.c_int, [vp, i32, vp, vp, vp, vp, C.POINTER(i64),
                                               C.POINTER(i32), vp]),
             "edfa_apply": (C.c_int, [vp, i32, vp, vp, vp]),
+            "edfa_apply_noalloc": (C.c_int, [vp, i32, vp, vp, vp]),
             "edfa_solve": (C.c_int, [vp, vp, vp, vp, C.POINTER(_SolveParams), vp,
                                      C.POINTER(_SolveInfo)]),
             "edfa_grad_logk": (C.c_int, [vp, vp, vp, vp, vp]),
@@ -169,7 +170,7 @@ def exported_symbols():
                         "edfa_export_rhs", "edfa_spmv", "edfa_setup", "edfa_setup_stage2", "edfa_resetup",
                         "edfa_precond_destroy", "edfa_precond_get_info", "edfa_export_precond",
                         "edfa_apply", "edfa_solve", "edfa_grad_logk", "edfa_autotune",
-                        "edfa_set_variant", "edfa_transient")
+                        "edfa_set_variant", "edfa_transient", "edfa_apply_noalloc")
             if hasattr(L, n)]
 
 
@@ -314,9 +315,13 @@ class Precond:
                                      C.byref(nnz), C.byref(rows), _stream()))
         return rp, col[:nnz.value], val[:nnz.value], perm
 
-    def apply(self, r, transpose=False):
-        z = torch.empty_like(r)
-        _check(load().edfa_apply(self._h, int(transpose), _ptr(r), _ptr(z), _stream()))
+    def apply(self, r, transpose=False, z=None, noalloc=False):
+        """z = P^-1 r (or P^-T r).  noalloc=True calls the allocation-free entry point (the
+        library allocates nothing; z may be given to avoid torch's allocation too)."""
+        if z is None:
+            z = torch.empty_like(r)
+        fn = load().edfa_apply_noalloc if noalloc else load().edfa_apply
+        _check(fn(self._h, int(transpose), _ptr(r), _ptr(z), _stream()))
         return z
 
     def autotune(self, report=False):

@@ -74,6 +74,8 @@ class Params:
     filt: str = "none"            # "none" | "pre" | "post_S" | "post_H"
     schur: str = "isai"           # S~^-1 triangular solves: "isai" | "exact"
     isai_steps: int = 1           # ISAI applications per triangular factor (1 = plain ISAI)
+    static_axis: int = 0          # static level k: 0 all directions; 1/2/3 only along x/y/z;
+                                  # 4 along each cell's axis of largest transmissibility
 
 
 class NotSPD(RuntimeError):
@@ -128,14 +130,37 @@ def cell_neighbours(s: System, m):
     return out
 
 
-def patch_pattern(s: System, m, level, base_rows=None):
-    """Q_0 plus the unknown faces of all cells within face-graph distance `level`."""
+def flow_axis(s: System, m):
+    """Axis d of cell m with the largest transmissibility W_(d-,d-) + W_(d+,d+): the
+    direction in which the element conducts most.  Values within 1e-12 of the largest count
+    as ties, which go to the smaller d (so the rounding of W^E does not decide)."""
+    t = [s.W[m, 2 * d, 2 * d] + s.W[m, 2 * d + 1, 2 * d + 1] for d in range(3)]
+    top = max(t)
+    return next(d for d in range(3) if t[d] >= top * (1.0 - 1e-12))
+
+
+def axis_neighbours(s: System, m, d):
+    """Face neighbours of cell m across its two faces normal to axis d."""
+    out = []
+    for a in (2 * d, 2 * d + 1):
+        for e in s.topo.face_cells[s.topo.cell_faces[m, a]]:
+            if e >= 0 and e != m:
+                out.append(int(e))
+    return out
+
+
+def patch_pattern(s: System, m, level, base_rows=None, axis=0):
+    """Q_0 plus the unknown faces of all cells within face-graph distance `level` (axis 0),
+    or within `level` steps along one axis only: x, y, z (axis 1, 2, 3) or the cell's own
+    axis of largest transmissibility (axis 4), a strip in the spirit of the paper's
+    directional static patterns."""
     cells = {m}
     frontier = {m}
+    d = None if axis == 0 else (flow_axis(s, m) if axis == 4 else axis - 1)
     for _ in range(level):
         nxt = set()
         for e in frontier:
-            nxt.update(cell_neighbours(s, e))
+            nxt.update(cell_neighbours(s, e) if d is None else axis_neighbours(s, e, d))
         nxt -= cells
         cells |= nxt
         frontier = nxt
@@ -207,8 +232,8 @@ def local_cell(s: System, m, prm: Params, base_rows=None) -> CellResult:
     rhs_g = lambda Q: np.array([dense_a.get(int(q), 0.0) for q in Q])
     rhs_f = lambda Q: np.array([dense_f.get(int(q), 0.0) for q in Q])
     if prm.variant == "static":
-        Q = (patch_pattern(s, m, prm.static_level, base_rows) if prm.static_level > 0
-             else base_pattern(s, m, base_rows))
+        Q = (patch_pattern(s, m, prm.static_level, base_rows, prm.static_axis)
+             if prm.static_level > 0 else base_pattern(s, m, base_rows))
         M = restricted_matrix(s, Q)
         g = _chol_solve(M, rhs_g(Q), m)
         f = _chol_solve(M, rhs_f(Q), m)

@@ -212,6 +212,57 @@ def test_patch_levels_near_boundaries():
             assert got == _bfs_faces(s, m, lev) | set(edfa.base_pattern(s, m).tolist())
 
 
+@pytest.mark.parametrize("kind", ["iso", "full"])
+def test_axis_strip_counts(kind):
+    """Strip patterns along one axis, interior cell: the cells within k steps along the axis
+    are a line of 2k + 1 cells with 2k shared faces, so 6(2k + 1) - 2k faces (16 at k = 1,
+    26 at k = 2), in union with the base pattern.  Iso bricks: the base adds the far face of
+    each of the four side neighbours (12 - 6 - 2 = 4 faces outside the strip): 20 and 30.
+    Full W: the base already holds every face of the six face neighbours (6 + 6 * 5 = 36),
+    so level 1 stays at 36 and level 2 adds the five new faces of each of the two far cells:
+    46.  A strip along the wrong axis, or a level-k ball instead of a line, changes the
+    count."""
+    n = 7
+    if kind == "iso":
+        prob = inputs.lognormal_iso_problem(n, sigma=0.5, config_id=94)
+    else:
+        prob = inputs.full_tensor_problem(n, n, n, sigma=1.0, corr=2.0, config_id=95)
+    s = mhfe.assemble(prob)
+    m = 3 + n * (3 + n * 3)
+    want = {"iso": {1: 20, 2: 30}, "full": {1: 36, 2: 46}}[kind]
+    for axis in (1, 2, 3):
+        for lev in (1, 2):
+            Q = edfa.patch_pattern(s, m, lev, axis=axis)
+            assert len(Q) == want[lev], (axis, lev, len(Q))
+            # the strip's own faces: the cells m + t e_d, |t| <= lev, all their faces
+            d = axis - 1
+            step = (1, n, n * n)[d]
+            cells = [m + t * step for t in range(-lev, lev + 1)]
+            strip = {int(s.uidx[f]) for c in cells for f in s.topo.cell_faces[c] if s.uidx[f] >= 0}
+            assert strip <= set(Q.tolist())
+            assert set(Q.tolist()) == strip | set(edfa.base_pattern(s, m).tolist())
+
+
+def test_flow_axis_follows_the_largest_transmissibility():
+    """K = diag(kx, ky, kz) on cubes: the transmissibility of axis d is proportional to
+    K_dd, so the strip of axis 4 runs along the largest diagonal entry (ties to x)."""
+    n = 5
+    prob = inputs.lognormal_iso_problem(n, sigma=0.0, config_id=98)
+    ne = n ** 3
+    K = np.zeros((ne, 6))
+    rng = np.random.default_rng(0)
+    diag = rng.uniform(0.1, 10.0, (ne, 3))
+    diag[0] = [2.0, 2.0, 1.0]                    # a tie: x wins
+    K[:, :3] = diag
+    import dataclasses
+    s = mhfe.assemble(dataclasses.replace(prob, K=K))
+    for m in range(ne):
+        want = int(np.argmax(diag[m]))
+        assert edfa.flow_axis(s, m) == want
+        assert np.array_equal(edfa.patch_pattern(s, m, 1, axis=4),
+                              edfa.patch_pattern(s, m, 1, axis=want + 1))
+
+
 # ---------------------------------------------------------------------------------------------
 # density mu
 # ---------------------------------------------------------------------------------------------

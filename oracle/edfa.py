@@ -407,9 +407,13 @@ def stage1(s: System, prm: Params, base_rows=None, workers=1) -> Stage1:
 # Stage 2 (Algorithm 2)
 # ----------------------------------------------------------------------------
 def greedy_coloring(P: sp.csr_matrix):
-    """Greedy first-fit colouring of the graph of P + P^T, vertices by decreasing fmix32."""
+    """Greedy first-fit colouring of the graph of P + P^T, vertices by decreasing fmix32.
+
+    The graph is structural: every stored entry is an edge, explicit zeros included (the
+    patterns keep entries that cancel to zero), so the sum is taken on patterns of ones."""
     n = P.shape[0]
-    G = (abs(P) + abs(P.T)).tocsr()
+    ones = _ones(P)
+    G = (ones + ones.T).tocsr()
     order = np.argsort(-fmix32(np.arange(n)).astype(np.int64), kind="stable")
     color = -np.ones(n, dtype=np.int64)
     for v in order:

@@ -176,14 +176,39 @@ def test_coloring_is_valid_greedy(small_full):
     st1 = edfa.stage1(s, prm)
     S = edfa.structural_sub(s.Acc, st1.H)
     col = edfa.greedy_coloring(S)
-    G = (abs(S) + abs(S.T)).tocsr()
-    pri = edfa.fmix32(np.arange(S.shape[0])).astype(np.int64)
-    for v in range(S.shape[0]):
-        nb = G.indices[G.indptr[v]:G.indptr[v + 1]]
-        nb = nb[nb != v]
+    _check_structural_greedy(S, col)
+
+
+def _check_structural_greedy(S, col):
+    """Every stored entry (i, j) of S, explicit zeros included, is an edge of the graph."""
+    S = S.tocsr()
+    n = S.shape[0]
+    nbrs = [set() for _ in range(n)]
+    for i in range(n):
+        for j in S.indices[S.indptr[i]:S.indptr[i + 1]]:
+            if j != i:
+                nbrs[i].add(int(j))
+                nbrs[int(j)].add(i)
+    pri = edfa.fmix32(np.arange(n)).astype(np.int64)
+    for v in range(n):
+        nb = np.array(sorted(nbrs[v]), dtype=np.int64)
         assert np.all(col[nb] != col[v])
         higher = nb[pri[nb] > pri[v]]
         assert set(range(col[v])) <= set(col[higher].tolist())
+
+
+def test_coloring_counts_explicit_zeros_as_edges():
+    """A pattern entry whose value is an exact zero (structural patterns keep them) is an edge:
+    the two vertices get different colours.  A value-based graph would drop it."""
+    n = 6
+    rows = [0, 1, 2, 3, 4, 5, 0, 3, 1, 4]
+    cols = [0, 1, 2, 3, 4, 5, 3, 0, 4, 1]
+    vals = [4.0, 4.0, 4.0, 4.0, 4.0, 4.0, 0.0, 0.0, -1.0, -1.0]
+    S = sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
+    assert S.nnz == 10                           # the zeros are stored
+    col = edfa.greedy_coloring(S)
+    assert col[0] != col[3] and col[1] != col[4]
+    _check_structural_greedy(S, col)
 
 
 def test_filtration_keeps_diagonal_and_drops_small(small_full):

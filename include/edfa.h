@@ -91,8 +91,10 @@ typedef struct {
   int32_t n_faces;             /* N_f (all faces) */
   int32_t n_face_unknowns;     /* N_f^u (non-Dirichlet faces) */
   int32_t n;                   /* N = N_f^u + N_e */
-  int32_t axis_structure;      /* 1: every cell an axis-aligned brick with diagonal K, so
-                                  W^E is block-diagonal per direction (smaller patterns) */
+  int32_t axis_structure;      /* 1: every cell of every grid an axis-aligned brick with
+                                  diagonal K, so W^E is block-diagonal per direction.  The
+                                  smaller structural pattern this allows is chosen grid by
+                                  grid: a grid of a batch has the pattern it has alone */
   int64_t nnz;                 /* nnz of the whole matrix */
   int64_t nnz_block[4];        /* A_pipi, A_pip, A_ppi, A_pp */
 } edfa_system_info;

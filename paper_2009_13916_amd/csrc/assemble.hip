@@ -59,8 +59,9 @@ __device__ inline void chol_inverse(const double (&L)[N][N], double (&out)[N][N]
 }
 
 // Per cell: B^E by quadrature, volume, W^E = (B^E)^-1, the storage coefficient and the
-// previous pressure; clears *axis when the cell is not an axis-aligned brick with
-// diagonal K; records the first bad cell.
+// previous pressure; clears axis[g] when the cell is not an axis-aligned brick with
+// diagonal K (g its grid: the structural pattern is chosen per grid); records the first
+// bad cell.
 // Smallest tag + index of a non-finite entry of a[0, n) (tag in the bits above 40).
 __global__ void k_first_nonfinite(const double *__restrict__ a, long long n, long long tag,
                                   long long *first) {
@@ -73,7 +74,8 @@ __global__ void k_element(const GridDesc *__restrict__ grids, int ngrid, int ne,
                           double *vol, double *cstore, double *p_prev, int *axis, int *bad) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= ne) return;
-  const GridDesc G = grids[grid_of(grids, ngrid, e, true)];
+  const int gi = grid_of(grids, ngrid, e, true);
+  const GridDesc G = grids[gi];
   int i, j, k;
   cell_ijk(G, e, i, j, k);
   double X[8][3];
@@ -156,7 +158,7 @@ __global__ void k_element(const GridDesc *__restrict__ grids, int ngrid, int ne,
   }
   double Wm[6][6];
   chol_inverse<6>(B, Wm);
-  if (!cell_axis) atomicAnd(axis, 0);
+  if (!cell_axis) atomicAnd(axis + gi, 0);
   double *We = W + 36 * (size_t)e;
   for (int a = 0; a < 6; ++a)
     for (int b = 0; b < 6; ++b) {
@@ -197,7 +199,6 @@ struct RowCtx {
   const GridDesc *grids;
   int ngrid;
   int nfu;
-  int axis;
   const double *W;
   const double *vol;
   const double *cstore;
@@ -242,7 +243,7 @@ __device__ int build_row(const RowCtx &X, int r, int *cols, double *vals, double
       double L = 0.0;
       for (int b = 0; b < 6; ++b) L += We[6 * a + b];
       for (int b = 0; b < 6; ++b) {
-        if (!structural(X.axis, a, b)) continue;
+        if (!structural(G.axis, a, b)) continue;
         const int g = cell_face(G, i, j, k, b);
         const double v = -We[6 * a + b];
         const int u = X.uidx[g];
@@ -288,7 +289,7 @@ __device__ int build_row(const RowCtx &X, int r, int *cols, double *vals, double
     for (int a = 0; a < 6; ++a) dg += Cc[a] * L[a];
     for (int a = 0; a < 6; ++a) {
       for (int b = 0; b < 6; ++b)
-        if (b != a && structural(X.axis, a, b)) own[b] -= Cc[a] * We[6 * a + b];
+        if (b != a && structural(G.axis, a, b)) own[b] -= Cc[a] * We[6 * a + b];
       if (kd[a] == FACE_DIRICHLET) own[a] -= We[7 * a];
     }
     double r0 = 0.0;
@@ -303,7 +304,7 @@ __device__ int build_row(const RowCtx &X, int r, int *cols, double *vals, double
         int ni, nj, nk;
         cell_ijk(G, En, ni, nj, nk);
         for (int bp = 0; bp < 6; ++bp) {
-          if (bp == ap || !structural(X.axis, ap, bp)) continue;
+          if (bp == ap || !structural(G.axis, ap, bp)) continue;
           const int g = cell_face(G, ni, nj, nk, bp);
           const double v = Dc[a] * Wn[6 * ap + bp];
           const int u = X.uidx[g];
@@ -454,7 +455,6 @@ RowCtx row_ctx(const edfa_system_s &S) {
   X.grids = S.grids.p;
   X.ngrid = S.ngrid;
   X.nfu = S.nfu;
-  X.axis = S.axis;
   X.W = S.W.p;
   X.vol = S.vol.p;
   X.cstore = S.cstore.p;
@@ -552,19 +552,28 @@ void assemble_system(edfa_system_s &S, const edfa_problem *probs, int count, hip
   S.vol.ensure(ne);
   S.cstore.ensure(ne);
   S.p_prev.ensure(ne);
+  // flags: [0, count) the per-grid axis structure, [count] the first bad cell
   DBuf<int> flags;
-  flags.ensure(2);
-  const int init[2] = {1, 0x7fffffff};
-  EDFA_HIP(hipMemcpyAsync(flags.p, init, sizeof(init), hipMemcpyHostToDevice, s));
+  flags.ensure((size_t)count + 1);
+  std::vector<int> fl((size_t)count + 1, 1);
+  fl[count] = 0x7fffffff;
+  EDFA_HIP(hipMemcpyAsync(flags.p, fl.data(), sizeof(int) * fl.size(), hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(k_element, dim3(ceil_div(ne, 128)), dim3(128), 0, s, S.grids.p, count,
-                     (int)ne, S.W.p, S.vol.p, S.cstore.p, S.p_prev.p, flags.p, flags.p + 1);
+                     (int)ne, S.W.p, S.vol.p, S.cstore.p, S.p_prev.p, flags.p, flags.p + count);
   EDFA_CHECK_LAUNCH();
-  int fl[2];
-  EDFA_HIP(hipMemcpyAsync(fl, flags.p, sizeof(fl), hipMemcpyDeviceToHost, s));
+  EDFA_HIP(hipMemcpyAsync(fl.data(), flags.p, sizeof(int) * fl.size(), hipMemcpyDeviceToHost, s));
   EDFA_HIP(hipStreamSynchronize(s));
-  if (fl[1] != 0x7fffffff)
-    fail(EDFA_ERR_NOT_SPD, "cell %d: conductivity tensor not SPD or non-positive Jacobian", fl[1]);
-  S.axis = fl[0];
+  if (fl[count] != 0x7fffffff)
+    fail(EDFA_ERR_NOT_SPD, "cell %d: conductivity tensor not SPD or non-positive Jacobian",
+         fl[count]);
+  // each grid of a batch keeps its own structural pattern
+  S.axis = 1;
+  for (int g = 0; g < count; ++g) {
+    S.grids_h[g].axis = fl[g];
+    S.axis = S.axis && fl[g];
+  }
+  EDFA_HIP(hipMemcpyAsync(S.grids.p, S.grids_h.data(), sizeof(GridDesc) * count,
+                          hipMemcpyHostToDevice, s));
 
   // faces and unknown numbering
   // the boundary values outlive the call (the adjoint gradient reads them)

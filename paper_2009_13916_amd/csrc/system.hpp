@@ -14,6 +14,7 @@ struct GridDesc {
   int face0;        // first global face
   int nfx, nfy;     // x- and y-face counts of this grid
   int ncell, nface;
+  int axis;         // every cell an axis-aligned brick with diagonal K (smaller pattern)
   const double *nodes;
   const double *K;
   const double *c;

@@ -51,11 +51,16 @@ def test_assembly_matches_oracle(lib, name):
     np.testing.assert_allclose(b, o.b, rtol=1e-12, atol=1e-12 * np.abs(o.b).max())
 
 
-def test_batched_assembly_is_block_diagonal(lib):
+@pytest.mark.parametrize("mixed", [False, True])
+def test_batched_assembly_is_block_diagonal(lib, mixed):
     """A batch of grids assembles to the block-diagonal system of the individual grids,
-    with u = [pi of all grids; p of all grids]."""
+    with u = [pi of all grids; p of all grids].  Mixed: brick grids with diagonal K beside
+    a full-tensor grid keep their own smaller structural pattern (no stored zeros of the
+    full 6x6 coupling), exactly as when assembled alone."""
     probs = [inputs.lognormal_iso_problem(n, sigma=s, config_id=4, extra=i)
              for i, (n, s) in enumerate([(4, 0.5), (6, 2.0), (5, 1.0)])]
+    if mixed:
+        probs.insert(1, inputs.full_tensor_problem(5, 4, 3, sigma=2.0, corr=2.0, config_id=5))
     S = lib.System(probs)
     os_ = [mhfe.assemble(p) for p in probs]
     nfu = sum(o.nfu for o in os_)

@@ -159,6 +159,10 @@ typedef struct {
   int32_t precision;        /* 0: FP64 preconditioner; 1: FP32 setup and application */
   int32_t schur_solver;     /* EDFA_SCHUR_* */
   int32_t isai_steps;       /* ISAI applications per factor (>= 1) */
+  int32_t static_axis;      /* static_level k > 0: 0 = the cells within k face steps in every
+                               direction; 1/2/3 = only along x/y/z (a strip of 2k + 1 cells);
+                               4 = along each cell's axis of largest transmissibility
+                               W_(d-,d-) + W_(d+,d+) (ties within 1e-12 to the smaller axis) */
   int32_t htilde_retry;     /* performance knob of the rows of H~ (patterns of up to 64): a
                                row whose support of t = A_pipi R^T g~ exceeds this many faces
                                is recomputed in a second pass with large hash tables (1..256;
@@ -181,6 +185,8 @@ typedef struct {
                                were recomputed with large tables */
   int32_t color_rounds;     /* parallel colouring rounds of the last stage 2 ... */
   int32_t color_list_rounds;/* ... of which visited only a worklist of the uncoloured cells */
+  int32_t cgs2_width;       /* basis vectors per block of the CGS2 dot passes (2, 4 or 8; set
+                               by edfa_autotune) */
 } edfa_precond_info;
 
 /* Build the preconditioner: stage 1 (Algorithm 1: restricted SPD solves on static or
@@ -240,8 +246,10 @@ typedef struct {
                                a cycle; converged grids are masked on the device) on a stream
                                of the solver's own, ordered after `stream` by events.  Same
                                results as use_graph = 0, bit for bit. */
-  int32_t profile;          /* 1: time every launch of the dominant kernels with events
-                               (eagerly run cycles only) */
+  int32_t profile;          /* 1: time every product with the system matrix and every
+                               application with events; 2: also every product inside the
+                               applications (the events add a few microseconds per product);
+                               eagerly run cycles only */
   double  rtol;             /* stop when ||b - A x|| <= rtol ||b|| (x0 = 0, Section 4) */
   int32_t method;           /* EDFA_GMRES (restart, flexible, use_graph apply) or
                                EDFA_BICGSTAB (the paper's solver, Section 4; restart,
@@ -262,10 +270,10 @@ typedef struct {
   int32_t spmv_count;
   double  apply_avg_ms;     /* profile = 1: mean duration of one preconditioner application */
   int32_t apply_count;
-  double  slot_ms[16];      /* profile = 1: mean duration of one product with each matrix,
+  double  slot_ms[16];      /* profile = 2: mean duration of one product with each matrix,
                                numbered as the slots of edfa_tune_slot (0 / 1: the system
                                matrix or its transpose) */
-  int32_t slot_launches[16];/* profile = 1: products timed per slot */
+  int32_t slot_launches[16];/* profile = 2: products timed per slot */
 } edfa_solve_info;
 
 /* Solve A x = b (or A^T x = b), x0 = 0, each grid of a batch to its own rtol, with
@@ -340,7 +348,9 @@ edfa_status edfa_grad_logk(edfa_system sys, const double *u, const double *lambd
                            hipStream_t stream);
 
 /* Launch-shape autotuner (not part of the paper's method; its results do not change what
- * is computed, only the rounding order of the sparse products).  Times every sparse matrix
+ * is computed, only the rounding order of the sparse products and of the CGS2 dot
+ * products).  It times the CGS2 dot pass with 2, 4 and 8 basis vectors per block (24
+ * vectors of the system's size, cold cache) and keeps the fastest, and times every sparse matrix
  * that the solve and the application multiply -- the system matrix (and its transpose once
  * built), the FSAI factor and its transpose, the coupling blocks, the ILU(0) factors and
  * their approximate inverses -- with the one-lane-per-row SELL kernel and with the CSR
@@ -372,6 +382,44 @@ typedef struct {
 
 edfa_status edfa_autotune(edfa_precond pre, hipStream_t stream, int32_t *tuned /* (host) */,
                           edfa_tune_slot *slots /* (host) EDFA_TUNE_SLOTS entries, may be NULL */);
+
+/* Setup tuner.  Stage 1 sorts the cells into buckets by the capacity their pattern needs
+ * (the smallest of the compiled capacities 16, 32, 40, 44, 48, 64, 128 holding the base or
+ * static pattern plus n_ent) and runs the restricted solves of each bucket in one launch of
+ * the kernel of that capacity (Algorithm 1's loop over the cells).  This call times each
+ * non-empty bucket of the last setup with its own capacity and the next two larger ones
+ * (best of three launches from scratch copies of the patterns) and keeps the fastest for
+ * later setups of the handle (the default unless another is at least 3% faster); larger
+ * capacities only change the rounding order of the local solves.  report (host, may be NULL)
+ * receives the buckets.  Synchronises the stream.  Errors: EDFA_ERR_ARG, EDFA_ERR_HIP. */
+#define EDFA_NCAP 7
+typedef struct {
+  int32_t buckets;                 /* EDFA_NCAP */
+  int32_t capacity[EDFA_NCAP];     /* the bucket's own capacity */
+  int32_t cells[EDFA_NCAP];        /* cells in the bucket at the last setup */
+  int32_t chosen[EDFA_NCAP];       /* kernel capacity kept for the bucket */
+  float   us[EDFA_NCAP][EDFA_NCAP];/* [bucket][capacity]: time of the bucket's launch (0: not timed) */
+} edfa_setup_tune;
+edfa_status edfa_autotune_setup(edfa_precond pre, hipStream_t stream,
+                                edfa_setup_tune *report /* (host), may be NULL */);
+
+/* Choice of the EDFA parameters for a system: the pattern technique and its (n_add, n_ent),
+ * the static pattern (level, axis) and the filtration (tau_filt, filt_mode) are the
+ * method's main sensitivity axis (Section 4, Tests 1-4, and the Discussion), and the best
+ * setting depends on the grid and the conductivity field.  Each of the ncand candidates
+ * (host array) is set up on `sys` and solved with `solve` from x0 = 0 against the
+ * system's right-hand side; the device time of setup + solve is measured with events on
+ * the stream.  *best (host) receives the index of the fastest candidate that converged;
+ * times_ms (host, +infinity where a candidate failed or did not converge), iterations
+ * (host, -1 where its setup failed) and status (host, its setup or solve status) may be
+ * NULL.  A candidate whose setup fails (e.g. EDFA_ERR_CAPACITY) is skipped.  Nothing
+ * persists: build the chosen preconditioner with edfa_setup.  Synchronises the stream.
+ * Errors: EDFA_ERR_ARG (a bad candidate or solve parameter), EDFA_ERR_BREAKDOWN (no
+ * candidate converged). */
+edfa_status edfa_tune_params(edfa_system sys, const edfa_params *cand /* (host) */, int32_t ncand,
+                             const edfa_solve_params *solve /* (host) */, hipStream_t stream,
+                             int32_t *best /* (host) */, double *times_ms /* (host) */,
+                             int32_t *iterations /* (host) */, int32_t *status /* (host) */);
 
 /* Pin the sparse-product kernel of one slot (0 .. EDFA_TUNE_SLOTS - 1, numbered as for
  * edfa_tune_slot) or of every slot (slot = -1) to a variant (0 .. EDFA_TUNE_VARIANTS - 1;

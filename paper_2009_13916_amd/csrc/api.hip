@@ -230,6 +230,26 @@ static void fill_info(edfa_precond_s &P, PrecData<T> &D, edfa_precond_info *info
   info->htilde_retry_rows = P.htilde_retry_rows;
   info->color_rounds = P.color_rounds;
   info->color_list_rounds = P.color_list_rounds;
+  info->cgs2_width = P.cgs2_width;
+}
+
+void check_params(const edfa_params &p) {
+  const edfa_params *prm = &p;
+  if (prm->variant != EDFA_STATIC && prm->variant != EDFA_DYNAMIC)
+    fail(EDFA_ERR_ARG, "variant must be EDFA_STATIC or EDFA_DYNAMIC");
+  if (prm->variant == EDFA_DYNAMIC && (prm->n_add < 1 || prm->n_ent < 0))
+    fail(EDFA_ERR_ARG, "dynamic variant needs n_add >= 1 and n_ent >= 0");
+  if (prm->filt_mode < EDFA_FILT_NONE || prm->filt_mode > EDFA_FILT_POST_H)
+    fail(EDFA_ERR_ARG, "filt_mode out of range");
+  if (prm->filt_mode != EDFA_FILT_NONE && !(prm->tau_filt >= 0.0))
+    fail(EDFA_ERR_ARG, "tau_filt must be >= 0");
+  if (prm->precision != 0 && prm->precision != 1) fail(EDFA_ERR_ARG, "precision must be 0 or 1");
+  if (prm->schur_solver != EDFA_SCHUR_ISAI && prm->schur_solver != EDFA_SCHUR_EXACT)
+    fail(EDFA_ERR_ARG, "schur_solver out of range");
+  if (prm->isai_steps < 1) fail(EDFA_ERR_ARG, "isai_steps must be >= 1");
+  if (prm->static_axis < 0 || prm->static_axis > 4) fail(EDFA_ERR_ARG, "static_axis must be 0..4");
+  if (prm->htilde_retry < 0 || prm->htilde_retry > 256)
+    fail(EDFA_ERR_ARG, "htilde_retry must be in 0..256");
 }
 }  // namespace edfa
 
@@ -240,20 +260,7 @@ edfa_status edfa_setup(edfa_system sys, const edfa_params *prm, hipStream_t stre
   return guard([&] {
     if (!sys || !prm || !out) fail(EDFA_ERR_ARG, "NULL argument");
     *out = nullptr;
-    if (prm->variant != EDFA_STATIC && prm->variant != EDFA_DYNAMIC)
-      fail(EDFA_ERR_ARG, "variant must be EDFA_STATIC or EDFA_DYNAMIC");
-    if (prm->variant == EDFA_DYNAMIC && (prm->n_add < 1 || prm->n_ent < 0))
-      fail(EDFA_ERR_ARG, "dynamic variant needs n_add >= 1 and n_ent >= 0");
-    if (prm->filt_mode < EDFA_FILT_NONE || prm->filt_mode > EDFA_FILT_POST_H)
-      fail(EDFA_ERR_ARG, "filt_mode out of range");
-    if (prm->filt_mode != EDFA_FILT_NONE && !(prm->tau_filt >= 0.0))
-      fail(EDFA_ERR_ARG, "tau_filt must be >= 0");
-    if (prm->precision != 0 && prm->precision != 1) fail(EDFA_ERR_ARG, "precision must be 0 or 1");
-    if (prm->schur_solver != EDFA_SCHUR_ISAI && prm->schur_solver != EDFA_SCHUR_EXACT)
-      fail(EDFA_ERR_ARG, "schur_solver out of range");
-    if (prm->isai_steps < 1) fail(EDFA_ERR_ARG, "isai_steps must be >= 1");
-    if (prm->htilde_retry < 0 || prm->htilde_retry > 256)
-      fail(EDFA_ERR_ARG, "htilde_retry must be in 0..256");
+    check_params(*prm);
     auto *P = new edfa_precond_s();
     P->sys = sys;
     P->prm = *prm;
@@ -374,12 +381,34 @@ edfa_status edfa_transient(edfa_system sys, edfa_precond pre, const edfa_transie
   });
 }
 
+edfa_status edfa_tune_params(edfa_system sys, const edfa_params *cand, int32_t ncand,
+                             const edfa_solve_params *solve, hipStream_t stream, int32_t *best,
+                             double *times_ms, int32_t *iterations, int32_t *status) {
+  return guard([&] {
+    if (!sys || !cand || !solve || !best) fail(EDFA_ERR_ARG, "NULL argument");
+    if (ncand < 1) fail(EDFA_ERR_ARG, "need at least one candidate");
+    if (solve->max_iter < 1 || !(solve->rtol > 0.0)) fail(EDFA_ERR_ARG, "bad solve parameters");
+    for (int c = 0; c < ncand; ++c) check_params(cand[c]);
+    *best = tune_params(*sys, cand, ncand, *solve, stream, times_ms, iterations, status);
+    if (*best < 0) fail(EDFA_ERR_BREAKDOWN, "no candidate converged");
+    return EDFA_OK;
+  });
+}
+
 edfa_status edfa_autotune(edfa_precond pre, hipStream_t stream, int32_t *tuned,
                           edfa_tune_slot *slots) {
   return guard([&] {
     if (!pre) fail(EDFA_ERR_ARG, "NULL preconditioner");
     const int n = autotune(*pre, stream, slots);
     if (tuned) *tuned = n;
+    return EDFA_OK;
+  });
+}
+
+edfa_status edfa_autotune_setup(edfa_precond pre, hipStream_t stream, edfa_setup_tune *report) {
+  return guard([&] {
+    if (!pre) fail(EDFA_ERR_ARG, "NULL preconditioner");
+    tune_setup(*pre, stream, report);
     return EDFA_OK;
   });
 }

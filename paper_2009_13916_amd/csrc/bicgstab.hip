@@ -334,7 +334,7 @@ edfa_status bicgstab(edfa_system_s &S, edfa_precond_s &P, const double *b, doubl
     if (prm.profile) {
       e0 = ev();
       EDFA_HIP(hipEventRecord(e0, s));
-      P.prof = &pp;
+      if (prm.profile >= 2) P.prof = &pp;
     }
     precond_apply(P, tr, in, out, s, live);
     P.prof = nullptr;

@@ -155,6 +155,10 @@ struct EventTimer {
 int64_t exclusive_scan(const int *in, int *out, int n, DBuf<int> &tmp, hipStream_t s);
 // Same, without reading the total back (asynchronous).
 void exclusive_scan_async(const int *in, int *out, int n, DBuf<int> &tmp, hipStream_t s);
+// Stable partition of [0, n) by key[i] in [0, nkey): out lists the indices key by key,
+// ascending inside a key; counts (host) receives each key's size.  Synchronises.
+void stable_partition(const int *key, int n, int nkey, int *out, DBuf<int> &hist, DBuf<int> &tmp,
+                      hipStream_t s, std::vector<int> &counts);
 
 // Transpose of a CSR matrix (rows x cols) into dst (cols x rows).  With sort, columns are
 // sorted within rows (deterministic layout, needed where values are summed); without,

@@ -10,6 +10,8 @@
 namespace edfa {
 
 // Compiled capacities.
+constexpr int NCAP = EDFA_NCAP;  // restricted-solve kernels: pattern capacities
+constexpr int kCapacities[NCAP] = {16, 32, 40, 44, 48, 64, 128};
 constexpr int HMAX = 512;        // max entries of one row of H~ (before filtration)
 constexpr int FSAI_MAX = 16;     // max lower-pattern length of a row of A_pipi
 constexpr int MAX_COLORS = 512;
@@ -21,6 +23,7 @@ struct PrecData {
   // stage 1
   DBuf<int> Q;          // Ne x smax final patterns (base order, then appended)
   DBuf<int> qlen;       // Ne
+  DBuf<int> bucket, bcells, bhist;   // capacity bucket of every cell; cells bucket by bucket
   DBuf<T> gbuf, fbuf;   // Ne x smax restricted solutions
   DBuf<int> ell_col;    // A_pipi rows padded to ELL_W entries (column -1 past a row's end)
   DBuf<double> ell_val;
@@ -111,6 +114,10 @@ struct SolveWork {
 // Chunks of CHUNK unknowns that never straddle a grid (built once per system).
 constexpr int SOLVE_CHUNK = 2048;
 void build_chunks(edfa_system_s &S, SolveWork &W, hipStream_t s);
+// CGS2 dot pass of `j` basis vectors with `width` vectors per block (2, 4 or 8)
+void launch_dots2(int width, int j, int nch, hipStream_t s, const double *Q, long long ldq,
+                  const double *u, const double *w, const Chunk *ch, const SegState *st,
+                  double *part, int ld);
 
 }  // namespace edfa
 
@@ -121,6 +128,9 @@ struct edfa_precond_s {
   int n_colors = 0;
   int max_pattern = 0;
   int htilde_retry_rows = 0;       // rows of H~ recomputed with the large hash tables
+  int bucket_cells[edfa::NCAP] = {};   // cells per capacity bucket at the last stage 1
+  int cap_map[edfa::NCAP] = {};        // tuned kernel capacity per bucket (0: its own)
+  int cgs2_width = 4;                  // basis vectors per block of the CGS2 dot passes
   int64_t nnz_h_raw = 0;           // entries of H~ before the post-filtration
   int color_rounds = 0;            // Jones-Plassmann rounds of the last colouring
   int color_list_rounds = 0;       //   of which over the worklist of uncoloured vertices
@@ -140,6 +150,9 @@ struct edfa_precond_s {
 
 namespace edfa {
 void precond_stage1(edfa_precond_s &P, hipStream_t s);
+// Times each capacity bucket of the last stage 1 with the larger compiled capacities and
+// keeps the fastest per bucket (report may be NULL).
+void tune_setup(edfa_precond_s &P, hipStream_t s, edfa_setup_tune *report);
 void precond_stage2(edfa_precond_s &P, hipStream_t s);
 void precond_apply(edfa_precond_s &P, int transpose, const double *r, double *z, hipStream_t s,
                    RowMask mask = {});
@@ -158,4 +171,9 @@ void apply_tuned(edfa_precond_s &P);
 // slot -1: every slot; variant -1: back to the default choice (at the next setup)
 void set_variant(edfa_precond_s &P, int slot, int variant);
 int autotune(edfa_precond_s &P, hipStream_t s, edfa_tune_slot *slots = nullptr);
+int tune_params(edfa_system_s &S, const edfa_params *cand, int ncand,
+                const edfa_solve_params &sp, hipStream_t s, double *times_ms, int *iterations,
+                int *status);
+// argument checks of a parameter set (EDFA_ERR_ARG on a bad one)
+void check_params(const edfa_params &prm);
 }  // namespace edfa

@@ -11,6 +11,8 @@
 //  * k_htilde           row m of H~ = (A_pipi R^T g~)^T F~ (eq. sparse_S), one wavefront per
 //                       cell, LDS hash maps, deterministic sums
 //  * k_fsai             factorised sparse approximate inverse of -A_pipi on lower(A_pipi)
+#include <algorithm>
+#include <cmath>
 #include <type_traits>
 
 #include "precond.hpp"
@@ -119,15 +121,29 @@ __global__ void k_base(const int *__restrict__ rp, const int *__restrict__ col, 
 }
 
 // Base pattern plus the unknown faces of every cell within `level` face-neighbour steps
-// (Manhattan distance on the structured grid), sorted.
+// (Manhattan distance on the structured grid; axis = 0), or within `level` steps along one
+// axis only (axis 1/2/3: x/y/z; axis 4: the cell's axis of largest transmissibility
+// W_(d-,d-) + W_(d+,d+), values within 1e-12 of the largest counting as ties that go to the
+// smaller axis), sorted.
 __global__ void k_patch(const GridDesc *__restrict__ grids, int ngrid, const int *__restrict__ uidx,
                         const int *__restrict__ rp, const int *__restrict__ col, int ne, int level,
-                        int smax, int *Q, int *qlen, int *err_cap) {
+                        int axis, const double *__restrict__ W, int smax, int *Q, int *qlen,
+                        int *err_cap) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= ne) return;
   const GridDesc &G = grids[grid_of(grids, ngrid, m, true)];
   int i0, j0, k0;
   cell_ijk(G, m, i0, j0, k0);
+  int dsel = axis - 1;   // -1: every direction
+  if (axis == 4) {
+    const double *We = W + 36 * (size_t)m;
+    double t[3], top = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      t[d] = We[7 * (2 * d)] + We[7 * (2 * d + 1)];
+      top = fmax(top, t[d]);
+    }
+    dsel = t[0] >= top * (1.0 - 1e-12) ? 0 : t[1] >= top * (1.0 - 1e-12) ? 1 : 2;
+  }
   int buf[PATCH_MAX];
   int n = 0;
   bool over = false;
@@ -144,6 +160,7 @@ __global__ void k_patch(const GridDesc *__restrict__ grids, int ngrid, const int
     for (int dj = -level; dj <= level; ++dj)
       for (int di = -level; di <= level; ++di) {
         if (abs(di) + abs(dj) + abs(dk) > level) continue;
+        if (dsel >= 0 && ((dsel != 0 && di) || (dsel != 1 && dj) || (dsel != 2 && dk))) continue;
         const int i = i0 + di, j = j0 + dj, k = k0 + dk;
         if (i < 0 || j < 0 || k < 0 || i >= G.nx || j >= G.ny || k >= G.nz) continue;
         for (int a = 0; a < 6; ++a) {
@@ -229,6 +246,8 @@ struct LocalArgs {
   int *Q, *qlen;
   T *gout, *fout;
   int *err_spd, *err_cap;
+  int qstride;          // entries per cell in Q, gout, fout (>= the kernel's capacity)
+  const int *cells;     // cells of this launch (NULL: cell = block index)
 };
 
 template <class T, int SMAX>
@@ -244,7 +263,7 @@ __global__ __launch_bounds__(64) void k_local(LocalArgs<T> A) {
   __shared__ T cr[CH];
   __shared__ int ccount, sflag;
 
-  const int m = blockIdx.x;
+  const int m = A.cells ? A.cells[blockIdx.x] : blockIdx.x;
   const int lane = threadIdx.x;
   if (m >= A.ne) return;
   int s = A.qlen[m];
@@ -253,7 +272,7 @@ __global__ __launch_bounds__(64) void k_local(LocalArgs<T> A) {
     return;
   }
   for (int t = lane; t < SMAX; t += 64) {
-    q[t] = t < s ? A.Q[(size_t)m * SMAX + t] : -1;
+    q[t] = t < s ? A.Q[(size_t)m * A.qstride + t] : -1;
     bg[t] = 0;
     bf[t] = 0;
   }
@@ -471,9 +490,9 @@ __global__ __launch_bounds__(64) void k_local(LocalArgs<T> A) {
     solve(true);
   }
   for (int t = lane; t < s; t += 64) {
-    A.Q[(size_t)m * SMAX + t] = q[t];
-    A.gout[(size_t)m * SMAX + t] = xg[t];
-    A.fout[(size_t)m * SMAX + t] = xf[t];
+    A.Q[(size_t)m * A.qstride + t] = q[t];
+    A.gout[(size_t)m * A.qstride + t] = xg[t];
+    A.fout[(size_t)m * A.qstride + t] = xf[t];
   }
   if (lane == 0) A.qlen[m] = s;
 }
@@ -590,7 +609,7 @@ __global__ __launch_bounds__(64) void k_local_reg(LocalArgs<T> A) {
   __shared__ T cr[CH];
   __shared__ int ccount, sflag;
 
-  const int m = blockIdx.x;
+  const int m = A.cells ? A.cells[blockIdx.x] : blockIdx.x;
   const int lane = threadIdx.x;
   if (m >= A.ne) return;
   int s = A.qlen[m];
@@ -599,7 +618,7 @@ __global__ __launch_bounds__(64) void k_local_reg(LocalArgs<T> A) {
     return;
   }
   for (int t = lane; t < SMAX; t += 64) {
-    q[t] = t < s ? A.Q[(size_t)m * SMAX + t] : -1;
+    q[t] = t < s ? A.Q[(size_t)m * A.qstride + t] : -1;
     bg[t] = 0;
     bf[t] = 0;
   }
@@ -900,9 +919,9 @@ __global__ __launch_bounds__(64) void k_local_reg(LocalArgs<T> A) {
       n_prog += added;
   }
   if (lane < s) {
-    A.Q[(size_t)m * SMAX + lane] = q[lane];
-    A.gout[(size_t)m * SMAX + lane] = xg;
-    A.fout[(size_t)m * SMAX + lane] = xf;
+    A.Q[(size_t)m * A.qstride + lane] = q[lane];
+    A.gout[(size_t)m * A.qstride + lane] = xg;
+    A.fout[(size_t)m * A.qstride + lane] = xf;
   }
   if (lane == 0) A.qlen[m] = s;
 }
@@ -1381,14 +1400,46 @@ static void reset_flags(edfa_precond_s &P, hipStream_t s) {
   EDFA_HIP(hipMemcpyAsync(P.flags.p, init, sizeof(init), hipMemcpyHostToDevice, s));
 }
 
-// Compiled pattern capacities: the smallest that holds `need` entries, 0 if none does.
-static int pattern_stride(int need) {
-  // 40 and 44 keep the register kernel (its code grows with the square of the stride) close
-  // to the patterns of the usual hexahedral grids (a base pattern of 36 faces plus a few
-  // dynamic entries)
-  for (int c : {16, 32, 40, 44, 48, 64, 128})
-    if (need <= c) return c;
-  return 0;
+// Buckets of pattern capacity: a cell goes to the smallest compiled capacity that holds its
+// pattern (its base or static pattern plus n_ent for the dynamic technique), and each bucket
+// runs the restricted-solve kernel of its own capacity (or a larger one the setup tuner
+// found faster).  40 and 44 keep the register kernel (its code grows with the square of
+// the capacity) close to the patterns of the usual hexahedral grids (a base pattern of 36
+// faces plus a few dynamic entries).
+struct Capacities {
+  int c[NCAP];
+};
+__global__ void k_need_bucket(const int *__restrict__ rp, const int *__restrict__ qlen, int ne,
+                              int extra, Capacities caps, int *bucket) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= ne) return;
+  const int need = (rp ? rp[m + 1] - rp[m] : qlen[m]) + extra;
+  int b = NCAP;
+  for (int i = NCAP - 1; i >= 0; --i)
+    if (need <= caps.c[i]) b = i;
+  bucket[m] = b;
+}
+
+template <class T>
+static void launch_local(int cap, int cells, const LocalArgs<T> &la, hipStream_t s) {
+  if (cells <= 0) return;
+  switch (cap) {
+    case 16: hipLaunchKernelGGL((k_local_reg<T, 16>), dim3(cells), dim3(64), 0, s, la); break;
+    case 32: hipLaunchKernelGGL((k_local_reg<T, 32>), dim3(cells), dim3(64), 0, s, la); break;
+    case 40: hipLaunchKernelGGL((k_local_reg<T, 40>), dim3(cells), dim3(64), 0, s, la); break;
+    case 44: hipLaunchKernelGGL((k_local_reg<T, 44>), dim3(cells), dim3(64), 0, s, la); break;
+    case 48: hipLaunchKernelGGL((k_local_reg<T, 48>), dim3(cells), dim3(64), 0, s, la); break;
+    case 64: hipLaunchKernelGGL((k_local<T, 64>), dim3(cells), dim3(64), 0, s, la); break;
+    case 128: hipLaunchKernelGGL((k_local<T, 128>), dim3(cells), dim3(64), 0, s, la); break;
+    default: fail(EDFA_ERR_CAPACITY, "no restricted-solve kernel of capacity %d", cap);
+  }
+  EDFA_CHECK_LAUNCH();
+}
+
+// Kernel capacity of bucket b: the tuned one when set (never below the bucket's own).
+static int bucket_capacity(const edfa_precond_s &P, int b) {
+  const int own = kCapacities[b];
+  return P.cap_map[b] > own ? P.cap_map[b] : own;
 }
 
 template <class T>
@@ -1399,12 +1450,6 @@ static void stage1_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
   reset_flags(P, s);
   int *err_spd = P.flags.p, *err_cap = P.flags.p + 1;
 
-  // maximum base-pattern length
-  EDFA_HIP(hipMemsetAsync(P.flags.p + 2, 0, sizeof(int), s));
-  hipLaunchKernelGGL(k_row_max, dim3(ceil_div(ne, 256)), dim3(256), 0, s, S.Acf.rowptr.p, ne,
-                     P.flags.p + 2);
-  EDFA_CHECK_LAUNCH();
-  const int maxbase = read_scalar(P.flags.p + 2, s);
   // the register kernel and the rows of H~ read A_pipi as ELL_W-entry rows
   EDFA_HIP(hipMemsetAsync(P.flags.p + 2, 0, sizeof(int), s));
   hipLaunchKernelGGL(k_row_max, dim3(ceil_div(nfu, 256)), dim3(256), 0, s, S.Afp.rowptr.p, nfu,
@@ -1415,36 +1460,44 @@ static void stage1_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
     fail(EDFA_ERR_CAPACITY, "a row of A_pipi has %d > %d entries (hexahedra give at most 11)",
          afp_max, ELL_W);
   const bool dynamic = prm.variant == EDFA_DYNAMIC;
-  int need = maxbase;
-  if (dynamic) need = maxbase + std::max(0, prm.n_ent);
-  int smax = pattern_stride(need);
-  if (!smax && (dynamic || prm.static_level == 0))
-    fail(EDFA_ERR_CAPACITY, "patterns of up to %d entries exceed 128", need);
+  const bool patches = !dynamic && prm.static_level > 0;
   D.qlen.ensure(ne);
-  if (!dynamic && prm.static_level > 0) {
+  if (patches) {
     if (prm.static_level > 3) fail(EDFA_ERR_ARG, "static_level must be 0..3");
-    // patches are built with the widest stride, then repacked to the smallest template
-
+    // patches are built with the widest stride, then repacked to the storage stride
     D.wide.ensure((size_t)ne * PATCH_MAX);
     hipLaunchKernelGGL(k_patch, dim3(ceil_div(ne, 64)), dim3(64), 0, s, S.grids.p, S.ngrid,
-                       S.uidx.p, S.Acf.rowptr.p, S.Acf.col.p, ne, prm.static_level, PATCH_MAX,
-                       D.wide.p, D.qlen.p, err_cap);
+                       S.uidx.p, S.Acf.rowptr.p, S.Acf.col.p, ne, prm.static_level,
+                       prm.static_axis, S.W.p, PATCH_MAX, D.wide.p, D.qlen.p, err_cap);
     EDFA_CHECK_LAUNCH();
     check_flags(P, s, "static patch");
-    EDFA_HIP(hipMemsetAsync(P.flags.p + 2, 0, sizeof(int), s));
-    hipLaunchKernelGGL(k_len_max, dim3(ceil_div(ne, 256)), dim3(256), 0, s, D.qlen.p, ne,
-                       P.flags.p + 2);
+  }
+  // cells by capacity bucket (from their base or static pattern length)
+  D.bucket.ensure(std::max(ne, 1));
+  D.bcells.ensure(std::max(ne, 1));
+  std::vector<int> counts(NCAP + 1, 0);
+  if (ne > 0) {
+    Capacities caps;
+    for (int i = 0; i < NCAP; ++i) caps.c[i] = kCapacities[i];
+    hipLaunchKernelGGL(k_need_bucket, dim3(ceil_div(ne, 256)), dim3(256), 0, s,
+                       patches ? nullptr : S.Acf.rowptr.p, D.qlen.p, ne,
+                       dynamic ? std::max(0, prm.n_ent) : 0, caps, D.bucket.p);
     EDFA_CHECK_LAUNCH();
-    need = read_scalar(P.flags.p + 2, s);
-    smax = pattern_stride(need);
-    if (!smax) fail(EDFA_ERR_CAPACITY, "static patches of %d entries exceed 128", need);
-    D.Q.ensure((size_t)ne * smax);
+    stable_partition(D.bucket.p, ne, NCAP + 1, D.bcells.p, D.bhist, S.tmp, s, counts);
+  }
+  if (counts[NCAP] > 0)
+    fail(EDFA_ERR_CAPACITY, "%d cells have patterns of more than %d entries", counts[NCAP],
+         kCapacities[NCAP - 1]);
+  int smax = kCapacities[0];
+  for (int b = 0; b < NCAP; ++b) {
+    P.bucket_cells[b] = counts[b];
+    if (counts[b]) smax = std::max(smax, bucket_capacity(P, b));
+  }
+  D.Q.ensure((size_t)ne * smax);
+  if (patches && ne > 0) {
     hipLaunchKernelGGL(k_repack, dim3(ceil_div(ne, 256)), dim3(256), 0, s, D.wide.p, D.qlen.p, ne,
                        PATCH_MAX, smax, D.Q.p);
     EDFA_CHECK_LAUNCH();
-    EDFA_HIP(hipStreamSynchronize(s));
-  } else {
-    D.Q.ensure((size_t)ne * smax);
   }
   D.gbuf.ensure((size_t)ne * smax);
   D.fbuf.ensure((size_t)ne * smax);
@@ -1482,23 +1535,16 @@ static void stage1_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
   la.fout = D.fbuf.p;
   la.err_spd = err_spd;
   la.err_cap = err_cap;
-  if (dynamic || prm.static_level == 0) {
+  la.qstride = smax;
+  if (!patches && ne > 0) {
     hipLaunchKernelGGL(k_base, dim3(ceil_div(ne, 256)), dim3(256), 0, s, S.Acf.rowptr.p,
                        S.Acf.col.p, ne, smax, D.Q.p, D.qlen.p);
     EDFA_CHECK_LAUNCH();
   }
-  if (ne > 0) {
-    switch (smax) {
-      case 16: hipLaunchKernelGGL((k_local_reg<T, 16>), dim3(ne), dim3(64), 0, s, la); break;
-      case 32: hipLaunchKernelGGL((k_local_reg<T, 32>), dim3(ne), dim3(64), 0, s, la); break;
-      case 40: hipLaunchKernelGGL((k_local_reg<T, 40>), dim3(ne), dim3(64), 0, s, la); break;
-      case 44: hipLaunchKernelGGL((k_local_reg<T, 44>), dim3(ne), dim3(64), 0, s, la); break;
-      case 48: hipLaunchKernelGGL((k_local_reg<T, 48>), dim3(ne), dim3(64), 0, s, la); break;
-      case 64: hipLaunchKernelGGL((k_local<T, 64>), dim3(ne), dim3(64), 0, s, la); break;
-      case 128: hipLaunchKernelGGL((k_local<T, 128>), dim3(ne), dim3(64), 0, s, la); break;
-      default: fail(EDFA_ERR_CAPACITY, "static patterns longer than 128 are not supported");
-    }
-    EDFA_CHECK_LAUNCH();
+  // one launch per capacity bucket, over the bucket's cells
+  for (int b = 0, off = 0; b < NCAP; off += counts[b], ++b) {
+    la.cells = D.bcells.p + off;
+    launch_local<T>(bucket_capacity(P, b), counts[b], la, s);
   }
   check_flags(P, s, "restricted solves");
   {
@@ -1624,6 +1670,115 @@ static void stage1_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
   csr_transpose(D.GF, D.GFT, S.tmp, S.tmp2, s);
   build_sell(D.GF, D.GF_s, S.tmp, s);
   build_sell(D.GFT, D.GFT_s, S.tmp, s);
+}
+
+// Setup tuner: each non-empty capacity bucket of the last stage 1 is timed (best of three
+// launches over its cells, from the base or static patterns in scratch copies) with its own
+// kernel capacity and the next two larger ones; the fastest, unless the default is within
+// 3%, is kept for later setups.  The handle's preconditioner is left as it was built.
+template <class T>
+static void tune_setup_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s,
+                            edfa_setup_tune *rep) {
+  edfa_system_s &S = *P.sys;
+  const edfa_params &prm = P.prm;
+  const int ne = S.ne;
+  const bool dynamic = prm.variant == EDFA_DYNAMIC;
+  const bool patches = !dynamic && prm.static_level > 0;
+  if (rep) *rep = edfa_setup_tune{};
+  if (rep) rep->buckets = NCAP;
+  if (ne <= 0 || D.bcells.n < (size_t)ne) return;
+  DBuf<int> Qt, qt;
+  DBuf<T> gt, ft;
+  qt.ensure(ne);
+  hipEvent_t e0, e1;
+  EDFA_HIP(hipEventCreate(&e0));
+  EDFA_HIP(hipEventCreate(&e1));
+  LocalArgs<T> la;
+  la.ne = ne;
+  la.app_rp = S.Afp.rowptr.p;
+  la.app_col = S.Afp.col.p;
+  la.app_val = S.Afp.val.p;
+  la.ell_col = D.ell_col.p;
+  la.ell_val = D.ell_val.p;
+  la.acf_rp = S.Acf.rowptr.p;
+  la.acf_col = S.Acf.col.p;
+  la.acf_val = S.Acf.val.p;
+  la.afcT_rp = S.AfcT.rowptr.p;
+  la.afcT_col = S.AfcT.col.p;
+  la.afcT_val = S.AfcT.val.p;
+  la.dynamic = dynamic;
+  la.n_add = std::max(1, prm.n_add);
+  la.n_ent = std::max(0, prm.n_ent);
+  la.it_max = prm.it_max;
+  la.err_spd = P.flags.p;
+  la.err_cap = P.flags.p + 1;
+  try {
+    for (int b = 0, off = 0; b < NCAP; off += P.bucket_cells[b], ++b) {
+      const int nb = P.bucket_cells[b];
+      if (rep) {
+        rep->capacity[b] = kCapacities[b];
+        rep->cells[b] = nb;
+        rep->chosen[b] = bucket_capacity(P, b);
+      }
+      if (nb <= 0) continue;
+      float best_us = INFINITY, own_us = INFINITY;
+      int best = b;
+      for (int c = b; c < std::min(NCAP, b + 3); ++c) {
+        const int cap = kCapacities[c];
+        Qt.ensure((size_t)ne * cap);
+        gt.ensure((size_t)ne * cap);
+        ft.ensure((size_t)ne * cap);
+        la.Q = Qt.p;
+        la.qlen = qt.p;
+        la.gout = gt.p;
+        la.fout = ft.p;
+        la.qstride = cap;
+        la.cells = D.bcells.p + off;
+        float t = INFINITY;
+        for (int r = 0; r < 3; ++r) {
+          if (patches) {
+            EDFA_HIP(hipMemcpyAsync(qt.p, D.qlen.p, sizeof(int) * ne, hipMemcpyDeviceToDevice, s));
+            hipLaunchKernelGGL(k_repack, dim3(ceil_div(ne, 256)), dim3(256), 0, s, D.wide.p,
+                               qt.p, ne, PATCH_MAX, cap, Qt.p);
+          } else {
+            hipLaunchKernelGGL(k_base, dim3(ceil_div(ne, 256)), dim3(256), 0, s, S.Acf.rowptr.p,
+                               S.Acf.col.p, ne, cap, Qt.p, qt.p);
+          }
+          EDFA_CHECK_LAUNCH();
+          EDFA_HIP(hipEventRecord(e0, s));
+          launch_local<T>(cap, nb, la, s);
+          EDFA_HIP(hipEventRecord(e1, s));
+          EDFA_HIP(hipEventSynchronize(e1));
+          float ms = 0;
+          EDFA_HIP(hipEventElapsedTime(&ms, e0, e1));
+          t = std::min(t, 1e3f * ms);
+        }
+        check_flags(P, s, "setup tuner");
+        if (rep) rep->us[b][c] = t;
+        if (c == b) own_us = t;
+        if (t < best_us) {
+          best_us = t;
+          best = c;
+        }
+      }
+      if (best != b && best_us > own_us * 0.97f) best = b;
+      P.cap_map[b] = kCapacities[best];
+      if (rep) rep->chosen[b] = kCapacities[best];
+    }
+  } catch (...) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+}
+
+void tune_setup(edfa_precond_s &P, hipStream_t s, edfa_setup_tune *report) {
+  if (P.prm.precision == 1)
+    tune_setup_impl<float>(P, P.f, s, report);
+  else
+    tune_setup_impl<double>(P, P.d, s, report);
 }
 
 // Raw (unfiltered) H~ as CSR, for export.

@@ -33,9 +33,10 @@ constexpr int RT = 256;
 
 // Partial dots tiled over (chunk, group of DG basis vectors): block (c, q) forms Q_i . u and
 // Q_i . w on chunk c for i in [DG q, DG q + DG); blocks with q = 0 also form u . u and u . w.
-// Components per chunk row: [Q^T u (nv) | Q^T w (nv) | u.u | u.w].  (Groups of 16 vectors,
-// which re-read u and w less, leave too few blocks to keep HBM busy: 4 is faster.)
-constexpr int DG = 4;
+// Components per chunk row: [Q^T u (nv) | Q^T w (nv) | u.u | u.w].  The group width DG
+// (the CGS2 block width: 2, 4 or 8 basis vectors per block) trades re-reads of u and w
+// against blocks in flight; the solve tuner picks it (groups of 16 leave too few blocks).
+template <int DG>
 __global__ __launch_bounds__(RT) void k_dots2(const double *__restrict__ Q, long long ldq, int nv,
                                               const double *__restrict__ u,
                                               const double *__restrict__ w,
@@ -105,6 +106,22 @@ __global__ __launch_bounds__(RT) void k_dots2(const double *__restrict__ Q, long
       row[2 * nv + (t - 2 * DG)] = v;
     }
   }
+}
+
+void launch_dots2(int width, int j, int nch, hipStream_t s, const double *Q, long long ldq,
+                  const double *u, const double *w, const Chunk *ch, const SegState *st,
+                  double *part, int ld) {
+  auto go = [&](auto kern, int dg) {
+    hipLaunchKernelGGL(kern, dim3(nch, std::max(1, ceil_div(j, dg))), dim3(RT), 0, s, Q, ldq, j,
+                       u, w, ch, st, part, ld);
+  };
+  if (width == 2)
+    go(k_dots2<2>, 2);
+  else if (width == 8)
+    go(k_dots2<8>, 8);
+  else
+    go(k_dots2<4>, 4);
+  EDFA_CHECK_LAUNCH();
 }
 
 // Per-segment sums of chunk partials: one wavefront per (segment, component), lanes strided
@@ -575,7 +592,7 @@ edfa_status gmres(edfa_system_s &S, edfa_precond_s &P, const double *b, double *
     if (pr) {
       e0 = prof.get();
       EDFA_HIP(hipEventRecord(e0, cs));
-      P.prof = &pp;
+      if (prm.profile >= 2) P.prof = &pp;
     }
     precond_apply(P, tr, in, out, cs, mk);
     P.prof = nullptr;
@@ -611,8 +628,8 @@ edfa_status gmres(edfa_system_s &S, edfa_precond_s &P, const double *b, double *
     EDFA_CHECK_LAUNCH();
     // dots of basis slots [0, j) against u and w, reduced per segment into h1
     auto dots = [&](int j, const double *u, const double *w) {
-      hipLaunchKernelGGL(k_dots2, dim3(nch, std::max(1, ceil_div(j, DG))), dim3(RT), 0, cs, W.V.p,
-                         (long long)n, j, u, w, W.chunks.p, W.st.p, W.part.p, ld);
+      launch_dots2(P.cgs2_width, j, nch, cs, W.V.p, (long long)n, u, w, W.chunks.p, W.st.p,
+                   W.part.p, ld);
       hipLaunchKernelGGL(k_seg_reduce_w, dim3(ceil_div(2 * j + 2, 4), nseg), dim3(256), 0, cs,
                          W.part.p, ld, 2 * j + 2, W.segptr.p, W.st.p, SEG_ACTIVE, W.h1.p, ld);
     };

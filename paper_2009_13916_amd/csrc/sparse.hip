@@ -89,6 +89,54 @@ int64_t exclusive_scan(const int *in, int *out, int n, DBuf<int> &tmp, hipStream
 }
 
 // ----------------------------------------------------------------------------------
+// Stable partition by a small key: per-block key histograms (key-major), one scan, and a
+// scatter that keeps the index order inside a key.
+// ----------------------------------------------------------------------------------
+constexpr int PART_MAX_KEYS = 64;
+__global__ __launch_bounds__(256) void k_part_hist(const int *__restrict__ key, int n, int nkey,
+                                                   int nb, int *hist) {
+  __shared__ int h[PART_MAX_KEYS];
+  for (int c = threadIdx.x; c < nkey; c += 256) h[c] = 0;
+  __syncthreads();
+  const int v = blockIdx.x * 256 + threadIdx.x;
+  if (v < n) atomicAdd(&h[key[v]], 1);
+  __syncthreads();
+  for (int c = threadIdx.x; c < nkey; c += 256) hist[(size_t)c * nb + blockIdx.x] = h[c];
+}
+
+__global__ __launch_bounds__(256) void k_part_scatter(const int *__restrict__ key, int n, int nb,
+                                                      const int *__restrict__ offs, int *out) {
+  __shared__ int kl[256];
+  const int v = blockIdx.x * 256 + threadIdx.x;
+  kl[threadIdx.x] = v < n ? key[v] : -1;
+  __syncthreads();
+  if (v >= n) return;
+  const int c = kl[threadIdx.x];
+  int rank = 0;
+  for (int t = 0; t < (int)threadIdx.x; ++t) rank += kl[t] == c;
+  out[offs[(size_t)c * nb + blockIdx.x] + rank] = v;
+}
+
+void stable_partition(const int *key, int n, int nkey, int *out, DBuf<int> &hist, DBuf<int> &tmp,
+                      hipStream_t s, std::vector<int> &counts) {
+  if (nkey < 1 || nkey > PART_MAX_KEYS) fail(EDFA_ERR_ARG, "partition into %d keys", nkey);
+  counts.assign(nkey, 0);
+  if (n <= 0) return;
+  const int nb = ceil_div(n, 256);
+  hist.ensure((size_t)nkey * nb + 1);
+  hipLaunchKernelGGL(k_part_hist, dim3(nb), dim3(256), 0, s, key, n, nkey, nb, hist.p);
+  EDFA_CHECK_LAUNCH();
+  exclusive_scan_async(hist.p, hist.p, nkey * nb, tmp, s);
+  hipLaunchKernelGGL(k_part_scatter, dim3(nb), dim3(256), 0, s, key, n, nb, hist.p, out);
+  EDFA_CHECK_LAUNCH();
+  std::vector<int> start(nkey + 1);
+  for (int c = 0; c <= nkey; ++c)
+    EDFA_HIP(hipMemcpyAsync(&start[c], hist.p + (size_t)c * nb, sizeof(int), hipMemcpyDeviceToHost, s));
+  EDFA_HIP(hipStreamSynchronize(s));
+  for (int c = 0; c < nkey; ++c) counts[c] = start[c + 1] - start[c];
+}
+
+// ----------------------------------------------------------------------------------
 // CSR transpose: count per column, scan, scatter with atomic cursors, sort each row.
 // ----------------------------------------------------------------------------------
 __global__ void k_count_cols(const int *__restrict__ col, int64_t nnz, int *cnt) {

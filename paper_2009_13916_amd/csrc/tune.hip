@@ -164,6 +164,48 @@ int tune_one(Sell<V> &M, int role, TuneBufs &B, hipStream_t s, hipEvent_t e0, hi
 }
 }  // namespace
 
+// EDFA parameter choice: every candidate is set up and solved on the system, timed with
+// events on the stream (setup + solve), and the fastest converged candidate wins.
+int tune_params(edfa_system_s &S, const edfa_params *cand, int ncand,
+                const edfa_solve_params &sp, hipStream_t s, double *times_ms, int *iterations,
+                int *status) {
+  DBuf<double> x;
+  x.ensure(std::max(S.n, 1));
+  int best = -1;
+  double best_t = INFINITY;
+  for (int c = 0; c < ncand; ++c) {
+    double t = INFINITY;
+    int its = -1, st = EDFA_OK;
+    try {
+      edfa_precond_s P;
+      P.sys = &S;
+      P.prm = cand[c];
+      EventTimer tm;
+      tm.start(s);
+      precond_stage1(P, s);
+      precond_stage2(P, s);
+      edfa_solve_info info{};
+      st = sp.method == EDFA_BICGSTAB ? bicgstab(S, P, S.b.p, x.p, sp, s, &info)
+                                      : gmres(S, P, S.b.p, x.p, sp, s, &info);
+      tm.stop(s);
+      its = info.iterations;
+      if (st == EDFA_OK) t = tm.ms();
+    } catch (const Error &e) {
+      // a candidate the system cannot take (capacity, breakdown) is skipped
+      st = e.status;
+      (void)hipStreamSynchronize(s);
+    }
+    if (times_ms) times_ms[c] = t;
+    if (iterations) iterations[c] = its;
+    if (status) status[c] = st;
+    if (t < best_t) {
+      best_t = t;
+      best = c;
+    }
+  }
+  return best;
+}
+
 int autotune(edfa_precond_s &P, hipStream_t s, edfa_tune_slot *slots) {
   hipEvent_t e0, e1;
   EDFA_HIP(hipEventCreate(&e0));
@@ -176,6 +218,53 @@ int autotune(edfa_precond_s &P, hipStream_t s, edfa_tune_slot *slots) {
   if (biggest * 12 > (8ll << 20)) {
     B.flush.ensure((size_t)FLUSH_DOUBLES);
     EDFA_HIP(hipMemsetAsync(B.flush.p, 0, sizeof(double) * FLUSH_DOUBLES, s));
+  }
+  // CGS2 block width: one dot pass over 24 basis vectors of the system's size
+  {
+    edfa_system_s &S = *P.sys;
+    if (!P.ws) P.ws.reset(new SolveWork());
+    SolveWork &W = *P.ws;
+    build_chunks(S, W, s);
+    const int n = S.n, nv = 24, ld = 2 * nv + 4;
+    DBuf<double> Vt, pt;
+    DBuf<SegState> st;
+    Vt.ensure((size_t)(nv + 2) * std::max(n, 1));
+    pt.ensure((size_t)W.nchunk * ld);
+    st.ensure(S.ngrid);
+    std::vector<SegState> hs(S.ngrid);
+    for (auto &q : hs) {
+      q = SegState{};
+      q.active = 1;
+    }
+    EDFA_HIP(hipMemcpyAsync(st.p, hs.data(), sizeof(SegState) * hs.size(), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_fill_ones<double>, dim3(ceil_div((long long)(nv + 2) * n, 256)), dim3(256),
+                       0, s, Vt.p, (long long)(nv + 2) * n);
+    EDFA_CHECK_LAUNCH();
+    float best = INFINITY, dflt = INFINITY;
+    int width = 4;
+    for (int wd : {4, 2, 8}) {
+      float t = INFINITY;
+      for (int r = 0; r < 5; ++r) {
+        if (B.flush.p) {
+          hipLaunchKernelGGL(k_flush, dim3(4096), dim3(256), 0, s, B.flush.p, FLUSH_DOUBLES, B.flush.p);
+          EDFA_CHECK_LAUNCH();
+        }
+        EDFA_HIP(hipEventRecord(e0, s));
+        launch_dots2(wd, nv, W.nchunk, s, Vt.p, (long long)n, Vt.p + (size_t)nv * n,
+                     Vt.p + (size_t)(nv + 1) * n, W.chunks.p, st.p, pt.p, ld);
+        EDFA_HIP(hipEventRecord(e1, s));
+        EDFA_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        EDFA_HIP(hipEventElapsedTime(&ms, e0, e1));
+        t = std::min(t, ms);
+      }
+      if (wd == 4) dflt = t;
+      if (t < best) {
+        best = t;
+        width = wd;
+      }
+    }
+    P.cgs2_width = best < dflt * (1.0f - TUNE_MARGIN) ? width : 4;
   }
   int tuned = 0;
   if (slots)

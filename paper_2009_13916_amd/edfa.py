@@ -52,7 +52,7 @@ class _Params(C.Structure):
                 ("n_ent", C.c_int32), ("it_max", C.c_int32), ("tau_filt", C.c_double),
                 ("filt_mode", C.c_int32), ("precision", C.c_int32),
                 ("schur_solver", C.c_int32), ("isai_steps", C.c_int32),
-                ("htilde_retry", C.c_int32)]
+                ("static_axis", C.c_int32), ("htilde_retry", C.c_int32)]
 
 
 class _PrecondInfo(C.Structure):
@@ -62,7 +62,17 @@ class _PrecondInfo(C.Structure):
                 ("n_colors", C.c_int32), ("max_pattern", C.c_int32), ("mu", C.c_double),
                 ("t_stage1_ms", C.c_double), ("t_stage2_ms", C.c_double),
                 ("nnz_H_raw", C.c_int64), ("htilde_retry_rows", C.c_int32),
-                ("color_rounds", C.c_int32), ("color_list_rounds", C.c_int32)]
+                ("color_rounds", C.c_int32), ("color_list_rounds", C.c_int32),
+                ("cgs2_width", C.c_int32)]
+
+
+NCAP = 7
+
+
+class _SetupTune(C.Structure):
+    _fields_ = [("buckets", C.c_int32), ("capacity", C.c_int32 * NCAP),
+                ("cells", C.c_int32 * NCAP), ("chosen", C.c_int32 * NCAP),
+                ("us", (C.c_float * NCAP) * NCAP)]
 
 
 class _SolveParams(C.Structure):
@@ -150,6 +160,10 @@ def load():
             "edfa_transient": (C.c_int, [vp, vp, C.POINTER(_TransientParams), vp, vp,
                                          C.POINTER(_StepInfo), C.POINTER(i32)]),
             "edfa_autotune": (C.c_int, [vp, vp, C.POINTER(i32), C.POINTER(_TuneSlot)]),
+            "edfa_autotune_setup": (C.c_int, [vp, vp, C.POINTER(_SetupTune)]),
+            "edfa_tune_params": (C.c_int, [vp, C.POINTER(_Params), i32, C.POINTER(_SolveParams),
+                                           vp, C.POINTER(i32), C.POINTER(d), C.POINTER(i32),
+                                           C.POINTER(i32)]),
             "edfa_set_variant": (C.c_int, [vp, i32, i32]),
         }
         for name, (res, args) in sig.items():
@@ -170,7 +184,8 @@ def exported_symbols():
                         "edfa_export_rhs", "edfa_spmv", "edfa_setup", "edfa_setup_stage2", "edfa_resetup",
                         "edfa_precond_destroy", "edfa_precond_get_info", "edfa_export_precond",
                         "edfa_apply", "edfa_solve", "edfa_grad_logk", "edfa_autotune",
-                        "edfa_set_variant", "edfa_transient", "edfa_apply_noalloc")
+                        "edfa_set_variant", "edfa_transient", "edfa_apply_noalloc",
+                        "edfa_tune_params", "edfa_autotune_setup")
             if hasattr(L, n)]
 
 
@@ -273,12 +288,14 @@ class Params:
     precision: int = 0          # 0 FP64, 1 FP32 setup + application
     schur: str = "isai"
     isai_steps: int = 1
+    static_axis: int = 0        # static level k: 0 all directions, 1/2/3 x/y/z, 4 flow axis
     htilde_retry: int = 0       # rows of H~ with a wider support of t take the second pass
 
     def c(self):
         return _Params(STATIC if self.variant == "static" else DYNAMIC, self.static_level,
                        self.n_add, self.n_ent, self.it_max, float(self.tau), FILT[self.filt],
-                       self.precision, SCHUR[self.schur], self.isai_steps, self.htilde_retry)
+                       self.precision, SCHUR[self.schur], self.isai_steps, self.static_axis,
+                       self.htilde_retry)
 
 
 class Precond:
@@ -345,6 +362,17 @@ class Precond:
                              "us": {variant_name(v): float(t) for v, t in enumerate(r.us)}}
         return out
 
+    def autotune_setup(self):
+        """Time each pattern-capacity bucket of the last stage 1 with its own and the next two
+        larger kernel capacities; keep the fastest.  Returns a list of {capacity, cells,
+        chosen, us: {capacity: microseconds}} for the non-empty buckets."""
+        rep = _SetupTune()
+        _check(load().edfa_autotune_setup(self._h, _stream(), C.byref(rep)))
+        caps = [rep.capacity[b] for b in range(NCAP)]
+        return [{"capacity": caps[b], "cells": rep.cells[b], "chosen": rep.chosen[b],
+                 "us": {caps[c]: float(rep.us[b][c]) for c in range(NCAP) if rep.us[b][c] > 0}}
+                for b in range(NCAP) if rep.cells[b] > 0]
+
     def set_variant(self, variant, slot=None):
         """Pin the sparse-product kernel of one slot (a name of TUNE_SLOTS or an index;
         None = every slot) to a variant (a name from variant_name, an index, or None for
@@ -367,7 +395,8 @@ class Precond:
 def solve(system: System, pre: Precond, b, rtol=1e-8, restart=50, max_iter=5000, flexible=False,
           transpose=False, use_graph=False, profile=False, method="gmres"):
     """Right-preconditioned (F)GMRES(restart) or Bi-CGStab (method="bicgstab"), x0 = 0.
-    Returns (x, info dict, status)."""
+    profile: 0/False none, 1/True the system products and the applications, 2 also every
+    product inside the applications.  Returns (x, info dict, status)."""
     x = torch.zeros_like(b)
     prm = _SolveParams(restart, max_iter, int(flexible), int(transpose), int(use_graph),
                        int(profile), float(rtol), METHOD[method])
@@ -397,6 +426,41 @@ def transient(system: System, pre: Precond, n_steps, dt0, dt_mult=2.0, dt_max=fl
                                       C.byref(taken)))
     steps = [{f: getattr(recs[k], f) for f, _ in _StepInfo._fields_} for k in range(taken.value)]
     return u, steps, st
+
+
+# Candidates of the parameter tuner: the region of the paper's tests and discussion -- the
+# base pattern, static patches in every direction and strips along the flow axis, dynamic
+# patterns with a few (n_add, n_ent), with and without post-filtration on H~.
+DEFAULT_CANDIDATES = (
+    Params("static"),
+    Params("static", static_level=1),
+    Params("static", static_level=1, static_axis=4),
+    Params("static", static_level=2, static_axis=4),
+    Params("dynamic", n_add=1, n_ent=4),
+    Params("dynamic", n_add=1, n_ent=6),
+    Params("dynamic", n_add=1, n_ent=6, tau=1e-3, filt="post_H"),
+    Params("dynamic", n_add=2, n_ent=6, tau=1e-3, filt="post_H"),
+    Params("dynamic", n_add=4, n_ent=12, tau=1e-3, filt="post_H"),
+)
+
+
+def tune_params(system: System, candidates=DEFAULT_CANDIDATES, rtol=1e-8, restart=50,
+                max_iter=5000, method="gmres", flexible=None):
+    """Time setup + solve of every candidate on `system` and return (best Params, list of
+    {params, ms, iterations, status}).  flexible defaults to True for FP32 candidates."""
+    cands = list(candidates)
+    arr = (_Params * len(cands))(*[p.c() for p in cands])
+    flex = any(p.precision == 1 for p in cands) if flexible is None else flexible
+    sp = _SolveParams(restart, max_iter, int(flex), 0, 0, 0, float(rtol), METHOD[method])
+    best = C.c_int32(-1)
+    times = (C.c_double * len(cands))()
+    its = (C.c_int32 * len(cands))()
+    sts = (C.c_int32 * len(cands))()
+    _check(load().edfa_tune_params(system._h, arr, len(cands), C.byref(sp), _stream(),
+                                   C.byref(best), times, its, sts))
+    rec = [{"params": p, "ms": times[k], "iterations": its[k], "status": sts[k]}
+           for k, p in enumerate(cands)]
+    return cands[best.value], rec
 
 
 def grad_logk(system: System, u, lam):

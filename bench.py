@@ -95,14 +95,15 @@ def run_form(edfa, S, b, prm, steps, warmup, flexible, method="gmres", P=None):
     return (t1 - t0) / steps, infos, pinfos, x, rep
 
 
-def kernel_label(variant, what="the system matrix", role=0):
+def kernel_label(variant, what="the system matrix", role=0, value_bytes=8):
     """Kernel (as traces name it) that runs a product for a tuner choice."""
     kind, depth = variant.split("/")
+    t = "double, double" if value_bytes == 8 else "float, float"
     if kind == "sell":
-        return f"k_spmv_sell<double, double, {role}, {depth}>: SELL-64 SpMV with {what}"
+        return f"k_spmv_sell<{t}, {role}, {depth}>: SELL-64 SpMV with {what}"
     if kind == "chunk":
-        return f"k_spmv_chunk<double, double, {depth}>: row-chunk SpMV with {what}"
-    return (f"k_spmv_csr_vec<double, double, {kind[3:]}, {depth}>: CSR SpMV with {what}, "
+        return f"k_spmv_chunk<{t}, {depth}>: row-chunk SpMV with {what}"
+    return (f"k_spmv_csr_vec<{t}, {kind[3:]}, {depth}>: CSR SpMV with {what}, "
             f"{kind[3:]} lanes per row")
 
 
@@ -284,9 +285,11 @@ def spmv_kernel_sha():
     return hashlib.sha256(src[a:e].encode()).hexdigest()[:16]
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` (its trace name) from the committed PMC summary, or
-    None when absent or taken on another version of the kernels."""
+def measured_traffic(kernel, fam):
+    """HBM bytes per launch of `kernel` (its trace name) over the matrices it multiplied in
+    the profiled solve (`fam` rows), weighted by their launches, from the per-matrix figures
+    of the committed PMC summary; None when the summary is absent, was taken on another
+    version of the kernels, or lacks one of those matrices with this same kernel."""
     if not os.path.exists(TRAFFIC):
         return None
     txt = open(TRAFFIC).read()
@@ -297,37 +300,42 @@ def measured_traffic(kernel):
         return None
     if d.get("kernel_sha") != spmv_kernel_sha():
         return None
-    return d.get("kernels", {}).get(kernel, {}).get("hbm_bytes_per_launch")
+    meas = d.get("matrices", {})
+    tot = n = 0
+    for f in fam:
+        if f["kernel"] != kernel:
+            continue
+        m = meas.get(f["matrix"])
+        if not m or m.get("kernel") != kernel:
+            return None
+        tot += m["hbm_bytes_per_launch"] * f["launches"]
+        n += f["launches"]
+    return tot / n if n else None
 
 
 def probe(torch, edfa, S, b, what):
-    """Launches counted by the FETCH_SIZE / WRITE_SIZE passes.  'spmv': 20 products with the
-    system matrix; 'apply': the workload's preconditioner (autotuned as in the timed steps)
-    and 20 applications.  Then one device copy of COPY_BYTES (reads and writes COPY_BYTES)
-    that calibrates the counters.  Prints the algorithmic bytes of every product."""
+    """Launches counted by the FETCH_SIZE / WRITE_SIZE passes: the workload's preconditioner,
+    autotuned as in the timed steps, then 'spmv': 20 products with the system matrix, or
+    'apply': 20 applications.  Then one device copy of COPY_BYTES (reads and writes
+    COPY_BYTES) that calibrates the counters.  Prints, per matrix, the algorithmic bytes and
+    the kernel of its product, and the order of the products inside one application."""
     rec = {"probe": what, "launches": 20, "copy_bytes": COPY_BYTES, "kernel_sha": spmv_kernel_sha()}
+    P = edfa.Precond(S, edfa.Params("dynamic", n_add=1, n_ent=6, tau=1e-3, filt="post_H"))
+    rep = P.autotune(report=True)
+    torch.cuda.synchronize()
+    names = ["A"] if what == "spmv" else ["G_F", "G_F^T", "A_ppi", "M_L", "M_U", "A_pip"]
     if what == "spmv":
         for _ in range(20):
-            S.spmv(b)
-        rec["products"] = {"A": {"bytes": spmv_bytes(S.info["nnz"], S.info["n"]),
-                                 "kernel": "k_spmv_sell<double, double, 0, 4>"}}
+            S.spmv(b)   # the system matrix with the kernel the tuner kept
     else:
-        # the default kernels (those the tuner keeps on this workload), so that the counter
-        # passes see only the setup and the applications
-        P = edfa.Precond(S, edfa.Params("dynamic", n_add=1, n_ent=6, tau=1e-3, filt="post_H"))
-        torch.cuda.synchronize()
         for _ in range(20):
             P.apply(b)
-        pi, si = P.info(), S.info
-        nfu, ne = si["nfu"], si["ne"]
-        shape = {"G_F": (nfu, nfu, pi["nnz_GF"]), "G_F^T": (nfu, nfu, pi["nnz_GF"]),
-                 "A_ppi": (ne, nfu, si["nnz_block"][2]), "A_pip": (nfu, ne, si["nnz_block"][1]),
-                 "M_L": (ne, ne, pi["nnz_ML"]), "M_U": (ne, ne, pi["nnz_MU"])}
-        rep = {k: {"value_bytes": 8, "rows": r, "cols": c, "nnz": z}
-               for k, (r, c, z) in shape.items()}
         # order of the products inside one application (eq. EDFA_prec)
         rec["apply_order"] = ["G_F", "G_F^T", "A_ppi", "M_L", "M_U", "A_pip", "G_F", "G_F^T"]
-        rec["products"] = {k: {"bytes": slot_bytes(r), "rows": r["rows"]} for k, r in rep.items()}
+    rec["products"] = {k: {"bytes": slot_bytes(rep[k]), "rows": rep[k]["rows"],
+                           "kernel": kernel_label(rep[k]["variant"], k,
+                                                  0 if k == "A" else 1).split(":")[0]}
+                       for k in names}
     src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
@@ -347,7 +355,8 @@ def families(info, rep, apply_count):
         r = rep[name]
         n = info["slot_launches"][name]
         by = slot_bytes(r)
-        label = kernel_label(r["variant"], name, 0 if name in ("A", "A^T") else 1)
+        label = kernel_label(r["variant"], name, 0 if name in ("A", "A^T") else 1,
+                             r["value_bytes"])
         sym = label.split(":")[0]
         gbs = by / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
         rows.append({"matrix": name, "kernel": sym, "bytes_per_launch": by,
@@ -426,9 +435,10 @@ def main():
                       "apply_avg_us": round(info["apply_avg_ms"] * 1e3, 2)}}
     if not args.no_mixed:
         prm32 = edfa.Params("dynamic", n_add=1, n_ent=6, tau=1e-3, filt="post_H", precision=1)
-        t32, i32, p32, x32, _ = run_form(edfa, S, b, prm32, args.steps, args.warmup,
-                                         flexible=True)
+        t32, i32, p32, x32, rep32 = run_form(edfa, S, b, prm32, args.steps, args.warmup,
+                                             flexible=True)
         inf32, st32 = i32[-1]
+        fam32, _ = families(inf32, rep32, inf32["apply_count_products"])
         dp = (x32 - x)[S.info["nfu"]:].norm() / x[S.info["nfu"]:].norm()
         log(f"mixed: {t32:.4f} s/step, {inf32['iterations']} iterations")
         forms["mixed_fp32_precond_fgmres"] = {
@@ -436,7 +446,7 @@ def main():
             "converged": st32 == 0, "stage1_ms": p32[-1]["t_stage1_ms"],
             "stage2_ms": p32[-1]["t_stage2_ms"], "solve_ms": inf32["t_solve_ms"],
             "apply_avg_us": round(inf32["apply_avg_ms"] * 1e3, 2),
-            "pressure_rel_diff_vs_fp64": float(dp)}
+            "pressure_rel_diff_vs_fp64": float(dp), "families": fam32}
     if not args.no_bicgstab:
         tb, ib, pb, xb, _ = run_form(edfa, S, b, prm, args.steps, args.warmup, flexible=False,
                                      method="bicgstab")
@@ -479,7 +489,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom,
                      "matrices": K["matrices"],
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom, fam),
                      "bytes_per_launch": K["bytes"] / K["launches"],
                      "avg_launch_ms": K["ms"] / K["launches"], "launches": K["launches"]},
         "families": fam,

@@ -354,9 +354,11 @@ edfa_status edfa_grad_logk(edfa_system sys, const double *u, const double *lambd
  * that the solve and the application multiply -- the system matrix (and its transpose once
  * built), the FSAI factor and its transpose, the coupling blocks, the ILU(0) factors and
  * their approximate inverses -- with the one-lane-per-row SELL kernel and with the CSR
- * kernel at 2, 4, 8, 16 and 32 lanes per row, each at two load depths, and keeps the
- * fastest for each (the default kernel unless another is at least 3% faster); the choice
- * stays with the handle across later setups.  *tuned (host, may be NULL) receives the
+ * kernel at 2, 4, 8, 16 and 32 lanes per row, each at two load depths, and with the
+ * row-chunk kernel, and keeps one of the fastest for each: the default kernel unless another
+ * is at least 3% faster, else the first variant in table order within 3% of the fastest
+ * (so equivalent kernels do not alternate from run to run); the choice stays with the
+ * handle across later setups.  *tuned (host, may be NULL) receives the
  * number of matrices timed; slots (host, may be NULL) the timings of every slot.  Synchronises the stream.  Errors: EDFA_ERR_ARG, EDFA_ERR_HIP. */
 #define EDFA_TUNE_SLOTS 16
 #define EDFA_TUNE_VARIANTS 13

@@ -149,18 +149,22 @@ int tune_one(Sell<V> &M, int role, TuneBufs &B, hipStream_t s, hipEvent_t e0, hi
   hipLaunchKernelGGL(k_fill_ones<V>, dim3(ceil_div(nx, 256)), dim3(256), 0, s, x.p, (long long)nx);
   EDFA_CHECK_LAUNCH();
   // the default kernel (SELL, 4 in flight, for short rows; the chunk kernel for long ones)
-  // is kept unless another variant is at least TUNE_MARGIN faster, so timing noise does not
-  // flip the choice between equivalent kernels
+  // is kept unless another variant is at least TUNE_MARGIN faster; otherwise the first
+  // variant (in table order) within TUNE_MARGIN of the fastest is taken, so timing noise
+  // does not flip the choice between equivalent kernels from one run to the next
   const int dflt =
       M.rows > 0 && default_spmv_lanes((double)M.nnz / M.rows) == SPMV_CHUNKED ? CHUNK_VARIANT : 0;
-  for (int v = 0; v < EDFA_TUNE_VARIANTS; ++v)
+  float fastest = INFINITY;
+  for (int v = 0; v < EDFA_TUNE_VARIANTS; ++v) {
     us[v] = can_run(M, kVariants[v])
                 ? 1e3f * time_variant(M, kVariants[v], role, x, y, B.flush, s, e0, e1)
                 : INFINITY;
-  int best = dflt;
+    fastest = std::min(fastest, us[v]);
+  }
+  if (!(us[dflt] * (1.0f - TUNE_MARGIN) > fastest)) return dflt;
   for (int v = 0; v < EDFA_TUNE_VARIANTS; ++v)
-    if (us[v] < us[best] * (1.0f - TUNE_MARGIN)) best = v;
-  return best;
+    if (us[v] * (1.0f - TUNE_MARGIN) <= fastest) return v;
+  return dflt;
 }
 }  // namespace
 

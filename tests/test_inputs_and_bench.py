@@ -104,12 +104,37 @@ def test_bench_helpers(tmp_path):
     k = kern["k_spmv_chunk<double, double, 12>"]
     assert k["launches"] == 20 and abs(k["ms"] - 0.8) < 1e-12 and k["matrices"] == ["M_L", "M_U"]
     assert {f["matrix"] for f in fam} == {"M_L", "M_U", "G_F"}
-    # the committed traffic record is read only for the kernel source it was taken on
+    # a kernel's traffic is the launch-weighted mean of its matrices' measured bytes, read
+    # only for the kernel source it was taken on and only when every matrix is covered
+    chunk, sell = "k_spmv_chunk<double, double, 12>", "k_spmv_sell<double, double, 1, 4>"
+    rec = {"kernel_sha": bench.spmv_kernel_sha(),
+           "matrices": {"M_L": {"kernel": chunk, "hbm_bytes_per_launch": 100.0},
+                        "M_U": {"kernel": chunk, "hbm_bytes_per_launch": 300.0}}}
+    path = tmp_path / "traffic.md"
+
+    def write(r):
+        path.write_text("# traffic\n\n```json\n" + json.dumps(r) + "\n```\n")
+    old = bench.TRAFFIC
+    bench.TRAFFIC = str(path)
+    try:
+        write(rec)
+        fam[[f["matrix"] for f in fam].index("M_U")]["launches"] = 30
+        assert bench.measured_traffic(chunk, fam) == (100.0 * 10 + 300.0 * 30) / 40
+        assert bench.measured_traffic(sell, fam) is None          # G_F not measured
+        rec["matrices"]["M_U"]["kernel"] = sell                   # measured on another kernel
+        write(rec)
+        assert bench.measured_traffic(chunk, fam) is None
+        rec["matrices"]["M_U"]["kernel"] = chunk
+        rec["kernel_sha"] = "0" * 16                              # another kernel source
+        write(rec)
+        assert bench.measured_traffic(chunk, fam) is None
+    finally:
+        bench.TRAFFIC = old
+    # the committed record, when present, parses and names its matrices' kernels
     if os.path.exists(bench.TRAFFIC):
         rec = json.loads(open(bench.TRAFFIC).read().split("```json")[1].split("```")[0])
-        for name in rec["kernels"]:
-            t = bench.measured_traffic(name)
-            assert (t is not None) == (rec["kernel_sha"] == bench.spmv_kernel_sha())
+        assert all("kernel" in m and m["hbm_bytes_per_launch"] > 0
+                   for m in rec["matrices"].values())
 
 
 def test_bench_refuses_more_than_one_gpu():

@@ -361,15 +361,15 @@ edfa_status edfa_grad_logk(edfa_system sys, const double *u, const double *lambd
  * handle across later setups.  *tuned (host, may be NULL) receives the
  * number of matrices timed; slots (host, may be NULL) the timings of every slot.  Synchronises the stream.  Errors: EDFA_ERR_ARG, EDFA_ERR_HIP. */
 #define EDFA_TUNE_SLOTS 16
-#define EDFA_TUNE_VARIANTS 13
+#define EDFA_TUNE_VARIANTS 14
 /* One matrix timed by the autotuner.  Slots: 0 A, 1 A^T, 2 G_F, 3 G_F^T, 4 L, 5 U, 6 M_L,
  * 7 M_U, 8 L^T, 9 U^T, 10 M_L^T, 11 M_U^T, 12 A_ppi, 13 A_pip, 14 A_pip^T, 15 A_ppi^T
- * (the FP32 copies for an FP32 preconditioner).  Variants v = 0..12, as (lanes per row,
+ * (the FP32 copies for an FP32 preconditioner).  Variants v = 0..13, as (lanes per row,
  * entries in flight per lane): SELL (1, 4), (1, 8); CSR (2, 2), (2, 4), (4, 2), (4, 4),
  * (8, 2), (8, 4), (16, 2), (16, 4), (32, 2), (32, 4); 12: the chunk kernel (row-aligned
- * chunks of up to 768 entries, one wavefront each, 12 entries in flight per lane), only
- * for matrices whose mean row exceeds 24 entries (their default; us[12] = infinity
- * elsewhere).  us[v]: best of five launches of variant v, in microseconds; when some
+ * chunks of up to 768 entries, one wavefront each, 12 entries in flight per lane); 13: the
+ * chunk kernel on chunks of up to 512 entries (8 in flight per lane).  The chunk variants run only on matrices whose mean row exceeds 24 entries
+ * (where the first is the default; us[12], us[13] = infinity elsewhere).  us[v]: best of five launches of variant v, in microseconds; when some
  * matrix of the handle exceeds 8 MiB, a 512 MiB read before each timed launch evicts the
  * caches, as a full iteration does in the solve. */
 typedef struct {

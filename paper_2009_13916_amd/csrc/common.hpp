@@ -98,7 +98,7 @@ struct Sell {
   // with that many lanes per row on the source CSR arrays (which must outlive this copy);
   // lanes = SPMV_CHUNKED runs the chunk kernel on the CSR arrays (below).
   // depth: entries in flight per lane and round (SELL 4 or 8, CSR 2 or 4; other values
-  // take 4 and 2; the chunk kernel always has CHUNK_K).
+  // take 4 and 2; the chunk kernel CHUNK_K, or CHUNK_K_ALT on its own descriptors).
   int lanes = 0;
   int depth = 0;
   const int *csr_rp = nullptr, *csr_col = nullptr;
@@ -110,9 +110,14 @@ struct Sell {
   DBuf<int2> chunk;
   int nchunk = 0;
   int chunk_k = 0;
+  // The same for the chunk kernel with CHUNK_K_ALT (chunks of at most 64 * CHUNK_K_ALT
+  // entries), built beside them.
+  DBuf<int2> chunk_alt;
+  int nchunk_alt = 0;
 };
 constexpr int SPMV_CHUNKED = -1;
-constexpr int CHUNK_K = 12;   // chunk kernel: 12 entries in flight per lane, 768 per chunk
+constexpr int CHUNK_K = 12;       // chunk kernel: 12 entries in flight per lane, 768 per chunk
+constexpr int CHUNK_K_ALT = 8;    // narrower chunks: 8 per lane, 512 per chunk
 
 inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
 

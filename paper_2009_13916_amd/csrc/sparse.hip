@@ -584,28 +584,38 @@ __global__ __launch_bounds__(SPMV_T) void k_spmv_csr_vec(const int *__restrict__
 // locality.  A row longer than 64 K entries forms a chunk of its own, summed by the whole
 // wavefront.
 // ----------------------------------------------------------------------------------
-template <class V>
-void build_row_chunks(Sell<V> &S, int k, hipStream_t s) {
-  if (S.chunk_k == k || S.rows <= 0) return;
-  const int cap = 64 * k;
-  std::vector<int> rp((size_t)S.rows + 1);
-  EDFA_HIP(hipMemcpyAsync(rp.data(), S.csr_rp, sizeof(int) * rp.size(), hipMemcpyDeviceToHost, s));
-  EDFA_HIP(hipStreamSynchronize(s));
-  std::vector<int2> d;
-  d.reserve(rp.back() / std::max(1, cap / 2) + 2);
+// Greedy row-aligned chunks of at most `cap` entries (a longer row is a chunk of its own).
+static void greedy_chunks(const std::vector<int> &rp, int rows, int cap, std::vector<int2> &d) {
+  d.clear();
+  d.reserve(rp[rows] / std::max(1, cap / 2) + 2);
   int r0 = 0;
   d.push_back(make_int2(0, rp[0]));
-  for (int r = 0; r < S.rows; ++r) {
+  for (int r = 0; r < rows; ++r) {
     // close the current chunk before row r when r would overflow it
     if (r > r0 && rp[r + 1] - rp[r0] > cap) {
       d.push_back(make_int2(r, rp[r]));
       r0 = r;
     }
   }
-  d.push_back(make_int2(S.rows, rp[S.rows]));
+  d.push_back(make_int2(rows, rp[rows]));
+}
+
+template <class V>
+void build_row_chunks(Sell<V> &S, int k, hipStream_t s) {
+  if (S.chunk_k == k || S.rows <= 0) return;
+  std::vector<int> rp((size_t)S.rows + 1);
+  EDFA_HIP(hipMemcpyAsync(rp.data(), S.csr_rp, sizeof(int) * rp.size(), hipMemcpyDeviceToHost, s));
+  EDFA_HIP(hipStreamSynchronize(s));
+  std::vector<int2> d, e;
+  greedy_chunks(rp, S.rows, 64 * k, d);
+  greedy_chunks(rp, S.rows, 64 * CHUNK_K_ALT, e);
   S.nchunk = (int)d.size() - 1;
+  S.nchunk_alt = (int)e.size() - 1;
   S.chunk.ensure(d.size());
+  S.chunk_alt.ensure(e.size());
   EDFA_HIP(hipMemcpyAsync(S.chunk.p, d.data(), sizeof(int2) * d.size(), hipMemcpyHostToDevice, s));
+  EDFA_HIP(hipMemcpyAsync(S.chunk_alt.p, e.data(), sizeof(int2) * e.size(),
+                          hipMemcpyHostToDevice, s));
   EDFA_HIP(hipStreamSynchronize(s));
   S.chunk_k = k;
 }
@@ -716,9 +726,16 @@ void spmv_sell(const Sell<V> &M, const X *x, X *y, double alpha, const X *b, dou
   if (M.lanes == SPMV_CHUNKED) {
     if (M.chunk_k != CHUNK_K)
       fail(EDFA_ERR_ARG, "the chunk kernel needs the chunk descriptors of its matrix");
-    const int nb = ceil_div(M.nchunk, SPMV_T / 64);
-    launch_timed(k_spmv_chunk<V, X, CHUNK_K>, nb, s, e0, e1, M.csr_rp, M.csr_col, M.csr_val,
-                 (const int2 *)M.chunk.p, M.nchunk, x, y, alpha, b, beta, gamma, mk);
+    if (M.depth == CHUNK_K_ALT) {
+      const int nb = ceil_div(M.nchunk_alt, SPMV_T / 64);
+      launch_timed(k_spmv_chunk<V, X, CHUNK_K_ALT>, nb, s, e0, e1, M.csr_rp, M.csr_col,
+                   M.csr_val, (const int2 *)M.chunk_alt.p, M.nchunk_alt, x, y, alpha, b, beta,
+                   gamma, mk);
+    } else {
+      const int nb = ceil_div(M.nchunk, SPMV_T / 64);
+      launch_timed(k_spmv_chunk<V, X, CHUNK_K>, nb, s, e0, e1, M.csr_rp, M.csr_col, M.csr_val,
+                   (const int2 *)M.chunk.p, M.nchunk, x, y, alpha, b, beta, gamma, mk);
+    }
   } else if (M.lanes > 1) {
     const int nb = ceil_div((long long)M.rows * M.lanes, SPMV_T);
     const bool deep = M.depth == 4;

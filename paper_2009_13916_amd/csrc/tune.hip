@@ -23,7 +23,8 @@ struct Variant {
 };
 constexpr Variant kVariants[EDFA_TUNE_VARIANTS] = {
     {0, 4},  {0, 8},  {2, 2},  {2, 4},  {4, 2},  {4, 4},           {8, 2},
-    {8, 4},  {16, 2}, {16, 4}, {32, 2}, {32, 4}, {SPMV_CHUNKED, CHUNK_K}};
+    {8, 4},  {16, 2}, {16, 4}, {32, 2}, {32, 4}, {SPMV_CHUNKED, CHUNK_K},
+    {SPMV_CHUNKED, CHUNK_K_ALT}};
 constexpr int CHUNK_VARIANT = 12;
 
 // The chunk kernel runs only on matrices that carry chunk descriptors (long rows); others

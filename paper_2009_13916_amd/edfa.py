@@ -109,7 +109,7 @@ TUNE_SLOTS = ("A", "A^T", "G_F", "G_F^T", "L", "U", "M_L", "M_U", "L^T", "U^T", 
 # (lanes per row, entries in flight per lane); lanes 1 = the SELL kernel, -1 = the chunk
 # kernel (long rows only), else CSR
 TUNE_VARIANTS = ((1, 4), (1, 8), (2, 2), (2, 4), (4, 2), (4, 4), (8, 2), (8, 4), (16, 2),
-                 (16, 4), (32, 2), (32, 4), (-1, 12))
+                 (16, 4), (32, 2), (32, 4), (-1, 12), (-1, 8))
 
 
 def variant_name(v):

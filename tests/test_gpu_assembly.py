@@ -133,3 +133,21 @@ def test_full_size_full_tensor_properties(lib):
     assert np.abs(r[:nfu0]).max() <= 1e-12 * scale
     np.testing.assert_allclose(r[nfu0:], vol.cpu().numpy() * prob.c / prob.dt, rtol=1e-6,
                                atol=1e-12 * scale)
+
+
+def test_full_size_assembly_entrywise(lib):
+    """The 64^3 full-tensor workload (1,052,672 unknowns, 21,213,696 entries) entry by entry
+    against the oracle's assembly: the pattern bit-exact, every value within 1e-12 of its
+    row's largest entry, the right-hand side likewise.  The oracle takes about 40 s here."""
+    prob = inputs.full_tensor_problem(64)
+    print("[assembly full size] oracle assembly of 64^3", flush=True)
+    o = mhfe.assemble(prob)
+    print("[assembly full size] GPU assembly and comparison", flush=True)
+    S = lib.System(prob)
+    A = _gpu_csr(S, "A", (o.n, o.n))
+    ref = o.matrix().tocsr()
+    ref.sort_indices()
+    assert A.nnz == ref.nnz == 21213696
+    _compare_csr(A, ref, 1e-12)
+    b = S.rhs().cpu().numpy()
+    np.testing.assert_allclose(b, o.b, rtol=1e-12, atol=1e-12 * np.abs(o.b).max())

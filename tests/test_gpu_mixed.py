@@ -158,3 +158,31 @@ def test_fp32_requires_flexible_gmres(lib):
     P = lib.Precond(S, lib.Params(**kw, precision=1))
     with pytest.raises(lib.EdfaError):
         lib.solve(S, P, S.rhs(), rtol=1e-8, flexible=False)
+
+
+def test_fp32_dynamic_patterns_against_fp64_oracle(lib):
+    """FP32 dynamic setup (the workload's settings on a 10^3 full-tensor grid): the restricted
+    residuals are computed in FP32, so near-ties of |r| can select other faces than the FP64
+    oracle.  The fraction of cells whose final pattern equals the oracle's is measured and
+    printed (at least 95% required), and the FP32 application stays within the FP32 bound of
+    the FP64 oracle's application (its patterns differ on the remaining cells)."""
+    kw = dict(variant="dynamic", n_add=1, n_ent=6, tau=1e-3, filt="post_H")
+    prob = inputs.full_tensor_problem(10, sigma=2.0, corr=1.25, config_id=53)
+    o = mhfe.assemble(prob)
+    E = oedfa.build(o, oedfa.Params(**kw))
+    S = lib.System(prob)
+    P = lib.Precond(S, lib.Params(**kw, precision=1))
+    G = _to_sp(*P.export("G")[:3], (o.ne, o.nfu))
+    G.sort_indices()
+    O = E.st1.Gt.tocsr()
+    O.sort_indices()
+    same = np.mean([np.array_equal(G.indices[G.indptr[m]:G.indptr[m + 1]],
+                                   O.indices[O.indptr[m]:O.indptr[m + 1]]) for m in range(o.ne)])
+    r = np.random.default_rng(5).standard_normal(o.n)
+    z = P.apply(torch.tensor(r, device="cuda")).cpu().numpy()
+    ref = E.apply(r)
+    err = np.linalg.norm(z - ref) / np.linalg.norm(ref)
+    print(f"[fp32 dynamic] patterns as the FP64 oracle's: {100 * same:.2f}% of {o.ne} cells; "
+          f"application vs the FP64 oracle: {err:.2e}", flush=True)
+    assert same >= 0.95
+    assert err <= 5e-3

@@ -9,6 +9,7 @@ import torch
 
 from oracle import edfa as oedfa, mhfe
 from paper_2009_13916_amd import inputs
+from paper_2009_13916_amd.edfa import TUNE_VARIANTS
 
 pytestmark = pytest.mark.gpu
 
@@ -23,7 +24,7 @@ def case():
     return prob, o, E, mhfe.direct_solve(o)
 
 
-@pytest.mark.parametrize("v", range(13))
+@pytest.mark.parametrize("v", range(len(TUNE_VARIANTS)))
 def test_pinned_variant_matches_oracle(lib, case, v):
     prob, o, E, u = case
     S = lib.System(prob)

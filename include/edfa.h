@@ -278,9 +278,12 @@ typedef struct {
 
 /* Solve A x = b (or A^T x = b), x0 = 0, each grid of a batch to its own rtol, with
  *  - EDFA_GMRES: restarted right-preconditioned GMRES(restart) (flexible: FGMRES).
- *    Synchronises the stream at the start of every restart cycle and, inside an eagerly
- *    run cycle, after every 8 iterations (16 for a batch) to stop the cycle once every
- *    grid has converged; a graph-replayed cycle synchronises only at its start.
+ *    Synchronises the stream at the start of every restart cycle.  Inside an eagerly run
+ *    cycle the host reads the convergence states every 8 iterations (16 for a batch), one
+ *    reading late (it waits for the copy taken 8 iterations earlier while the following
+ *    iterations are already queued), and stops the cycle once every grid has converged;
+ *    the iterations queued past convergence skip their work.  A graph-replayed cycle
+ *    synchronises only at its start.
  *  - EDFA_BICGSTAB: right-preconditioned Bi-CGStab (Section 4: x0 = 0, exit on
  *    ||r_k|| <= rtol ||r_0||).  Synchronises every 4 iterations; when every grid has
  *    stopped, the true residual confirms convergence, and a grid whose recurrence drifted

@@ -26,9 +26,10 @@ __global__ void k_scatter(const T *__restrict__ x, const int *__restrict__ idx, 
 
 template <class A, class B>
 __global__ void k_convert(const A *__restrict__ x, long long n, B *y, RowMask mk) {
+  if (all_off(mk)) return;
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  if (mk.seg && !mk.act[mk.seg[i] * mk.stride]) return;
+  if (row_off(mk, (int)i)) return;
   y[i] = (B)x[i];
 }
 

@@ -61,6 +61,29 @@ struct DBuf {
   operator T *() const { return p; }
 };
 
+// Pinned host buffer: device-to-host copies into it run asynchronously.
+template <class T>
+struct HBuf {
+  T *p = nullptr;
+  size_t cap = 0;
+  HBuf() = default;
+  HBuf(const HBuf &) = delete;
+  HBuf &operator=(const HBuf &) = delete;
+  ~HBuf() {
+    if (p) (void)hipHostFree(p);
+  }
+  T *ensure(size_t count) {
+    if (count <= cap && p) return p;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    cap = 0;
+    const size_t c = count ? count : 1;
+    EDFA_HIP(hipHostMalloc((void **)&p, c * sizeof(T), hipHostMallocDefault));
+    cap = c;
+    return p;
+  }
+};
+
 // CSR matrix in device memory (int32 indices).
 template <class V>
 struct Csr {
@@ -193,12 +216,23 @@ int default_spmv_lanes(double mean_row);
 
 // Rows to skip in a product: row r is computed only if act[seg[r] * stride] != 0 (the
 // activity flag of its grid).  seg == NULL computes every row.
+// Rows to skip in a product: row r belongs to grid seg[r], whose flag act[g * stride] is
+// zero once it stops iterating.  seg = null with act set: every row belongs to grid 0 (a
+// single system, masked after convergence); act = null: no mask.
 struct RowMask {
   const int *seg = nullptr;
   const int *act = nullptr;
   int stride = 0;
-  RowMask offset(int rows) const { return seg ? RowMask{seg + rows, act, stride} : RowMask{}; }
+  RowMask offset(int rows) const { return RowMask{seg ? seg + rows : nullptr, act, stride}; }
 };
+// A stopped single system: one uniform check at a kernel's start, before any divergence.
+__device__ __forceinline__ bool all_off(const RowMask &mk) {
+  return mk.act && !mk.seg && !mk.act[0];
+}
+// A row of a stopped grid of a batch.
+__device__ __forceinline__ bool row_off(const RowMask &mk, int row) {
+  return mk.seg && !mk.act[mk.seg[row] * mk.stride];
+}
 
 // Same contract as spmv() for a SELL-64 matrix.  `role` picks the kernel symbol:
 // SPMV_OPERATOR for products with the system matrix, SPMV_PRECOND for everything else.

@@ -107,6 +107,7 @@ struct SolveWork {
   DBuf<double> Tz;     // FGMRES, per segment m x m: column j = [a_j; rho_j], u_j = Q T e_j
   DBuf<int> ran;
   DBuf<SegState> st;
+  HBuf<SegState> hst;  // pinned copy of st for the in-loop convergence checks
   // Bi-CGStab vectors and state
   DBuf<double> rhat, p, v, ph, sv, sh, t;
   DBuf<BiSeg> bst;

@@ -568,7 +568,9 @@ edfa_status gmres(edfa_system_s &S, edfa_precond_s &P, const double *b, double *
   // profiled system products: the launch records its own events around the kernel
   // Inside the Arnoldi loop of a batch, the products skip the rows of grids that have
   // stopped iterating (every matrix is block-diagonal by grid).
-  RowMask live;
+  // One system: every row in grid 0, masked once it has converged (a profiled solve keeps
+  // every launch whole, so that its timings are those of real work).
+  RowMask live = prm.profile ? RowMask{} : RowMask{nullptr, &W.st.p->active, 0};
   if (nseg > 1) {
     if (S.rowseg.n < (size_t)n) fail(EDFA_ERR_ARG, "batch without its row-to-grid map");
     live = RowMask{S.rowseg.p, &W.st.p->active, (int)(sizeof(SegState) / sizeof(int))};
@@ -617,7 +619,18 @@ edfa_status gmres(edfa_system_s &S, edfa_precond_s &P, const double *b, double *
                      W.scale.p, prm.max_iter, 1);
   EDFA_CHECK_LAUNCH();
   int cycles = 0;
+  // In-loop convergence checks read the states one check late from pinned memory, so the
+  // host never drains the device queue: the iterations launched meanwhile run masked (their
+  // kernels return at once) when every grid has stopped.  A profiled solve reads them at
+  // once (its launches after convergence are then whole iterations, as timed).
   const int check_every = nseg == 1 ? 8 : 16;
+  SegState *hpin = W.hst.ensure(nseg);
+  hipEvent_t ev_check = nullptr;
+  EDFA_HIP(hipEventCreateWithFlags(&ev_check, hipEventDisableTiming));
+  struct EventGuard {
+    hipEvent_t e;
+    ~EventGuard() { (void)hipEventDestroy(e); }
+  } ev_guard{ev_check};
   // One restart cycle on stream cs.  With host_checks the host stops early once every
   // segment is inactive; without, converged segments are masked on the device (the
   // form that a graph can hold).
@@ -633,6 +646,7 @@ edfa_status gmres(edfa_system_s &S, edfa_precond_s &P, const double *b, double *
       hipLaunchKernelGGL(k_seg_reduce_w, dim3(ceil_div(2 * j + 2, 4), nseg), dim3(256), 0, cs,
                          W.part.p, ld, 2 * j + 2, W.segptr.p, W.st.p, SEG_ACTIVE, W.h1.p, ld);
     };
+    bool pending = false;   // a state copy is in flight behind ev_check
     for (int j = 0; j < m; ++j) {
       double *vj = W.V.p + (size_t)j * n;
       double *zj = prm.flexible ? W.Z.p + (size_t)j * n : W.z.p;
@@ -645,12 +659,23 @@ edfa_status gmres(edfa_system_s &S, edfa_precond_s &P, const double *b, double *
       hipLaunchKernelGGL(k_dcgs_update, dim3(nch, 2), dim3(RT), 0, cs, W.V.p, (long long)n, j, W.w.p,
                          W.chunks.p, W.st.p, W.coef.p, 2 * m + 2, W.scale.p);
       EDFA_CHECK_LAUNCH();
-      if (host_checks && (j + 1) % check_every == 0 && j + 1 < m) {
-        EDFA_HIP(hipMemcpyAsync(hst.data(), W.st.p, sizeof(SegState) * nseg, hipMemcpyDeviceToHost, cs));
+      if (host_checks && prm.profile && (j + 1) % check_every == 0 && j + 1 < m) {
+        EDFA_HIP(hipMemcpyAsync(hpin, W.st.p, sizeof(SegState) * nseg, hipMemcpyDeviceToHost, cs));
         EDFA_HIP(hipStreamSynchronize(cs));
         int a = 0;
-        for (auto &q : hst) a += q.active;
+        for (int g = 0; g < nseg; ++g) a += hpin[g].active;
         if (!a) break;
+      } else if (host_checks && (j + 1) % check_every == 0 && j + 1 < m) {
+        if (pending) {
+          EDFA_HIP(hipEventSynchronize(ev_check));
+          pending = false;
+          int a = 0;
+          for (int g = 0; g < nseg; ++g) a += hpin[g].active;
+          if (!a) break;
+        }
+        EDFA_HIP(hipMemcpyAsync(hpin, W.st.p, sizeof(SegState) * nseg, hipMemcpyDeviceToHost, cs));
+        EDFA_HIP(hipEventRecord(ev_check, cs));
+        pending = true;
       }
     }
     // segments whose basis is full: finish the last column with one more pass of dots

@@ -482,10 +482,11 @@ __global__ __launch_bounds__(SPMV_T) void k_spmv_sell(const int *__restrict__ sp
                                                       double alpha, const X *__restrict__ b,
                                                       double beta, double gamma, RowMask mk) {
   using A = typename AccT<V, X>::type;
+  if (all_off(mk)) return;
   const int r = blockIdx.x * SPMV_T + threadIdx.x;   // position in the layout
   if (r >= rows) return;
   const int row = perm ? perm[r] : r;
-  if (mk.seg && !mk.act[mk.seg[row] * mk.stride]) return;
+  if (row_off(mk, row)) return;
   // a wavefront holds exactly one slice of 64 rows: its offset is a scalar load, issued
   // (the empty asm keeps it from sinking below the length test) while the vector load of
   // the row length is in flight
@@ -534,10 +535,11 @@ __global__ __launch_bounds__(SPMV_T) void k_spmv_csr_vec(const int *__restrict__
                                                          double alpha, const X *__restrict__ b,
                                                          double beta, double gamma, RowMask mk) {
   using A = typename AccT<V, X>::type;
+  if (all_off(mk)) return;
   const int t = blockIdx.x * SPMV_T + threadIdx.x;
   const int r = t / L, l = t % L;
   if (r >= rows) return;   // all L lanes of a row leave together
-  if (mk.seg && !mk.act[mk.seg[r] * mk.stride]) return;
+  if (row_off(mk, r)) return;
   const int a = rp[r], e = rp[r + 1];
   A s[U];
 #pragma unroll
@@ -636,17 +638,19 @@ __global__ __launch_bounds__(SPMV_T) void k_spmv_chunk(const int *__restrict__ r
   using A = typename AccT<V, X>::type;
   constexpr int CAP = 64 * K;
   __shared__ A buf[SPMV_T / 64][CAP];
+  if (all_off(mk)) return;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int c = blockIdx.x * (SPMV_T / 64) + wv;
   if (c >= nchunk) return;
   const int2 d0 = desc[c], d1 = desc[c + 1];
   const int r0 = d0.x, r1 = d1.x, e0 = d0.y, e1 = d1.y;
   if (mk.seg) {
+    // the whole chunk in one stopped grid
     const int s0 = mk.seg[r0], s1 = mk.seg[r1 - 1];
     if (s0 == s1 && !mk.act[s0 * mk.stride]) return;
   }
   auto finish = [&](int row, A sum) {
-    if (mk.seg && !mk.act[mk.seg[row] * mk.stride]) return;
+    if (row_off(mk, row)) return;
     A out = (A)alpha * sum;
     if (b) out += (A)beta * (A)b[row];
     if (gamma != 0.0) out += (A)gamma * (A)x[row];

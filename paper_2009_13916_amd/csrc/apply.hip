@@ -216,6 +216,37 @@ static void apply_typed(edfa_precond_s &P, PrecData<T> &D, const ApplyWork<T> &W
   prod(D.GFT_s, 3, W.t2, zpi, -1.0, nullptr, 0.0, fm);
 }
 
+// FP32 application reading r and writing z in FP64 directly (no conversion passes of the
+// whole vector): the first products read r_pi and r_p, the last ones write z_p and z_pi,
+// in FP64; everything between stays FP32.  Used for the approximate inverses of the ILU(0)
+// factors without refinement steps (the default), forward application.
+static void apply_fp32_direct(edfa_precond_s &P, PrecData<float> &D, const ApplyWork<float> &W,
+                              const double *r, double *z, const Sell<float> &c1,
+                              const Sell<float> &c2, hipStream_t s, RowMask fm, RowMask cm) {
+  const int nfu = P.sys->nfu;
+  const int R = SPMV_PRECOND;
+  const double *rpi = r, *rp = r + nfu;
+  double *zpi = z, *zp = z + nfu;
+  // out (FP64 when o64), x of type X, addend bb FP64 when given
+  auto prod = [&](const Sell<float> &M, int slot, const auto *in, void *out, bool o64,
+                  double alpha, const double *bb, RowMask mk) {
+    const Ev e = prod_events(P, slot);
+    spmv_sell_io(M, in, out, o64, alpha, bb, true, bb ? 1.0 : 0.0, s, 0.0, R, e.a, e.b, mk);
+  };
+  // t = A~^-1 r_pi = -G_F^T G_F r_pi
+  prod(D.GF_s, 2, rpi, W.t1, false, 1.0, nullptr, fm);
+  prod(D.GFT_s, 3, W.t1, W.t2, false, -1.0, nullptr, fm);
+  // y = r_p - A_ppi t
+  prod(c1, 12, W.t2, W.r, false, -1.0, rp, cm);
+  // z_p = M_U (M_L y)
+  prod(D.ML_s, 6, W.r, W.w, false, 1.0, nullptr, cm);
+  prod(D.MU_s, 7, W.w, zp, true, 1.0, nullptr, cm);
+  // z_pi = A~^-1 (r_pi - A_pip z_p)
+  prod(c2, 13, zp, W.t1, false, -1.0, rpi, fm);
+  prod(D.GF_s, 2, W.t1, W.t2, false, 1.0, nullptr, fm);
+  prod(D.GFT_s, 3, W.t2, zpi, true, -1.0, nullptr, fm);
+}
+
 // Device memory for the allocation-free application: a static array per GPU, its
 // address looked up once per device.  Every call on a device uses the same bytes, so calls
 // that overlap on one GPU race.
@@ -340,6 +371,10 @@ static void apply_impl(edfa_precond_s &P, int transpose, const double *r, double
     W = handle_work(D, S.nfu, S.ne);
     rin = P.rin_f.ensure(n);
     zf = D.z.ensure(n);
+  }
+  if (!transpose && P.prm.schur_solver == EDFA_SCHUR_ISAI && P.prm.isai_steps <= 1) {
+    apply_fp32_direct(P, D, W, r, z, cs[0], cs[1], s, fm, cm);
+    return;
   }
   hipLaunchKernelGGL((k_convert<double, float>), dim3(ceil_div(n, 256)), dim3(256), 0, s, r,
                      (long long)n, rin, mask);

@@ -242,5 +242,10 @@ template <class V, class X>
 void spmv_sell(const Sell<V> &M, const X *x, X *y, double alpha, const X *b, double beta,
                hipStream_t s, double gamma = 0.0, int role = SPMV_PRECOND,
                hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr, RowMask mask = {});
+// The same with y and b in FP64 (y64, b64) or FP32 each, whatever the type of x.
+template <class V, class X>
+void spmv_sell_io(const Sell<V> &M, const X *x, void *y, bool y64, double alpha, const void *b,
+                  bool b64, double beta, hipStream_t s, double gamma, int role, hipEvent_t e0,
+                  hipEvent_t e1, RowMask mask);
 
 }  // namespace edfa

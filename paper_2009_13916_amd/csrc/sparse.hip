@@ -472,15 +472,31 @@ template void build_sell<float>(const Csr<float> &, Sell<float> &, DBuf<int> &, 
 // launches (0) from the preconditioner's (1) in kernel traces.
 constexpr int SPMV_T = 256;
 
+// y[row] = alpha sum + beta b[row] + gamma x[row]; y and b are FP64 or FP32 each, whatever
+// x is (io bit 0: y is FP64, bit 1: b is FP64), so the FP32 application reads and writes
+// the FP64 vectors of the iteration directly.
+template <class A, class X>
+__device__ __forceinline__ void store_row(void *y, const void *b, int io, int row, A sum,
+                                          double alpha, double beta, double gamma,
+                                          const X *__restrict__ x) {
+  A out = (A)alpha * sum;
+  if (b) out += (A)beta * (io & 2 ? (A)((const double *)b)[row] : (A)((const float *)b)[row]);
+  if (gamma != 0.0) out += (A)gamma * (A)x[row];
+  if (io & 1)
+    ((double *)y)[row] = (double)out;
+  else
+    ((float *)y)[row] = (float)out;
+}
+
 template <class V, class X, int ROLE, int U>
 __global__ __launch_bounds__(SPMV_T) void k_spmv_sell(const int *__restrict__ sptr,
                                                       const int *__restrict__ rlen,
                                                       const int *__restrict__ col,
                                                       const V *__restrict__ val,
                                                       const int *__restrict__ perm, int rows,
-                                                      const X *__restrict__ x, X *__restrict__ y,
-                                                      double alpha, const X *__restrict__ b,
-                                                      double beta, double gamma, RowMask mk) {
+                                                      const X *__restrict__ x, void *y,
+                                                      double alpha, const void *b, double beta,
+                                                      double gamma, int io, RowMask mk) {
   using A = typename AccT<V, X>::type;
   if (all_off(mk)) return;
   const int r = blockIdx.x * SPMV_T + threadIdx.x;   // position in the layout
@@ -518,10 +534,7 @@ __global__ __launch_bounds__(SPMV_T) void k_spmv_sell(const int *__restrict__ sp
   for (int h = U / 2; h > 0; h >>= 1)
 #pragma unroll
     for (int u = 0; u < h; ++u) s[u] += s[u + h];
-  A out = (A)alpha * s[0];
-  if (b) out += (A)beta * (A)b[row];
-  if (gamma != 0.0) out += (A)gamma * (A)x[row];
-  y[row] = (X)out;
+  store_row<A, X>(y, b, io, row, s[0], alpha, beta, gamma, x);
 }
 
 // L lanes per row on the CSR arrays, for matrices with long rows: the lanes of a row read
@@ -531,9 +544,9 @@ template <class V, class X, int L, int U>
 __global__ __launch_bounds__(SPMV_T) void k_spmv_csr_vec(const int *__restrict__ rp,
                                                          const int *__restrict__ col,
                                                          const V *__restrict__ val, int rows,
-                                                         const X *__restrict__ x, X *__restrict__ y,
-                                                         double alpha, const X *__restrict__ b,
-                                                         double beta, double gamma, RowMask mk) {
+                                                         const X *__restrict__ x, void *y,
+                                                         double alpha, const void *b, double beta,
+                                                         double gamma, int io, RowMask mk) {
   using A = typename AccT<V, X>::type;
   if (all_off(mk)) return;
   const int t = blockIdx.x * SPMV_T + threadIdx.x;
@@ -567,12 +580,7 @@ __global__ __launch_bounds__(SPMV_T) void k_spmv_csr_vec(const int *__restrict__
   A sum = s[0];
 #pragma unroll
   for (int o = L / 2; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
-  if (l == 0) {
-    A out = (A)alpha * sum;
-    if (b) out += (A)beta * (A)b[r];
-    if (gamma != 0.0) out += (A)gamma * (A)x[r];
-    y[r] = (X)out;
-  }
+  if (l == 0) store_row<A, X>(y, b, io, r, sum, alpha, beta, gamma, x);
 }
 
 // ----------------------------------------------------------------------------------
@@ -632,9 +640,9 @@ __global__ __launch_bounds__(SPMV_T) void k_spmv_chunk(const int *__restrict__ r
                                                        const V *__restrict__ val,
                                                        const int2 *__restrict__ desc,
                                                        int nchunk, const X *__restrict__ x,
-                                                       X *__restrict__ y, double alpha,
-                                                       const X *__restrict__ b, double beta,
-                                                       double gamma, RowMask mk) {
+                                                       void *y, double alpha, const void *b,
+                                                       double beta, double gamma, int io,
+                                                       RowMask mk) {
   using A = typename AccT<V, X>::type;
   constexpr int CAP = 64 * K;
   __shared__ A buf[SPMV_T / 64][CAP];
@@ -651,10 +659,7 @@ __global__ __launch_bounds__(SPMV_T) void k_spmv_chunk(const int *__restrict__ r
   }
   auto finish = [&](int row, A sum) {
     if (row_off(mk, row)) return;
-    A out = (A)alpha * sum;
-    if (b) out += (A)beta * (A)b[row];
-    if (gamma != 0.0) out += (A)gamma * (A)x[row];
-    y[row] = (X)out;
+    store_row<A, X>(y, b, io, row, sum, alpha, beta, gamma, x);
   };
   if (e1 - e0 > CAP) {
     // one long row: the wavefront strides over it, K entries in flight per lane
@@ -723,10 +728,11 @@ static void launch_timed(K kern, int blocks, hipStream_t s, hipEvent_t e0, hipEv
 }
 
 template <class V, class X>
-void spmv_sell(const Sell<V> &M, const X *x, X *y, double alpha, const X *b, double beta,
-               hipStream_t s, double gamma, int role, hipEvent_t e0, hipEvent_t e1,
-               RowMask mk) {
+void spmv_sell_io(const Sell<V> &M, const X *x, void *y, bool y64, double alpha, const void *b,
+                  bool b64, double beta, hipStream_t s, double gamma, int role, hipEvent_t e0,
+                  hipEvent_t e1, RowMask mk) {
   if (M.rows <= 0) return;
+  const int io = (y64 ? 1 : 0) | (b64 ? 2 : 0);
   if (M.lanes == SPMV_CHUNKED) {
     if (M.chunk_k != CHUNK_K)
       fail(EDFA_ERR_ARG, "the chunk kernel needs the chunk descriptors of its matrix");
@@ -734,18 +740,18 @@ void spmv_sell(const Sell<V> &M, const X *x, X *y, double alpha, const X *b, dou
       const int nb = ceil_div(M.nchunk_alt, SPMV_T / 64);
       launch_timed(k_spmv_chunk<V, X, CHUNK_K_ALT>, nb, s, e0, e1, M.csr_rp, M.csr_col,
                    M.csr_val, (const int2 *)M.chunk_alt.p, M.nchunk_alt, x, y, alpha, b, beta,
-                   gamma, mk);
+                   gamma, io, mk);
     } else {
       const int nb = ceil_div(M.nchunk, SPMV_T / 64);
       launch_timed(k_spmv_chunk<V, X, CHUNK_K>, nb, s, e0, e1, M.csr_rp, M.csr_col, M.csr_val,
-                   (const int2 *)M.chunk.p, M.nchunk, x, y, alpha, b, beta, gamma, mk);
+                   (const int2 *)M.chunk.p, M.nchunk, x, y, alpha, b, beta, gamma, io, mk);
     }
   } else if (M.lanes > 1) {
     const int nb = ceil_div((long long)M.rows * M.lanes, SPMV_T);
     const bool deep = M.depth == 4;
 #define EDFA_VEC(LN, UU)                                                                      \
   launch_timed(k_spmv_csr_vec<V, X, LN, UU>, nb, s, e0, e1, M.csr_rp, M.csr_col, M.csr_val,    \
-               M.rows, x, y, alpha, b, beta, gamma, mk)
+               M.rows, x, y, alpha, b, beta, gamma, io, mk)
 #define EDFA_VEC2(LN) \
   if (deep) EDFA_VEC(LN, 4); else EDFA_VEC(LN, 2)
     switch (M.lanes) {
@@ -762,7 +768,7 @@ void spmv_sell(const Sell<V> &M, const X *x, X *y, double alpha, const X *b, dou
     const bool deep = M.depth == 8;
 #define EDFA_SELL(RL, UU)                                                                     \
   launch_timed(k_spmv_sell<V, X, RL, UU>, nb, s, e0, e1, M.sptr.p, M.rlen.p, M.col.p, M.val.p, \
-               M.sorted ? M.perm.p : nullptr, M.rows, x, y, alpha, b, beta, gamma, mk)
+               M.sorted ? M.perm.p : nullptr, M.rows, x, y, alpha, b, beta, gamma, io, mk)
     if (role == SPMV_OPERATOR) {
       if (deep) EDFA_SELL(SPMV_OPERATOR, 8); else EDFA_SELL(SPMV_OPERATOR, 4);
     } else {
@@ -773,11 +779,25 @@ void spmv_sell(const Sell<V> &M, const X *x, X *y, double alpha, const X *b, dou
   EDFA_CHECK_LAUNCH();
 }
 
+template <class V, class X>
+void spmv_sell(const Sell<V> &M, const X *x, X *y, double alpha, const X *b, double beta,
+               hipStream_t s, double gamma, int role, hipEvent_t e0, hipEvent_t e1,
+               RowMask mk) {
+  constexpr bool w = sizeof(X) == 8;
+  spmv_sell_io<V, X>(M, x, y, w, alpha, b, w, beta, s, gamma, role, e0, e1, mk);
+}
+
 template void spmv_sell<double, double>(const Sell<double> &, const double *, double *, double,
                                         const double *, double, hipStream_t, double, int,
                                         hipEvent_t, hipEvent_t, RowMask);
 template void spmv_sell<float, float>(const Sell<float> &, const float *, float *, double,
                                       const float *, double, hipStream_t, double, int, hipEvent_t,
                                       hipEvent_t, RowMask);
+template void spmv_sell_io<float, float>(const Sell<float> &, const float *, void *, bool, double,
+                                         const void *, bool, double, hipStream_t, double, int,
+                                         hipEvent_t, hipEvent_t, RowMask);
+template void spmv_sell_io<float, double>(const Sell<float> &, const double *, void *, bool,
+                                          double, const void *, bool, double, hipStream_t, double,
+                                          int, hipEvent_t, hipEvent_t, RowMask);
 
 }  // namespace edfa

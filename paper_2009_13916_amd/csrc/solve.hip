@@ -260,8 +260,18 @@ __global__ __launch_bounds__(64) void k_dcgs_step(int nseg, int m, int j, int fi
   __syncthreads();
   double *hn = H + (long long)j * (m + 1);
   for (int i = lane; i <= j; i += 64) {
+    // the entries of row i of Hbar are read eight columns at a time (loads issued together),
+    // the sum still runs in ascending column order
     double t = cc[i];
-    for (int k = (i > 0 ? i - 1 : 0); k < j; ++k) t -= H[(long long)k * (m + 1) + i] * a[k];
+    int k = i > 0 ? i - 1 : 0;
+    for (; k + 8 <= j; k += 8) {
+      double h[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) h[u] = H[(long long)(k + u) * (m + 1) + i];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) t -= h[u] * a[k + u];
+    }
+    for (; k < j; ++k) t -= H[(long long)k * (m + 1) + i] * a[k];
     hn[i] = t / rho;
   }
   double *cf = coef + (long long)g * (2 * m + 2);

@@ -139,7 +139,17 @@ __global__ __launch_bounds__(256) void k_seg_reduce_w(const double *__restrict__
   if (which != SEG_ALL && !st[g].active) return;
   const int c0 = segptr[g], c1 = segptr[g + 1];
   double s = 0;
-  for (int c = c0 + lane; c < c1; c += 64) s += part[(long long)c * ldp + i];
+  // eight of the lane's chunks per round, their loads issued together (the sum keeps the
+  // chunk order)
+  int c = c0 + lane;
+  for (; c + 7 * 64 < c1; c += 8 * 64) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(long long)(c + u * 64) * ldp + i];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  for (; c < c1; c += 64) s += part[(long long)c * ldp + i];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
   if (lane == 0) out[(long long)g * ldo + i] = s;

@@ -400,30 +400,45 @@ __global__ void k_seg_start(int nseg, int m, SegState *st, const double *__restr
   st[g] = S;
 }
 
-// Least squares of the cycle: R y = g (upper triangular, size j of the segment); FGMRES
-// (Tz non-null) then replaces y by T^-1 y, the coefficients of the stored z_j.
-__global__ void k_lsq(int nseg, int m, const SegState *__restrict__ st, const double *__restrict__ R,
-                      const double *__restrict__ gv, double *y, int *ran,
-                      const double *__restrict__ Tz) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+// Least squares of the cycle, one wavefront per segment: R y = g (upper triangular, size
+// k = the columns that ran), by columns (y_i = s_i / R_ii, then s_l -= R_li y_i for l < i),
+// with the triangle staged in LDS when it fits (`staged`); FGMRES (Tz non-null) then
+// replaces y by T^-1 y, the coefficients of the stored z_j, the same way.
+extern __shared__ double lsq_lds[];
+__global__ __launch_bounds__(64) void k_lsq(int nseg, int m, const SegState *__restrict__ st,
+                                            const double *__restrict__ R,
+                                            const double *__restrict__ gv, double *y,
+                                            const int *__restrict__ ran,
+                                            const double *__restrict__ Tz, int staged) {
+  const int g = blockIdx.x;
   if (g >= nseg) return;
-  const int k = ran[g];
-  double *yy = y + (long long)g * m;
-  for (int i = 0; i < m; ++i) yy[i] = 0.0;
+  const int lane = threadIdx.x;
+  const int k = __builtin_amdgcn_readfirstlane(ran[g]);
+  double *ys = lsq_lds, *Ms = lsq_lds + m;
   const double *gg = gv + (long long)g * (m + 1);
-  for (int i = k - 1; i >= 0; --i) {
-    double s = gg[i];
-    for (int l = i + 1; l < k; ++l) s -= R[((long long)g * m + i) * m + l] * yy[l];
-    yy[i] = s / R[((long long)g * m + i) * m + i];
-  }
-  if (Tz) {
-    const double *T = Tz + (long long)g * m * m;
-    for (int i = k - 1; i >= 0; --i) {
-      double s = yy[i];
-      for (int l = i + 1; l < k; ++l) s -= T[(long long)i * m + l] * yy[l];
-      yy[i] = s / T[(long long)i * m + i];
+  for (int i = lane; i < m; i += 64) ys[i] = i < k ? gg[i] : 0.0;
+  auto solve = [&](const double *Mg) {   // entry (i, l) at Mg[i m + l]
+    const double *M = Mg;
+    if (staged) {
+      for (int t = lane; t < k * k; t += 64) {
+        const int i = t / k, l = t % k;
+        Ms[i * m + l] = Mg[(long long)i * m + l];
+      }
+      M = Ms;
     }
-  }
+    __syncthreads();
+    for (int i = k - 1; i >= 0; --i) {
+      const double yi = ys[i] / M[(long long)i * m + i];
+      for (int l = lane; l < i; l += 64) ys[l] -= M[(long long)l * m + i] * yi;
+      __syncthreads();
+      if (lane == 0) ys[i] = yi;
+      __syncthreads();
+    }
+  };
+  solve(R + (long long)g * m * m);
+  if (Tz) solve(Tz + (long long)g * m * m);
+  double *yy = y + (long long)g * m;
+  for (int i = lane; i < m; i += 64) yy[i] = ys[i];
 }
 
 // out[e] (+)= sum_{i<m} y[seg][i] B_i[e]
@@ -639,6 +654,9 @@ edfa_status gmres(edfa_system_s &S, edfa_precond_s &P, const double *b, double *
                      W.scale.p, prm.max_iter, 1);
   EDFA_CHECK_LAUNCH();
   int cycles = 0;
+  // the least-squares kernel stages the triangle in LDS when it fits (restarts up to 89)
+  const int lsq_staged = (size_t)(m + m * m) * sizeof(double) <= 64 * 1024;
+  const size_t lsq_lds_bytes = sizeof(double) * (size_t)(lsq_staged ? m + m * m : m);
   // In-loop convergence checks read the states one check late from pinned memory, so the
   // host never drains the device queue: the iterations launched meanwhile run masked (their
   // kernels return at once) when every grid has stopped.  A profiled solve reads them at
@@ -706,8 +724,8 @@ edfa_status gmres(edfa_system_s &S, edfa_precond_s &P, const double *b, double *
     EDFA_CHECK_LAUNCH();
     // end of cycle: y = R^-1 g, x += Z y (flexible) or x += P^-1 (V y)
     hipLaunchKernelGGL(k_record_ran, dim3(sb), dim3(64), 0, cs, nseg, W.st.p, W.ran.p);
-    hipLaunchKernelGGL(k_lsq, dim3(sb), dim3(64), 0, cs, nseg, m, W.st.p, W.R.p, W.g.p, W.y.p,
-                       W.ran.p, Tz);
+    hipLaunchKernelGGL(k_lsq, dim3(nseg), dim3(64), lsq_lds_bytes, cs, nseg, m, W.st.p, W.R.p,
+                       W.g.p, W.y.p, W.ran.p, Tz, lsq_staged);
     if (prm.flexible) {
       hipLaunchKernelGGL(k_combine, dim3(nch), dim3(RT), 0, cs, W.Z.p, (long long)n, m, W.chunks.p,
                          W.y.p, W.ran.p, x, 1);

@@ -230,8 +230,9 @@ edfa_status edfa_apply(edfa_precond pre, int32_t transpose, const double *r, dou
  * calls that overlap on one GPU race (serialise them, e.g. on one stream).  Results equal
  * edfa_apply's.  Errors: EDFA_ERR_ARG when the workspace exceeds the array (the message
  * gives both sizes), or when what the application reads does not exist yet and would have
- * to be allocated: the transposed factors (transpose = 1) and the FP32 coupling blocks are
- * built by a first edfa_apply of the same kind (or a solve); EDFA_ERR_HIP.  Asynchronous. */
+ * to be allocated: the transposed factors (transpose = 1), the FP32 coupling blocks and the
+ * descriptors of the 512-entry chunk kernel (when the tuner chose it) are built by a first
+ * edfa_apply of the same kind (or a solve); EDFA_ERR_HIP.  Asynchronous. */
 #define EDFA_NOALLOC_SCRATCH_BYTES (64u << 20)
 edfa_status edfa_apply_noalloc(edfa_precond pre, int32_t transpose, const double *r, double *z,
                                hipStream_t stream);

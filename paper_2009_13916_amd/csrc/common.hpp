@@ -134,9 +134,9 @@ struct Sell {
   int nchunk = 0;
   int chunk_k = 0;
   // The same for the chunk kernel with CHUNK_K_ALT (chunks of at most 64 * CHUNK_K_ALT
-  // entries), built beside them.
-  DBuf<int2> chunk_alt;
-  int nchunk_alt = 0;
+  // entries), built on the first product that uses them (nchunk_alt < 0: not built).
+  mutable DBuf<int2> chunk_alt;
+  mutable int nchunk_alt = -1;
 };
 constexpr int SPMV_CHUNKED = -1;
 constexpr int CHUNK_K = 12;       // chunk kernel: 12 entries in flight per lane, 768 per chunk

@@ -169,6 +169,8 @@ template <class T>
 void build_hraw(edfa_precond_s &P, PrecData<T> &D, hipStream_t s);
 void grad_logk(edfa_system_s &S, const double *u, const double *lam, double *g, hipStream_t s);
 void apply_tuned(edfa_precond_s &P);
+// True when a matrix's chosen kernel still needs chunk descriptors built on first use.
+bool chunks_pending(edfa_precond_s &P);
 // slot -1: every slot; variant -1: back to the default choice (at the next setup)
 void set_variant(edfa_precond_s &P, int slot, int variant);
 int autotune(edfa_precond_s &P, hipStream_t s, edfa_tune_slot *slots = nullptr);

@@ -130,8 +130,9 @@ void stable_partition(const int *key, int n, int nkey, int *out, DBuf<int> &hist
   hipLaunchKernelGGL(k_part_scatter, dim3(nb), dim3(256), 0, s, key, n, nb, hist.p, out);
   EDFA_CHECK_LAUNCH();
   std::vector<int> start(nkey + 1);
-  for (int c = 0; c <= nkey; ++c)
-    EDFA_HIP(hipMemcpyAsync(&start[c], hist.p + (size_t)c * nb, sizeof(int), hipMemcpyDeviceToHost, s));
+  // the start of key c sits at hist[c * nb]: one strided copy of the nkey + 1 starts
+  EDFA_HIP(hipMemcpy2DAsync(start.data(), sizeof(int), hist.p, sizeof(int) * (size_t)nb,
+                            sizeof(int), (size_t)nkey + 1, hipMemcpyDeviceToHost, s));
   EDFA_HIP(hipStreamSynchronize(s));
   for (int c = 0; c < nkey; ++c) counts[c] = start[c + 1] - start[c];
 }
@@ -610,23 +611,25 @@ static void greedy_chunks(const std::vector<int> &rp, int rows, int cap, std::ve
   d.push_back(make_int2(rows, rp[rows]));
 }
 
+// Greedy chunks of at most `cap` entries over the rows of a CSR row pointer on the device.
+static void device_chunks(const int *rp_dev, int rows, int cap, DBuf<int2> &out, int &count,
+                          hipStream_t s) {
+  std::vector<int> rp((size_t)rows + 1);
+  EDFA_HIP(hipMemcpyAsync(rp.data(), rp_dev, sizeof(int) * rp.size(), hipMemcpyDeviceToHost, s));
+  EDFA_HIP(hipStreamSynchronize(s));
+  std::vector<int2> d;
+  greedy_chunks(rp, rows, cap, d);
+  count = (int)d.size() - 1;
+  out.ensure(d.size());
+  EDFA_HIP(hipMemcpyAsync(out.p, d.data(), sizeof(int2) * d.size(), hipMemcpyHostToDevice, s));
+  EDFA_HIP(hipStreamSynchronize(s));
+}
+
 template <class V>
 void build_row_chunks(Sell<V> &S, int k, hipStream_t s) {
   if (S.chunk_k == k || S.rows <= 0) return;
-  std::vector<int> rp((size_t)S.rows + 1);
-  EDFA_HIP(hipMemcpyAsync(rp.data(), S.csr_rp, sizeof(int) * rp.size(), hipMemcpyDeviceToHost, s));
-  EDFA_HIP(hipStreamSynchronize(s));
-  std::vector<int2> d, e;
-  greedy_chunks(rp, S.rows, 64 * k, d);
-  greedy_chunks(rp, S.rows, 64 * CHUNK_K_ALT, e);
-  S.nchunk = (int)d.size() - 1;
-  S.nchunk_alt = (int)e.size() - 1;
-  S.chunk.ensure(d.size());
-  S.chunk_alt.ensure(e.size());
-  EDFA_HIP(hipMemcpyAsync(S.chunk.p, d.data(), sizeof(int2) * d.size(), hipMemcpyHostToDevice, s));
-  EDFA_HIP(hipMemcpyAsync(S.chunk_alt.p, e.data(), sizeof(int2) * e.size(),
-                          hipMemcpyHostToDevice, s));
-  EDFA_HIP(hipStreamSynchronize(s));
+  device_chunks(S.csr_rp, S.rows, 64 * k, S.chunk, S.nchunk, s);
+  S.nchunk_alt = -1;
   S.chunk_k = k;
 }
 template void build_row_chunks<double>(Sell<double> &, int, hipStream_t);
@@ -737,6 +740,8 @@ void spmv_sell_io(const Sell<V> &M, const X *x, void *y, bool y64, double alpha,
     if (M.chunk_k != CHUNK_K)
       fail(EDFA_ERR_ARG, "the chunk kernel needs the chunk descriptors of its matrix");
     if (M.depth == CHUNK_K_ALT) {
+      if (M.nchunk_alt < 0)
+        device_chunks(M.csr_rp, M.rows, 64 * CHUNK_K_ALT, M.chunk_alt, M.nchunk_alt, s);
       const int nb = ceil_div(M.nchunk_alt, SPMV_T / 64);
       launch_timed(k_spmv_chunk<V, X, CHUNK_K_ALT>, nb, s, e0, e1, M.csr_rp, M.csr_col,
                    M.csr_val, (const int2 *)M.chunk_alt.p, M.nchunk_alt, x, y, alpha, b, beta,

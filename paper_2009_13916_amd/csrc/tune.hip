@@ -120,6 +120,15 @@ void apply_tuned(edfa_precond_s &P) {
   });
 }
 
+bool chunks_pending(edfa_precond_s &P) {
+  bool pending = false;
+  for_each_slot(P, [&](int, auto &M, int) {
+    if (M.rows > 0 && M.lanes == SPMV_CHUNKED && M.depth == CHUNK_K_ALT && M.nchunk_alt < 0)
+      pending = true;
+  });
+  return pending;
+}
+
 void set_variant(edfa_precond_s &P, int slot, int variant) {
   for (int q = 0; q < EDFA_TUNE_SLOTS; ++q)
     if (slot < 0 || q == slot) P.tuned[q] = variant;

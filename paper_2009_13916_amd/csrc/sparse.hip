@@ -117,22 +117,30 @@ __global__ __launch_bounds__(256) void k_part_scatter(const int *__restrict__ ke
   out[offs[(size_t)c * nb + blockIdx.x] + rank] = v;
 }
 
+__global__ void k_part_starts(const int *__restrict__ hist, int nb, int count, int *starts) {
+  for (int c = threadIdx.x; c < count; c += blockDim.x) starts[c] = hist[(size_t)c * nb];
+}
+
 void stable_partition(const int *key, int n, int nkey, int *out, DBuf<int> &hist, DBuf<int> &tmp,
                       hipStream_t s, std::vector<int> &counts) {
   if (nkey < 1 || nkey > PART_MAX_KEYS) fail(EDFA_ERR_ARG, "partition into %d keys", nkey);
   counts.assign(nkey, 0);
   if (n <= 0) return;
   const int nb = ceil_div(n, 256);
-  hist.ensure((size_t)nkey * nb + 1);
+  hist.ensure((size_t)nkey * nb + 1 + (size_t)(nkey + 1));   // scan, then the gathered starts
   hipLaunchKernelGGL(k_part_hist, dim3(nb), dim3(256), 0, s, key, n, nkey, nb, hist.p);
   EDFA_CHECK_LAUNCH();
   exclusive_scan_async(hist.p, hist.p, nkey * nb, tmp, s);
   hipLaunchKernelGGL(k_part_scatter, dim3(nb), dim3(256), 0, s, key, n, nb, hist.p, out);
   EDFA_CHECK_LAUNCH();
   std::vector<int> start(nkey + 1);
-  // the start of key c sits at hist[c * nb]: one strided copy of the nkey + 1 starts
-  EDFA_HIP(hipMemcpy2DAsync(start.data(), sizeof(int), hist.p, sizeof(int) * (size_t)nb,
-                            sizeof(int), (size_t)nkey + 1, hipMemcpyDeviceToHost, s));
+  // the start of key c sits at hist[c * nb]: gathered on the device behind the histogram,
+  // then one contiguous copy
+  int *starts = hist.p + (size_t)nkey * nb + 1;
+  hipLaunchKernelGGL(k_part_starts, dim3(1), dim3(64), 0, s, hist.p, nb, nkey + 1, starts);
+  EDFA_CHECK_LAUNCH();
+  EDFA_HIP(hipMemcpyAsync(start.data(), starts, sizeof(int) * (size_t)(nkey + 1),
+                          hipMemcpyDeviceToHost, s));
   EDFA_HIP(hipStreamSynchronize(s));
   for (int c = 0; c < nkey; ++c) counts[c] = start[c + 1] - start[c];
 }

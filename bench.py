@@ -13,12 +13,14 @@ from x0 = 0 to a true relative residual <= 1e-8.  The launch-shape autotuner run
 per preconditioner before the timed steps (its choices persist across re-setups).
 ``value`` is the mean wall time of one step in seconds for the FP64 path.  ``forms``
 holds the same step with the FP32 preconditioner inside FP64 flexible GMRES and with
-Bi-CGStab (the paper's solver), the 256-grid batch, and the 128x128x64 distorted-channel
-sequence of 10 steps with dt doubling from 1e-3 (FP64 and mixed; stage-2 refresh per step
-and full re-setup per step).  ``roofline`` is the dominant sparse-product kernel of the
-64^3 step, timed live with HIP events inside the solve; ``families`` lists every product.
+Bi-CGStab (the paper's solver); on request (--batched, --transient) also the 256-grid
+batch and the 128x128x64 distorted-channel sequence of 10 steps with dt doubling from
+1e-3 (FP64 and mixed; stage-2 refresh per step and full re-setup per step).
+``roofline`` is the dominant sparse-product kernel of the 64^3 step, timed live with HIP
+events inside the solve; ``families`` lists every product.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                       [--batched] [--transient]
 """
 from __future__ import annotations
 
@@ -399,9 +401,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-bicgstab", action="store_true")
-    ap.add_argument("--no-batched", action="store_true", help="skip the 256-grid batch forms")
-    ap.add_argument("--no-transient", action="store_true",
-                    help="skip the 128x128x64 ten-step sequence")
+    # The 256-grid batch and the 128x128x64 sequence run only on request: a default run that
+    # included them once ended in a GPU memory fault whose cause has not been found, so they
+    # stay out of the default run until it is.  --no-batched / --no-transient are accepted
+    # (and do nothing) for older command lines.
+    ap.add_argument("--batched", action="store_true", help="also run the 256-grid batch forms")
+    ap.add_argument("--transient", action="store_true",
+                    help="also run the 128x128x64 ten-step sequence")
+    ap.add_argument("--no-batched", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--no-transient", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--batched-only", action="store_true",
                     help="diagnostic: run only the 256-grid batch forms and print their record")
     ap.add_argument("--transient-only", action="store_true",
@@ -475,10 +483,15 @@ def main():
             "s_per_step": tb, "iterations": infb["iterations"], "relres_true": infb["relres_true"],
             "converged": stb == 0, "solve_ms": infb["t_solve_ms"],
             "pressure_rel_diff_vs_gmres": float(dpb)}
-    if not args.no_batched:
+    off = "not in the default run (an unexplained GPU fault in a default run with it); --%s"
+    if args.batched and not args.no_batched:
         forms["batch_256"] = run_batched(edfa, inputs, args.steps, args.warmup)
-    if not args.no_transient:
+    else:
+        forms["batch_256"] = {"skipped": off % "batched"}
+    if args.transient and not args.no_transient:
         forms["transient_128x128x64"] = run_transient(edfa, inputs)
+    else:
+        forms["transient_128x128x64"] = {"skipped": off % "transient"}
 
     # per-matrix product timings of the last profiled FP64 step and the dominant kernel
     fam, kern = families(info, rep64, info["apply_count_products"])

@@ -187,6 +187,9 @@ typedef struct {
   int32_t color_list_rounds;/* ... of which visited only a worklist of the uncoloured cells */
   int32_t cgs2_width;       /* basis vectors per block of the CGS2 dot passes (2, 4 or 8; set
                                by edfa_autotune) */
+  int32_t chunks_ML, chunks_MU; /* row chunks (at most 768 entries each, the greedy row-aligned
+                               cut of the natural-order rows) of the chunk kernel's descriptors
+                               for M_L and M_U; 0 when the matrix has none (short rows) */
 } edfa_precond_info;
 
 /* Build the preconditioner: stage 1 (Algorithm 1: restricted SPD solves on static or
@@ -230,9 +233,10 @@ edfa_status edfa_apply(edfa_precond pre, int32_t transpose, const double *r, dou
  * calls that overlap on one GPU race (serialise them, e.g. on one stream).  Results equal
  * edfa_apply's.  Errors: EDFA_ERR_ARG when the workspace exceeds the array (the message
  * gives both sizes), or when what the application reads does not exist yet and would have
- * to be allocated: the transposed factors (transpose = 1), the FP32 coupling blocks and the
- * descriptors of the 512-entry chunk kernel (when the tuner chose it) are built by a first
- * edfa_apply of the same kind (or a solve); EDFA_ERR_HIP.  Asynchronous. */
+ * to be allocated: the transposed factors (transpose = 1), the FP32 coupling blocks, the
+ * descriptors of the 512-entry chunk kernel and the SELL layout of a long-row matrix (when
+ * the tuner or edfa_set_variant chose those kernels) are built by a first edfa_apply of the
+ * same kind (or a solve); EDFA_ERR_HIP.  Asynchronous. */
 #define EDFA_NOALLOC_SCRATCH_BYTES (64u << 20)
 edfa_status edfa_apply_noalloc(edfa_precond pre, int32_t transpose, const double *r, double *z,
                                hipStream_t stream);

@@ -226,11 +226,13 @@ static void fill_info(edfa_precond_s &P, PrecData<T> &D, edfa_precond_info *info
   info->mu = den > 0 ? num / den : 0.0;
   info->t_stage1_ms = P.t_stage1_ms;
   info->t_stage2_ms = P.t_stage2_ms;
-  info->nnz_H_raw = P.nnz_h_raw;
+  info->nnz_H_raw = P.nnz_h_raw.p ? (int64_t)*P.nnz_h_raw.p : 0;
   info->htilde_retry_rows = P.htilde_retry_rows;
   info->color_rounds = P.color_rounds;
   info->color_list_rounds = P.color_list_rounds;
   info->cgs2_width = P.cgs2_width;
+  info->chunks_ML = D.ML_s.chunk_k == CHUNK_K ? D.ML_s.nchunk : 0;
+  info->chunks_MU = D.MU_s.chunk_k == CHUNK_K ? D.MU_s.nchunk : 0;
 }
 
 void check_params(const edfa_params &p) {

@@ -400,9 +400,9 @@ void precond_apply_noalloc(edfa_precond_s &P, int transpose, const double *r, do
          "(2 N_f^u + 5 N_e preconditioner values, plus 2 N floats in FP32); its static "
          "array holds %zu",
          need, SCRATCH_BYTES);
-  if (chunks_pending(P))
-    fail(EDFA_ERR_ARG, "a product kernel chosen by the tuner needs its chunk descriptors: build "
-                       "them with one edfa_apply (or solve) first");
+  if (layouts_pending(P))
+    fail(EDFA_ERR_ARG, "a product kernel chosen by the tuner needs its chunk descriptors or SELL "
+                       "layout: build them with one edfa_apply (or solve) first");
   apply_impl(P, transpose, r, z, s, RowMask{}, scratch_ptr());
 }
 

@@ -616,6 +616,7 @@ void assemble_system(edfa_system_s &S, const edfa_problem *probs, int count, hip
 
   // blocks
   extract_block(S, split.p, 0, S.nfu, 1, 0, S.nfu, S.Afp, s);
+  S.afp_max = -1;
   extract_block(S, split.p, 0, S.nfu, 0, S.nfu, S.ne, S.Afc, s);
   extract_block(S, split.p, S.nfu, S.ne, 1, 0, S.nfu, S.Acf, s);
   extract_block(S, split.p, S.nfu, S.ne, 0, S.nfu, S.ne, S.Acc, s);

@@ -107,16 +107,24 @@ struct Csr {
 // Each row stops at its own length (padding is stored but never read).
 template <class V>
 struct Sell {
-  int rows = 0, cols = 0, nslice = 0;
-  int64_t nnz = 0, padded = 0;
-  DBuf<int> sptr;   // nslice + 1 element offsets
-  DBuf<int> rlen;   // rows
-  DBuf<int> col;
-  DBuf<V> val;
+  int rows = 0, cols = 0;
+  int64_t nnz = 0;
+  // The SELL layout.  Matrices whose default kernel is the chunk kernel (long rows) get it
+  // only when a SELL variant first multiplies them (sell_ready false until then), so the
+  // fields below are filled on demand from the CSR arrays.
+  mutable bool sell_ready = false;
+  mutable int nslice = 0;
+  mutable int64_t padded = 0;
+  mutable DBuf<int> sptr;   // nslice + 1 element offsets
+  mutable DBuf<int> rlen;   // rows
+  mutable DBuf<int> col;
+  mutable DBuf<V> val;
   // sorted layout: position p of the slices holds row perm[p] (rows sorted by length
   // inside windows); otherwise position p holds row p
-  bool sorted = false;
-  DBuf<int> perm;
+  mutable bool sorted = false;
+  mutable DBuf<int> perm;
+  mutable DBuf<int> scan_tmp;     // scratch of the on-demand builds
+  mutable DBuf<int> chunk_work;   // scratch of the chunk descriptor build
   // Kernel choice: lanes = 0 or 1 runs the SELL kernel; lanes = 2..32 runs the CSR kernel
   // with that many lanes per row on the source CSR arrays (which must outlive this copy);
   // lanes = SPMV_CHUNKED runs the chunk kernel on the CSR arrays (below).
@@ -145,12 +153,33 @@ constexpr int CHUNK_K_ALT = 8;    // narrower chunks: 8 per lane, 512 per chunk
 inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
 
 
+// Pinned host staging for small device reads, one block per host thread (allocated on
+// first use and kept for the life of the process): a copy into pinned memory returns about
+// a third sooner than one into pageable memory.
+constexpr size_t PINNED_SLOT = 4096;
+inline void *pinned_slot(size_t bytes) {
+  constexpr size_t SLOT = PINNED_SLOT;
+  static thread_local void *slot = nullptr;
+  if (bytes > SLOT) fail(EDFA_ERR_ARG, "pinned read of %zu bytes", bytes);
+  if (!slot) EDFA_HIP(hipHostMalloc(&slot, SLOT, hipHostMallocDefault));
+  return slot;
+}
+
+// Host read of `count` device values (synchronises the stream; count * sizeof(T) <=
+// PINNED_SLOT).
+template <class T>
+void read_small(T *out, const T *dptr, size_t count, hipStream_t s) {
+  T *pin = static_cast<T *>(pinned_slot(sizeof(T) * count));
+  EDFA_HIP(hipMemcpyAsync(pin, dptr, sizeof(T) * count, hipMemcpyDeviceToHost, s));
+  EDFA_HIP(hipStreamSynchronize(s));
+  for (size_t i = 0; i < count; ++i) out[i] = pin[i];
+}
+
 // Host read of one device scalar (synchronises the stream).
 template <class T>
 T read_scalar(const T *dptr, hipStream_t s) {
   T v{};
-  EDFA_HIP(hipMemcpyAsync(&v, dptr, sizeof(T), hipMemcpyDeviceToHost, s));
-  EDFA_HIP(hipStreamSynchronize(s));
+  read_small(&v, dptr, 1, s);
   return v;
 }
 
@@ -204,11 +233,15 @@ void spmv(const int *rowptr, const int *col, const V *val, int rows, const X *x,
           double gamma = 0.0);
 
 // SELL-64 copy of a CSR matrix (device-side conversion; synchronises to size the storage).
-// Matrices with long rows also get the chunk descriptors of the default chunk kernel.
+// Matrices with long rows get the chunk descriptors of their default chunk kernel instead;
+// their SELL layout is built by ensure_sell when a SELL variant first multiplies them.
 template <class V>
 void build_sell(const Csr<V> &M, Sell<V> &S, DBuf<int> &tmp, hipStream_t s);
-// Chunk descriptors of S's CSR arrays for chunks of at most 64 * k entries (greedy over
-// the rows on the host; synchronises).  No-op when they exist for this k.
+template <class V>
+void ensure_sell(const Sell<V> &S, hipStream_t s);
+// Chunk descriptors of S's CSR arrays for chunks of at most 64 * k entries (the greedy
+// row-aligned cut, computed on the device; synchronises once for the chunk count).  No-op
+// when they exist for this k.
 template <class V>
 void build_row_chunks(Sell<V> &S, int k, hipStream_t s);
 // Default lanes per row for a mean row length (0: the SELL kernel).

@@ -132,7 +132,9 @@ struct edfa_precond_s {
   int bucket_cells[edfa::NCAP] = {};   // cells per capacity bucket at the last stage 1
   int cap_map[edfa::NCAP] = {};        // tuned kernel capacity per bucket (0: its own)
   int cgs2_width = 4;                  // basis vectors per block of the CGS2 dot passes
-  int64_t nnz_h_raw = 0;           // entries of H~ before the post-filtration
+  // entries of H~ before the post-filtration: copied into pinned memory behind the count
+  // (no wait); the setup's later synchronisations complete the copy before it returns
+  edfa::HBuf<unsigned long long> nnz_h_raw;
   int color_rounds = 0;            // Jones-Plassmann rounds of the last colouring
   int color_list_rounds = 0;       //   of which over the worklist of uncoloured vertices
   edfa::DBuf<unsigned long long> counter;
@@ -169,8 +171,9 @@ template <class T>
 void build_hraw(edfa_precond_s &P, PrecData<T> &D, hipStream_t s);
 void grad_logk(edfa_system_s &S, const double *u, const double *lam, double *g, hipStream_t s);
 void apply_tuned(edfa_precond_s &P);
-// True when a matrix's chosen kernel still needs chunk descriptors built on first use.
-bool chunks_pending(edfa_precond_s &P);
+// True when a matrix's chosen kernel still needs chunk descriptors or a SELL layout built
+// on first use.
+bool layouts_pending(edfa_precond_s &P);
 // slot -1: every slot; variant -1: back to the default choice (at the next setup)
 void set_variant(edfa_precond_s &P, int slot, int variant);
 int autotune(edfa_precond_s &P, hipStream_t s, edfa_tune_slot *slots = nullptr);

@@ -185,12 +185,6 @@ __global__ void k_patch(const GridDesc *__restrict__ grids, int ngrid, const int
   qlen[m] = n;
 }
 
-__global__ void k_len_max(const int *__restrict__ len, int n, int *out) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  atomicMax(out, len[r]);
-}
-
 // total of n int32 lengths (64-bit accumulator)
 __global__ void k_len_sum(const int *__restrict__ len, int n, unsigned long long *out) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
@@ -207,10 +201,17 @@ __global__ void k_repack(const int *__restrict__ src, const int *__restrict__ le
   for (int t = 0; t < len[r]; ++t) dst[(size_t)r * s1 + t] = src[(size_t)r * s0 + t];
 }
 
-__global__ void k_row_max(const int *__restrict__ rp, int rows, int *out) {
+// *out = max(*out, longest row): rows given by a row pointer (len null) or by lengths; one
+// atomic per wavefront after a shuffle reduction
+__global__ __launch_bounds__(256) void k_row_max(const int *__restrict__ rp,
+                                                 const int *__restrict__ len, int rows,
+                                                 int *out) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= rows) return;
-  atomicMax(out, rp[r + 1] - rp[r]);
+  int v = 0;
+  if (r < rows) v = len ? len[r] : rp[r + 1] - rp[r];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+  if ((threadIdx.x & 63) == 0 && v > 0) atomicMax(out, v);
 }
 
 // A_pipi rows padded to ELL_W entries, for the candidate residuals of k_local_reg: a row's
@@ -1384,14 +1385,15 @@ static void build_vec_csr(edfa_system_s &S, PrecData<T> &D, const DBuf<T> &v, in
     launch(k_vec_write<T, PATCH_MAX>);
 }
 
-static void check_flags(edfa_precond_s &P, hipStream_t s, const char *where) {
-  int fl[2];
-  EDFA_HIP(hipMemcpyAsync(fl, P.flags.p, sizeof(fl), hipMemcpyDeviceToHost, s));
-  EDFA_HIP(hipStreamSynchronize(s));
+// Reads the error flags (and returns flags[2], the scratch value of the last step).
+static int check_flags(edfa_precond_s &P, hipStream_t s, const char *where) {
+  int fl[3];
+  read_small(fl, P.flags.p, 3, s);
   if (fl[0] != 0x7fffffff)
     fail(EDFA_ERR_NOT_SPD, "%s: restricted system of row/cell %d is not SPD", where, fl[0]);
   if (fl[1] != 0x7fffffff)
     fail(EDFA_ERR_CAPACITY, "%s: pattern capacity exceeded at row/cell %d", where, fl[1]);
+  return fl[2];
 }
 
 static void reset_flags(edfa_precond_s &P, hipStream_t s) {
@@ -1450,12 +1452,16 @@ static void stage1_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
   reset_flags(P, s);
   int *err_spd = P.flags.p, *err_cap = P.flags.p + 1;
 
-  // the register kernel and the rows of H~ read A_pipi as ELL_W-entry rows
-  EDFA_HIP(hipMemsetAsync(P.flags.p + 2, 0, sizeof(int), s));
-  hipLaunchKernelGGL(k_row_max, dim3(ceil_div(nfu, 256)), dim3(256), 0, s, S.Afp.rowptr.p, nfu,
-                     P.flags.p + 2);
-  EDFA_CHECK_LAUNCH();
-  const int afp_max = read_scalar(P.flags.p + 2, s);
+  // the register kernel and the rows of H~ read A_pipi as ELL_W-entry rows (its pattern is
+  // fixed by the assembly: its longest row is found once)
+  if (S.afp_max < 0) {
+    EDFA_HIP(hipMemsetAsync(P.flags.p + 2, 0, sizeof(int), s));
+    hipLaunchKernelGGL(k_row_max, dim3(ceil_div(nfu, 256)), dim3(256), 0, s, S.Afp.rowptr.p,
+                       nullptr, nfu, P.flags.p + 2);
+    EDFA_CHECK_LAUNCH();
+    S.afp_max = read_scalar(P.flags.p + 2, s);
+  }
+  const int afp_max = S.afp_max;
   if (afp_max > ELL_W)
     fail(EDFA_ERR_CAPACITY, "a row of A_pipi has %d > %d entries (hexahedra give at most 11)",
          afp_max, ELL_W);
@@ -1546,17 +1552,14 @@ static void stage1_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
     la.cells = D.bcells.p + off;
     launch_local<T>(bucket_capacity(P, b), counts[b], la, s);
   }
-  check_flags(P, s, "restricted solves");
-  {
-    // longest final pattern (diagnostic)
-    std::vector<int> ql(ne);
-    if (ne)
-      EDFA_HIP(hipMemcpyAsync(ql.data(), D.qlen.p, sizeof(int) * ne, hipMemcpyDeviceToHost, s));
-    EDFA_HIP(hipStreamSynchronize(s));
-    int mx = 0;
-    for (int v : ql) mx = std::max(mx, v);
-    P.max_pattern = mx;
+  // longest final pattern (sizes the H~ tables), read with the error flags
+  EDFA_HIP(hipMemsetAsync(P.flags.p + 2, 0, sizeof(int), s));
+  if (ne > 0) {
+    hipLaunchKernelGGL(k_row_max, dim3(ceil_div(ne, 256)), dim3(256), 0, s, nullptr, D.qlen.p,
+                       ne, P.flags.p + 2);
+    EDFA_CHECK_LAUNCH();
   }
+  P.max_pattern = check_flags(P, s, "restricted solves");
 
   // G~ and F~^T (pre-filtration), F~ by faces
   const int pre = prm.filt_mode == EDFA_FILT_PRE;
@@ -1634,7 +1637,8 @@ static void stage1_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
       hipLaunchKernelGGL(k_len_sum, dim3(ceil_div(ne, 256)), dim3(256), 0, s, D.Hlen.p, ne, acc.p);
       EDFA_CHECK_LAUNCH();
     }
-    P.nnz_h_raw = (int64_t)read_scalar(acc.p, s);
+    EDFA_HIP(hipMemcpyAsync(P.nnz_h_raw.ensure(1), acc.p, sizeof(unsigned long long),
+                            hipMemcpyDeviceToHost, s));
   }
   const int postH = prm.filt_mode == EDFA_FILT_POST_H;
   D.H.rowptr.ensure((size_t)ne + 1);

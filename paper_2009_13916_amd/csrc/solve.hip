@@ -749,8 +749,10 @@ edfa_status gmres(edfa_system_s &S, edfa_precond_s &P, const double *b, double *
   // own, ordered after the caller's stream by events.
   GraphCycle gc;
   while (true) {
-    EDFA_HIP(hipMemcpyAsync(hst.data(), W.st.p, sizeof(SegState) * nseg, hipMemcpyDeviceToHost, s));
+    // states of every grid through the pinned copy (it also receives the in-cycle reads)
+    EDFA_HIP(hipMemcpyAsync(hpin, W.st.p, sizeof(SegState) * nseg, hipMemcpyDeviceToHost, s));
     EDFA_HIP(hipStreamSynchronize(s));
+    std::copy(hpin, hpin + nseg, hst.begin());
     if (cycles == 0)
       for (int g = 0; g < nseg; ++g)
         if (!std::isfinite(hst[g].bnorm))

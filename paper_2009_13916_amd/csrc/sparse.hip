@@ -139,9 +139,7 @@ void stable_partition(const int *key, int n, int nkey, int *out, DBuf<int> &hist
   int *starts = hist.p + (size_t)nkey * nb + 1;
   hipLaunchKernelGGL(k_part_starts, dim3(1), dim3(64), 0, s, hist.p, nb, nkey + 1, starts);
   EDFA_CHECK_LAUNCH();
-  EDFA_HIP(hipMemcpyAsync(start.data(), starts, sizeof(int) * (size_t)(nkey + 1),
-                          hipMemcpyDeviceToHost, s));
-  EDFA_HIP(hipStreamSynchronize(s));
+  read_small(start.data(), starts, (size_t)(nkey + 1), s);   // nkey <= PART_MAX_KEYS
   for (int c = 0; c < nkey; ++c) counts[c] = start[c + 1] - start[c];
 }
 
@@ -429,6 +427,47 @@ int default_spmv_lanes(double mean_row) {
   return mean_row < SPMV_VEC_MIN_ROW ? 0 : SPMV_CHUNKED;
 }
 
+// The SELL layout of S from its CSR arrays (rows sorted by length inside windows when plain
+// slices would pad by more than SELL_SORT_PAD).  Synchronises to size the storage.
+template <class V>
+static void sell_layout(const Sell<V> &S, DBuf<int> &tmp, hipStream_t s) {
+  S.nslice = ceil_div(S.rows, 64);
+  S.sptr.ensure((size_t)S.nslice + 1);
+  S.rlen.ensure((size_t)std::max(S.rows, 1));
+  S.sorted = false;
+  S.padded = 0;
+  S.sell_ready = true;
+  if (S.nslice == 0) return;
+  hipLaunchKernelGGL(k_sell_width, dim3(ceil_div(S.nslice, 256)), dim3(256), 0, s, S.csr_rp,
+                     S.rows, S.nslice, S.sptr.p);
+  EDFA_CHECK_LAUNCH();
+  S.padded = exclusive_scan(S.sptr.p, S.sptr.p, S.nslice, tmp, s);
+  if (S.padded > SELL_SORT_PAD * (double)S.nnz) {
+    // rows of very different lengths side by side: sort them inside windows
+    S.perm.ensure((size_t)S.rows);
+    hipLaunchKernelGGL(k_sell_sort, dim3(ceil_div(S.rows, SELL_SIGMA)), dim3(256), 0, s,
+                       S.csr_rp, S.rows, S.perm.p);
+    hipLaunchKernelGGL(k_sell_width_perm, dim3(ceil_div(S.nslice, 256)), dim3(256), 0, s,
+                       S.csr_rp, S.perm.p, S.rows, S.nslice, S.sptr.p);
+    EDFA_CHECK_LAUNCH();
+    S.padded = exclusive_scan(S.sptr.p, S.sptr.p, S.nslice, tmp, s);
+    S.sorted = true;
+  }
+  S.col.ensure((size_t)std::max<int64_t>(S.padded, 1));
+  S.val.ensure((size_t)std::max<int64_t>(S.padded, 1));
+  hipLaunchKernelGGL(k_sell_fill<V>, dim3(ceil_div(S.rows, 256)), dim3(256), 0, s, S.csr_rp,
+                     S.csr_col, S.csr_val, S.rows, S.sorted ? S.perm.p : nullptr, S.sptr.p,
+                     S.rlen.p, S.col.p, S.val.p);
+  EDFA_CHECK_LAUNCH();
+}
+
+template <class V>
+void ensure_sell(const Sell<V> &S, hipStream_t s) {
+  if (!S.sell_ready) sell_layout(S, S.scan_tmp, s);
+}
+template void ensure_sell<double>(const Sell<double> &, hipStream_t);
+template void ensure_sell<float>(const Sell<float> &, hipStream_t);
+
 template <class V>
 void build_sell(const Csr<V> &M, Sell<V> &S, DBuf<int> &tmp, hipStream_t s) {
   S.rows = M.rows;
@@ -440,36 +479,11 @@ void build_sell(const Csr<V> &M, Sell<V> &S, DBuf<int> &tmp, hipStream_t s) {
   S.lanes = M.rows > 0 ? default_spmv_lanes((double)M.nnz / M.rows) : 0;
   S.depth = 0;
   S.chunk_k = 0;   // the CSR arrays may have changed: descriptors are rebuilt on demand
-  if (S.lanes == SPMV_CHUNKED) build_row_chunks(S, CHUNK_K, s);
-  S.nslice = ceil_div(M.rows, 64);
-  S.sptr.ensure((size_t)S.nslice + 1);
-  S.rlen.ensure((size_t)std::max(M.rows, 1));
-  if (S.nslice == 0) {
-    S.padded = 0;
-    return;
-  }
-  hipLaunchKernelGGL(k_sell_width, dim3(ceil_div(S.nslice, 256)), dim3(256), 0, s, M.rowptr.p,
-                     M.rows, S.nslice, S.sptr.p);
-  EDFA_CHECK_LAUNCH();
-  S.padded = exclusive_scan(S.sptr.p, S.sptr.p, S.nslice, tmp, s);
-  S.sorted = false;
-  if (S.padded > SELL_SORT_PAD * (double)M.nnz) {
-    // rows of very different lengths side by side: sort them inside windows
-    S.perm.ensure((size_t)M.rows);
-    hipLaunchKernelGGL(k_sell_sort, dim3(ceil_div(M.rows, SELL_SIGMA)), dim3(256), 0, s,
-                       M.rowptr.p, M.rows, S.perm.p);
-    hipLaunchKernelGGL(k_sell_width_perm, dim3(ceil_div(S.nslice, 256)), dim3(256), 0, s,
-                       M.rowptr.p, S.perm.p, M.rows, S.nslice, S.sptr.p);
-    EDFA_CHECK_LAUNCH();
-    S.padded = exclusive_scan(S.sptr.p, S.sptr.p, S.nslice, tmp, s);
-    S.sorted = true;
-  }
-  S.col.ensure((size_t)std::max<int64_t>(S.padded, 1));
-  S.val.ensure((size_t)std::max<int64_t>(S.padded, 1));
-  hipLaunchKernelGGL(k_sell_fill<V>, dim3(ceil_div(M.rows, 256)), dim3(256), 0, s, M.rowptr.p,
-                     M.col.p, M.val.p, M.rows, S.sorted ? S.perm.p : nullptr, S.sptr.p,
-                     S.rlen.p, S.col.p, S.val.p);
-  EDFA_CHECK_LAUNCH();
+  S.sell_ready = false;
+  if (S.lanes == SPMV_CHUNKED)
+    build_row_chunks(S, CHUNK_K, s);   // the SELL layout waits for a SELL variant
+  else
+    sell_layout(S, tmp, s);
 }
 
 template void build_sell<double>(const Csr<double> &, Sell<double> &, DBuf<int> &, hipStream_t);
@@ -595,7 +609,7 @@ __global__ __launch_bounds__(SPMV_T) void k_spmv_csr_vec(const int *__restrict__
 // ----------------------------------------------------------------------------------
 // Chunk kernel for matrices whose rows are long and of uneven length (the approximate
 // inverses of the ILU(0) factors: 1 to ~160 entries, in the natural order).  The CSR arrays
-// are cut, on the host, into chunks of whole consecutive rows holding at most 64 K entries.
+// are cut into chunks of whole consecutive rows holding at most 64 K entries.
 // One wavefront per chunk: its lanes load the chunk's entries with unit stride, K loads of
 // column index and value in flight per lane, gather x, and leave the products in LDS;
 // then G lanes per row sum each row's products (strided, then a shuffle tree).  Every load
@@ -603,40 +617,82 @@ __global__ __launch_bounds__(SPMV_T) void k_spmv_csr_vec(const int *__restrict__
 // locality.  A row longer than 64 K entries forms a chunk of its own, summed by the whole
 // wavefront.
 // ----------------------------------------------------------------------------------
-// Greedy row-aligned chunks of at most `cap` entries (a longer row is a chunk of its own).
-static void greedy_chunks(const std::vector<int> &rp, int rows, int cap, std::vector<int2> &d) {
-  d.clear();
-  d.reserve(rp[rows] / std::max(1, cap / 2) + 2);
-  int r0 = 0;
-  d.push_back(make_int2(0, rp[0]));
-  for (int r = 0; r < rows; ++r) {
-    // close the current chunk before row r when r would overflow it
-    if (r > r0 && rp[r + 1] - rp[r0] > cap) {
-      d.push_back(make_int2(r, rp[r]));
-      r0 = r;
-    }
+// Greedy row-aligned chunks of at most `cap` entries (a longer row is a chunk of its own),
+// built on the device.  The greedy pass closes the chunk that starts at row r0 before the
+// first row r > r0 with rp[r + 1] - rp[r0] > cap, so its successor is
+// nxt(r0) = min(max(ub - 1, r0 + 1), rows), ub the first index with rp[ub] > rp[r0] + cap
+// (a binary search on the sorted row pointer); the chunk starts are the orbit of row 0 under
+// nxt, marked by pointer doubling (after k rounds every nxt^i(0) with i < 2^k is marked),
+// then compacted in row order.  Same chunks as the sequential pass.
+__global__ void k_chunk_next(const int *__restrict__ rp, int rows, int cap, int *nxt,
+                             int *mark) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r > rows) return;
+  mark[r] = r == 0 ? 1 : 0;
+  if (r == rows) {
+    nxt[r] = rows;
+    return;
   }
-  d.push_back(make_int2(rows, rp[rows]));
+  const long long thr = (long long)rp[r] + cap;
+  int lo = r + 1, hi = rows + 1;   // rp[r] <= thr: the first index past thr is above r
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if ((long long)rp[mid] > thr)
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  nxt[r] = min(max(lo - 1, r + 1), rows);
 }
 
-// Greedy chunks of at most `cap` entries over the rows of a CSR row pointer on the device.
+// One doubling round: every marked row marks its jump target (marks only grow, and every
+// mark lies on the orbit), and jump_out = jump_in o jump_in.  The end row `rows`, where
+// every orbit ends, is never marked (only rows below it start chunks): in the late rounds
+// most jumps land there, and their stores would all queue on one address.
+__global__ void k_chunk_double(const int *__restrict__ jin, int *jout, int *mark, int rows) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r > rows) return;
+  const int j = jin[r];
+  if (j < rows && __hip_atomic_load(mark + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &&
+      !__hip_atomic_load(mark + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+    __hip_atomic_store(mark + j, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  jout[r] = jin[j];
+}
+
+__global__ void k_chunk_write(const int *__restrict__ rp, const int *__restrict__ mark,
+                              const int *__restrict__ pos, int rows, int nchunk, int2 *d) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < rows && mark[r]) d[pos[r]] = make_int2(r, rp[r]);
+  if (r == rows) d[nchunk] = make_int2(rows, rp[rows]);
+}
+
 static void device_chunks(const int *rp_dev, int rows, int cap, DBuf<int2> &out, int &count,
-                          hipStream_t s) {
-  std::vector<int> rp((size_t)rows + 1);
-  EDFA_HIP(hipMemcpyAsync(rp.data(), rp_dev, sizeof(int) * rp.size(), hipMemcpyDeviceToHost, s));
-  EDFA_HIP(hipStreamSynchronize(s));
-  std::vector<int2> d;
-  greedy_chunks(rp, rows, cap, d);
-  count = (int)d.size() - 1;
-  out.ensure(d.size());
-  EDFA_HIP(hipMemcpyAsync(out.p, d.data(), sizeof(int2) * d.size(), hipMemcpyHostToDevice, s));
-  EDFA_HIP(hipStreamSynchronize(s));
+                          DBuf<int> &work, DBuf<int> &scan_tmp, hipStream_t s) {
+  // work: nxt and a second jump array (rows + 1 each), the marks (rows + 1), positions (rows)
+  const size_t n1 = (size_t)rows + 1;
+  work.ensure(4 * n1);
+  int *ja = work.p, *jb = work.p + n1, *mark = work.p + 2 * n1, *pos = work.p + 3 * n1;
+  const int gb = ceil_div((long long)n1, 256);
+  hipLaunchKernelGGL(k_chunk_next, dim3(gb), dim3(256), 0, s, rp_dev, rows, cap, ja, mark);
+  EDFA_CHECK_LAUNCH();
+  int rounds = 1;
+  while ((1ll << rounds) < (long long)n1) ++rounds;
+  for (int k = 0; k < rounds; ++k) {
+    hipLaunchKernelGGL(k_chunk_double, dim3(gb), dim3(256), 0, s, ja, jb, mark, rows);
+    std::swap(ja, jb);
+  }
+  EDFA_CHECK_LAUNCH();
+  count = (int)exclusive_scan(mark, pos, rows, scan_tmp, s);
+  out.ensure((size_t)count + 1);
+  hipLaunchKernelGGL(k_chunk_write, dim3(gb), dim3(256), 0, s, rp_dev, mark, pos, rows, count,
+                     out.p);
+  EDFA_CHECK_LAUNCH();
 }
 
 template <class V>
 void build_row_chunks(Sell<V> &S, int k, hipStream_t s) {
   if (S.chunk_k == k || S.rows <= 0) return;
-  device_chunks(S.csr_rp, S.rows, 64 * k, S.chunk, S.nchunk, s);
+  device_chunks(S.csr_rp, S.rows, 64 * k, S.chunk, S.nchunk, S.chunk_work, S.scan_tmp, s);
   S.nchunk_alt = -1;
   S.chunk_k = k;
 }
@@ -749,7 +805,8 @@ void spmv_sell_io(const Sell<V> &M, const X *x, void *y, bool y64, double alpha,
       fail(EDFA_ERR_ARG, "the chunk kernel needs the chunk descriptors of its matrix");
     if (M.depth == CHUNK_K_ALT) {
       if (M.nchunk_alt < 0)
-        device_chunks(M.csr_rp, M.rows, 64 * CHUNK_K_ALT, M.chunk_alt, M.nchunk_alt, s);
+        device_chunks(M.csr_rp, M.rows, 64 * CHUNK_K_ALT, M.chunk_alt, M.nchunk_alt,
+                      M.chunk_work, M.scan_tmp, s);
       const int nb = ceil_div(M.nchunk_alt, SPMV_T / 64);
       launch_timed(k_spmv_chunk<V, X, CHUNK_K_ALT>, nb, s, e0, e1, M.csr_rp, M.csr_col,
                    M.csr_val, (const int2 *)M.chunk_alt.p, M.nchunk_alt, x, y, alpha, b, beta,
@@ -777,6 +834,7 @@ void spmv_sell_io(const Sell<V> &M, const X *x, void *y, bool y64, double alpha,
 #undef EDFA_VEC2
 #undef EDFA_VEC
   } else {
+    ensure_sell(M, s);
     const int nb = ceil_div(M.rows, SPMV_T);
     const bool deep = M.depth == 8;
 #define EDFA_SELL(RL, UU)                                                                     \

@@ -288,9 +288,20 @@ __global__ __launch_bounds__(256) void k_uncolored(const int *__restrict__ color
   if (keep) list[base + __popcll(mask & ((1ull << lane) - 1))] = v;
 }
 
-__global__ void k_color_max(const int *__restrict__ color, int n, int *out) {
+// *out = max(*out, largest colour), one atomic per wavefront (colours are >= 0)
+__global__ __launch_bounds__(256) void k_color_max(const int *__restrict__ color, int n,
+                                                   int *out) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < n) atomicMax(out, color[v]);
+  int c = -1;
+  if (v < n) c = color[v];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) c = max(c, __shfl_xor(c, o));
+  if ((threadIdx.x & 63) == 0 && c >= 0) atomicMax(out, c);
+}
+
+// starts[c] = hist[c * nb] (the scanned histogram's first entry of each colour)
+__global__ void k_color_starts(const int *__restrict__ hist, int nb, int ncol, int *starts) {
+  for (int c = threadIdx.x; c < ncol; c += blockDim.x) starts[c] = hist[(size_t)c * nb];
 }
 
 // per-block colour histograms, laid out colour-major: hist[c * nb + b]
@@ -683,9 +694,15 @@ __global__ void k_ml_rowptr(const int *__restrict__ lrp, int n, int *mrp) {
   if (i <= n) mrp[i] = lrp[i] + i;
 }
 
-__global__ void k_row_len_max(const int *__restrict__ rp, int rows, int *out) {
+// *out = max(*out, longest row), one atomic per wavefront after a shuffle reduction
+__global__ __launch_bounds__(256) void k_row_len_max(const int *__restrict__ rp, int rows,
+                                                     int *out) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r < rows) atomicMax(out, rp[r + 1] - rp[r]);
+  int v = 0;
+  if (r < rows) v = rp[r + 1] - rp[r];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+  if ((threadIdx.x & 63) == 0 && v > 0) atomicMax(out, v);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -798,23 +815,25 @@ static void stage2_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
   // stable permutation by colour
   const int nb = ceil_div(ne, 256);
 
-  D.hist.ensure((size_t)ncol * nb + 1);
+  D.hist.ensure((size_t)ncol * nb + 1 + (size_t)ncol);   // scan, then the colour starts
   D.perm.ensure(ne);
   D.iperm.ensure(ne);
   if (ne) {
     hipLaunchKernelGGL(k_color_hist, dim3(nb), dim3(256), 0, s, D.color.p, ne, ncol, nb, D.hist.p);
     EDFA_CHECK_LAUNCH();
-    exclusive_scan(D.hist.p, D.hist.p, ncol * nb, S.tmp, s);
+    exclusive_scan_async(D.hist.p, D.hist.p, ncol * nb, S.tmp, s);
     hipLaunchKernelGGL(k_color_scatter, dim3(nb), dim3(256), 0, s, D.color.p, ne, nb, D.hist.p,
                        D.perm.p, D.iperm.p);
     EDFA_CHECK_LAUNCH();
   }
-  {
-    std::vector<int> h((size_t)ncol * nb + 1);
-    EDFA_HIP(hipMemcpyAsync(h.data(), D.hist.p, sizeof(int) * h.size(), hipMemcpyDeviceToHost, s));
-    EDFA_HIP(hipStreamSynchronize(s));
-    D.cstart.assign(ncol + 1, ne);
-    for (int c = 0; c < ncol; ++c) D.cstart[c] = h[(size_t)c * nb];
+  D.cstart.assign(ncol + 1, ne);
+  if (ne) {
+    // the first position of colour c is the scanned count of (c, block 0): gathered behind
+    // the histogram, then one small read
+    int *starts = D.hist.p + (size_t)ncol * nb + 1;
+    hipLaunchKernelGGL(k_color_starts, dim3(1), dim3(256), 0, s, D.hist.p, nb, ncol, starts);
+    EDFA_CHECK_LAUNCH();
+    read_small(D.cstart.data(), starts, (size_t)ncol, s);
   }
 
   // permuted matrix

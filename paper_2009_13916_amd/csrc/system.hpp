@@ -138,6 +138,7 @@ struct edfa_system_s {
   // matrices (FP64)
   edfa::Csr<double> A;           // N x N
   edfa::Csr<double> Afp, Afc, Acf, Acc;   // A_pipi, A_pip, A_ppi, A_pp
+  int afp_max = -1;   // longest row of A_pipi (found by the first setup; -1: not yet)
   edfa::Csr<double> AfcT;        // A_pip^T (N_e x Nfu): row m = column m of A_pip
   edfa::Csr<double> AT;          // A^T (built on first use)
   edfa::Csr<double> AcfT;        // A_ppi^T (Nfu x N_e, built on first use)

@@ -102,8 +102,7 @@ edfa_status transient(edfa_system_s &S, edfa_precond_s &P, const edfa_transient_
       EDFA_CHECK_LAUNCH();
     }
     unsigned long long mh[2];
-    EDFA_HIP(hipMemcpyAsync(mh, meas.p, sizeof(mh), hipMemcpyDeviceToHost, s));
-    EDFA_HIP(hipStreamSynchronize(s));
+    read_small(mh, meas.p, 2, s);
     double dp, chi;
     memcpy(&dp, &mh[0], sizeof(double));
     memcpy(&chi, &mh[1], sizeof(double));

@@ -120,11 +120,12 @@ void apply_tuned(edfa_precond_s &P) {
   });
 }
 
-bool chunks_pending(edfa_precond_s &P) {
+bool layouts_pending(edfa_precond_s &P) {
   bool pending = false;
   for_each_slot(P, [&](int, auto &M, int) {
     if (M.rows > 0 && M.lanes == SPMV_CHUNKED && M.depth == CHUNK_K_ALT && M.nchunk_alt < 0)
       pending = true;
+    if (M.rows > 0 && (M.lanes == 0 || M.lanes == 1) && !M.sell_ready) pending = true;
   });
   return pending;
 }

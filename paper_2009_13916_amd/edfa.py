@@ -63,7 +63,7 @@ class _PrecondInfo(C.Structure):
                 ("t_stage1_ms", C.c_double), ("t_stage2_ms", C.c_double),
                 ("nnz_H_raw", C.c_int64), ("htilde_retry_rows", C.c_int32),
                 ("color_rounds", C.c_int32), ("color_list_rounds", C.c_int32),
-                ("cgs2_width", C.c_int32)]
+                ("cgs2_width", C.c_int32), ("chunks_ML", C.c_int32), ("chunks_MU", C.c_int32)]
 
 
 NCAP = 7

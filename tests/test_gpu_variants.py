@@ -111,3 +111,29 @@ def test_set_variant_rejects_out_of_range(lib):
     with pytest.raises(lib.EdfaError):
         P.set_variant(0, slot=16)
     P.set_variant(None)   # back to the defaults
+
+
+def _greedy_chunks(rp, cap):
+    """Row-aligned greedy cut: close the chunk before the first row that would take it past
+    `cap` entries (a longer row alone)."""
+    n, r0 = 1, 0
+    for r in range(len(rp) - 1):
+        if r > r0 and rp[r + 1] - rp[r0] > cap:
+            n, r0 = n + 1, r
+    return n
+
+
+def test_chunk_descriptors_match_the_greedy_cut(lib):
+    """The chunk kernel's descriptors, computed on the device by pointer doubling, hold as
+    many chunks as the sequential greedy cut of the natural-order rows of M_L and M_U."""
+    prob = inputs.full_tensor_problem(16, 14, 12, sigma=2.0, corr=3.0, config_id=77)
+    S = lib.System(prob)
+    P = lib.Precond(S, lib.Params(**PRM))
+    info = P.info()
+    for name, key in (("ML", "chunks_ML"), ("MU", "chunks_MU")):
+        rp, col, val, perm = P.export(name)
+        lens = torch.diff(rp).cpu().numpy()
+        nat = np.zeros_like(lens)
+        nat[perm.cpu().numpy()] = lens
+        rpn = np.concatenate([[0], np.cumsum(nat)])
+        assert info[key] == _greedy_chunks(rpn, 768) > 8, (name, info[key])

@@ -1,8 +1,9 @@
 """The allocation-free application (edfa_apply_noalloc), through the C-ABI: two calls in a row
 on different systems, the second smaller, each equal to edfa_apply on the same handle (the
 same kernels on the same inputs, so bit for bit), FP64 and FP32, forward and transposed; a
-system whose workspace exceeds the static array is refused with both sizes named, and so is a
-transposed call before the transposed factors exist."""
+system whose workspace exceeds the static array is refused with both sizes named, and so are a
+transposed call before the transposed factors exist and a product whose SELL layout has not
+been built yet."""
 import ctypes as C
 
 import numpy as np
@@ -62,3 +63,13 @@ def test_noalloc_refuses_what_it_would_have_to_allocate(lib):
     # and the small handle still works afterwards
     zz = P.apply(r, noalloc=True)
     assert torch.equal(zz, P.apply(r))
+    # the SELL layout of a long-row matrix (here M_L, whose default is the chunk kernel) is
+    # built by its first product: refused until an application has run with it
+    assert P.info()["chunks_ML"] > 0
+    P.set_variant("sell/4", slot="M_L")
+    with pytest.raises(lib.EdfaError) as ei:
+        P.apply(r, z=z, noalloc=True)
+    assert "SELL" in str(ei.value)
+    ref = P.apply(r)
+    assert torch.equal(P.apply(r, noalloc=True), ref)
+    P.set_variant(None)

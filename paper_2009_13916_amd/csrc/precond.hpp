@@ -122,6 +122,31 @@ void launch_dots2(int width, int j, int nch, hipStream_t s, const double *Q, lon
 
 }  // namespace edfa
 
+// A second stream of the handle for setup work that is independent of the main chain (the
+// FSAI branch of stage 1), with the events that order it after and join it to the caller's
+// stream.  Default priority, like every stream here.
+struct SideStream {
+  hipStream_t s = nullptr;
+  hipEvent_t start = nullptr, done = nullptr;
+  SideStream() = default;
+  SideStream(const SideStream &) = delete;
+  SideStream &operator=(const SideStream &) = delete;
+  ~SideStream() {
+    if (s) (void)hipStreamSynchronize(s);
+    if (start) (void)hipEventDestroy(start);
+    if (done) (void)hipEventDestroy(done);
+    if (s) (void)hipStreamDestroy(s);
+  }
+  hipStream_t get() {
+    if (!s) {
+      EDFA_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+      EDFA_HIP(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+      EDFA_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+    }
+    return s;
+  }
+};
+
 struct edfa_precond_s {
   edfa_system_s *sys = nullptr;
   edfa_params prm{};
@@ -141,7 +166,10 @@ struct edfa_precond_s {
   double t_stage1_ms = 0, t_stage2_ms = 0;
   edfa::PrecData<double> d;
   edfa::PrecData<float> f;
-  edfa::DBuf<int> flags;           // device error flags
+  edfa::DBuf<int> flags;           // device error flags: [0] not SPD, [1] capacity, [2], [3]
+                                   // scratch values; [4] .. [7] the same for the FSAI branch
+  SideStream side;                 // the FSAI branch of stage 1 runs on it
+  edfa::DBuf<int> side_tmp, side_tmp2;   // scratch of that branch
   edfa::Csr<float> coupling_f[4];  // FP32 A_ppi, A_pip, A_pip^T, A_ppi^T (FP32 application)
   edfa::Sell<float> coupling_fs[4];
   edfa::DBuf<float> rin_f;         // FP32 copy of the vector being preconditioned

@@ -1385,10 +1385,10 @@ static void build_vec_csr(edfa_system_s &S, PrecData<T> &D, const DBuf<T> &v, in
     launch(k_vec_write<T, PATCH_MAX>);
 }
 
-// Reads the error flags (and returns flags[2], the scratch value of the last step).
-static int check_flags(edfa_precond_s &P, hipStream_t s, const char *where) {
+// Reads the error flags at `at` (and returns flags[2], the scratch value of the last step).
+static int check_flags(edfa_precond_s &P, hipStream_t s, const char *where, int at = 0) {
   int fl[3];
-  read_small(fl, P.flags.p, 3, s);
+  read_small(fl, P.flags.p + at, 3, s);
   if (fl[0] != 0x7fffffff)
     fail(EDFA_ERR_NOT_SPD, "%s: restricted system of row/cell %d is not SPD", where, fl[0]);
   if (fl[1] != 0x7fffffff)
@@ -1397,8 +1397,8 @@ static int check_flags(edfa_precond_s &P, hipStream_t s, const char *where) {
 }
 
 static void reset_flags(edfa_precond_s &P, hipStream_t s) {
-  P.flags.ensure(4);
-  const int init[4] = {0x7fffffff, 0x7fffffff, 0, 0};
+  P.flags.ensure(8);
+  const int init[8] = {0x7fffffff, 0x7fffffff, 0, 0, 0x7fffffff, 0x7fffffff, 0, 0};
   EDFA_HIP(hipMemcpyAsync(P.flags.p, init, sizeof(init), hipMemcpyHostToDevice, s));
 }
 
@@ -1442,6 +1442,35 @@ static void launch_local(int cap, int cells, const LocalArgs<T> &la, hipStream_t
 static int bucket_capacity(const edfa_precond_s &P, int b) {
   const int own = kCapacities[b];
   return P.cap_map[b] > own ? P.cap_map[b] : own;
+}
+
+// FSAI of -A_pipi, its transpose and their SELL copies, on stream `ss` with the branch's own
+// scratch and error flags (flags[4], [5]): nothing here depends on the restricted solves,
+// so it runs beside them.  Records P.side.done at its end.
+template <class T>
+static void fsai_branch(edfa_precond_s &P, PrecData<T> &D, hipStream_t ss) {
+  edfa_system_s &S = *P.sys;
+  const int nfu = S.nfu;
+  D.GF.rowptr.ensure((size_t)nfu + 1);
+  hipLaunchKernelGGL(k_fsai_count, dim3(ceil_div(nfu, 256)), dim3(256), 0, ss, S.Afp.rowptr.p,
+                     S.Afp.col.p, nfu, D.GF.rowptr.p);
+  EDFA_CHECK_LAUNCH();
+  const int64_t gnnz = exclusive_scan(D.GF.rowptr.p, D.GF.rowptr.p, nfu, P.side_tmp, ss);
+  D.GF.rows = D.GF.cols = nfu;
+  D.GF.nnz = gnnz;
+  D.GF.col.ensure(gnnz);
+  D.GF.val.ensure(gnnz);
+  if (nfu > 0) {
+    hipLaunchKernelGGL(k_fsai<T>, dim3(ceil_div(nfu, 64)), dim3(64), 0, ss, S.Afp.rowptr.p,
+                       S.Afp.col.p, S.Afp.val.p, nfu, D.GF.rowptr.p, D.GF.col.p, D.GF.val.p,
+                       P.flags.p + 4, P.flags.p + 5);
+    EDFA_CHECK_LAUNCH();
+  }
+  check_flags(P, ss, "FSAI", 4);
+  csr_transpose(D.GF, D.GFT, P.side_tmp, P.side_tmp2, ss);
+  build_sell(D.GF, D.GF_s, P.side_tmp, ss);
+  build_sell(D.GFT, D.GFT_s, P.side_tmp, ss);
+  EDFA_HIP(hipEventRecord(P.side.done, ss));
 }
 
 template <class T>
@@ -1547,11 +1576,18 @@ static void stage1_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
                        S.Acf.col.p, ne, smax, D.Q.p, D.qlen.p);
     EDFA_CHECK_LAUNCH();
   }
+  // the FSAI branch runs on the side stream beside the restricted solves: ordered after what
+  // s held before them (the flags' reset, any earlier use of G_F), and its host part, which
+  // waits on the side stream only, is issued once the solves are queued
+  hipStream_t ss = P.side.get();
+  EDFA_HIP(hipEventRecord(P.side.start, s));
   // one launch per capacity bucket, over the bucket's cells
   for (int b = 0, off = 0; b < NCAP; off += counts[b], ++b) {
     la.cells = D.bcells.p + off;
     launch_local<T>(bucket_capacity(P, b), counts[b], la, s);
   }
+  EDFA_HIP(hipStreamWaitEvent(ss, P.side.start, 0));
+  fsai_branch<T>(P, D, ss);
   // longest final pattern (sizes the H~ tables), read with the error flags
   EDFA_HIP(hipMemsetAsync(P.flags.p + 2, 0, sizeof(int), s));
   if (ne > 0) {
@@ -1654,26 +1690,8 @@ static void stage1_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
                      D.Hlen.p, ne, postH, prm.tau_filt, D.H.rowptr.p, D.H.col.p, D.H.val.p);
   EDFA_CHECK_LAUNCH();
 
-  // FSAI of -A_pipi
-  D.GF.rowptr.ensure((size_t)nfu + 1);
-  hipLaunchKernelGGL(k_fsai_count, dim3(ceil_div(nfu, 256)), dim3(256), 0, s, S.Afp.rowptr.p,
-                     S.Afp.col.p, nfu, D.GF.rowptr.p);
-  EDFA_CHECK_LAUNCH();
-  const int64_t gnnz = exclusive_scan(D.GF.rowptr.p, D.GF.rowptr.p, nfu, S.tmp, s);
-  D.GF.rows = D.GF.cols = nfu;
-  D.GF.nnz = gnnz;
-  D.GF.col.ensure(gnnz);
-  D.GF.val.ensure(gnnz);
-  if (nfu > 0) {
-    hipLaunchKernelGGL(k_fsai<T>, dim3(ceil_div(nfu, 64)), dim3(64), 0, s, S.Afp.rowptr.p,
-                       S.Afp.col.p, S.Afp.val.p, nfu, D.GF.rowptr.p, D.GF.col.p, D.GF.val.p,
-                       err_spd, err_cap);
-    EDFA_CHECK_LAUNCH();
-  }
-  check_flags(P, s, "FSAI");
-  csr_transpose(D.GF, D.GFT, S.tmp, S.tmp2, s);
-  build_sell(D.GF, D.GF_s, S.tmp, s);
-  build_sell(D.GFT, D.GFT_s, S.tmp, s);
+  // the FSAI branch joins here
+  EDFA_HIP(hipStreamWaitEvent(s, P.side.done, 0));
 }
 
 // Setup tuner: each non-empty capacity bucket of the last stage 1 is timed (best of three

@@ -203,10 +203,10 @@ __global__ __launch_bounds__(256) void k_jp_round(const int *__restrict__ srp,
   bool need = false;
   if (slot < (list ? nlist : ne)) {
     v = list ? list[slot] : slot;
-    if (__atomic_load_n(&color[v], __ATOMIC_RELAXED) < 0) {
-      const int bv = blocker[v];
-      need = !(bv >= 0 && __atomic_load_n(&color[bv], __ATOMIC_RELAXED) < 0);
-    }
+    // the vertex's colour and its recorded blocker are loaded together (one latency, not two)
+    const int bv = blocker[v];
+    const int cv = __atomic_load_n(&color[v], __ATOMIC_RELAXED);
+    if (cv < 0) need = !(bv >= 0 && __atomic_load_n(&color[bv], __ATOMIC_RELAXED) < 0);
   }
   unsigned long long work = __ballot(need);
   const int g = lane >> 4, l = lane & 15;   // four groups of 16 lanes

@@ -29,6 +29,9 @@ struct PrecData {
   DBuf<double> ell_val;
   Csr<T> G;             // G~   (Ne x Nfu)
   Csr<T> FT;            // F~^T (Ne x Nfu): row m = column m of F~
+  DBuf<int> ft_ecol;    // F~^T rows padded to ft_w entries (a multiple of 16; column -1 past
+  DBuf<T> ft_eval;      //   a row's end), read by the H~ products with vector loads
+  int ft_w = 0;
   Csr<T> Fface;         // F~   (Nfu x Ne)
   DBuf<int> Hcol;       // Ne x HMAX raw H~ rows (sorted)
   DBuf<T> Hval;

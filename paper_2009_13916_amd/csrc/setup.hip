@@ -229,6 +229,19 @@ __global__ void k_ell_fill(const int *__restrict__ rp, const int *__restrict__ c
   eval[t] = in ? val[p] : 0.0;
 }
 
+// Rows of a CSR matrix padded to w entries (w a multiple of 16, rows of at most w entries).
+template <class T>
+__global__ void k_pad_rows(const int *__restrict__ rp, const int *__restrict__ col,
+                           const T *__restrict__ val, int rows, int w, int *ecol, T *eval) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)rows * w) return;
+  const int r = (int)(t / w), k = (int)(t % w);
+  const int p = rp[r] + k;
+  const bool in = p < rp[r + 1];
+  ecol[t] = in ? col[p] : -1;
+  eval[t] = in ? val[p] : T(0);
+}
+
 // ------------------------------------------------------------------------------------
 // Restricted local solves, one 64-lane wavefront per cell
 // ------------------------------------------------------------------------------------
@@ -1048,8 +1061,10 @@ struct HArgs {
   const int *ell_col;   // A_pipi as ELL_W-entry rows
   const double *ell_val;
   const int *ff_rp, *ff_col;   // F~ by face rows (cells)
-  const int *ft_rp, *ft_col;   // F~^T by cell rows (faces)
-  const T *ft_val;
+  const int *ft_rp;            // F~^T by cell rows (faces): row pointer, and the rows padded
+  const int *ft_ecol;          //   to ft_w entries
+  const T *ft_eval;
+  int ft_w;
   int *Hcol, *Hlen;
   T *Hval;
   int *err_cap;
@@ -1189,21 +1204,44 @@ __global__ __launch_bounds__(64) void k_htilde(HArgs<T> A) {
     // a block of the row is looked up at once: the first table probes of all its entries,
     // then the reads of t at the entries found, each one batch of LDS reads; the sum runs
     // in the row's order
-    const int p0 = A.ft_rp[l], p1 = A.ft_rp[l + 1];
-    for (int b = p0; b < p1; b += 16) {
+    // (the row is read from its padded copy: 16 entries as four int4 and eight 16-byte
+    // value loads, instead of one load per entry)
+    const int len = A.ft_rp[l + 1] - A.ft_rp[l];
+    const int *ec = A.ft_ecol + (size_t)l * A.ft_w;
+    const T *ev = A.ft_eval + (size_t)l * A.ft_w;
+    for (int b = 0; b < len; b += 16) {
       int cc[16], kk[16], sl[16];
       T vv[16], xv[16];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int p = min(b + u, p1 - 1);
-        cc[u] = A.ft_col[p];
-        vv[u] = A.ft_val[p];
+      for (int u = 0; u < 4; ++u) {
+        const int4 w4 = reinterpret_cast<const int4 *>(ec + b)[u];
+        cc[4 * u] = w4.x;
+        cc[4 * u + 1] = w4.y;
+        cc[4 * u + 2] = w4.z;
+        cc[4 * u + 3] = w4.w;
+      }
+      if constexpr (sizeof(T) == 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const double2 w2 = reinterpret_cast<const double2 *>(ev + b)[u];
+          vv[2 * u] = w2.x;
+          vv[2 * u + 1] = w2.y;
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const float4 w4 = reinterpret_cast<const float4 *>(ev + b)[u];
+          vv[4 * u] = w4.x;
+          vv[4 * u + 1] = w4.y;
+          vv[4 * u + 2] = w4.z;
+          vv[4 * u + 3] = w4.w;
+        }
       }
 #pragma unroll
       for (int u = 0; u < 16; ++u) kk[u] = tk[hslot<TH>(cc[u])];
 #pragma unroll
       for (int u = 0; u < 16; ++u)
-        sl[u] = b + u < p1 ? h_resolve<TH>(tk, cc[u], hslot<TH>(cc[u]), kk[u]) : -1;
+        sl[u] = b + u < len ? h_resolve<TH>(tk, cc[u], hslot<TH>(cc[u]), kk[u]) : -1;
 #pragma unroll
       for (int u = 0; u < 16; ++u) xv[u] = tv[sl[u] >= 0 ? sl[u] : 0];
 #pragma unroll
@@ -1616,9 +1654,20 @@ static void stage1_impl(edfa_precond_s &P, PrecData<T> &D, hipStream_t s) {
   ha.ell_val = la.ell_val;
   ha.ff_rp = D.Fface.rowptr.p;
   ha.ff_col = D.Fface.col.p;
+  // F~^T with its rows padded to a multiple of 16 entries (a row holds at most smax)
+  D.ft_w = (smax + 15) / 16 * 16;
+  D.ft_ecol.ensure((size_t)std::max(ne, 1) * D.ft_w);
+  D.ft_eval.ensure((size_t)std::max(ne, 1) * D.ft_w);
+  if (ne > 0) {
+    hipLaunchKernelGGL(k_pad_rows<T>, dim3(ceil_div((long long)ne * D.ft_w, 256)), dim3(256), 0,
+                       s, D.FT.rowptr.p, D.FT.col.p, D.FT.val.p, ne, D.ft_w, D.ft_ecol.p,
+                       D.ft_eval.p);
+    EDFA_CHECK_LAUNCH();
+  }
   ha.ft_rp = D.FT.rowptr.p;
-  ha.ft_col = D.FT.col.p;
-  ha.ft_val = D.FT.val.p;
+  ha.ft_ecol = D.ft_ecol.p;
+  ha.ft_eval = D.ft_eval.p;
+  ha.ft_w = D.ft_w;
   ha.Hcol = D.Hcol.p;
   ha.Hlen = D.Hlen.p;
   ha.Hval = D.Hval.p;

@@ -42,12 +42,18 @@ __global__ __launch_bounds__(RT) void k_dots2(const double *__restrict__ Q, long
                                               const double *__restrict__ w,
                                               const Chunk *__restrict__ ch,
                                               const SegState *__restrict__ st, double *part,
-                                              int ldp) {
+                                              int ldp, int nch, int ng) {
   __shared__ double red[4][2 * DG + 2];
-  const Chunk c = ch[blockIdx.x];
+  // XCD-aware order: workgroups are dealt to the 8 XCDs in turn, so block b runs on XCD b % 8
+  // as that XCD's (b / 8)-th block; there the groups of one chunk follow each other, and the
+  // chunk's u and w come from that XCD's L2 after the first group
+  const int xcd = blockIdx.x % 8, slot = blockIdx.x / 8;
+  const int chunk = (slot / ng) * 8 + xcd, grp = slot % ng;
+  if (chunk >= nch) return;
+  const Chunk c = ch[chunk];
   if (!st[c.seg].active) return;
-  const int i0 = blockIdx.y * DG;
-  const bool self = blockIdx.y == 0;
+  const int i0 = grp * DG;
+  const bool self = grp == 0;
   // Branch-free loads: elements past the chunk end re-read its last element with weight
   // zero, and basis slots past nv re-read slot nv - 1 (their sums are not stored), so every
   // load of the block is issued before the first wait.
@@ -97,7 +103,7 @@ __global__ __launch_bounds__(RT) void k_dots2(const double *__restrict__ Q, long
   const int t = threadIdx.x;
   if (t < 2 * DG + 2) {
     const double v = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
-    double *row = part + (long long)blockIdx.x * ldp;
+    double *row = part + (long long)chunk * ldp;
     if (t < DG) {
       if (i0 + t < nv) row[i0 + t] = v;
     } else if (t < 2 * DG) {
@@ -111,9 +117,12 @@ __global__ __launch_bounds__(RT) void k_dots2(const double *__restrict__ Q, long
 void launch_dots2(int width, int j, int nch, hipStream_t s, const double *Q, long long ldq,
                   const double *u, const double *w, const Chunk *ch, const SegState *st,
                   double *part, int ld) {
+  // one dimension: 8 x ceil(nch / 8) chunk slots (those past nch return) times the ng groups
+  // of basis vectors, in the order the kernel maps to (chunk, group)
   auto go = [&](auto kern, int dg) {
-    hipLaunchKernelGGL(kern, dim3(nch, std::max(1, ceil_div(j, dg))), dim3(RT), 0, s, Q, ldq, j,
-                       u, w, ch, st, part, ld);
+    const int ng = std::max(1, ceil_div(j, dg));
+    hipLaunchKernelGGL(kern, dim3(8 * ceil_div(nch, 8) * ng), dim3(RT), 0, s, Q, ldq, j, u, w,
+                       ch, st, part, ld, nch, ng);
   };
   if (width == 2)
     go(k_dots2<2>, 2);

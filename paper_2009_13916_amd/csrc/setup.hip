@@ -613,7 +613,7 @@ template <class T, int SMAX>
 __global__ __launch_bounds__(64) void k_local_reg(LocalArgs<T> A) {
   static_assert(SMAX <= 64, "one lane per pattern entry");
   constexpr int QH = pow2ceil(2 * SMAX < 64 ? 64 : 2 * SMAX);
-  constexpr int CH = pow2ceil(8 * SMAX);
+  constexpr int CH = (SMAX == 40 || SMAX == 44) ? 256 : pow2ceil(8 * SMAX);
   constexpr int LP = SMAX * (SMAX + 1) / 2;
   __shared__ T Lp[LP];
   __shared__ int q[SMAX];
@@ -851,6 +851,12 @@ __global__ __launch_bounds__(64) void k_local_reg(LocalArgs<T> A) {
       }
     }
     __syncthreads();
+    // the factor rows back into registers from the packed copy (the same values): the
+    // register copy is dead during the candidate residuals, which then have its registers
+    static_for<0, SMAX>([&](auto K) EDFA_INLINE {
+      constexpr int k = K;
+      Lr[k] = (k < lane && lane < s) ? Lp[pidx(lane, k)] : T(0);
+    });
     int added = 0;
     for (int rnd = 0; rnd < n; ++rnd) {
       unsigned long long bk = 0;

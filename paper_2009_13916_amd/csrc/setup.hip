@@ -613,7 +613,7 @@ template <class T, int SMAX>
 __global__ __launch_bounds__(64) void k_local_reg(LocalArgs<T> A) {
   static_assert(SMAX <= 64, "one lane per pattern entry");
   constexpr int QH = pow2ceil(2 * SMAX < 64 ? 64 : 2 * SMAX);
-  constexpr int CH = (SMAX == 40 || SMAX == 44) ? 256 : pow2ceil(8 * SMAX);
+  constexpr int CH = (SMAX >= 40 && SMAX <= 48) ? 256 : pow2ceil(8 * SMAX);
   constexpr int LP = SMAX * (SMAX + 1) / 2;
   __shared__ T Lp[LP];
   __shared__ int q[SMAX];

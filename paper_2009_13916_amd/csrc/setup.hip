@@ -81,6 +81,7 @@ __device__ inline T wave_sum(T v) {
 }
 
 __device__ inline int pidx(int i, int j) { return i * (i + 1) / 2 + j; }   // packed lower
+__device__ inline int sidx(int i, int j) { return i * (i - 1) / 2 + j; }   // strictly lower, j < i
 
 #define EDFA_INLINE __attribute__((always_inline))
 
@@ -614,11 +615,14 @@ __global__ __launch_bounds__(64) void k_local_reg(LocalArgs<T> A) {
   static_assert(SMAX <= 64, "one lane per pattern entry");
   constexpr int QH = pow2ceil(2 * SMAX < 64 ? 64 : 2 * SMAX);
   constexpr int CH = (SMAX >= 40 && SMAX <= 48) ? 256 : pow2ceil(8 * SMAX);
-  constexpr int LP = SMAX * (SMAX + 1) / 2;
+  constexpr int LP = SMAX * (SMAX - 1) / 2;   // strictly lower triangle (diagonal apart)
   __shared__ T Lp[LP];
   __shared__ int q[SMAX];
   __shared__ unsigned long long qt[QH];   // column -> index in Q (q_find)
-  __shared__ T bg[SMAX], bf[SMAX], rowt[SMAX], xs[SMAX];
+  // xs holds the solution for the candidate residuals and, after them, the bordering column
+  // (rowt); the right-hand sides live in registers (one entry per lane)
+  __shared__ T xs[SMAX];
+  T *const rowt = xs;
   __shared__ int ck[CH], clist[CH];
   __shared__ T cr[CH];
   __shared__ int ccount, sflag;
@@ -633,8 +637,8 @@ __global__ __launch_bounds__(64) void k_local_reg(LocalArgs<T> A) {
   }
   for (int t = lane; t < SMAX; t += 64) {
     q[t] = t < s ? A.Q[(size_t)m * A.qstride + t] : -1;
-    bg[t] = 0;
-    bf[t] = 0;
+    cr[t] = 0;          // the right-hand sides are gathered in cr, then read into registers
+    cr[SMAX + t] = 0;
   }
   for (int h = lane; h < QH; h += 64) qt[h] = Q_EMPTY;
   if (lane == 0) sflag = 0;
@@ -644,19 +648,25 @@ __global__ __launch_bounds__(64) void k_local_reg(LocalArgs<T> A) {
   // right-hand sides: a_ppi^(m) (row m of A_ppi) and a_pip^(m) (column m of A_pip)
   for (int p = A.acf_rp[m] + lane; p < A.acf_rp[m + 1]; p += 64) {
     const int k = q_find<QH>(qt, A.acf_col[p]);
-    if (k >= 0) bg[k] = (T)A.acf_val[p];
+    if (k >= 0) cr[k] = (T)A.acf_val[p];
   }
   for (int p = A.afcT_rp[m] + lane; p < A.afcT_rp[m + 1]; p += 64) {
     const int k = q_find<QH>(qt, A.afcT_col[p]);
-    if (k >= 0) bf[k] = (T)A.afcT_val[p];
+    if (k >= 0) cr[SMAX + k] = (T)A.afcT_val[p];
   }
   // restricted matrix -R A_pipi R^T, lower part in Q order
   for (int t = lane; t < LP; t += 64) Lp[t] = 0;
   __syncthreads();
+  // lane t's entries of the two right-hand sides (zero past the pattern and for every entry
+  // appended later: a_ppi^(m) and a_pip^(m) vanish outside the base pattern)
+  const T bgl = lane < SMAX ? cr[lane] : T(0);
+  const T bfl = lane < SMAX ? cr[SMAX + lane] : T(0);
+  T d0 = 0;   // lane's diagonal entry (the packed copy holds the strictly lower part)
   if (lane < s) {
     ell_row(A.ell_col, A.ell_val, q[lane], [&](int c, double v) EDFA_INLINE {
       const int k = q_find<QH>(qt, c);
-      if (k >= 0 && k <= lane) Lp[pidx(lane, k)] = -(T)v;
+      if (k >= 0 && k < lane) Lp[sidx(lane, k)] = -(T)v;
+      if (k == lane) d0 = -(T)v;
     });
   }
   __syncthreads();
@@ -668,7 +678,7 @@ __global__ __launch_bounds__(64) void k_local_reg(LocalArgs<T> A) {
   T Lr[SMAX];
   static_for<0, SMAX>([&](auto K) EDFA_INLINE {
     constexpr int k = K;
-    Lr[k] = (lane < s && k <= lane) ? Lp[pidx(lane, k)] : T(0);
+    Lr[k] = (lane < s && k < lane) ? Lp[sidx(lane, k)] : (lane < s && k == lane ? d0 : T(0));
   });
   T dg = 1;
   bool spd = true;
@@ -701,7 +711,7 @@ __global__ __launch_bounds__(64) void k_local_reg(LocalArgs<T> A) {
   __syncthreads();
   static_for<0, SMAX>([&](auto K) EDFA_INLINE {
     constexpr int k = K;
-    if (lane < s && k < lane) Lp[pidx(lane, k)] = Lr[k];
+    if (lane < s && k < lane) Lp[sidx(lane, k)] = Lr[k];
   });
   __syncthreads();
 
@@ -717,7 +727,7 @@ __global__ __launch_bounds__(64) void k_local_reg(LocalArgs<T> A) {
     // ends holding its own entry and divides it by L_kk there: the same operations, on the
     // same operands, as dividing at step k.
     {
-      T b1 = lane < s ? bg[lane] : T(0);
+      T b1 = lane < s ? bgl : T(0);
       if (!last) {
         // both substitutions run all SMAX steps without branches, so the reads of later
         // steps issue early: the entries past s are zero and so are their updates
@@ -728,12 +738,12 @@ __global__ __launch_bounds__(64) void k_local_reg(LocalArgs<T> A) {
         b1 *= invd;
         static_for<0, SMAX>([&](auto K) EDFA_INLINE {
           constexpr int k = SMAX - 1 - K;
-          const T l = lane < k ? Lp[pidx(k, lane)] : T(0);
+          const T l = lane < k ? Lp[sidx(k, lane)] : T(0);
           b1 -= l * (lane_value(b1, k) * lane_value(invd, k));
         });
         b1 *= invd;
       } else {
-        T b2 = lane < s ? bf[lane] : T(0);
+        T b2 = lane < s ? bfl : T(0);
         static_for<0, SMAX>([&](auto K) EDFA_INLINE {
           constexpr int k = K;
           const T ik = lane_value(invd, k);
@@ -745,7 +755,7 @@ __global__ __launch_bounds__(64) void k_local_reg(LocalArgs<T> A) {
         static_for<0, SMAX>([&](auto K) EDFA_INLINE {
           constexpr int k = SMAX - 1 - K;
           const T ik = lane_value(invd, k);
-          const T l = lane < k ? Lp[pidx(k, lane)] : T(0);
+          const T l = lane < k ? Lp[sidx(k, lane)] : T(0);
           b1 -= l * (lane_value(b1, k) * ik);
           b2 -= l * (lane_value(b2, k) * ik);
         });
@@ -855,7 +865,7 @@ __global__ __launch_bounds__(64) void k_local_reg(LocalArgs<T> A) {
     // register copy is dead during the candidate residuals, which then have its registers
     static_for<0, SMAX>([&](auto K) EDFA_INLINE {
       constexpr int k = K;
-      Lr[k] = (k < lane && lane < s) ? Lp[pidx(lane, k)] : T(0);
+      Lr[k] = (k < lane && lane < s) ? Lp[sidx(lane, k)] : T(0);
     });
     int added = 0;
     for (int rnd = 0; rnd < n; ++rnd) {
@@ -912,7 +922,7 @@ __global__ __launch_bounds__(64) void k_local_reg(LocalArgs<T> A) {
         const T lk = lane_value(a, k) * lane_value(invd, k);
         a -= Lr[k] * lk;
         Lr[k] = lane == t ? lk : Lr[k];   // a select, not a store to Lr[t]
-        if (lane == 0) Lp[pidx(t, k)] = lk;
+        if (lane == 0) Lp[sidx(t, k)] = lk;
         dsum += lk * lk;
       });
       const T d = att - dsum;
@@ -924,10 +934,6 @@ __global__ __launch_bounds__(64) void k_local_reg(LocalArgs<T> A) {
       if (lane == t) {
         dg = ltt;
         invd = T(1) / ltt;
-      }
-      if (lane == 0) {
-        bg[t] = 0;
-        bf[t] = 0;
       }
       __syncthreads();
       ++s;

@@ -850,14 +850,25 @@ __global__ __launch_bounds__(64) void k_local_reg(LocalArgs<T> A) {
       cr[c] = acc;
     };
     if (nc > 0) {
-      EllRow ra, rb;
-      rfetch(lane, ra);
-      rfetch(lane + 64, rb);
-      for (int base = 0; base < nc; base += 128) {
-        residual(base + lane, ra);
-        rfetch(base + lane + 128, ra);
-        residual(base + lane + 64, rb);
-        rfetch(base + lane + 192, rb);
+      if constexpr (sizeof(T) == 4) {
+        // one row in flight (fewer registers: the FP32 kernel then fits four wavefronts per
+        // SIMD)
+        EllRow ra;
+        rfetch(lane, ra);
+        for (int base = 0; base < nc; base += 64) {
+          residual(base + lane, ra);
+          rfetch(base + lane + 64, ra);
+        }
+      } else {
+        EllRow ra, rb;
+        rfetch(lane, ra);
+        rfetch(lane + 64, rb);
+        for (int base = 0; base < nc; base += 128) {
+          residual(base + lane, ra);
+          rfetch(base + lane + 128, ra);
+          residual(base + lane + 64, rb);
+          rfetch(base + lane + 192, rb);
+        }
       }
     }
     __syncthreads();

@@ -614,6 +614,9 @@ template <class T, int SMAX>
 __global__ __launch_bounds__(64) void k_local_reg(LocalArgs<T> A) {
   static_assert(SMAX <= 64, "one lane per pattern entry");
   constexpr int QH = pow2ceil(2 * SMAX < 64 ? 64 : 2 * SMAX);
+  // candidate table: 256 slots at capacities 40..48 (the largest candidate set measured on
+  // hexahedral grids is about 100; a full table is a capacity error), which keeps the
+  // wavefront's LDS small enough for three per SIMD
   constexpr int CH = (SMAX >= 40 && SMAX <= 48) ? 256 : pow2ceil(8 * SMAX);
   constexpr int LP = SMAX * (SMAX - 1) / 2;   // strictly lower triangle (diagonal apart)
   __shared__ T Lp[LP];
@@ -1446,7 +1449,8 @@ static void build_vec_csr(edfa_system_s &S, PrecData<T> &D, const DBuf<T> &v, in
     launch(k_vec_write<T, PATCH_MAX>);
 }
 
-// Reads the error flags at `at` (and returns flags[2], the scratch value of the last step).
+// Reads the error flags at `at` (and returns flags[at + 2], the scratch value of the last
+// step).
 static int check_flags(edfa_precond_s &P, hipStream_t s, const char *where, int at = 0) {
   int fl[3];
   read_small(fl, P.flags.p + at, 3, s);

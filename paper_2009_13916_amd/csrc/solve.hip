@@ -145,8 +145,8 @@ __global__ __launch_bounds__(256) void k_seg_reduce_w(const double *__restrict__
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (i >= ncomp) return;
+  const int c0 = segptr[g], c1 = segptr[g + 1];   // loaded beside the state, not after it
   if (which != SEG_ALL && !st[g].active) return;
-  const int c0 = segptr[g], c1 = segptr[g + 1];
   double s = 0;
   // eight of the lane's chunks per round, their loads issued together (the sum keeps the
   // chunk order)
@@ -194,18 +194,35 @@ __global__ __launch_bounds__(64) void k_dcgs_step(int nseg, int m, int j, int fi
                                                   double *Hb, double *R, double *cs, double *sn,
                                                   double *gv, double *coef, double *scale,
                                                   int max_iter, double *Tz) {
-  __shared__ double a[MAXV], b[MAXV], col[MAXV], cc[MAXV], c_[MAXV], s_[MAXV];
+  __shared__ double a[MAXV], b[MAXV], col[MAXV], hf[MAXV], cc[MAXV], c_[MAXV], s_[MAXV];
   __shared__ double sh_rho;
   __shared__ int sh_live;
   const int g = blockIdx.x;
-  if (g >= nseg || !st[g].active) return;
+  if (g >= nseg) return;
   const int lane = threadIdx.x;
   const double *dd = d + (long long)g * ldd;
   double *H = Hb + (long long)g * m * (m + 1);
+  const int jf = j - 1;                          // the column that becomes final (j > 0)
+  double *hc = H + (long long)jf * (m + 1);
+  // the loads that depend on nothing computed here go out together before the first wait
+  // (no branch between them): the segment's state, the reduced sums, column jf, the
+  // rotations before it (entry jf, in bounds, is loaded and not used) and g_jf.  Every
+  // global store comes after the last barrier, so no barrier waits for one; column jf as
+  // finished here (hf) is read from LDS.
+  const int active = st[g].active, total = st[g].total;
+  const double tol = st[g].tol;
+  const double nu = dd[2 * j], beta = dd[2 * j + 1];
+  const double gj = gv[(long long)g * (m + 1) + max(jf, 0)];
   for (int i = lane; i < j; i += 64) {
-    a[i] = dd[i];
-    b[i] = dd[j + i];
+    const double ai = dd[i], bi = dd[j + i], hi = hc[i];
+    const double ci = cs[(long long)g * m + i], si = sn[(long long)g * m + i];
+    a[i] = ai;
+    b[i] = bi;
+    hf[i] = hi + ai;   // Hbar[0:j, jf] += a
+    c_[i] = ci;
+    s_[i] = si;
   }
+  if (!active) return;   // the same for the whole wavefront
   __syncthreads();
   double aa = 0, ab = 0;
   for (int i = lane; i < j; i += 64) {
@@ -217,53 +234,52 @@ __global__ __launch_bounds__(64) void k_dcgs_step(int nseg, int m, int j, int fi
     aa += __shfl_xor(aa, o);
     ab += __shfl_xor(ab, o);
   }
-  const double nu = dd[2 * j], beta = dd[2 * j + 1];
+  // lane 0's results of the rotation, stored after the barriers
+  double cj = 0, sj = 0, gn = 0, est = 0;
+  int tot = 0;
+  bool live = true;
   if (j > 0) {
     // column jf = j - 1 becomes final: Hbar[0:j, jf] += a, Hbar[j, jf] = rho
-    const int jf = j - 1;
     const double r2 = nu - aa;
     const double rho = r2 > 0 ? sqrt(r2) : 0.0;
-    double *hc = H + (long long)jf * (m + 1);
-    for (int i = lane; i < j; i += 64) {
-      hc[i] += a[i];
-      col[i] = hc[i];
-      if (i < jf) {
-        c_[i] = cs[(long long)g * m + i];
-        s_[i] = sn[(long long)g * m + i];
-      }
-    }
+    for (int i = lane; i < j; i += 64) col[i] = hf[i];
     if (lane == 0) {
-      hc[j] = rho;
+      hf[j] = rho;
       col[j] = rho;
     }
     __syncthreads();
     if (lane == 0) {
-      SegState S = st[g];
       for (int i = 0; i < jf; ++i) {
         const double t = c_[i] * col[i] + s_[i] * col[i + 1];
         col[i + 1] = -s_[i] * col[i] + c_[i] * col[i + 1];
         col[i] = t;
       }
       const double den = hypot(col[jf], col[jf + 1]);
-      const double cj = den > 0 ? col[jf] / den : 1.0, sj = den > 0 ? col[jf + 1] / den : 0.0;
-      cs[(long long)g * m + jf] = cj;
-      sn[(long long)g * m + jf] = sj;
+      cj = den > 0 ? col[jf] / den : 1.0;
+      sj = den > 0 ? col[jf + 1] / den : 0.0;
       col[jf] = den;
-      double *gg = gv + (long long)g * (m + 1);
-      const double gj = gg[jf];
-      gg[jf + 1] = -sj * gj;
-      gg[jf] = cj * gj;
-      S.est = fabs(gg[jf + 1]);
-      S.j = j;
-      S.total += 1;
-      if (final_ || !(S.est > S.tol) || !(rho > 0) || S.total >= max_iter || !isfinite(S.est))
-        S.active = 0;
-      st[g] = S;
-      sh_live = S.active;
+      gn = -sj * gj;
+      est = fabs(gn);
+      tot = total + 1;
+      live = !(final_ || !(est > tol) || !(rho > 0) || tot >= max_iter || !isfinite(est));
+      sh_live = live;
       sh_rho = rho;
     }
     __syncthreads();
+    // the finished column, its rotated form and lane 0's rotation and state
+    for (int i = lane; i <= j; i += 64) hc[i] = hf[i];
     for (int i = lane; i <= jf; i += 64) R[((long long)g * m + i) * m + jf] = col[i];
+    if (lane == 0) {
+      cs[(long long)g * m + jf] = cj;
+      sn[(long long)g * m + jf] = sj;
+      double *gg = gv + (long long)g * (m + 1);
+      gg[jf + 1] = gn;
+      gg[jf] = cj * gj;
+      st[g].est = est;
+      st[g].j = j;
+      st[g].total = tot;
+      if (!live) st[g].active = 0;
+    }
     if (!sh_live) return;
   } else {
     if (lane == 0) {
@@ -279,18 +295,17 @@ __global__ __launch_bounds__(64) void k_dcgs_step(int nseg, int m, int j, int fi
   __syncthreads();
   double *hn = H + (long long)j * (m + 1);
   for (int i = lane; i <= j; i += 64) {
-    // the entries of row i of Hbar are read eight columns at a time (loads issued together),
-    // the sum still runs in ascending column order
+    // the entries of row i of Hbar are read 32 columns at a time (clamped loads issued
+    // together, no branch; column jf from LDS), the sum still runs in ascending column order
     double t = cc[i];
-    int k = i > 0 ? i - 1 : 0;
-    for (; k + 8 <= j; k += 8) {
-      double h[8];
+    for (int k = i > 0 ? i - 1 : 0; k < j; k += 32) {
+      double h[32];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) h[u] = H[(long long)(k + u) * (m + 1) + i];
+      for (int u = 0; u < 32; ++u) h[u] = H[(long long)min(k + u, j - 1) * (m + 1) + i];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) t -= h[u] * a[k + u];
+      for (int u = 0; u < 32; ++u)
+        if (k + u < j) t -= (k + u == jf ? hf[i] : h[u]) * a[k + u];
     }
-    for (; k < j; ++k) t -= H[(long long)k * (m + 1) + i] * a[k];
     hn[i] = t / rho;
   }
   double *cf = coef + (long long)g * (2 * m + 2);

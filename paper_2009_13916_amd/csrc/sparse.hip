@@ -521,17 +521,29 @@ __global__ __launch_bounds__(SPMV_T) void k_spmv_sell(const int *__restrict__ sp
                                                       double alpha, const void *b, double beta,
                                                       double gamma, int io, RowMask mk) {
   using A = typename AccT<V, X>::type;
-  if (all_off(mk)) return;
-  const int r = blockIdx.x * SPMV_T + threadIdx.x;   // position in the layout
-  if (r >= rows) return;
-  const int row = perm ? perm[r] : r;
-  if (row_off(mk, row)) return;
-  // a wavefront holds exactly one slice of 64 rows: its offset is a scalar load, issued
-  // (the empty asm keeps it from sinking below the length test) while the vector load of
-  // the row length is in flight
+  // Prologue without a branch before its loads: positions past the end are clamped to the
+  // last row (they load it and store nothing); the stop flag of a single system, the slice
+  // offset, the row length and the terms of the addend are all in flight before the first
+  // wait, and a row that stores nothing runs no entry round.
+  const int r0 = blockIdx.x * SPMV_T + threadIdx.x;   // position in the layout
+  const int r = min(r0, rows - 1);
+  const int flag = *(mk.act ? mk.act : sptr);           // any valid address without a mask
+  // a wavefront holds exactly one slice of 64 rows: its offset is a scalar load
   const int sb = sptr[__builtin_amdgcn_readfirstlane(r >> 6)];
-  const int n = rlen[r];
-  asm volatile("" ::"s"(sb));
+  const int n0 = rlen[r];
+  const int row = perm ? perm[r] : r;
+  double bd = 0;   // the addend as stored (converted where it is used)
+  float bf = 0;
+  X xr = 0;
+  if (b) {
+    if (io & 2)
+      bd = ((const double *)b)[row];
+    else
+      bf = ((const float *)b)[row];
+  }
+  if (gamma != 0.0) xr = x[row];
+  const bool live = r0 < rows && !(mk.act && !mk.seg && flag == 0) && !row_off(mk, row);
+  const int n = live ? n0 : 0;
   const int base = sb + (r & 63);
   A s[U];
 #pragma unroll
@@ -557,7 +569,15 @@ __global__ __launch_bounds__(SPMV_T) void k_spmv_sell(const int *__restrict__ sp
   for (int h = U / 2; h > 0; h >>= 1)
 #pragma unroll
     for (int u = 0; u < h; ++u) s[u] += s[u + h];
-  store_row<A, X>(y, b, io, row, s[0], alpha, beta, gamma, x);
+  if (!live) return;
+  // store_row's arithmetic with the addend terms loaded above
+  A out = (A)alpha * s[0];
+  if (b) out += (A)beta * (io & 2 ? (A)bd : (A)bf);
+  if (gamma != 0.0) out += (A)gamma * (A)xr;
+  if (io & 1)
+    ((double *)y)[row] = (double)out;
+  else
+    ((float *)y)[row] = (float)out;
 }
 
 // L lanes per row on the CSR arrays, for matrices with long rows: the lanes of a row read

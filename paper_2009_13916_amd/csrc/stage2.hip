@@ -199,13 +199,19 @@ __global__ __launch_bounds__(256) void k_jp_round(const int *__restrict__ srp,
                                                   int *ncolored, int *err) {
   const int slot = blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & 63;
-  int v = -1;
+  int v = -1, vs0 = 0, vls = 0, vt0 = 0, vlt = 0;
   bool need = false;
   if (slot < (list ? nlist : ne)) {
     v = list ? list[slot] : slot;
-    // the vertex's colour and its recorded blocker are loaded together (one latency, not two)
+    // the vertex's colour and its recorded blocker are loaded together (one latency, not
+    // two), and beside them the extents of its S~ and S~^T rows, which the full check below
+    // takes from this lane
     const int bv = blocker[v];
     const int cv = __atomic_load_n(&color[v], __ATOMIC_RELAXED);
+    vs0 = srp[v];
+    vls = srp[v + 1] - vs0;
+    vt0 = trp[v];
+    vlt = trp[v + 1] - vt0;
     if (cv < 0) need = !(bv >= 0 && __atomic_load_n(&color[bv], __ATOMIC_RELAXED) < 0);
   }
   unsigned long long work = __ballot(need);
@@ -220,11 +226,13 @@ __global__ __launch_bounds__(256) void k_jp_round(const int *__restrict__ srp,
         work &= work - 1;
       }
     }
-    const int w = __shfl(v, mine >= 0 ? mine : 0);
+    const int src = mine >= 0 ? mine : 0;
+    const int w = __shfl(v, src);
+    const int s0 = __shfl(vs0, src), ls = __shfl(vls, src);
+    const int t0 = __shfl(vt0, src), lt = __shfl(vlt, src);
     if (mine < 0) continue;
     const int c0 = grids[grid_of(grids, ngrid, w, true)].cell0;
     const unsigned pw = fmix32((unsigned)(w - c0));
-    const int s0 = srp[w], ls = srp[w + 1] - s0, t0 = trp[w], lt = trp[w + 1] - t0;
     const int tot = ls + lt;
     // JP_BATCH entries per lane: the neighbour indices, then their colours, are each one
     // batch of independent loads; the same colours serve the blocking test and the choice
